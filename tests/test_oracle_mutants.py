@@ -1,0 +1,90 @@
+"""Planted mistakes in a copy of the oracle must each fail at least one pin.
+
+Each mutant edits one expression of burgers_oracle.cpp (a dropped term, a flipped sign, a wrong index,
+swapped cyclic corners), compiles it into a temporary library on the CPU, swaps it in for the real one
+and runs the pin tests of test_oracle.py against it.  A mutant that passes every pin would mean the pins
+do not cover that part of the method.
+"""
+import ctypes
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle
+from oracle import build as obuild
+
+import test_oracle as T
+
+MUTANTS = {
+    "diffusion_sign": ("T lap = (up + um) - two * ui;", "T lap = (up - um) - two * ui;"),
+    "diffusion_dropped": ("+ D * lap;", "+ zero * lap;"),
+    "upwind_always_backward": ("- cneg * (up - ui))", "- cneg * (ui - um))"),
+    "upwind_direction_swapped": ("T cpos = c > zero ? c : zero;      // max(c, 0): backward difference",
+                                 "T cpos = c < zero ? c : zero;      // max(c, 0): backward difference"),
+    "periodic_wrap_index": ("um = u[i == 0 ? n - 1 : i - 1];", "um = u[i == 0 ? n - 2 : i - 1];"),
+    "dirichlet_left_value": ("um = (i == 1) ? a : u[i - 1];", "um = (i == 1) ? b : u[i - 1];"),
+    "btcs_diag_missing_D": ("d[k] = (one + two * D) + cabs;", "d[k] = one + cabs;"),
+    "btcs_sub_sign": ("l[k] = -(D + cpos);", "l[k] = (D + cpos);"),
+    "btcs_super_uses_cpos": ("p[k] = cneg - D;", "p[k] = -cpos - D;"),
+    "btcs_dirichlet_rhs": ("rhs[0] = rhs[0] - l[0] * a;", "rhs[0] = rhs[0] + l[0] * a;"),
+    "cyclic_corners_swapped": ("const T beta = l[0];\n  const T alpha = p[m - 1];",
+                               "const T beta = p[m - 1];\n  const T alpha = l[0];"),
+    "cyclic_gamma_sign": ("const T g = -d[0];", "const T g = d[0];"),
+    "thomas_back_sub": ("x[k] = yw[k] - cw[k] * x[k + 1];", "x[k] = yw[k] + cw[k] * x[k + 1];"),
+    "cfl_diffusive_factor": ("lim = std::min(lim, dx * dx / (2.0 * nu));", "lim = std::min(lim, dx * dx / nu);"),
+    "dx_dirichlet": ("length / (double)(n - 1);", "length / (double)n;"),
+    "cole_hopf_speed": ("std::fmod(x - 4.0 * t, two_pi)", "std::fmod(x - 3.0 * t, two_pi)"),
+}
+
+PINS = [name for name in dir(T) if name.startswith("test_")]
+
+
+def _call_pin(fn):
+    import inspect
+    params = inspect.signature(fn).parameters
+    marks = getattr(fn, "pytestmark", [])
+    cases = [dict()]
+    for m in marks:
+        if m.name == "parametrize":
+            argnames = [a.strip() for a in m.args[0].split(",")]
+            new = []
+            for c in cases:
+                for vals in m.args[1]:
+                    vals = vals if isinstance(vals, tuple) else (vals,)
+                    d = dict(c)
+                    d.update(zip(argnames, vals))
+                    new.append(d)
+            cases = new
+    for c in cases:
+        kwargs = {k: v for k, v in c.items() if k in params}
+        fn(oracle, **kwargs)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name):
+    src = open(obuild.SOURCE).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) >= 1, f"mutation site missing: {old!r}"
+    with tempfile.TemporaryDirectory() as tmp:
+        cpp = os.path.join(tmp, "mutant.cpp")
+        so = os.path.join(tmp, "libmutant.so")
+        open(cpp, "w").write(src.replace(old, new))
+        subprocess.run(["g++", "-O2", "-ffp-contract=off", "-fopenmp", "-std=c++17", "-shared", "-fPIC",
+                        "-o", so, cpp], check=True)
+        lib = oracle.configure(ctypes.CDLL(so))
+        saved = oracle._load()
+        oracle._lib = lib
+        failed = []
+        try:
+            for pin in PINS:
+                try:
+                    _call_pin(getattr(T, pin))
+                except Exception:                    # assertion, overflow or a non-converging loop
+                    failed.append(pin)
+                    break
+        finally:
+            oracle._lib = saved
+        assert failed, f"mutant {name} passed every pin"
