@@ -1,0 +1,253 @@
+"""Benchmark of the viscous-Burgers hot path on one MI355X.
+
+One step = the whole hot path over one batch: the 4096-instance periodic batch (N = 8192 each, FP64,
+nu ~ U[0.005, 0.1], eight-mode sine initial states) advanced 10^4 explicit steps at CFL 0.5 and then
+10^3 BTCS steps at ten times that dt.  value = grid-point updates per second over the step (GLUPS,
+inputs resident in HBM).  Per-kernel durations come from HIP events on the stream the kernels run on;
+the FP32 batch, the single-instance latency case and the long Dirichlet grid are reported beside it, as
+is the CPU oracle on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_VECTOR_PEAK = 78.6e12     # flop/s
+METRIC = "grid-point updates/sec (GLUPS) + % HBM roofline; served p50/p99 latency"
+
+
+def log(msg):
+    sys.stderr.write(f"[bench] {msg}\n")
+    sys.stderr.flush()
+
+
+def cfl_batch(B, batch, factor):
+    for i, p in enumerate(batch.problems):
+        p.dt = factor * B.burgers_cfl_dt(p, float(batch.umax[i]), 0.5)
+
+
+class PhaseTimer:
+    """HIP events recorded on the current torch stream, which is the stream the contexts launch on."""
+
+    def __init__(self):
+        import torch
+        self.torch = torch
+        self.marks = []
+
+    def mark(self, name):
+        ev = self.torch.cuda.Event(enable_timing=True)
+        ev.record()
+        self.marks.append((name, ev))
+
+    def spans(self):
+        self.torch.cuda.synchronize()
+        out = {}
+        for (n0, e0), (n1, e1) in zip(self.marks[:-1], self.marks[1:]):
+            out.setdefault(n0, []).append(e0.elapsed_time(e1))
+        return out
+
+
+def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000):
+    import workloads as W
+    batch = W.c2_batch()
+    exp_batch = W.c2_batch()
+    cfl_batch(B, exp_batch, 1.0)
+    btcs_batch = W.c2_batch()
+    cfl_batch(B, btcs_batch, 10.0)
+    s_exp = B.Solver(exp_batch.problems, dtype=dtype)
+    s_btcs = B.Solver(btcs_batch.problems, dtype=dtype)
+    u_init = s_exp.pack_flat(batch.u0, batch.offsets)
+    u = torch.empty_like(u_init)
+    timer = PhaseTimer()
+    for it in range(warmup + steps):
+        u.copy_(u_init)
+        if it == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        if it >= warmup:
+            timer.mark("explicit")
+        s_exp.step_explicit(u, n_exp)
+        if it >= warmup:
+            timer.mark("btcs")
+        s_btcs.step_btcs(u, n_btcs)
+        if it >= warmup:
+            timer.mark("copy")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s_exp.sync()
+    s_btcs.sync()
+    spans = timer.spans()
+    nodes = 4096 * 8192
+    exp_ms = float(np.mean(spans["explicit"]))
+    btcs_ms = float(np.mean(spans["btcs"]))
+    step_ms = exp_ms + btcs_ms
+    res = {
+        "updates_per_step": nodes * (n_exp + n_btcs),
+        "step_ms": step_ms,
+        "wall_ms_per_step": wall * 1e3 / steps,
+        "glups": nodes * (n_exp + n_btcs) / (step_ms * 1e-3) / 1e9,
+        "explicit_glups": nodes * n_exp / (exp_ms * 1e-3) / 1e9,
+        "btcs_glups": nodes * n_btcs / (btcs_ms * 1e-3) / 1e9,
+        "explicit_launch_ms": exp_ms / n_exp,
+        "btcs_step_ms": btcs_ms / n_btcs,
+        "plan_explicit": s_exp.get_plan(),
+        "plan_btcs": s_btcs.get_plan(),
+    }
+    s_exp.close()
+    s_btcs.close()
+    return res
+
+
+def bench_c1_latency(B, torch, solves=200):
+    """Single periodic N=101 sawtooth to t=0.5: latency of one whole solve (explicit 113 steps, BTCS 12)."""
+    import workloads as W
+    out = {}
+    for scheme, name, factor in ((W.EXPLICIT, "explicit", 1.0), (W.BTCS, "btcs", 10.0)):
+        b = W.c1_problem(scheme)
+        p = b.problems[0]
+        dtmax = factor * B.burgers_cfl_dt(p, float(b.umax[0]), 0.5)
+        nsteps = int(math.ceil(W.C1_T / dtmax))
+        p.dt = W.C1_T / nsteps
+        s = B.Solver([p], dtype=torch.float64)
+        u0 = s.pack_flat(b.u0, b.offsets)
+        u = torch.empty_like(u0)
+        lat = []
+        for i in range(solves + 5):
+            u.copy_(u0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            s.run(u, nsteps)
+            torch.cuda.synchronize()
+            if i >= 5:
+                lat.append((time.perf_counter() - t) * 1e3)
+        s.close()
+        out[name] = {"steps": nsteps, "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99))}
+    return out
+
+
+def bench_c3(B, torch, n_exp=1024, n_btcs=32):
+    import workloads as W
+    b = W.c3_problem()
+    p = b.problems[0]
+    p.dt = B.burgers_cfl_dt(p, float(b.umax[0]), 0.5)
+    s = B.Solver([p], dtype=torch.float64)
+    u = s.pack_flat(b.u0, b.offsets)
+    timer = PhaseTimer()
+    s.step_explicit(u, 8)
+    timer.mark("explicit")
+    s.step_explicit(u, n_exp)
+    timer.mark("end")
+    s.close()
+    q = W.c3_problem(scheme=W.BTCS).problems[0]
+    q.dt = 10 * p.dt
+    s2 = B.Solver([q], dtype=torch.float64)
+    s2.step_btcs(u, 2)
+    timer.mark("btcs")
+    s2.step_btcs(u, n_btcs)
+    timer.mark("end2")
+    spans = timer.spans()
+    s2.close()
+    upd = p.n - 2
+    return {"explicit_glups": upd * n_exp / (spans["explicit"][0] * 1e-3) / 1e9,
+            "btcs_glups": upd * n_btcs / (spans["btcs"][0] * 1e-3) / 1e9,
+            "explicit_steps": n_exp, "btcs_steps": n_btcs}
+
+
+def cpu_baseline(target_s=12.0):
+    """The oracle as it stands on the host cores, on a bounded sample of the same workload."""
+    import oracle
+    import workloads as W
+    threads = oracle.max_threads()
+    batch = W.c2_batch()
+    sub = W.subset(batch, range(min(4096, 4 * threads)))
+    for i, p in enumerate(sub.problems):
+        p.dt = oracle.cfl_dt(p.n, p.length, p.nu, p.bc, float(sub.umax[i]), 0.5)
+    # calibrate on a short run, then size the sample to about target_s
+    t = time.perf_counter()
+    oracle.run(sub.problems, sub.u0, sub.offsets, 20, scheme=W.EXPLICIT, threads=threads)
+    per_step = (time.perf_counter() - t) / 20
+    n_exp = max(20, int(0.9 * target_s / per_step / 10) * 10)
+    n_btcs = max(2, n_exp // 10)
+    t = time.perf_counter()
+    oracle.run(sub.problems, sub.u0, sub.offsets, n_exp, scheme=W.EXPLICIT, threads=threads)
+    t_exp = time.perf_counter() - t
+    for i, p in enumerate(sub.problems):
+        p.dt *= 10
+    t = time.perf_counter()
+    oracle.run(sub.problems, sub.u0, sub.offsets, n_btcs, scheme=W.BTCS, threads=threads)
+    t_btcs = time.perf_counter() - t
+    nodes = sub.count * 8192
+    glups = nodes * (n_exp + n_btcs) / (t_exp + t_btcs) / 1e9
+    return {"value": glups, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{sub.count} of the 4096 instances (N=8192, FP64), {n_exp} explicit + {n_btcs} BTCS "
+                      f"steps (same 10:1 step mix as the GPU step), {t_exp + t_btcs:.1f} s",
+            "explicit_glups": nodes * n_exp / t_exp / 1e9, "btcs_glups": nodes * n_btcs / t_btcs / 1e9}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--quick", action="store_true", help="skip the side measurements")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (instances shard "
+              "across GPUs without communication, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2601_12204_amd as B
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+
+    log("C2 FP64")
+    c2 = bench_c2(B, torch, torch.float64, args.steps, args.warmup)
+    extra = {"c2_f64": c2}
+    if not args.quick:
+        log("C2 FP32")
+        extra["c2_f32"] = bench_c2(B, torch, torch.float32, 1, 1)
+        log("C1 latency")
+        extra["c1_latency"] = bench_c1_latency(B, torch)
+        log("C3")
+        extra["c3_f64"] = bench_c3(B, torch)
+
+    # dominant kernel: the explicit step (10^4 launches per step)
+    word = 8
+    nodes = 4096 * 8192
+    bytes_per_launch = 2 * word * nodes
+    achieved = bytes_per_launch / (c2["explicit_launch_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": "explicit_stream_kernel<double>",
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        cpu = cpu_baseline()
+    line = {
+        "metric": METRIC, "value": c2["glups"], "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": c2["step_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "4096 periodic instances x N=8192 on [0,2pi], nu~U[0.005,0.1], 8-mode sine "
+                               "IC + 1; 1e4 explicit steps at CFL 0.5 then 1e3 BTCS steps at 10x dt",
+                   "instances": 4096, "n": 8192, "explicit_steps": 10_000, "btcs_steps": 1_000,
+                   "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

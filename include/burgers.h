@@ -1,0 +1,189 @@
+/*
+ * burgers.h - C ABI of the MI355X (gfx950) viscous-Burgers steppers.
+ *
+ * Method: Potluri et al., "Explicit and implicit finite difference solvers implemented in JAX for
+ * shock wave physics", arXiv 2601.12204.  The library advances batches of independent 1D viscous
+ * Burgers problems u_t + u u_x = nu u_xx (eq. 1) on uniform grids with
+ *   - the explicit forward-Euler step with first-order upwind convection and second-order central
+ *     diffusion (Sec. 2.3, eq. 21; the upwind side follows the sign of u_i as the text after eq. 3
+ *     describes), and
+ *   - the implicit BTCS step (Sec. 2.4, eq. 23): the spatial operator at t^{n+1} with its convective
+ *     coefficient lagged at u^n, i.e. one tridiagonal solve A(u^n) u^{n+1} = u^n per step, cyclic
+ *     under periodic boundaries (eq. 18) and plain under Dirichlet boundaries (eqs. 16-17).
+ *
+ * Conventions shared by every entry point
+ *   - Plain C types only; every pointer is either host memory (problem descriptions, offsets) or
+ *     device memory on the context's device (states, gradients).  Device buffers are owned by the
+ *     caller; the library never frees or reallocates them.
+ *   - Packed layout: instance b occupies elements [off[b], off[b] + n_b) of a state buffer, with off
+ *     from burgers_offsets().  Instance starts are aligned to BURGERS_ALIGN elements; the gaps are
+ *     padding that the library neither reads for results nor writes.  A uniform batch whose n is a
+ *     multiple of BURGERS_ALIGN is therefore plain row-major [count, n].
+ *   - Element type is the context's dtype (IEEE binary32 or binary64), for every device buffer.
+ *   - Calls enqueue work on the context's HIP stream and return without waiting.  Argument errors are
+ *     reported synchronously and leave the state untouched.  Device errors are sticky: they are
+ *     returned by the failing call if detected there, else by the next call or burgers_sync().
+ *   - A context is not thread-safe.  Distinct contexts on distinct streams may be used concurrently.
+ */
+#ifndef BURGERS_H
+#define BURGERS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BURGERS_ABI_VERSION 1
+#define BURGERS_ALIGN 64 /* instance start alignment in elements */
+
+typedef enum {
+  BURGERS_OK = 0,
+  BURGERS_E_INVALID = -1,     /* bad argument; nothing was enqueued */
+  BURGERS_E_UNSUPPORTED = -2, /* valid request this build cannot serve (e.g. a forced path that
+                                 does not fit the problem) */
+  BURGERS_E_NOMEM = -3,       /* device allocation failed; the context stays usable */
+  BURGERS_E_DEVICE = -4,      /* HIP runtime or kernel error (sticky) */
+  BURGERS_E_NONFINITE = -5,   /* reserved: non-finite values reported by a checking call */
+  BURGERS_E_BUDGET = -6       /* reserved: request exceeds a memory budget */
+} burgers_status;
+
+typedef enum { BURGERS_BC_PERIODIC = 0, BURGERS_BC_DIRICHLET = 1 } burgers_bc; /* eq. 18; eqs. 16-17 */
+typedef enum { BURGERS_EXPLICIT = 0, BURGERS_BTCS = 1 } burgers_scheme;       /* Sec. 2.3; Sec. 2.4 */
+typedef enum { BURGERS_F32 = 0, BURGERS_F64 = 1 } burgers_dtype;
+
+/*
+ * One problem instance (Sec. 2.2 and 2.5).
+ *   n       stored grid nodes, 3 <= n <= 2^31-1.  Periodic: nodes x_i = i*dx, dx = length/n, node n is
+ *           node 0 again (eq. 18).  Dirichlet: dx = length/(n-1); nodes 0 and n-1 hold left and right
+ *           (eqs. 16-17), and the n-2 interior nodes are the unknowns.
+ *   length  domain length L > 0.
+ *   nu      viscosity nu >= 0.
+ *   dt      time step > 0.  The CFL limits (eqs. 7-8) are NOT enforced: the paper studies runs beyond
+ *           them (Sec. 3.1); burgers_cfl_dt() computes a step inside them.
+ *   bc      burgers_bc.    scheme  burgers_scheme (used by burgers_run and burgers_adjoint).
+ *   left, right  Dirichlet values a, b; ignored for periodic instances.
+ * The kernels use r = dt/dx and D = nu*dt/dx^2, computed once in binary64 on the host and rounded to
+ * the working type.
+ */
+typedef struct {
+  int64_t n;
+  double length;
+  double nu;
+  double dt;
+  int32_t bc;
+  int32_t scheme;
+  double left;
+  double right;
+} burgers_problem;
+
+typedef struct burgers_ctx burgers_ctx; /* opaque */
+
+/*
+ * Kernel path selection.  0 means automatic (the library's tuned choice).  Forcing a path that cannot
+ * serve some instance makes the stepping call return BURGERS_E_UNSUPPORTED.
+ *   explicit_path  1 stream: one step per pass over HBM;
+ *                  2 resident: a whole instance held on chip for many steps (n <= resident limit);
+ *                  3 tiled: temporal blocking, tblock_depth steps per pass over HBM tiles.
+ *   tblock_depth   steps per HBM pass for path 3 (1..32), 0 = automatic.
+ *   btcs_path      1 workgroup: one workgroup solves one system per step (n <= workgroup limit);
+ *                  2 resident: one workgroup per system for many steps;
+ *                  3 multilevel: recursive partition across workgroups (any n).
+ *   use_graph      1 replays the launch sequence of a stepping call from a captured HIP graph,
+ *                  0 launches eagerly, -1 automatic.
+ */
+typedef struct {
+  int32_t explicit_path;
+  int32_t tblock_depth;
+  int32_t btcs_path;
+  int32_t use_graph;
+  int32_t reserved[4];
+} burgers_plan;
+
+/*
+ * Create a context for `count` instances (count >= 1) of element type `dtype` whose work is enqueued
+ * on `hip_stream` (a hipStream_t; NULL means the null stream) of the current device.  The problems
+ * are copied; the context owns its workspace (a second state buffer for ping-pong stepping and the
+ * solver's reduced systems), which is allocated here.
+ * Errors: BURGERS_E_INVALID for a NULL pointer, count < 1 or an invalid problem (n < 3, length <= 0,
+ * nu < 0, dt <= 0, bc or scheme out of range, any non-finite value); BURGERS_E_NOMEM when the
+ * workspace cannot be allocated; BURGERS_E_DEVICE for a HIP failure.  *out is NULL on error.
+ */
+burgers_status burgers_create(const burgers_problem* problems, int64_t count, burgers_dtype dtype,
+                              void* hip_stream, burgers_ctx** out);
+
+/* Release the context and its workspace after draining its stream.  NULL is a no-op. */
+void burgers_destroy(burgers_ctx* ctx);
+
+/* Write the count+1 packed offsets (host array, elements) of the state layout into out. */
+burgers_status burgers_offsets(const burgers_ctx* ctx, int64_t* out);
+
+/* Number of elements a state buffer must hold (= the last offset). */
+int64_t burgers_state_elems(const burgers_ctx* ctx);
+
+/*
+ * Advance every instance nsteps >= 0 explicit forward-Euler steps (Sec. 2.3, eq. 21, upwind side by
+ * the sign of u_i), whatever its `scheme`.  u: device state buffer in the packed layout, updated in
+ * place (the final state always lands in u).  Dirichlet nodes 0 and n-1 are set to left/right.
+ * Errors: BURGERS_E_INVALID (NULL ctx or u, nsteps < 0), BURGERS_E_UNSUPPORTED (forced path unfit),
+ * BURGERS_E_DEVICE.
+ */
+burgers_status burgers_step_explicit(burgers_ctx* ctx, void* u, int64_t nsteps);
+
+/*
+ * Advance every instance nsteps >= 0 BTCS steps (Sec. 2.4, eq. 23): solve
+ *   -(D + max(c_i,0)) u_{i-1} + (1 + 2D + |c_i|) u_i + (min(c_i,0) - D) u_{i+1} = u_i^n,
+ * c_i = r u_i^n, for u^{n+1}; periodic systems are cyclic, Dirichlet systems carry the boundary values
+ * on the right-hand side.  u as for burgers_step_explicit.  Errors as for burgers_step_explicit.
+ */
+burgers_status burgers_step_btcs(burgers_ctx* ctx, void* u, int64_t nsteps);
+
+/*
+ * Advance every instance nsteps >= 0 steps of its own `scheme` (explicit and BTCS instances may be
+ * mixed in one context).  u as for burgers_step_explicit.  Errors as for burgers_step_explicit.
+ */
+burgers_status burgers_run(burgers_ctx* ctx, void* u, int64_t nsteps);
+
+/*
+ * Discrete adjoint of burgers_run (the paper differentiates its solvers by reverse-mode AD, Sec. 2.7.1
+ * and 2.7.3).  Given the initial state u0 and lambda_T = dJ/du(t_T) after nsteps steps of each
+ * instance's scheme, write grad_u0 = dJ/du0 (packed layout) and grad_nu[b] = dJ/dnu_b (count values,
+ * element type of the context).  Forward states are recomputed from checkpoints stored every
+ * ckpt_every >= 1 steps.  All four pointers are device memory; u0 and lambda_T are not modified.
+ * Dirichlet boundary nodes are constants, so their entries of grad_u0 are zero.  The upwind switch is
+ * differentiated on its u_i >= 0 branch at u_i = 0.
+ * Errors: BURGERS_E_INVALID, BURGERS_E_NOMEM (checkpoint storage), BURGERS_E_DEVICE.
+ */
+burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lambda_T, int64_t nsteps,
+                               int64_t ckpt_every, void* grad_u0, void* grad_nu);
+
+/* Wait for the context's stream and return the first sticky device error, if any. */
+burgers_status burgers_sync(burgers_ctx* ctx);
+
+/* Read or force the kernel path selection (see burgers_plan). */
+burgers_status burgers_get_plan(const burgers_ctx* ctx, burgers_plan* out);
+burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan);
+
+/* Static text for a status code. */
+const char* burgers_status_string(burgers_status status);
+
+/*
+ * Time step inside the CFL limits of eqs. 7-8 with safety factor sigma:
+ *   dt = sigma * min(dx / umax, dx^2 / (2 nu)),
+ * dx from p->n, p->length and p->bc (p->dt is ignored).  A zero umax or nu drops that limit; returns
+ * +inf when both are zero and NaN for an invalid p or sigma <= 0.  With sigma = 0.5 the step satisfies
+ * |C| + 2D <= 1, the condition under which every explicit update is a convex combination.
+ */
+double burgers_cfl_dt(const burgers_problem* p, double umax, double sigma);
+
+/* r = dt/dx and D = nu dt/dx^2 of a problem, in binary64, exactly as the kernels receive them. */
+burgers_status burgers_ratios(const burgers_problem* p, double* r, double* D);
+
+/* ABI version of the loaded library (BURGERS_ABI_VERSION at build time). */
+int32_t burgers_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BURGERS_H */

@@ -209,3 +209,18 @@ def rms(a: np.ndarray, ref: np.ndarray) -> float:
     """Root-mean-square error, the paper's L2 norm (Nomenclature)."""
     d = np.asarray(a, dtype=np.float64) - np.asarray(ref, dtype=np.float64)
     return float(np.sqrt(np.mean(d * d)))
+
+
+def run_ratios(u: np.ndarray, bc: int, a: float, b: float, r: float, D: float, nsteps: int,
+               scheme: int = 0) -> np.ndarray:
+    """Advance one instance with given r and D (used to follow the dependency cone of a few nodes of a
+    long grid: a window of half-width k + 1 around a node, with its ends held, reproduces that node after
+    k explicit steps)."""
+    out = np.array(u, copy=True, order="C")
+    offs = np.array([0, len(out)], dtype=np.int64)
+    one = lambda v, t: np.array([v], dtype=t)
+    getattr(_load(), f"oracle_run_{_tag(out.dtype)}")(1, _ptr(offs), _ptr(one(bc, np.int32)),
+                                                      _ptr(one(scheme, np.int32)), _ptr(one(r, np.float64)),
+                                                      _ptr(one(D, np.float64)), _ptr(one(a, np.float64)),
+                                                      _ptr(one(b, np.float64)), _ptr(out), nsteps, 1)
+    return out

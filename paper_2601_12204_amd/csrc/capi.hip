@@ -1,0 +1,365 @@
+// C ABI and host runtime of the gfx950 Burgers library: contexts, packed layout, launch plans and the
+// stepping loops (ping-pong between the caller's state buffer and the context's second buffer).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+
+using burgers::ChunkBlock;
+using burgers::DevBuf;
+using burgers::InstDesc;
+using burgers::SysDesc;
+using burgers::Tile;
+
+namespace {
+
+enum SetId { kSetAll = 0, kSetExplicit = 1, kSetBtcs = 2 };
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+double grid_dx(const burgers_problem& p) {
+  return p.bc == BURGERS_BC_PERIODIC ? p.length / static_cast<double>(p.n)
+                                     : p.length / static_cast<double>(p.n - 1);
+}
+
+bool valid_problem(const burgers_problem& p) {
+  if (p.n < 3 || p.n > INT32_MAX) return false;
+  if (!is_finite(p.length) || p.length <= 0) return false;
+  if (!is_finite(p.nu) || p.nu < 0) return false;
+  if (!is_finite(p.dt) || p.dt <= 0) return false;
+  if (p.bc != BURGERS_BC_PERIODIC && p.bc != BURGERS_BC_DIRICHLET) return false;
+  if (p.scheme != BURGERS_EXPLICIT && p.scheme != BURGERS_BTCS) return false;
+  if (!is_finite(p.left) || !is_finite(p.right)) return false;
+  return true;
+}
+
+burgers_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return BURGERS_OK;
+  if (e == hipErrorOutOfMemory) return BURGERS_E_NOMEM;
+  return BURGERS_E_DEVICE;
+}
+
+// Record a device error as sticky and translate it.
+burgers_status note(burgers_ctx* ctx, hipError_t e) {
+  if (e != hipSuccess && ctx->sticky == hipSuccess) ctx->sticky = e;
+  return from_hip(e);
+}
+
+const std::vector<int32_t>& set_members(const burgers_ctx* ctx, int set) {
+  return set == kSetAll ? ctx->set_all : (set == kSetExplicit ? ctx->set_explicit : ctx->set_btcs);
+}
+
+template <typename T>
+hipError_t upload(DevBuf& buf, const std::vector<T>& v) {
+  hipError_t e = buf.alloc(v.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  if (v.empty()) return hipSuccess;
+  return hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Streaming tiles of one instance subset.
+hipError_t ensure_tiles(burgers_ctx* ctx, int set) {
+  if (ctx->tiles.count(set)) return hipSuccess;
+  const int tile = burgers::explicit_tile_nodes(ctx->dtype);
+  std::vector<Tile> tiles;
+  for (int32_t i : set_members(ctx, set)) {
+    const int32_t n = static_cast<int32_t>(ctx->probs[i].n);
+    for (int32_t s = 0; s < n; s += tile) tiles.push_back(Tile{i, s});
+  }
+  auto buf = std::make_unique<DevBuf>();
+  hipError_t e = upload(*buf, tiles);
+  if (e != hipSuccess) return e;
+  ctx->n_tiles[set] = static_cast<int64_t>(tiles.size());
+  ctx->tiles[set] = std::move(buf);
+  return hipSuccess;
+}
+
+// BTCS launch plan of one instance subset: whole-system solves for short systems, partition levels for
+// long ones.  Reduced-system rows are carved from the context's level arrays.
+hipError_t ensure_btcs(burgers_ctx* ctx, int set) {
+  if (ctx->btcs.count(set)) return hipSuccess;
+  auto plan = std::make_unique<burgers::BtcsPlan>();
+  const int cap = burgers::btcs_wg_capacity();
+  const int chunk = burgers::btcs_reduce_chunk();
+  std::vector<SysDesc> wg_state;
+  std::vector<std::vector<SysDesc>> red_sys, wg_sys;
+  int64_t rows_used = 0;
+  for (int32_t i : set_members(ctx, set)) {
+    const burgers_problem& p = ctx->probs[i];
+    const int32_t R0 = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
+    if (R0 <= cap) {
+      wg_state.push_back(SysDesc{0, -1, R0, burgers::btcs_wg_chunks(R0), i, 0});
+      continue;
+    }
+    int32_t R = R0;
+    int64_t in_off = 0;
+    for (int level = 0;; ++level) {
+      if (static_cast<int>(red_sys.size()) <= level) {
+        red_sys.resize(level + 1);
+        wg_sys.resize(level + 1);
+      }
+      if (level > 0 && R <= cap) {
+        wg_sys[level].push_back(SysDesc{in_off, -1, R, burgers::btcs_wg_chunks(R), i, level});
+        break;
+      }
+      const int32_t P = (R + chunk - 1) / chunk;
+      const int64_t red = rows_used;
+      rows_used += 2 * static_cast<int64_t>(P);
+      red_sys[level].push_back(SysDesc{in_off, red, R, P, i, level});
+      in_off = red;
+      R = 2 * P;
+    }
+  }
+  if (rows_used > ctx->level_capacity) return hipErrorOutOfMemory;   // sized at create
+  plan->level_rows = rows_used;
+  plan->n_wg_state = static_cast<int32_t>(wg_state.size());
+  plan->wg_state = std::make_unique<DevBuf>();
+  hipError_t e = upload(*plan->wg_state, wg_state);
+  if (e != hipSuccess) return e;
+  plan->levels.resize(red_sys.size());
+  for (size_t l = 0; l < red_sys.size(); ++l) {
+    auto& lv = plan->levels[l];
+    std::vector<ChunkBlock> blocks;
+    for (size_t si = 0; si < red_sys[l].size(); ++si)
+      for (int32_t c = 0; c < red_sys[l][si].chunks; c += burgers::kReduceBlock)
+        blocks.push_back(ChunkBlock{static_cast<int32_t>(si), c});
+    lv.sys = std::make_unique<DevBuf>();
+    lv.blocks = std::make_unique<DevBuf>();
+    lv.wg = std::make_unique<DevBuf>();
+    if ((e = upload(*lv.sys, red_sys[l])) != hipSuccess) return e;
+    if ((e = upload(*lv.blocks, blocks)) != hipSuccess) return e;
+    if ((e = upload(*lv.wg, wg_sys[l])) != hipSuccess) return e;
+    lv.n_blocks = static_cast<int32_t>(blocks.size());
+    lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
+  }
+  ctx->btcs[set] = std::move(plan);
+  return hipSuccess;
+}
+
+// Rows of the partition levels all long instances need (upper bound used to size the level arrays).
+int64_t level_rows_needed(const burgers_ctx* ctx) {
+  const int cap = burgers::btcs_wg_capacity();
+  const int chunk = burgers::btcs_reduce_chunk();
+  int64_t rows = 0;
+  for (const auto& p : ctx->probs) {
+    int64_t R = p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2;
+    if (R <= cap) continue;
+    for (int level = 0;; ++level) {
+      if (level > 0 && R <= cap) break;
+      const int64_t P = (R + chunk - 1) / chunk;
+      rows += 2 * P;
+      R = 2 * P;
+    }
+  }
+  return rows;
+}
+
+// One step of every instance of `set` from src into dst with `scheme` (-1: each instance's own).
+hipError_t enqueue_step(burgers_ctx* ctx, int set, int scheme, const void* src, void* dst) {
+  hipError_t e = hipSuccess;
+  if (scheme == BURGERS_EXPLICIT) {
+    return burgers::launch_explicit_stream(ctx, ctx->tiles[set]->as<Tile>(), ctx->n_tiles[set], src,
+                                           dst);
+  }
+  if (scheme == BURGERS_BTCS) return burgers::launch_btcs_step(ctx, *ctx->btcs[set], src, dst);
+  // mixed: the explicit members, then the BTCS members
+  if (!ctx->set_explicit.empty()) {
+    e = burgers::launch_explicit_stream(ctx, ctx->tiles[kSetExplicit]->as<Tile>(),
+                                        ctx->n_tiles[kSetExplicit], src, dst);
+    if (e != hipSuccess) return e;
+  }
+  if (!ctx->set_btcs.empty()) e = burgers::launch_btcs_step(ctx, *ctx->btcs[kSetBtcs], src, dst);
+  return e;
+}
+
+hipError_t prepare(burgers_ctx* ctx, int set, int scheme) {
+  hipError_t e = hipSuccess;
+  const bool need_explicit = scheme == BURGERS_EXPLICIT || (scheme < 0 && !ctx->set_explicit.empty());
+  const bool need_btcs = scheme == BURGERS_BTCS || (scheme < 0 && !ctx->set_btcs.empty());
+  const int es = scheme < 0 ? kSetExplicit : set;
+  const int bs = scheme < 0 ? kSetBtcs : set;
+  if (need_explicit && (e = ensure_tiles(ctx, es)) != hipSuccess) return e;
+  if (need_btcs && (e = ensure_btcs(ctx, bs)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+// nsteps steps with ping-pong; the final state lands in u.
+burgers_status advance(burgers_ctx* ctx, void* u, int64_t nsteps, int set, int scheme) {
+  if (!ctx || !u || nsteps < 0) return BURGERS_E_INVALID;
+  if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
+  if (nsteps == 0) return BURGERS_OK;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return note(ctx, e);
+  if ((e = prepare(ctx, set, scheme)) != hipSuccess) return note(ctx, e);
+  void* bufs[2] = {u, ctx->work.ptr};
+  int cur = 0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    e = enqueue_step(ctx, set, scheme, bufs[cur], bufs[cur ^ 1]);
+    if (e != hipSuccess) return note(ctx, e);
+    cur ^= 1;
+  }
+  if (cur != 0) {
+    e = hipMemcpyAsync(u, ctx->work.ptr, static_cast<size_t>(ctx->total) * ctx->word,
+                       hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) return note(ctx, e);
+  }
+  return BURGERS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t burgers_abi_version(void) { return BURGERS_ABI_VERSION; }
+
+const char* burgers_status_string(burgers_status s) {
+  switch (s) {
+    case BURGERS_OK: return "ok";
+    case BURGERS_E_INVALID: return "invalid argument";
+    case BURGERS_E_UNSUPPORTED: return "unsupported request";
+    case BURGERS_E_NOMEM: return "out of device memory";
+    case BURGERS_E_DEVICE: return "device error";
+    case BURGERS_E_NONFINITE: return "non-finite value";
+    case BURGERS_E_BUDGET: return "memory budget exceeded";
+  }
+  return "unknown status";
+}
+
+double burgers_cfl_dt(const burgers_problem* p, double umax, double sigma) {
+  if (!p || p->n < 3 || !(p->length > 0) || !is_finite(p->length) || !(p->nu >= 0) ||
+      !(sigma > 0) || !(umax >= 0) || (p->bc != BURGERS_BC_PERIODIC && p->bc != BURGERS_BC_DIRICHLET))
+    return NAN;
+  const double dx = grid_dx(*p);
+  double lim = INFINITY;
+  if (umax > 0) lim = std::min(lim, dx / umax);
+  if (p->nu > 0) lim = std::min(lim, dx * dx / (2.0 * p->nu));
+  return sigma * lim;
+}
+
+burgers_status burgers_ratios(const burgers_problem* p, double* r, double* D) {
+  if (!p || !r || !D || !valid_problem(*p)) return BURGERS_E_INVALID;
+  const double dx = grid_dx(*p);
+  *r = p->dt / dx;
+  *D = p->nu * p->dt / (dx * dx);
+  return BURGERS_OK;
+}
+
+burgers_status burgers_create(const burgers_problem* problems, int64_t count, burgers_dtype dtype,
+                              void* hip_stream, burgers_ctx** out) {
+  if (!out) return BURGERS_E_INVALID;
+  *out = nullptr;
+  if (!problems || count < 1 || (dtype != BURGERS_F32 && dtype != BURGERS_F64))
+    return BURGERS_E_INVALID;
+  for (int64_t i = 0; i < count; ++i)
+    if (!valid_problem(problems[i])) return BURGERS_E_INVALID;
+  if (count > INT32_MAX) return BURGERS_E_INVALID;
+  burgers_ctx* ctx = new (std::nothrow) burgers_ctx();
+  if (!ctx) return BURGERS_E_NOMEM;
+  hipError_t e = hipGetDevice(&ctx->device);
+  if (e != hipSuccess) { delete ctx; return BURGERS_E_DEVICE; }
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  ctx->dtype = dtype;
+  ctx->word = dtype == BURGERS_F64 ? 8 : 4;
+  ctx->count = count;
+  ctx->probs.assign(problems, problems + count);
+  ctx->offsets.resize(count + 1);
+  ctx->offsets[0] = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t padded = (problems[i].n + BURGERS_ALIGN - 1) / BURGERS_ALIGN * BURGERS_ALIGN;
+    ctx->offsets[i + 1] = ctx->offsets[i] + padded;
+  }
+  ctx->total = ctx->offsets[count];
+  ctx->inst_host.resize(count);
+  for (int64_t i = 0; i < count; ++i) {
+    const burgers_problem& p = problems[i];
+    InstDesc& d = ctx->inst_host[i];
+    d.off = ctx->offsets[i];
+    d.n = static_cast<int32_t>(p.n);
+    d.bc = p.bc;
+    burgers_ratios(&p, &d.r, &d.D);
+    d.a = p.bc == BURGERS_BC_DIRICHLET ? p.left : 0.0;
+    d.b = p.bc == BURGERS_BC_DIRICHLET ? p.right : 0.0;
+    ctx->set_all.push_back(static_cast<int32_t>(i));
+    (p.scheme == BURGERS_EXPLICIT ? ctx->set_explicit : ctx->set_btcs).push_back(static_cast<int32_t>(i));
+  }
+  burgers_status st = BURGERS_OK;
+  if ((e = upload(ctx->inst, ctx->inst_host)) != hipSuccess) st = from_hip(e);
+  if (st == BURGERS_OK && (e = ctx->work.alloc(static_cast<size_t>(ctx->total) * ctx->word)) != hipSuccess)
+    st = from_hip(e);
+  if (st == BURGERS_OK) {
+    ctx->level_capacity = level_rows_needed(ctx);
+    const size_t lb = static_cast<size_t>(ctx->level_capacity) * sizeof(double);   // binary64 solve
+    if ((e = ctx->level_a.alloc(lb)) != hipSuccess || (e = ctx->level_c.alloc(lb)) != hipSuccess ||
+        (e = ctx->level_d.alloc(lb)) != hipSuccess || (e = ctx->level_x.alloc(lb)) != hipSuccess)
+      st = from_hip(e);
+  }
+  if (st != BURGERS_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return BURGERS_OK;
+}
+
+void burgers_destroy(burgers_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  delete ctx;
+}
+
+burgers_status burgers_offsets(const burgers_ctx* ctx, int64_t* out) {
+  if (!ctx || !out) return BURGERS_E_INVALID;
+  std::memcpy(out, ctx->offsets.data(), sizeof(int64_t) * ctx->offsets.size());
+  return BURGERS_OK;
+}
+
+int64_t burgers_state_elems(const burgers_ctx* ctx) { return ctx ? ctx->total : -1; }
+
+burgers_status burgers_step_explicit(burgers_ctx* ctx, void* u, int64_t nsteps) {
+  return advance(ctx, u, nsteps, kSetAll, BURGERS_EXPLICIT);
+}
+
+burgers_status burgers_step_btcs(burgers_ctx* ctx, void* u, int64_t nsteps) {
+  return advance(ctx, u, nsteps, kSetAll, BURGERS_BTCS);
+}
+
+burgers_status burgers_run(burgers_ctx* ctx, void* u, int64_t nsteps) {
+  return advance(ctx, u, nsteps, kSetAll, -1);
+}
+
+burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lambda_T, int64_t nsteps,
+                               int64_t ckpt_every, void* grad_u0, void* grad_nu) {
+  if (!ctx || !u0 || !lambda_T || !grad_u0 || !grad_nu || nsteps < 0 || ckpt_every < 1)
+    return BURGERS_E_INVALID;
+  return BURGERS_E_UNSUPPORTED;
+}
+
+burgers_status burgers_sync(burgers_ctx* ctx) {
+  if (!ctx) return BURGERS_E_INVALID;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  note(ctx, e);
+  return from_hip(ctx->sticky);
+}
+
+burgers_status burgers_get_plan(const burgers_ctx* ctx, burgers_plan* out) {
+  if (!ctx || !out) return BURGERS_E_INVALID;
+  *out = ctx->plan;
+  return BURGERS_OK;
+}
+
+burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan) {
+  if (!ctx || !plan) return BURGERS_E_INVALID;
+  if (plan->explicit_path < 0 || plan->explicit_path > 3 || plan->btcs_path < 0 || plan->btcs_path > 3 ||
+      plan->tblock_depth < 0 || plan->tblock_depth > 32 || plan->use_graph < -1 || plan->use_graph > 1)
+    return BURGERS_E_INVALID;
+  ctx->plan = *plan;
+  return BURGERS_OK;
+}
+
+}  // extern "C"
