@@ -58,6 +58,7 @@ class PhaseTimer:
 
 
 def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000):
+    """Time `steps` passes (after `warmup`) of the explicit and BTCS runs over the 4096 x 8192 batch."""
     import workloads as W
     batch = W.c2_batch()
     exp_batch = W.c2_batch()
@@ -89,6 +90,7 @@ def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000):
     spans = timer.spans()
     nodes = 4096 * 8192
     exp_ms = float(np.mean(spans["explicit"]))
+    n_exp, n_btcs = max(n_exp, 1), max(n_btcs, 1)
     btcs_ms = float(np.mean(spans["btcs"]))
     step_ms = exp_ms + btcs_ms
     res = {
@@ -173,11 +175,18 @@ def cpu_baseline(target_s=12.0):
     sub = W.subset(batch, range(min(4096, 4 * threads)))
     for i, p in enumerate(sub.problems):
         p.dt = oracle.cfl_dt(p.n, p.length, p.nu, p.bc, float(sub.umax[i]), 0.5)
-    # calibrate on a short run, then size the sample to about target_s
+    # calibrate both legs on short runs, then size the sample (10:1 step mix) to about target_s
     t = time.perf_counter()
     oracle.run(sub.problems, sub.u0, sub.offsets, 20, scheme=W.EXPLICIT, threads=threads)
-    per_step = (time.perf_counter() - t) / 20
-    n_exp = max(20, int(0.9 * target_s / per_step / 10) * 10)
+    per_exp = (time.perf_counter() - t) / 20
+    for i, p in enumerate(sub.problems):
+        p.dt *= 10
+    t = time.perf_counter()
+    oracle.run(sub.problems, sub.u0, sub.offsets, 2, scheme=W.BTCS, threads=threads)
+    per_btcs = (time.perf_counter() - t) / 2
+    for i, p in enumerate(sub.problems):
+        p.dt /= 10
+    n_exp = max(20, int(target_s / (per_exp + per_btcs / 10) / 10) * 10)
     n_btcs = max(2, n_exp // 10)
     t = time.perf_counter()
     oracle.run(sub.problems, sub.u0, sub.offsets, n_exp, scheme=W.EXPLICIT, threads=threads)
@@ -202,6 +211,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--exp-steps", type=int, default=10_000, help="explicit steps per step (profiling runs)")
+    ap.add_argument("--btcs-steps", type=int, default=1_000, help="BTCS steps per step (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (instances shard "
@@ -213,7 +224,7 @@ def main():
     torch.cuda.set_device(0)
 
     log("C2 FP64")
-    c2 = bench_c2(B, torch, torch.float64, args.steps, args.warmup)
+    c2 = bench_c2(B, torch, torch.float64, args.steps, args.warmup, args.exp_steps, args.btcs_steps)
     extra = {"c2_f64": c2}
     if not args.quick:
         log("C2 FP32")
@@ -242,7 +253,8 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "4096 periodic instances x N=8192 on [0,2pi], nu~U[0.005,0.1], 8-mode sine "
                                "IC + 1; 1e4 explicit steps at CFL 0.5 then 1e3 BTCS steps at 10x dt",
-                   "instances": 4096, "n": 8192, "explicit_steps": 10_000, "btcs_steps": 1_000,
+                   "instances": 4096, "n": 8192, "explicit_steps": args.exp_steps,
+                   "btcs_steps": args.btcs_steps,
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
     }

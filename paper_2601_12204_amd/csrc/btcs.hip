@@ -27,34 +27,16 @@
 namespace burgers {
 namespace {
 
-constexpr int kWgThreads = 256;   // threads of the whole-system solver
-constexpr int kWgChunk = 32;      // longest chunk a thread of the whole-system solver eliminates
+constexpr int kWgThreads = 512;   // threads of the whole-system solver
+constexpr int kWgChunk = 16;      // longest chunk a thread of the whole-system solver eliminates
 constexpr int kRedChunk = 16;     // chunk length in the partition levels
+constexpr int kWgRows = kWgThreads * kWgChunk;            // longest system solved whole
+constexpr int kRedRows = kReduceBlock * kRedChunk;        // rows one partition workgroup stages
 
-// Rows of a level-0 system, assembled from the old state (type S) of one instance.
-template <typename S>
-struct StateRows {
-  const S* __restrict__ u;   // node 0 of the instance
-  double r, D, a, b;
-  int first;                 // node of row 0: 0 periodic, 1 Dirichlet
-  bool dirichlet;
-  __device__ __forceinline__ void row(int k, int R, double& al, double& be, double& ga,
-                                      double& de) const {
-    const double ui = static_cast<double>(u[first + k]);
-    btcs_row(ui, r, D, al, be, ga);
-    de = ui;
-    if (dirichlet) {
-      if (k == 0) { de = de - al * a; al = 0.0; }
-      if (k == R - 1) { de = de - ga * b; ga = 0.0; }
-    }
-  }
-};
-
-template <typename S>
-__device__ __forceinline__ StateRows<S> state_rows(const InstDesc& d, const S* u) {
-  const bool dir = d.bc == kDirichlet;
-  return StateRows<S>{u + d.off, d.r, d.D, d.a, d.b, dir ? 1 : 0, dir};
-}
+// Rows staged in LDS are padded by one element every 32 rows: a thread reads its chunk with a lane
+// stride of q rows, and without the pad q = 16 or 32 would put every lane of a wave on one bank.
+__device__ __forceinline__ int padded(int i) { return i + (i >> 5); }
+constexpr int padded_size(int rows) { return rows + rows / 32 + 1; }
 
 // Rows of a reduced system stored with unit diagonal.
 template <typename T>
@@ -68,6 +50,33 @@ struct ArrayRows {
     ga = C[k];
     de = Dv[k];
   }
+};
+
+// Rows of a level-0 system whose old values sit in LDS (staged coalesced from HBM); row k is held at
+// padded(k - base).
+template <typename S>
+struct LdsRows {
+  const S* st;
+  int base;
+  double r, D, a, b;
+  bool dirichlet;
+  __device__ __forceinline__ void row(int k, int R, double& al, double& be, double& ga,
+                                      double& de) const {
+    const double ui = static_cast<double>(st[padded(k - base)]);
+    btcs_row(ui, r, D, al, be, ga);
+    de = ui;
+    if (dirichlet) {
+      if (k == 0) { de = de - al * a; al = 0.0; }
+      if (k == R - 1) { de = de - ga * b; ga = 0.0; }
+    }
+  }
+};
+
+template <typename S>
+struct LdsDst {
+  S* st;
+  int base;
+  __device__ __forceinline__ void write(int k, double v) const { st[padded(k - base)] = static_cast<S>(v); }
 };
 
 // Chunk elimination.  Rows s..s+m-1 (2 <= m <= M) of a system with R rows.  On return, for
@@ -197,31 +206,47 @@ __device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, int R2) {
   __syncthreads();
 }
 
-// Whole-system solver: one workgroup per system.  Level-0 systems read the old state and write the
-// new state (and the Dirichlet boundary nodes); reduced systems read (A, C, D) and write X.
+// Whole-system solver: one workgroup per system.  Level-0 systems stage the old state through LDS
+// (coalesced loads), eliminate chunks from LDS, solve the reduced system by PCR in the same LDS, write
+// the new values back into the staging buffer and store them coalesced, with the Dirichlet boundary
+// nodes.  Reduced systems of the partition levels read (A, C, D) and write X in HBM directly.
 template <typename S, bool FromState>
-__global__ __launch_bounds__(kWgThreads) void btcs_wg_kernel(
+__global__ __launch_bounds__(kWgThreads, 4) void btcs_wg_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, const S* __restrict__ u,
     S* __restrict__ out, const double* __restrict__ LA, const double* __restrict__ LC,
     const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
-  __shared__ T sA[2 * kWgThreads], sB[2 * kWgThreads], sC[2 * kWgThreads], sD[2 * kWgThreads];
+  constexpr int kPcrBytes = 4 * 2 * kWgThreads * static_cast<int>(sizeof(T));
+  constexpr int kStageBytes = FromState ? padded_size(kWgRows) * static_cast<int>(sizeof(S)) : 0;
+  constexpr int kBytes = kStageBytes > kPcrBytes ? kStageBytes : kPcrBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  T* sA = reinterpret_cast<T*>(smem);
+  T* sB = sA + 2 * kWgThreads;
+  T* sC = sB + 2 * kWgThreads;
+  T* sD = sC + 2 * kWgThreads;
+  S* stage = reinterpret_cast<S*>(smem);
+
   const SysDesc sys = systems[blockIdx.x];
   const int R = sys.rows, P = sys.chunks;
   const int tid = threadIdx.x;
 
-  StateRows<S> ssrc{};
+  LdsRows<S> ssrc{};
   ArrayRows<T> asrc{};
-  PtrDst<S> sdst{};
+  LdsDst<S> sdst{};
   PtrDst<T> adst{};
+  InstDesc d{};
   if constexpr (FromState) {
-    const InstDesc d = inst[sys.inst];
-    ssrc = state_rows(d, u);
-    sdst.x = out + d.off + ssrc.first;
-    if (ssrc.dirichlet && tid == 0) {
+    d = inst[sys.inst];
+    const bool dir = d.bc == kDirichlet;
+    const S* src = u + d.off + (dir ? 1 : 0);
+    for (int i = tid; i < R; i += kWgThreads) stage[padded(i)] = src[i];
+    ssrc = LdsRows<S>{stage, 0, d.r, d.D, d.a, d.b, dir};
+    sdst = LdsDst<S>{stage, 0};
+    if (dir && tid == 0) {
       out[d.off] = static_cast<S>(d.a);
       out[d.off + d.n - 1] = static_cast<S>(d.b);
     }
+    __syncthreads();
   } else {
     asrc = ArrayRows<T>{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
     adst.x = LX + sys.in_off;
@@ -232,7 +257,7 @@ __global__ __launch_bounds__(kWgThreads) void btcs_wg_kernel(
       T al, be, ga, de;
       if constexpr (FromState) {
         ssrc.row(0, 1, al, be, ga, de);
-        sdst.write(0, de / be);
+        out[d.off + 1] = static_cast<S>(de / be);
       } else {
         asrc.row(0, 1, al, be, ga, de);
         adst.write(0, de / be);
@@ -251,41 +276,74 @@ __global__ __launch_bounds__(kWgThreads) void btcs_wg_kernel(
     } else {
       chunk_eliminate<T, kWgChunk>(asrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
     }
+  }
+  if constexpr (FromState) __syncthreads();   // the PCR arrays overlay the staged rows
+  if (tid < P) {
     sA[2 * tid] = AF; sB[2 * tid] = T(1); sC[2 * tid] = CF; sD[2 * tid] = DF;
     sA[2 * tid + 1] = AE; sB[2 * tid + 1] = T(1); sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
   }
   __syncthreads();
   pcr_cyclic<T, kWgThreads>(sA, sB, sC, sD, 2 * P);
+  T F = T(0), E = T(0);
   if (tid < P) {
-    if constexpr (FromState) {
-      chunk_recover<T, kWgChunk>(sdst, s, m, al, ga, de, sD[2 * tid], sD[2 * tid + 1]);
-    } else {
-      chunk_recover<T, kWgChunk>(adst, s, m, al, ga, de, sD[2 * tid], sD[2 * tid + 1]);
-    }
+    F = sD[2 * tid];
+    E = sD[2 * tid + 1];
+  }
+  if constexpr (FromState) {
+    __syncthreads();                           // all ends read before the staging buffer is reused
+    if (tid < P) chunk_recover<T, kWgChunk>(sdst, s, m, al, ga, de, F, E);
+    __syncthreads();
+    S* dst = out + d.off + (d.bc == kDirichlet ? 1 : 0);
+    for (int i = tid; i < R; i += kWgThreads) dst[i] = stage[padded(i)];
+  } else {
+    if (tid < P) chunk_recover<T, kWgChunk>(adst, s, m, al, ga, de, F, E);
+  }
+}
+
+// Rows [rs, re) of the chunks a partition workgroup owns: chunk k spans chunk_span(k).
+__device__ __forceinline__ void block_rows(const SysDesc& sys, int c0, int& rs, int& re) {
+  int m;
+  chunk_span(c0, sys.rows, sys.chunks, rs, m);
+  const int c1 = c0 + kReduceBlock;
+  if (c1 >= sys.chunks) {
+    re = sys.rows;
+  } else {
+    chunk_span(c1, sys.rows, sys.chunks, re, m);
   }
 }
 
 // Partition level, forward half: every thread eliminates one chunk and stores its two reduced rows.
+// At level 0 the workgroup's rows are staged through LDS first (coalesced loads).
 template <typename S, bool FromState>
 __global__ __launch_bounds__(kReduceBlock) void btcs_reduce_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
     const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, double* __restrict__ LA,
     double* __restrict__ LC, double* __restrict__ LD) {
   using T = double;
+  __shared__ S stage[FromState ? padded_size(kRedRows) : 1];
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
-  if (k >= sys.chunks) return;
-  int s, m;
-  chunk_span(k, sys.rows, sys.chunks, s, m);
   T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
   T AF, CF, DF, AE, CE, DE;
+  int s = 0, m = 0;
   if constexpr (FromState) {
-    const StateRows<S> src = state_rows(inst[sys.inst], u);
-    chunk_eliminate<T, kRedChunk>(src, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
+    const InstDesc d = inst[sys.inst];
+    const bool dir = d.bc == kDirichlet;
+    int rs, re;
+    block_rows(sys, cb.chunk0, rs, re);
+    const S* src = u + d.off + (dir ? 1 : 0);
+    for (int i = rs + static_cast<int>(threadIdx.x); i < re; i += kReduceBlock) stage[padded(i - rs)] = src[i];
+    __syncthreads();
+    if (k >= sys.chunks) return;
+    chunk_span(k, sys.rows, sys.chunks, s, m);
+    const LdsRows<S> rows{stage, rs, d.r, d.D, d.a, d.b, dir};
+    chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   } else {
-    const ArrayRows<T> src{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
-    chunk_eliminate<T, kRedChunk>(src, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
+    if (k >= sys.chunks) return;
+    chunk_span(k, sys.rows, sys.chunks, s, m);
+    const ArrayRows<T> rows{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
+    chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
   const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
   LA[o] = AF; LC[o] = CF; LD[o] = DF;
@@ -293,7 +351,7 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_reduce_kernel(
 }
 
 // Partition level, backward half: re-eliminate the chunk and recover its rows from the solved
-// reduced unknowns.
+// reduced unknowns.  At level 0 the rows are staged through LDS both ways.
 template <typename S, bool FromState>
 __global__ __launch_bounds__(kReduceBlock) void btcs_backsub_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
@@ -301,28 +359,46 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_backsub_kernel(
     const double* __restrict__ LA, const double* __restrict__ LC, const double* __restrict__ LD,
     double* __restrict__ LX) {
   using T = double;
+  __shared__ S stage[FromState ? padded_size(kRedRows) : 1];
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
-  if (k >= sys.chunks) return;
-  int s, m;
-  chunk_span(k, sys.rows, sys.chunks, s, m);
+  const bool active = k < sys.chunks;
   T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
   T AF, CF, DF, AE, CE, DE;
-  const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
-  const T F = LX[o], E = LX[o + 1];
+  int s = 0, m = 0;
+  T F = T(0), E = T(0);
+  if (active) {
+    chunk_span(k, sys.rows, sys.chunks, s, m);
+    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
+    F = LX[o];
+    E = LX[o + 1];
+  }
   if constexpr (FromState) {
     const InstDesc d = inst[sys.inst];
-    const StateRows<S> src = state_rows(d, u);
-    chunk_eliminate<T, kRedChunk>(src, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-    chunk_recover<T, kRedChunk>(PtrDst<S>{out + d.off + src.first}, s, m, al, ga, de, F, E);
-    if (src.dirichlet) {
-      if (k == 0) out[d.off] = static_cast<S>(d.a);
-      if (k == sys.chunks - 1) out[d.off + d.n - 1] = static_cast<S>(d.b);
+    const bool dir = d.bc == kDirichlet;
+    int rs, re;
+    block_rows(sys, cb.chunk0, rs, re);
+    const S* src = u + d.off + (dir ? 1 : 0);
+    for (int i = rs + static_cast<int>(threadIdx.x); i < re; i += kReduceBlock) stage[padded(i - rs)] = src[i];
+    __syncthreads();
+    if (active) {
+      const LdsRows<S> rows{stage, rs, d.r, d.D, d.a, d.b, dir};
+      chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
+    }
+    __syncthreads();                           // every chunk read before the buffer is overwritten
+    if (active) chunk_recover<T, kRedChunk>(LdsDst<S>{stage, rs}, s, m, al, ga, de, F, E);
+    __syncthreads();
+    S* dst = out + d.off + (dir ? 1 : 0);
+    for (int i = rs + static_cast<int>(threadIdx.x); i < re; i += kReduceBlock) dst[i] = stage[padded(i - rs)];
+    if (dir && threadIdx.x == 0) {
+      if (cb.chunk0 == 0) out[d.off] = static_cast<S>(d.a);
+      if (cb.chunk0 + kReduceBlock >= sys.chunks) out[d.off + d.n - 1] = static_cast<S>(d.b);
     }
   } else {
-    const ArrayRows<T> src{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
-    chunk_eliminate<T, kRedChunk>(src, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
+    if (!active) return;
+    const ArrayRows<T> rows{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
+    chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
     chunk_recover<T, kRedChunk>(PtrDst<T>{LX + sys.in_off}, s, m, al, ga, de, F, E);
   }
 }
@@ -376,7 +452,7 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
 
 }  // namespace
 
-int btcs_wg_capacity() { return kWgThreads * kWgChunk; }
+int btcs_wg_capacity() { return kWgRows; }
 
 int btcs_wg_chunks(int rows) {
   // largest power of two P <= min(threads, rows / 2); rows <= capacity keeps every chunk <= kWgChunk

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <tuple>
 
 #include "internal.hpp"
 
@@ -12,6 +13,7 @@ using burgers::DevBuf;
 using burgers::InstDesc;
 using burgers::SysDesc;
 using burgers::Tile;
+using burgers::BlockTile;
 
 namespace {
 
@@ -59,21 +61,101 @@ hipError_t upload(DevBuf& buf, const std::vector<T>& v) {
   return hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
-// Streaming tiles of one instance subset.
-hipError_t ensure_tiles(burgers_ctx* ctx, int set) {
-  if (ctx->tiles.count(set)) return hipSuccess;
+// Streaming tiles covering every node of the members of one subset.
+std::vector<Tile> stream_tiles(const burgers_ctx* ctx, const std::vector<int32_t>& members) {
   const int tile = burgers::explicit_tile_nodes(ctx->dtype);
   std::vector<Tile> tiles;
-  for (int32_t i : set_members(ctx, set)) {
+  for (int32_t i : members) {
     const int32_t n = static_cast<int32_t>(ctx->probs[i].n);
-    for (int32_t s = 0; s < n; s += tile) tiles.push_back(Tile{i, s});
+    for (int32_t s = 0; s < n; s += tile)
+      tiles.push_back(Tile{ctx->offsets[i], n, ctx->probs[i].bc, i, s});
   }
+  return tiles;
+}
+
+// Tiles of a subset used to copy its instances back from the second buffer.
+hipError_t ensure_copy(burgers_ctx* ctx, int set) {
+  if (ctx->copy_tiles.count(set)) return hipSuccess;
+  auto tiles = stream_tiles(ctx, set_members(ctx, set));
   auto buf = std::make_unique<DevBuf>();
   hipError_t e = upload(*buf, tiles);
   if (e != hipSuccess) return e;
-  ctx->n_tiles[set] = static_cast<int64_t>(tiles.size());
-  ctx->tiles[set] = std::move(buf);
+  ctx->copy_tiles[set] = {std::move(buf), static_cast<int64_t>(tiles.size())};
   return hipSuccess;
+}
+
+constexpr int kDefaultDepth = 16;
+
+// Explicit launch plan of one subset under the context's forced path (0 = automatic).
+//   path 1: streaming kernel, one step per launch.
+//   path 2: whole instances on chip, all steps in one launch (every instance must fit).
+//   path 3: temporal blocking with `depth` steps per launch for every instance.
+//   automatic: whole instances for those that fit, windows of `depth` steps for longer ones.
+burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
+  auto it = ctx->explicit_plans.find(set);
+  const int want_path = ctx->plan.explicit_path;
+  const int want_depth = ctx->plan.tblock_depth > 0 ? ctx->plan.tblock_depth : kDefaultDepth;
+  if (it != ctx->explicit_plans.end() && it->second->path == (want_path ? want_path : 0) &&
+      it->second->depth == want_depth)
+    return BURGERS_OK;
+  auto plan = std::make_unique<burgers::ExplicitPlan>();
+  plan->path = want_path ? want_path : 0;
+  plan->depth = want_depth;
+  const auto& members = set_members(ctx, set);
+  hipError_t e;
+  auto st = stream_tiles(ctx, members);
+  plan->stream = std::make_unique<DevBuf>();
+  if ((e = upload(*plan->stream, st)) != hipSuccess) return from_hip(e);
+  plan->n_stream = static_cast<int64_t>(st.size());
+  if (plan->path != 1) {
+    const int cap = burgers::explicit_block_capacity();
+    const int T = plan->depth;
+    std::vector<BlockTile> we, wg, ne, ng;
+    std::vector<int32_t> windowed;
+    for (int32_t i : members) {
+      const burgers_problem& p = ctx->probs[i];
+      const int32_t n = static_cast<int32_t>(p.n);
+      const bool periodic = p.bc == BURGERS_BC_PERIODIC;
+      if (n <= cap) {
+        (n == cap ? we : wg).push_back(BlockTile{i, 0, n, 0, n, periodic ? 1 : 0});
+        continue;
+      }
+      if (plan->path == 2) return BURGERS_E_UNSUPPORTED;
+      windowed.push_back(i);
+      const int32_t wout = cap - 2 * T;
+      for (int32_t lo = 0; lo < n; lo += wout) {
+        const int32_t hi = std::min(n, lo + wout);
+        BlockTile bt{i, 0, 0, 0, hi - lo, 0};
+        if (periodic) {
+          bt.first = ((lo - T) % n + n) % n;
+          bt.width = (hi - lo) + 2 * T;
+          bt.lo = T;
+        } else {
+          bt.first = std::max(0, lo - T);
+          bt.width = std::min(n, hi + T) - bt.first;
+          bt.lo = lo - bt.first;
+        }
+        (bt.width == cap ? ne : ng).push_back(bt);
+      }
+    }
+    plan->whole_exact = std::make_unique<DevBuf>();
+    plan->whole_generic = std::make_unique<DevBuf>();
+    plan->win_exact = std::make_unique<DevBuf>();
+    plan->win_generic = std::make_unique<DevBuf>();
+    plan->win_copy = std::make_unique<DevBuf>();
+    auto wc = stream_tiles(ctx, windowed);
+    if ((e = upload(*plan->whole_exact, we)) != hipSuccess || (e = upload(*plan->whole_generic, wg)) != hipSuccess ||
+        (e = upload(*plan->win_exact, ne)) != hipSuccess || (e = upload(*plan->win_generic, ng)) != hipSuccess ||
+        (e = upload(*plan->win_copy, wc)) != hipSuccess)
+      return from_hip(e);
+    plan->n_whole_exact = static_cast<int64_t>(we.size());
+    plan->n_whole_generic = static_cast<int64_t>(wg.size());
+    plan->n_win_exact = static_cast<int64_t>(ne.size());
+    plan->n_win_generic = static_cast<int64_t>(ng.size());
+    plan->n_win_copy = static_cast<int64_t>(wc.size());
+  }
+  ctx->explicit_plans[set] = std::move(plan);
+  return BURGERS_OK;
 }
 
 // BTCS launch plan of one instance subset: whole-system solves for short systems, partition levels for
@@ -156,55 +238,132 @@ int64_t level_rows_needed(const burgers_ctx* ctx) {
   return rows;
 }
 
-// One step of every instance of `set` from src into dst with `scheme` (-1: each instance's own).
-hipError_t enqueue_step(burgers_ctx* ctx, int set, int scheme, const void* src, void* dst) {
+// Enqueue nsteps explicit steps of one subset; the final state lands in u.
+hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
+  const burgers::ExplicitPlan& pl = *ctx->explicit_plans[set];
+  void* work = ctx->work.ptr;
   hipError_t e = hipSuccess;
-  if (scheme == BURGERS_EXPLICIT) {
-    return burgers::launch_explicit_stream(ctx, ctx->tiles[set]->as<Tile>(), ctx->n_tiles[set], src,
-                                           dst);
+  if (pl.path == 1) {
+    void* bufs[2] = {u, work};
+    int cur = 0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+      if ((e = burgers::launch_explicit_stream(ctx, pl.stream->as<Tile>(), pl.n_stream, bufs[cur], bufs[cur ^ 1])) != hipSuccess)
+        return e;
+      cur ^= 1;
+    }
+    if (cur) e = burgers::launch_copy_tiles(ctx, pl.stream->as<Tile>(), pl.n_stream, work, u);
+    return e;
   }
-  if (scheme == BURGERS_BTCS) return burgers::launch_btcs_step(ctx, *ctx->btcs[set], src, dst);
-  // mixed: the explicit members, then the BTCS members
-  if (!ctx->set_explicit.empty()) {
-    e = burgers::launch_explicit_stream(ctx, ctx->tiles[kSetExplicit]->as<Tile>(),
-                                        ctx->n_tiles[kSetExplicit], src, dst);
-    if (e != hipSuccess) return e;
+  // whole instances, in place: all steps at once, or `depth` per launch on path 3
+  const int64_t whole_chunk = pl.path == 3 ? pl.depth : (int64_t{1} << 30);
+  for (int64_t done = 0; done < nsteps;) {
+    const int k = static_cast<int>(std::min(whole_chunk, nsteps - done));
+    if ((e = burgers::launch_explicit_block(ctx, pl.whole_exact->as<BlockTile>(), pl.n_whole_exact, true, u, u, k)) != hipSuccess)
+      return e;
+    if ((e = burgers::launch_explicit_block(ctx, pl.whole_generic->as<BlockTile>(), pl.n_whole_generic, false, u, u, k)) != hipSuccess)
+      return e;
+    done += k;
   }
-  if (!ctx->set_btcs.empty()) e = burgers::launch_btcs_step(ctx, *ctx->btcs[kSetBtcs], src, dst);
+  // windows of long instances: `depth` steps per launch, ping-pong
+  if (pl.n_win_exact + pl.n_win_generic > 0) {
+    void* bufs[2] = {u, work};
+    int cur = 0;
+    for (int64_t done = 0; done < nsteps;) {
+      const int k = static_cast<int>(std::min<int64_t>(pl.depth, nsteps - done));
+      if ((e = burgers::launch_explicit_block(ctx, pl.win_exact->as<BlockTile>(), pl.n_win_exact, true, bufs[cur], bufs[cur ^ 1], k)) != hipSuccess)
+        return e;
+      if ((e = burgers::launch_explicit_block(ctx, pl.win_generic->as<BlockTile>(), pl.n_win_generic, false, bufs[cur], bufs[cur ^ 1], k)) != hipSuccess)
+        return e;
+      cur ^= 1;
+      done += k;
+    }
+    if (cur) e = burgers::launch_copy_tiles(ctx, pl.win_copy->as<Tile>(), pl.n_win_copy, work, u);
+  }
   return e;
 }
 
-hipError_t prepare(burgers_ctx* ctx, int set, int scheme) {
+// Enqueue nsteps BTCS steps of one subset; the final state lands in u.
+hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
+  void* bufs[2] = {u, ctx->work.ptr};
+  int cur = 0;
   hipError_t e = hipSuccess;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if ((e = burgers::launch_btcs_step(ctx, *ctx->btcs[set], bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+    cur ^= 1;
+  }
+  if (cur) {
+    auto& ct = ctx->copy_tiles[set];
+    e = burgers::launch_copy_tiles(ctx, ct.first->as<Tile>(), ct.second, ctx->work.ptr, u);
+  }
+  return e;
+}
+
+hipError_t enqueue_all(burgers_ctx* ctx, int set, int scheme, void* u, int64_t nsteps) {
+  hipError_t e = hipSuccess;
+  if (scheme == BURGERS_EXPLICIT) return enqueue_explicit(ctx, set, u, nsteps);
+  if (scheme == BURGERS_BTCS) return enqueue_btcs(ctx, set, u, nsteps);
+  if (!ctx->set_explicit.empty() && (e = enqueue_explicit(ctx, kSetExplicit, u, nsteps)) != hipSuccess) return e;
+  if (!ctx->set_btcs.empty()) e = enqueue_btcs(ctx, kSetBtcs, u, nsteps);
+  return e;
+}
+
+burgers_status prepare(burgers_ctx* ctx, int set, int scheme) {
+  burgers_status st;
+  hipError_t e;
   const bool need_explicit = scheme == BURGERS_EXPLICIT || (scheme < 0 && !ctx->set_explicit.empty());
   const bool need_btcs = scheme == BURGERS_BTCS || (scheme < 0 && !ctx->set_btcs.empty());
   const int es = scheme < 0 ? kSetExplicit : set;
   const int bs = scheme < 0 ? kSetBtcs : set;
-  if (need_explicit && (e = ensure_tiles(ctx, es)) != hipSuccess) return e;
-  if (need_btcs && (e = ensure_btcs(ctx, bs)) != hipSuccess) return e;
-  return hipSuccess;
+  if (need_explicit && (st = ensure_explicit(ctx, es)) != BURGERS_OK) return st;
+  if (need_btcs) {
+    if ((e = ensure_btcs(ctx, bs)) != hipSuccess) return from_hip(e);
+    if ((e = ensure_copy(ctx, bs)) != hipSuccess) return from_hip(e);
+  }
+  return BURGERS_OK;
 }
 
-// nsteps steps with ping-pong; the final state lands in u.
+// Replay the launch sequence of (set, scheme, nsteps, u) from a captured graph, capturing it on first use.
+hipError_t enqueue_graph(burgers_ctx* ctx, int set, int scheme, void* u, int64_t nsteps) {
+  const auto key = std::make_tuple(set, scheme, nsteps, u);
+  auto it = ctx->graph_cache.find(key);
+  if (it == ctx->graph_cache.end()) {
+    hipError_t e;
+    if (!ctx->capture_stream &&
+        (e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+      return e;
+    hipStream_t user = ctx->stream;
+    ctx->stream = ctx->capture_stream;
+    if ((e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+      ctx->stream = user;
+      return e;
+    }
+    hipError_t le = enqueue_all(ctx, set, scheme, u, nsteps);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    ctx->stream = user;
+    if (le != hipSuccess) { if (graph) (void)hipGraphDestroy(graph); return le; }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    it = ctx->graph_cache.emplace(key, exec).first;
+  }
+  return hipGraphLaunch(it->second, ctx->stream);
+}
+
+// nsteps steps of `set` with `scheme` (-1: each instance's own); the final state lands in u.
 burgers_status advance(burgers_ctx* ctx, void* u, int64_t nsteps, int set, int scheme) {
   if (!ctx || !u || nsteps < 0) return BURGERS_E_INVALID;
   if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
   if (nsteps == 0) return BURGERS_OK;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return note(ctx, e);
-  if ((e = prepare(ctx, set, scheme)) != hipSuccess) return note(ctx, e);
-  void* bufs[2] = {u, ctx->work.ptr};
-  int cur = 0;
-  for (int64_t s = 0; s < nsteps; ++s) {
-    e = enqueue_step(ctx, set, scheme, bufs[cur], bufs[cur ^ 1]);
-    if (e != hipSuccess) return note(ctx, e);
-    cur ^= 1;
-  }
-  if (cur != 0) {
-    e = hipMemcpyAsync(u, ctx->work.ptr, static_cast<size_t>(ctx->total) * ctx->word,
-                       hipMemcpyDeviceToDevice, ctx->stream);
-    if (e != hipSuccess) return note(ctx, e);
-  }
+  burgers_status st = prepare(ctx, set, scheme);
+  if (st != BURGERS_OK) return st == BURGERS_E_UNSUPPORTED || st == BURGERS_E_INVALID ? st : note(ctx, hipErrorOutOfMemory);
+  if (ctx->plan.use_graph == 1) e = enqueue_graph(ctx, set, scheme, u, nsteps);
+  else e = enqueue_all(ctx, set, scheme, u, nsteps);
+  if (e != hipSuccess) return note(ctx, e);
   return BURGERS_OK;
 }
 
@@ -307,7 +466,8 @@ void burgers_destroy(burgers_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : ctx->graph_cache) (void)hipGraphExecDestroy(kv.second);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   delete ctx;
 }
 
@@ -358,7 +518,12 @@ burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan) {
   if (plan->explicit_path < 0 || plan->explicit_path > 3 || plan->btcs_path < 0 || plan->btcs_path > 3 ||
       plan->tblock_depth < 0 || plan->tblock_depth > 32 || plan->use_graph < -1 || plan->use_graph > 1)
     return BURGERS_E_INVALID;
+  const bool explicit_changed = plan->explicit_path != ctx->plan.explicit_path ||
+                                plan->tblock_depth != ctx->plan.tblock_depth;
   ctx->plan = *plan;
+  if (explicit_changed) ctx->explicit_plans.clear();
+  for (auto& kv : ctx->graph_cache) (void)hipGraphExecDestroy(kv.second);
+  ctx->graph_cache.clear();
   return BURGERS_OK;
 }
 

@@ -1,16 +1,24 @@
 // Explicit forward-Euler upwind/central step (Sec. 2.3, eq. 21) for gfx950.
 //
-// One step is a 3-point stencil per node; it moves 2 words per node-step (read u^n, write u^{n+1}) and
-// does about a dozen flops, far below the machine balance, so the streaming kernel is bound by HBM:
-// every workgroup streams one tile of 256 x (16 bytes / word) nodes with 16-byte vector loads and
-// stores, and the two neighbours a lane needs beyond its own vector come from the same cache lines.
-//
-// The update is evaluated in exactly this association, with contraction disabled, so that it rounds
-// like a plain scalar evaluation of the formula:
+// The update of one node is a 3-point stencil evaluated in exactly this association, with contraction
+// disabled, so that every kernel here rounds like a plain scalar evaluation of the formula:
 //   c = r u_i;  lap = (u_{i+1} + u_{i-1}) - 2 u_i
 //   u_i' = ((u_i - max(c,0) (u_i - u_{i-1})) - min(c,0) (u_{i+1} - u_i)) + D lap
 // The upwind side follows the sign of u_i (backward difference for u_i >= 0, eq. 3; forward for
 // u_i < 0, as the text after eq. 3 prescribes).  Diffusion uses the central difference of eq. 4.
+//
+// Two kernels:
+//  * explicit_stream_kernel: one step per pass over HBM.  It moves 2 words per node-step and does 11
+//    flops, far below the machine balance, so it is bound by HBM: each workgroup streams one tile of
+//    256 lanes x 16 bytes with vector loads and stores; a tile's descriptor carries everything needed
+//    to address it, so the vector load issues after a single scalar load.
+//  * explicit_block_kernel: temporal blocking.  A workgroup holds a window of up to 8192 nodes in
+//    registers (32 per lane), exchanges only the chunk end values through LDS each step (double
+//    buffered, one barrier per step) and advances many steps per pass over HBM.  A whole instance that
+//    fits is advanced for all its steps in one launch with exact boundaries; longer grids are cut into
+//    windows with a halo of T nodes per side that are recomputed redundantly, so that after T steps the
+//    window's interior is exact.  Every node goes through the same arithmetic as in the streaming
+//    kernel, so both kernels give bitwise identical results.
 #include "internal.hpp"
 #include "stencil.hpp"
 
@@ -20,6 +28,8 @@ namespace burgers {
 namespace {
 
 constexpr int kStreamThreads = 256;
+constexpr int kBlockThreads = 256;
+constexpr int kBlockChunk = 32;
 
 template <typename T> struct Vec;
 template <> struct Vec<double> { using type = double2; static constexpr int n = 2; };
@@ -32,19 +42,19 @@ __global__ __launch_bounds__(kStreamThreads) void explicit_stream_kernel(
   constexpr int V = Vec<T>::n;
   using VT = typename Vec<T>::type;
   const Tile t = tiles[blockIdx.x];
-  const InstDesc d = inst[t.inst];
-  const int n = d.n;
+  const int n = t.n;
   const int i0 = t.start + static_cast<int>(threadIdx.x) * V;
   if (i0 >= n) return;
-  const T* __restrict__ src = u + d.off;
-  T* __restrict__ dst = out + d.off;
-  const T r = static_cast<T>(d.r), D = static_cast<T>(d.D);
-  const T a = static_cast<T>(d.a), b = static_cast<T>(d.b);
-  const bool periodic = d.bc == kPeriodic;
+  const T* __restrict__ src = u + t.off;
+  T* __restrict__ dst = out + t.off;
+  const bool periodic = t.bc == kPeriodic;
 
   // Instance starts are aligned to 64 elements and i0 is a multiple of V, so this vector lies inside
   // the instance's padded extent even when it runs past node n-1.
   const VT vv = *reinterpret_cast<const VT*>(src + i0);
+  const InstDesc d = inst[t.inst];
+  const T r = static_cast<T>(d.r), D = static_cast<T>(d.D);
+  const T a = static_cast<T>(d.a), b = static_cast<T>(d.b);
   T v[V];
   __builtin_memcpy(v, &vv, sizeof(VT));
   const T left = i0 > 0 ? src[i0 - 1] : (periodic ? src[n - 1] : a);
@@ -80,11 +90,153 @@ __global__ __launch_bounds__(kStreamThreads) void explicit_stream_kernel(
   }
 }
 
+// Chunk of the window held by lane t: nodes [s, s + m) of a window of W nodes split over P lanes.
+__device__ __forceinline__ void lane_span(int t, int W, int P, int& s, int& m) {
+  const int q = W / P, rho = W - q * P;
+  s = t * q + (t < rho ? t : rho);
+  m = q + (t < rho ? 1 : 0);
+}
+
+// Temporal blocking.  EXACT: the window has exactly kBlockThreads * kBlockChunk nodes, so every lane
+// holds a full chunk and the guards below fold away.
+template <typename T, bool EXACT>
+__global__ __launch_bounds__(kBlockThreads) void explicit_block_kernel(
+    const InstDesc* __restrict__ inst, const BlockTile* __restrict__ tiles, const T* __restrict__ u,
+    T* __restrict__ out, int steps) {
+  constexpr int M = kBlockChunk;
+  __shared__ T s_first[2][kBlockThreads];
+  __shared__ T s_last[2][kBlockThreads];
+  const BlockTile bt = tiles[blockIdx.x];
+  const InstDesc d = inst[bt.inst];
+  const T r = static_cast<T>(d.r), D = static_cast<T>(d.D);
+  const int n = d.n;
+  const bool periodic = d.bc == kPeriodic;
+  const int W = bt.width;                       // window nodes
+  const int P = EXACT ? kBlockThreads : (W < kBlockThreads ? W : kBlockThreads);
+  const int t = threadIdx.x;
+  const bool active = t < P;
+  int s = 0, m = 0;
+  if (active) lane_span(t, W, P, s, m);
+  if (EXACT) m = M;
+  // window node w is instance node (bt.first + w) mod n; the window wraps only for periodic instances
+  const T* __restrict__ src = u + d.off;
+  T v[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (active && j < m) {
+      int g = bt.first + s + j;
+      if (g >= n) g -= n;
+      v[j] = src[g];
+    }
+  }
+  // Window ends that are not periodic neighbours are held fixed: at a Dirichlet boundary they carry
+  // a or b (and node 1 then reads a exactly as the streaming kernel does); at an interior window edge
+  // their stale value only corrupts nodes within `steps` of the edge, which lie in the halo.
+  const bool wraps = bt.wrap != 0;
+  const bool fix_first = active && t == 0 && !wraps;
+  const bool fix_last = active && t == P - 1 && !wraps;
+  if (!periodic && active) {
+    if (bt.first + s == 0) v[0] = static_cast<T>(d.a);
+#pragma unroll
+    for (int j = 0; j < M; ++j)
+      if (j == m - 1 && bt.first + s + j == n - 1) v[j] = static_cast<T>(d.b);
+  }
+
+  for (int step = 0; step < steps; ++step) {
+    const int buf = step & 1;
+    if (active) {
+      s_first[buf][t] = v[0];
+      T last = v[M - 1];
+      if (!EXACT) {
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+          if (j == m - 1) last = v[j];
+      }
+      s_last[buf][t] = last;
+    }
+    __syncthreads();
+    if (active) {
+      const T left = t > 0 ? s_last[buf][t - 1] : s_last[buf][P - 1];
+      const T right = t < P - 1 ? s_first[buf][t + 1] : s_first[buf][0];
+      T prev = left;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        if (EXACT || j < m) {
+          const T old = v[j];
+          T up;
+          if (EXACT) {
+            up = j + 1 < M ? v[j + 1 < M ? j + 1 : j] : right;
+          } else {
+            up = right;
+            if (j + 1 < M && j + 1 < m) up = v[j + 1 < M ? j + 1 : j];
+          }
+          const bool fixed = (j == 0 && fix_first) || (EXACT ? (j == M - 1 && fix_last)
+                                                              : (j == m - 1 && fix_last));
+          if (!fixed) v[j] = upwind_central(old, prev, up, r, D);
+          prev = old;
+        }
+      }
+    }
+  }
+
+  // store the window's output nodes [bt.lo, bt.lo + bt.count)
+  T* __restrict__ dst = out + d.off;
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const int w = s + j;
+      if ((EXACT || j < m) && w >= bt.lo && w < bt.lo + bt.count) {
+        int g = bt.first + w;
+        if (g >= n) g -= n;
+        dst[g] = v[j];
+      }
+    }
+  }
+}
+
+// Copy the nodes of a set of tiles (the instances of one subset) from src to dst.
+template <typename T>
+__global__ __launch_bounds__(kStreamThreads) void copy_tiles_kernel(const Tile* __restrict__ tiles,
+                                                                    const T* __restrict__ src,
+                                                                    T* __restrict__ dst) {
+  constexpr int V = Vec<T>::n;
+  using VT = typename Vec<T>::type;
+  const Tile t = tiles[blockIdx.x];
+  const int i0 = t.start + static_cast<int>(threadIdx.x) * V;
+  if (i0 >= t.n) return;
+  const VT v = *reinterpret_cast<const VT*>(src + t.off + i0);
+  if (i0 + V <= t.n) {
+    *reinterpret_cast<VT*>(dst + t.off + i0) = v;
+  } else {
+    T e[V];
+    __builtin_memcpy(e, &v, sizeof(VT));
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+      if (i0 + k < t.n) dst[t.off + i0 + k] = e[k];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_copy_tiles(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* src,
+                             void* dst) {
+  if (n_tiles <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(n_tiles)), block(kStreamThreads);
+  if (ctx->dtype == BURGERS_F64) {
+    copy_tiles_kernel<double><<<grid, block, 0, ctx->stream>>>(tiles, static_cast<const double*>(src),
+                                                               static_cast<double*>(dst));
+  } else {
+    copy_tiles_kernel<float><<<grid, block, 0, ctx->stream>>>(tiles, static_cast<const float*>(src),
+                                                              static_cast<float*>(dst));
+  }
+  return hipGetLastError();
+}
 
 int explicit_tile_nodes(burgers_dtype dt) {
   return kStreamThreads * (dt == BURGERS_F64 ? Vec<double>::n : Vec<float>::n);
 }
+
+int explicit_block_capacity() { return kBlockThreads * kBlockChunk; }
 
 hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles,
                                   const void* u, void* out) {
@@ -96,6 +248,25 @@ hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int
   } else {
     explicit_stream_kernel<float><<<grid, block, 0, ctx->stream>>>(
         ctx->inst.as<InstDesc>(), tiles, static_cast<const float*>(u), static_cast<float*>(out));
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_tiles,
+                                 bool exact, const void* u, void* out, int steps) {
+  if (n_tiles <= 0 || steps <= 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(n_tiles)), block(kBlockThreads);
+  const InstDesc* inst = ctx->inst.as<InstDesc>();
+  if (ctx->dtype == BURGERS_F64) {
+    const double* uu = static_cast<const double*>(u);
+    double* oo = static_cast<double*>(out);
+    if (exact) explicit_block_kernel<double, true><<<grid, block, 0, ctx->stream>>>(inst, tiles, uu, oo, steps);
+    else explicit_block_kernel<double, false><<<grid, block, 0, ctx->stream>>>(inst, tiles, uu, oo, steps);
+  } else {
+    const float* uu = static_cast<const float*>(u);
+    float* oo = static_cast<float*>(out);
+    if (exact) explicit_block_kernel<float, true><<<grid, block, 0, ctx->stream>>>(inst, tiles, uu, oo, steps);
+    else explicit_block_kernel<float, false><<<grid, block, 0, ctx->stream>>>(inst, tiles, uu, oo, steps);
   }
   return hipGetLastError();
 }

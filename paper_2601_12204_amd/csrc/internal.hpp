@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <map>
 #include <memory>
+#include <tuple>
 #include <vector>
 
 #include "burgers.h"
@@ -27,10 +28,26 @@ struct InstDesc {
   double b;     // Dirichlet right value
 };
 
-// A run of consecutive nodes of one instance handled by one workgroup of a streaming kernel.
+// A run of consecutive nodes of one instance handled by one workgroup of a streaming kernel.  It
+// carries the instance's offset, size and boundary type so that a kernel can address its data after a
+// single scalar load.
 struct Tile {
+  int64_t off;
+  int32_t n;
+  int32_t bc;
   int32_t inst;
   int32_t start;
+};
+
+// A window of one instance advanced several steps per launch by the temporal-blocking kernel.  Window
+// node w is instance node (first + w) mod n; nodes [lo, lo + count) of the window are written back.
+struct BlockTile {
+  int32_t inst;
+  int32_t first;
+  int32_t width;
+  int32_t lo;
+  int32_t count;
+  int32_t wrap;   // 1: the window is a whole periodic instance and its ends are neighbours
 };
 
 // One tridiagonal system of the BTCS solve at some level of the partition hierarchy.
@@ -81,9 +98,17 @@ struct BtcsPlan {
   int64_t level_rows = 0;                    // rows of A, C, D, X used by this plan
 };
 
-struct Plan {
-  burgers_plan user{};
-  int resident_explicit_limit = 0;
+// Launch lists of the explicit scheme for a set of instances.
+struct ExplicitPlan {
+  std::unique_ptr<DevBuf> stream;            // Tile[] covering every node of the set
+  int64_t n_stream = 0;
+  // temporal blocking: whole instances (all steps in place) and windows of long instances
+  std::unique_ptr<DevBuf> whole_exact, whole_generic, win_exact, win_generic;   // BlockTile[]
+  int64_t n_whole_exact = 0, n_whole_generic = 0, n_win_exact = 0, n_win_generic = 0;
+  std::unique_ptr<DevBuf> win_copy;          // Tile[] of the windowed instances (copy-back)
+  int64_t n_win_copy = 0;
+  int path = 1;                              // 1 stream, 2 resident, 3 tiled
+  int depth = 0;                             // steps per launch of the windows (and whole tiles, path 3)
 };
 
 }  // namespace burgers
@@ -105,12 +130,13 @@ struct burgers_ctx {
   burgers_plan plan{};
   // instance subsets: all, explicit-scheme, btcs-scheme
   std::vector<int32_t> set_all, set_explicit, set_btcs;
-  // explicit streaming tiles per subset (device)
-  std::map<int, std::unique_ptr<burgers::DevBuf>> tiles;
-  std::map<int, int64_t> n_tiles;
+  // launch plans per instance subset
+  std::map<int, std::unique_ptr<burgers::ExplicitPlan>> explicit_plans;
   std::map<int, std::unique_ptr<burgers::BtcsPlan>> btcs;
-  // captured graphs keyed by (kind, steps)
-  std::map<std::pair<int, int64_t>, hipGraphExec_t> graphs;
+  std::map<int, std::pair<std::unique_ptr<burgers::DevBuf>, int64_t>> copy_tiles;   // per subset
+  // launch sequences captured as graphs, keyed by (subset, scheme, steps, state buffer)
+  std::map<std::tuple<int, int, int64_t, void*>, hipGraphExec_t> graph_cache;
+  hipStream_t capture_stream = nullptr;      // private non-blocking stream used only for capture
   hipError_t sticky = hipSuccess;
 };
 
@@ -119,7 +145,12 @@ namespace burgers {
 // explicit.hip
 hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles,
                                   const void* u, void* out);
+hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_tiles,
+                                 bool exact, const void* u, void* out, int steps);
+hipError_t launch_copy_tiles(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* src,
+                             void* dst);
 int explicit_tile_nodes(burgers_dtype dt);
+int explicit_block_capacity();
 
 // btcs.hip
 int btcs_wg_capacity();                 // longest system one workgroup solves whole

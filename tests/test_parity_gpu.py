@@ -175,3 +175,69 @@ def test_repeatable_and_resumable():
     s.sync()
     assert np.array_equal(s.unpack_flat(u), a)
     s.close()
+
+
+def _ragged_long_batch(seed):
+    """Sizes around the on-chip capacity (8192) and long grids that need windows, both BCs."""
+    sizes = [3, 4, 17, 255, 256, 257, 8191, 8192, 8193, 16384, 24577, 40000]
+    problems, states = [], []
+    for k, n in enumerate(sizes):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            b = W.random_batch(seed + 17 * k + bc, 1, n, n, bc=bc, amplitude=3.0)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    return set_cfl_steps(W._pack(problems, states), scheme=W.EXPLICIT)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("path,depth", [(1, 0), (3, 1), (3, 5), (3, 16), (3, 32), (0, 0), (0, 7)])
+def test_explicit_paths_bitwise(dtype, path, depth):
+    """Streaming, whole-instance and windowed temporal blocking at several depths, including step counts
+    that are not multiples of the depth, are all bitwise equal to the oracle."""
+    batch = _ragged_long_batch(31)
+    announce(f"explicit path={path} depth={depth} {dtype} 37 steps")
+    got = device_run(batch, 37, dtype, how="step_explicit", plan=dict(explicit_path=path, tblock_depth=depth))
+    ref = oracle_run(batch, 37, dtype, scheme=W.EXPLICIT)
+    assert np.array_equal(got, ref)
+
+
+def test_explicit_resident_path_rejects_long_instances():
+    import paper_2601_12204_amd as B
+    batch = _ragged_long_batch(32)
+    announce("explicit resident path with long instances -> unsupported")
+    with pytest.raises(B.BurgersError) as err:
+        device_run(batch, 3, "f64", how="step_explicit", plan=dict(explicit_path=2))
+    assert err.value.status == -2
+
+
+@pytest.mark.parametrize("how", ["step_explicit", "step_btcs", "run"])
+def test_graph_replay_matches_eager(how):
+    """A captured launch sequence replayed several times, with eager work between replays, reproduces
+    the eager result every time."""
+    import torch
+    import paper_2601_12204_amd as B
+    batch = set_cfl_steps(W.random_batch(33, 24, 3, 20000, amplitude=2.0))
+    announce(f"graph replay {how}")
+    eager = device_run(batch, 11, "f64", how=how)
+    s = B.Solver(batch.problems, dtype=torch.float64)
+    s.set_plan(use_graph=1)
+    u0 = s.pack_flat(batch.u0, batch.offsets)
+    u = torch.empty_like(u0)
+    scratch = torch.zeros(1 << 20, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        u.copy_(u0)
+        scratch.add_(1.0)                      # eager work between replays
+        getattr(s, how)(u, 11)
+        s.sync()
+        assert np.array_equal(s.unpack_flat(u), eager), rep
+    s.close()
+
+
+@pytest.mark.parametrize("nsteps", [1, 2, 7])
+def test_run_mixed_odd_even_steps(nsteps):
+    """Mixed explicit/BTCS contexts share the second buffer: each group copies back only its own
+    instances, so odd and even step counts leave every instance right."""
+    batch = set_cfl_steps(W.random_batch(34, 40, 3, 30000, amplitude=2.0))
+    announce(f"mixed run {nsteps} steps")
+    got = device_run(batch, nsteps, "f64", how="run")
+    check_batch(batch, got, nsteps, "f64")
