@@ -14,6 +14,7 @@ Functions and the passages they follow (Potluri et al., arXiv 2601.12204):
   btcs_step         assemble + solve
   run               n fixed-dt steps of a packed batch, OpenMP over instances
   cole_hopf         closed-form sawtooth solution (Sec. 2.6 verification by Cole-Hopf)
+  adjoint, tangent  discrete adjoint and tangent-linear sweeps of run (gradients, Sec. 2.7.1 / 2.7.3)
 """
 from __future__ import annotations
 
@@ -76,6 +77,12 @@ def configure(lib):
     lib.oracle_cole_hopf.argtypes = [i64, _dp, dbl, dbl, _dp]
     lib.oracle_max_threads.restype = c_int
     lib.oracle_max_threads.argtypes = []
+    lib.oracle_adjoint_run.restype = None
+    lib.oracle_adjoint_run.argtypes = [i64, _i64p, _i32p, _i32p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, i64,
+                                       _dp, _dp, c_int]
+    lib.oracle_tangent_run.restype = None
+    lib.oracle_tangent_run.argtypes = [i64, _i64p, _i32p, _i32p, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                       i64, _dp, c_int]
     return lib
 
 
@@ -223,4 +230,47 @@ def run_ratios(u: np.ndarray, bc: int, a: float, b: float, r: float, D: float, n
                                                       _ptr(one(scheme, np.int32)), _ptr(one(r, np.float64)),
                                                       _ptr(one(D, np.float64)), _ptr(one(a, np.float64)),
                                                       _ptr(one(b, np.float64)), _ptr(out), nsteps, 1)
+    return out
+
+
+def _scalars(problems, scheme):
+    count = len(problems)
+    bc = np.array([q.bc for q in problems], dtype=np.int32)
+    sch = np.array([q.scheme if scheme is None else scheme for q in problems], dtype=np.int32)
+    rd = np.array([ratios(q) for q in problems], dtype=np.float64).reshape(count, 2)
+    r = np.ascontiguousarray(rd[:, 0])
+    D = np.ascontiguousarray(rd[:, 1])
+    a = np.array([q.left for q in problems], dtype=np.float64)
+    b = np.array([q.right for q in problems], dtype=np.float64)
+    dtdx2 = np.array([q.dt / dx(q.n, q.length, q.bc) ** 2 for q in problems], dtype=np.float64)
+    return bc, sch, r, D, a, b, dtdx2
+
+
+def adjoint(problems: Sequence, u0: np.ndarray, offsets: np.ndarray, lam_T: np.ndarray, nsteps: int,
+            scheme: Optional[int] = None, threads: int = 0):
+    """(dJ/du0, dJ/dnu) for dJ/du_T = lam_T after nsteps steps (FP64, all forward states kept)."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    lam = np.ascontiguousarray(lam_T, dtype=np.float64)
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    bc, sch, r, D, a, b, dtdx2 = _scalars(problems, scheme)
+    g_u0 = np.zeros_like(u0)
+    g_nu = np.zeros(len(problems))
+    _load().oracle_adjoint_run(len(problems), _ptr(offs), _ptr(bc), _ptr(sch), _ptr(r), _ptr(D), _ptr(a),
+                               _ptr(b), _ptr(dtdx2), _ptr(u0), _ptr(lam), nsteps, _ptr(g_u0), _ptr(g_nu),
+                               threads)
+    return g_u0, g_nu
+
+
+def tangent(problems: Sequence, u0: np.ndarray, offsets: np.ndarray, du0: np.ndarray, dnu: np.ndarray,
+            nsteps: int, scheme: Optional[int] = None, threads: int = 0) -> np.ndarray:
+    """Directional derivative du_T of the final state for perturbations du0 and dnu (FP64)."""
+    u0 = np.ascontiguousarray(u0, dtype=np.float64)
+    du0 = np.ascontiguousarray(du0, dtype=np.float64)
+    dnu = np.ascontiguousarray(dnu, dtype=np.float64)
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    bc, sch, r, D, a, b, dtdx2 = _scalars(problems, scheme)
+    out = np.zeros_like(u0)
+    _load().oracle_tangent_run(len(problems), _ptr(offs), _ptr(bc), _ptr(sch), _ptr(r), _ptr(D), _ptr(a),
+                               _ptr(b), _ptr(dtdx2), _ptr(u0), _ptr(du0), _ptr(dnu), nsteps, _ptr(out),
+                               threads)
     return out

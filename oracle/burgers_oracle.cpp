@@ -242,6 +242,165 @@ double cole_hopf_point(double x, double t, double nu) {
   return 4.0 + (num / den) / (t + 1.0);
 }
 
+
+// ---------------------------------------------------------------------------------------------------
+// Differentiation of the steppers (the paper computes gradients with respect to initial data by
+// reverse-mode AD through its solvers, Sec. 2.7.1 and 2.7.3).  Written out by hand for the discrete
+// steps above.  The upwind switch is differentiated on its u_i >= 0 branch at u_i = 0 (H = [u_i >= 0]),
+// and dt is a constant.  The viscosity enters through D = nu dt/dx^2 only, so dD = dnu dt/dx^2.
+// Dirichlet boundary nodes are constants: they carry no tangent and receive no adjoint.
+
+// Neighbour values of node i as the explicit step reads them (Dirichlet: node 1 reads a, node n-2
+// reads b); `um_state`/`up_state` tell whether the neighbour is a state node (carries a tangent).
+void neighbours(int64_t n, int bc, int64_t i, int64_t& im, int64_t& ip, bool& um_state, bool& up_state) {
+  if (bc == PERIODIC) {
+    im = i == 0 ? n - 1 : i - 1;
+    ip = i == n - 1 ? 0 : i + 1;
+    um_state = up_state = true;
+  } else {
+    im = i - 1;
+    ip = i + 1;
+    um_state = i != 1;
+    up_state = i != n - 2;
+  }
+}
+
+// Tangent-linear explicit step: dout = d(u')/du . du + d(u')/dD . dD.
+void explicit_tangent(int64_t n, int bc, double a, double b, double r, double D, const double* u,
+                      const double* du, double dD, double* dout) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (bc == DIRICHLET && (i == 0 || i == n - 1)) { dout[i] = 0.0; continue; }
+    int64_t im, ip;
+    bool ms, ps;
+    neighbours(n, bc, i, im, ip, ms, ps);
+    const double um = ms ? u[im] : a, up = ps ? u[ip] : b;
+    const double dum = ms ? du[im] : 0.0, dup = ps ? du[ip] : 0.0;
+    const double ui = u[i], dui = du[i];
+    const double lap = (up + um) - 2.0 * ui;
+    const double dlap = (dup + dum) - 2.0 * dui;
+    double v;
+    if (ui >= 0) {   // u' = u - r u (u - um) + D lap
+      v = dui - r * dui * (ui - um) - r * ui * (dui - dum);
+    } else {         // u' = u - r u (up - u) + D lap
+      v = dui - r * dui * (up - ui) - r * ui * (dup - dui);
+    }
+    dout[i] = v + D * dlap + dD * lap;
+  }
+}
+
+// Adjoint explicit step: lam = (d u'/du)^T lamp; returns lamp . d(u')/dD.
+double explicit_adjoint(int64_t n, int bc, double a, double b, double r, double D, const double* u,
+                        const double* lamp, double* lam) {
+  for (int64_t i = 0; i < n; ++i) lam[i] = 0.0;
+  double gD = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (bc == DIRICHLET && (i == 0 || i == n - 1)) continue;
+    int64_t im, ip;
+    bool ms, ps;
+    neighbours(n, bc, i, im, ip, ms, ps);
+    const double um = ms ? u[im] : a, up = ps ? u[ip] : b;
+    const double ui = u[i], li = lamp[i];
+    double self, left, right;   // coefficients of du_i, du_{i-1}, du_{i+1} in du'_i
+    if (ui >= 0) {
+      self = 1.0 - r * (ui - um) - r * ui - 2.0 * D;
+      left = r * ui + D;
+      right = D;
+    } else {
+      self = 1.0 - r * (up - ui) + r * ui - 2.0 * D;
+      left = D;
+      right = D - r * ui;
+    }
+    lam[i] += self * li;
+    if (ms) lam[im] += left * li;
+    if (ps) lam[ip] += right * li;
+    gD += li * ((up + um) - 2.0 * ui);
+  }
+  return gD;
+}
+
+// Shared pieces of the BTCS derivatives for x = u^{n+1} solving A(y) x = y (y = u^n), written on the
+// full rows with the Dirichlet boundary values standing in as x_0 = a, x_{n-1} = b:
+//   G_i = r [H (x_i - x_{i-1}) + (1 - H)(x_{i+1} - x_i)]   (derivative of row i of A x w.r.t. y_i)
+//   (L x)_i = 2 x_i - x_{i-1} - x_{i+1}                     (derivative of row i of A x w.r.t. D)
+void btcs_g_and_l(int64_t n, int bc, double a, double b, double r, const double* y, const double* x,
+                  std::vector<double>& G, std::vector<double>& Lx) {
+  G.assign(n, 0.0);
+  Lx.assign(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (bc == DIRICHLET && (i == 0 || i == n - 1)) continue;
+    double xm, xp;
+    if (bc == PERIODIC) {
+      xm = x[i == 0 ? n - 1 : i - 1];
+      xp = x[i == n - 1 ? 0 : i + 1];
+    } else {
+      xm = i == 1 ? a : x[i - 1];
+      xp = i == n - 2 ? b : x[i + 1];
+    }
+    G[i] = y[i] >= 0 ? r * (x[i] - xm) : r * (xp - x[i]);
+    Lx[i] = (2.0 * x[i] - xm) - xp;
+  }
+}
+
+// Solve A z = f (transpose = false) or A^T z = f (transpose = true) for the BTCS matrix of state y,
+// over the unknown nodes; z and f are full-length node arrays (Dirichlet ends ignored, z ends = 0).
+void btcs_matrix_solve(int64_t n, int bc, double r, double D, const double* y, const double* f, double* z,
+                       bool transpose) {
+  std::vector<double> l(n), d(n), p(n), rhs(n), cw(n), yw(n);
+  // assemble with a = b = 0: only the matrix is needed here
+  const int64_t m = btcs_assemble<double>(n, bc, 0.0, 0.0, r, D, y, l.data(), d.data(), p.data(), rhs.data());
+  const int64_t first = bc == PERIODIC ? 0 : 1;
+  for (int64_t k = 0; k < m; ++k) rhs[k] = f[first + k];
+  std::vector<double> tl(m), tp(m);
+  if (transpose) {   // (A^T)_{k,k-1} = p_{k-1}, (A^T)_{k,k+1} = l_{k+1}, corners swapped likewise
+    for (int64_t k = 0; k < m; ++k) {
+      tl[k] = bc == PERIODIC ? p[(k - 1 + m) % m] : (k > 0 ? p[k - 1] : 0.0);
+      tp[k] = bc == PERIODIC ? l[(k + 1) % m] : (k + 1 < m ? l[k + 1] : 0.0);
+    }
+  } else {
+    for (int64_t k = 0; k < m; ++k) { tl[k] = l[k]; tp[k] = p[k]; }
+  }
+  std::vector<double> sol(m);
+  if (bc == PERIODIC) cyclic_solve<double>(m, tl.data(), d.data(), tp.data(), rhs.data(), sol.data());
+  else thomas<double>(m, tl.data(), d.data(), tp.data(), rhs.data(), sol.data(), cw.data(), yw.data());
+  for (int64_t i = 0; i < n; ++i) z[i] = 0.0;
+  for (int64_t k = 0; k < m; ++k) z[first + k] = sol[k];
+}
+
+// Tangent-linear BTCS step: A dx = dy - G dy - dD L x.
+void btcs_tangent(int64_t n, int bc, double a, double b, double r, double D, const double* y,
+                  const double* x, const double* dy, double dD, double* dx) {
+  std::vector<double> G, Lx, f(n);
+  btcs_g_and_l(n, bc, a, b, r, y, x, G, Lx);
+  for (int64_t i = 0; i < n; ++i) f[i] = dy[i] - G[i] * dy[i] - dD * Lx[i];
+  btcs_matrix_solve(n, bc, r, D, y, f.data(), dx, false);
+}
+
+// Adjoint BTCS step: mu = A^{-T} lamp; lam = (1 - G) mu; returns -mu . L x (the D-derivative).
+double btcs_adjoint(int64_t n, int bc, double a, double b, double r, double D, const double* y,
+                    const double* x, const double* lamp, double* lam) {
+  std::vector<double> G, Lx, mu(n);
+  btcs_g_and_l(n, bc, a, b, r, y, x, G, Lx);
+  btcs_matrix_solve(n, bc, r, D, y, lamp, mu.data(), true);
+  double gD = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    lam[i] = (1.0 - G[i]) * mu[i];
+    gD -= mu[i] * Lx[i];
+  }
+  return gD;
+}
+
+// Forward states u^0..u^nsteps of one instance.
+std::vector<std::vector<double>> forward_states(int64_t n, int bc, int scheme, double a, double b, double r,
+                                                double D, const double* u0, int64_t nsteps) {
+  std::vector<std::vector<double>> st(nsteps + 1, std::vector<double>(n));
+  for (int64_t i = 0; i < n; ++i) st[0][i] = u0[i];
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if (scheme == SCHEME_EXPLICIT) explicit_step<double>(n, bc, a, b, r, D, st[s].data(), st[s + 1].data());
+    else btcs_step<double>(n, bc, a, b, r, D, st[s].data(), st[s + 1].data());
+  }
+  return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -317,6 +476,62 @@ void oracle_run_explicit_large_f64(int64_t n, int bc, double a, double b, double
 
 void oracle_cole_hopf(int64_t m, const double* x, double t, double nu, double* out) {
   for (int64_t i = 0; i < m; ++i) out[i] = cole_hopf_point(x[i], t, nu);
+}
+
+
+// Reverse sweep through nsteps steps of each instance (all forward states kept).  lamT = dJ/du_T;
+// writes grad_u0 = dJ/du0 and grad_nu[i] = dJ/dnu_i; dtdx2[i] = dt/dx^2 = dD/dnu.
+void oracle_adjoint_run(int64_t count, const int64_t* offsets, const int32_t* bc, const int32_t* scheme,
+                        const double* r, const double* D, const double* a, const double* b,
+                        const double* dtdx2, const double* u0, const double* lamT, int64_t nsteps,
+                        double* grad_u0, double* grad_nu, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    auto st = forward_states(n, bc[i], scheme[i], a[i], b[i], r[i], D[i], u0 + offsets[i], nsteps);
+    std::vector<double> lam(lamT + offsets[i], lamT + offsets[i] + n), prev(n);
+    double gD = 0.0;
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+      if (scheme[i] == SCHEME_EXPLICIT)
+        gD += explicit_adjoint(n, bc[i], a[i], b[i], r[i], D[i], st[s].data(), lam.data(), prev.data());
+      else
+        gD += btcs_adjoint(n, bc[i], a[i], b[i], r[i], D[i], st[s].data(), st[s + 1].data(), lam.data(),
+                           prev.data());
+      lam.swap(prev);
+    }
+    if (bc[i] == DIRICHLET) { lam[0] = 0.0; lam[n - 1] = 0.0; }
+    for (int64_t k = 0; k < n; ++k) grad_u0[offsets[i] + k] = lam[k];
+    grad_nu[i] = gD * dtdx2[i];
+  }
+}
+
+// Tangent-linear sweep: du_T from du0 and dnu[i].
+void oracle_tangent_run(int64_t count, const int64_t* offsets, const int32_t* bc, const int32_t* scheme,
+                        const double* r, const double* D, const double* a, const double* b,
+                        const double* dtdx2, const double* u0, const double* du0, const double* dnu,
+                        int64_t nsteps, double* duT, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    auto st = forward_states(n, bc[i], scheme[i], a[i], b[i], r[i], D[i], u0 + offsets[i], nsteps);
+    std::vector<double> du(du0 + offsets[i], du0 + offsets[i] + n), nxt(n);
+    if (bc[i] == DIRICHLET) { du[0] = 0.0; du[n - 1] = 0.0; }
+    const double dD = dnu[i] * dtdx2[i];
+    for (int64_t s = 0; s < nsteps; ++s) {
+      if (scheme[i] == SCHEME_EXPLICIT)
+        explicit_tangent(n, bc[i], a[i], b[i], r[i], D[i], st[s].data(), du.data(), dD, nxt.data());
+      else
+        btcs_tangent(n, bc[i], a[i], b[i], r[i], D[i], st[s].data(), st[s + 1].data(), du.data(), dD, nxt.data());
+      du.swap(nxt);
+    }
+    for (int64_t k = 0; k < n; ++k) duT[offsets[i] + k] = du[k];
+  }
 }
 
 int oracle_max_threads(void) {

@@ -425,3 +425,77 @@ def test_fp32_oracle_tracks_fp64(oracle_lib):
     u64 = oracle_lib.run([p], b.u0, b.offsets, 100)
     u32 = oracle_lib.run([p], b.u0.astype(np.float32), b.offsets, 100)
     assert oracle_lib.rel_max_abs(u32, u64) < 1e-5
+
+
+# ------------------------------------------------------------------------------------ adjoint
+def _grad_case(seed, bc, scheme, positive):
+    """Small batch for gradient checks: J = 1/2 sum (u_T - target)^2 after a few steps."""
+    b = W.random_batch(seed, 3, 12, 40, bc=bc, scheme=scheme, amplitude=0.3 if positive else 2.0)
+    if positive:
+        b.u0 = b.u0 + 2.0
+        for i, p in enumerate(b.problems):
+            if p.bc == W.BC_DIRICHLET:
+                p.left, p.right = b.u0[b.offsets[i]], b.u0[b.offsets[i + 1] - 1]
+        b.umax = np.array([np.max(np.abs(b.instance(i))) for i in range(b.count)])
+    for i, p in enumerate(b.problems):
+        f = 1.0 if scheme == W.EXPLICIT else 6.0
+        p.dt = f * 0.5 * min(p.length / p.n / b.umax[i], (p.length / p.n) ** 2 / (2 * p.nu))
+    target = np.random.default_rng(seed + 1).standard_normal(len(b.u0)) * 0.1 + 1.0
+    return b, target
+
+
+def _loss(oracle_lib, b, u0, target, nsteps):
+    uT = oracle_lib.run(b.problems, u0, b.offsets, nsteps)
+    return 0.5 * float(np.sum((uT - target) ** 2)), uT
+
+
+@pytest.mark.parametrize("scheme", [W.EXPLICIT, W.BTCS])
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_DIRICHLET])
+@pytest.mark.parametrize("positive", [True, False])
+def test_adjoint_matches_finite_differences(oracle_lib, scheme, bc, positive):
+    """dJ/du0 along random directions and dJ/dnu by central differences of the (pinned) forward oracle."""
+    b, target = _grad_case(60 + 2 * bc + scheme, bc, scheme, positive)
+    nsteps = 7
+    J0, uT = _loss(oracle_lib, b, b.u0, target, nsteps)
+    g_u0, g_nu = oracle_lib.adjoint(b.problems, b.u0, b.offsets, uT - target, nsteps)
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    for _ in range(3):
+        e = rng.standard_normal(len(b.u0))
+        fd = (_loss(oracle_lib, b, b.u0 + h * e, target, nsteps)[0]
+              - _loss(oracle_lib, b, b.u0 - h * e, target, nsteps)[0]) / (2 * h)
+        assert abs(fd - np.dot(g_u0, e)) <= 1e-6 * (abs(fd) + 1e-8), (fd, np.dot(g_u0, e))
+    for i, p in enumerate(b.problems):
+        nu0 = p.nu
+        hn = 1e-4 * nu0          # J ~ 100 while nu dJ/dnu ~ 1e-3: a smaller step drowns in rounding
+        p.nu = nu0 + hn
+        Jp = _loss(oracle_lib, b, b.u0, target, nsteps)[0]
+        p.nu = nu0 - hn
+        Jm = _loss(oracle_lib, b, b.u0, target, nsteps)[0]
+        p.nu = nu0
+        fd = (Jp - Jm) / (2 * hn)
+        assert abs(fd - g_nu[i]) <= 1e-6 * (abs(fd) + 1e-8), (i, fd, g_nu[i])
+    if bc == W.BC_DIRICHLET:
+        for i in range(b.count):
+            assert g_u0[b.offsets[i]] == 0.0 and g_u0[b.offsets[i + 1] - 1] == 0.0
+
+
+@pytest.mark.parametrize("scheme", [W.EXPLICIT, W.BTCS])
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_DIRICHLET])
+def test_adjoint_is_transpose_of_tangent(oracle_lib, scheme, bc):
+    """Dot-product test <T v, w> = <v, T^T w> with v = (du0, dnu): adjoint and tangent sweeps are written
+    separately, so this fixes every transposition, corner and sign between them."""
+    b, _ = _grad_case(80 + bc + 2 * scheme, bc, scheme, False)
+    rng = np.random.default_rng(9)
+    du0 = rng.standard_normal(len(b.u0))
+    dnu = rng.standard_normal(b.count)
+    w = rng.standard_normal(len(b.u0))
+    for i, p in enumerate(b.problems):
+        if p.bc == W.BC_DIRICHLET:
+            w[b.offsets[i]] = w[b.offsets[i + 1] - 1] = 0.0
+    nsteps = 9
+    tv = oracle_lib.tangent(b.problems, b.u0, b.offsets, du0, dnu, nsteps)
+    g_u0, g_nu = oracle_lib.adjoint(b.problems, b.u0, b.offsets, w, nsteps)
+    lhs = float(np.dot(tv, w))
+    rhs = float(np.dot(du0, g_u0) + np.dot(dnu, g_nu))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + abs(rhs)), (lhs, rhs)

@@ -36,6 +36,17 @@ MUTANTS = {
     "cfl_diffusive_factor": ("lim = std::min(lim, dx * dx / (2.0 * nu));", "lim = std::min(lim, dx * dx / nu);"),
     "dx_dirichlet": ("length / (double)(n - 1);", "length / (double)n;"),
     "cole_hopf_speed": ("std::fmod(x - 4.0 * t, two_pi)", "std::fmod(x - 3.0 * t, two_pi)"),
+    "adj_explicit_self": ("self = 1.0 - r * (ui - um) - r * ui - 2.0 * D;", "self = 1.0 - r * (ui - um) + r * ui - 2.0 * D;"),
+    "adj_explicit_left": ("left = r * ui + D;", "left = D;"),
+    "adj_explicit_nu": ("gD += li * ((up + um) - 2.0 * ui);", "gD += li * ((up - um) - 2.0 * ui);"),
+    "adj_btcs_untransposed": ("btcs_matrix_solve(n, bc, r, D, y, lamp, mu.data(), true);",
+                              "btcs_matrix_solve(n, bc, r, D, y, lamp, mu.data(), false);"),
+    "adj_btcs_g_sign": ("lam[i] = (1.0 - G[i]) * mu[i];", "lam[i] = (1.0 + G[i]) * mu[i];"),
+    "adj_btcs_nu_sign": ("gD -= mu[i] * Lx[i];", "gD += mu[i] * Lx[i];"),
+    "adj_transpose_corner": ("tp[k] = bc == PERIODIC ? l[(k + 1) % m]", "tp[k] = bc == PERIODIC ? l[k]"),
+    "adj_g_upwind_side": ("G[i] = y[i] >= 0 ? r * (x[i] - xm) : r * (xp - x[i]);",
+                          "G[i] = y[i] >= 0 ? r * (xp - x[i]) : r * (x[i] - xm);"),
+    "tangent_drops_nu": ("dout[i] = v + D * dlap + dD * lap;", "dout[i] = v + D * dlap;"),
 }
 
 PINS = [name for name in dir(T) if name.startswith("test_")]
