@@ -57,7 +57,8 @@ class PhaseTimer:
         return out
 
 
-def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000):
+def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000, explicit_path=0, btcs_path=0,
+             btcs_block=0):
     """Time `steps` passes (after `warmup`) of the explicit and BTCS runs over the 4096 x 8192 batch."""
     import workloads as W
     batch = W.c2_batch()
@@ -67,6 +68,8 @@ def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000):
     cfl_batch(B, btcs_batch, 10.0)
     s_exp = B.Solver(exp_batch.problems, dtype=dtype)
     s_btcs = B.Solver(btcs_batch.problems, dtype=dtype)
+    s_exp.set_plan(explicit_path=explicit_path)
+    s_btcs.set_plan(btcs_path=btcs_path, btcs_block=btcs_block)
     u_init = s_exp.pack_flat(batch.u0, batch.offsets)
     u = torch.empty_like(u_init)
     timer = PhaseTimer()
@@ -94,6 +97,9 @@ def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000):
     btcs_ms = float(np.mean(spans["btcs"]))
     step_ms = exp_ms + btcs_ms
     res = {
+        "explicit_ms": exp_ms, "btcs_ms": btcs_ms, "n_exp": n_exp, "n_btcs": n_btcs,
+        "explicit_launches": 1 if s_exp.get_plan()["explicit_path"] in (0, 2) else n_exp,
+        "btcs_launches": 1 if s_btcs.get_plan()["btcs_path"] in (0, 2) else n_btcs,
         "updates_per_step": nodes * (n_exp + n_btcs),
         "step_ms": step_ms,
         "wall_ms_per_step": wall * 1e3 / steps,
@@ -166,6 +172,36 @@ def bench_c3(B, torch, n_exp=1024, n_btcs=32):
             "explicit_steps": n_exp, "btcs_steps": n_btcs}
 
 
+EXPLICIT_FLOPS_PER_UPDATE = 12     # mul, 4 sub, 1 add, 4 mul... counted in the design doc
+
+
+def dominant_roofline(c2):
+    """Roofline of the kernel that takes most of the C2 step (per-launch figures from HIP events)."""
+    nodes = 4096 * 8192
+    word = 8
+    exp_ms, btcs_ms = c2["explicit_ms"], c2["btcs_ms"]
+    if exp_ms >= btcs_ms:
+        # explicit: all steps of an instance in one on-chip launch -> bound by vector ALU
+        flops = EXPLICIT_FLOPS_PER_UPDATE * nodes * c2["n_exp"]
+        achieved = flops / (exp_ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / (FP64_VECTOR_PEAK / 1e12), "traffic": None,
+                "kernel": "explicit_block_kernel<double, true>", "launches": c2["explicit_launches"],
+                "algorithmic_flops_per_launch": flops / c2["explicit_launches"]}
+    per_launch = btcs_ms / c2["btcs_launches"]
+    if c2["btcs_launches"] == 1:
+        # resident BTCS: state on chip for all steps; the HBM traffic is one read and one write per launch
+        bytes_ = 2 * word * nodes
+        achieved = bytes_ * c2["n_btcs"] / (btcs_ms * 1e-3) / 1e9
+        return {"bound": "alu", "achieved_equiv_GBs": achieved, "kernel": "btcs_resident_kernel<double>",
+                "launches": 1, "note": "equivalent per-step HBM rate; the kernel moves the state once"}
+    bytes_ = 2 * word * nodes
+    achieved = bytes_ / (per_launch * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "btcs_wg_kernel<double, true>",
+            "launches": c2["btcs_launches"], "algorithmic_bytes_per_launch": bytes_}
+
+
 def cpu_baseline(target_s=12.0):
     """The oracle as it stands on the host cores, on a bounded sample of the same workload."""
     import oracle
@@ -213,6 +249,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--exp-steps", type=int, default=10_000, help="explicit steps per step (profiling runs)")
     ap.add_argument("--btcs-steps", type=int, default=1_000, help="BTCS steps per step (profiling runs)")
+    ap.add_argument("--explicit-path", type=int, default=0, help="force an explicit kernel path (0 auto)")
+    ap.add_argument("--btcs-path", type=int, default=0, help="force a BTCS kernel path (0 auto)")
+    ap.add_argument("--btcs-block", type=int, default=0, help="lanes per system of the BTCS solver (0 auto)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (instances shard "
@@ -224,7 +263,8 @@ def main():
     torch.cuda.set_device(0)
 
     log("C2 FP64")
-    c2 = bench_c2(B, torch, torch.float64, args.steps, args.warmup, args.exp_steps, args.btcs_steps)
+    c2 = bench_c2(B, torch, torch.float64, args.steps, args.warmup, args.exp_steps, args.btcs_steps,
+                  args.explicit_path, args.btcs_path, args.btcs_block)
     extra = {"c2_f64": c2}
     if not args.quick:
         log("C2 FP32")
@@ -234,15 +274,7 @@ def main():
         log("C3")
         extra["c3_f64"] = bench_c3(B, torch)
 
-    # dominant kernel: the explicit step (10^4 launches per step)
-    word = 8
-    nodes = 4096 * 8192
-    bytes_per_launch = 2 * word * nodes
-    achieved = bytes_per_launch / (c2["explicit_launch_ms"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "explicit_stream_kernel<double>",
-                "algorithmic_bytes_per_launch": bytes_per_launch}
+    roofline = dominant_roofline(c2)
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")

@@ -91,13 +91,16 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *                  3 multilevel: recursive partition across workgroups (any n).
  *   use_graph      1 replays the launch sequence of a stepping call from a captured HIP graph,
  *                  0 launches eagerly, -1 automatic.
+ *   btcs_block     lanes per system of the on-chip BTCS solver (512 or 1024; 0 automatic).
+ * burgers_set_plan rejects values outside these ranges with BURGERS_E_INVALID.
  */
 typedef struct {
   int32_t explicit_path;
   int32_t tblock_depth;
   int32_t btcs_path;
   int32_t use_graph;
-  int32_t reserved[4];
+  int32_t btcs_block;      /* lanes per system of the on-chip BTCS solver: 512, 1024, or 0 = automatic */
+  int32_t reserved[3];
 } burgers_plan;
 
 /*

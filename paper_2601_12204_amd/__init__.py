@@ -42,7 +42,7 @@ class CProblem(ctypes.Structure):
 class CPlan(ctypes.Structure):
     _fields_ = [("explicit_path", ctypes.c_int32), ("tblock_depth", ctypes.c_int32),
                 ("btcs_path", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("btcs_block", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -192,11 +192,11 @@ def burgers_get_plan(ctx) -> dict:
     plan = CPlan()
     _check(load().burgers_get_plan(ctx, ctypes.byref(plan)), "burgers_get_plan")
     return {"explicit_path": plan.explicit_path, "tblock_depth": plan.tblock_depth,
-            "btcs_path": plan.btcs_path, "use_graph": plan.use_graph}
+            "btcs_path": plan.btcs_path, "use_graph": plan.use_graph, "btcs_block": plan.btcs_block}
 
 
-def burgers_set_plan(ctx, explicit_path=0, tblock_depth=0, btcs_path=0, use_graph=-1) -> None:
-    plan = CPlan(int(explicit_path), int(tblock_depth), int(btcs_path), int(use_graph))
+def burgers_set_plan(ctx, explicit_path=0, tblock_depth=0, btcs_path=0, use_graph=-1, btcs_block=0) -> None:
+    plan = CPlan(int(explicit_path), int(tblock_depth), int(btcs_path), int(use_graph), int(btcs_block))
     _check(load().burgers_set_plan(ctx, ctypes.byref(plan)), "burgers_set_plan")
 
 
@@ -284,3 +284,55 @@ class Solver:
 
     def get_plan(self) -> dict:
         return burgers_get_plan(self.ctx)
+
+
+def adjoint_into(solver: "Solver", u0, lam_T, nsteps: int, ckpt_every: int, grad_u0, grad_nu) -> None:
+    """burgers_adjoint through a Solver (FP64 contexts): device buffers in the packed layout."""
+    solver._check_state(u0)
+    solver._check_state(lam_T)
+    solver._check_state(grad_u0)
+    if not (grad_nu.is_cuda and grad_nu.dtype == solver.torch_dtype and grad_nu.numel() >= solver.count):
+        raise ValueError("grad_nu must be a device tensor of the context dtype with >= count elements")
+    burgers_adjoint(solver.ctx, u0, lam_T, nsteps, ckpt_every, grad_u0, grad_nu)
+
+
+class BurgersSolve:
+    """torch.autograd.Function over burgers_run / burgers_adjoint.
+
+    ``u_T = BurgersSolve.apply(u0, nu, problems, nsteps, ckpt_every)`` advances the packed FP64 state u0
+    (layout of a Solver over ``problems``) nsteps steps of each instance's scheme, with the viscosities
+    taken from the tensor ``nu`` (one per instance).  Backward returns dJ/du0 and dJ/dnu from the
+    library's discrete adjoint, recomputing forward states from checkpoints every ckpt_every steps.
+    """
+
+    @staticmethod
+    def _function():
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, u0, nu, problems, nsteps, ckpt_every):
+                import dataclasses
+                nus = nu.detach().cpu().double().tolist()
+                probs = [dataclasses.replace(p, nu=float(v)) for p, v in zip(problems, nus)]
+                solver = Solver(probs, dtype=torch.float64)
+                u = u0.detach().clone()
+                solver.run(u, nsteps)
+                ctx.save_for_backward(u0.detach())
+                ctx.solver, ctx.nsteps, ctx.ckpt, ctx.nu_dtype = solver, nsteps, ckpt_every, nu.dtype
+                return u
+
+            @staticmethod
+            def backward(ctx, grad_uT):
+                (u0,) = ctx.saved_tensors
+                solver = ctx.solver
+                grad_u0 = torch.zeros_like(u0)
+                grad_nu = torch.zeros(solver.count, dtype=torch.float64, device=u0.device)
+                adjoint_into(solver, u0, grad_uT.contiguous(), ctx.nsteps, ctx.ckpt, grad_u0, grad_nu)
+                return grad_u0, grad_nu.to(ctx.nu_dtype), None, None, None
+
+        return _Fn
+
+    @staticmethod
+    def apply(u0, nu, problems, nsteps: int, ckpt_every: int = 100):
+        return BurgersSolve._function().apply(u0, nu, problems, nsteps, ckpt_every)

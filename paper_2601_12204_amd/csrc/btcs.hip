@@ -38,13 +38,27 @@ constexpr int kRedRows = kReduceBlock * kRedChunk;        // rows one partition 
 __device__ __forceinline__ int padded(int i) { return i + (i >> 5); }
 constexpr int padded_size(int rows) { return rows + rows / 32 + 1; }
 
+// Reciprocal of a binary64 value to about one ulp: the hardware estimate refined by two Newton steps
+// (written with explicit fused multiply-adds).  The solve only multiplies by reciprocals of pivots; in
+// binary64 the resulting per-step bias stays near 1e-17 and does not show at the 1e-12 parity bar.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+
+// Couplings below this fraction of a row's diagonal are below binary64 rounding of the solution.
+constexpr double kNegligible = 0x1p-60;
+
 // Rows of a reduced system stored with unit diagonal.
 template <typename T>
 struct ArrayRows {
   const T* __restrict__ A;
   const T* __restrict__ C;
   const T* __restrict__ Dv;
-  __device__ __forceinline__ void row(int k, int, T& al, T& be, T& ga, T& de) const {
+  __device__ __forceinline__ void row(int, int k, int, T& al, T& be, T& ga, T& de) const {
     al = A[k];
     be = T(1);
     ga = C[k];
@@ -60,7 +74,7 @@ struct LdsRows {
   int base;
   double r, D, a, b;
   bool dirichlet;
-  __device__ __forceinline__ void row(int k, int R, double& al, double& be, double& ga,
+  __device__ __forceinline__ void row(int, int k, int R, double& al, double& be, double& ga,
                                       double& de) const {
     const double ui = static_cast<double>(st[padded(k - base)]);
     btcs_row(ui, r, D, al, be, ga);
@@ -76,7 +90,22 @@ template <typename S>
 struct LdsDst {
   S* st;
   int base;
-  __device__ __forceinline__ void write(int k, double v) const { st[padded(k - base)] = static_cast<S>(v); }
+  __device__ __forceinline__ void write(int, int k, double v) const { st[padded(k - base)] = static_cast<S>(v); }
+};
+
+// Row k of a level-0 system from its old value ui (resident solver, where the values live in registers).
+struct ValueRows {
+  double r, D, a, b;
+  bool dirichlet;
+  __device__ __forceinline__ void row_value(double ui, int k, int R, double& al, double& be, double& ga,
+                                            double& de) const {
+    btcs_row(ui, r, D, al, be, ga);
+    de = ui;
+    if (dirichlet) {
+      if (k == 0) { de = de - al * a; al = 0.0; }
+      if (k == R - 1) { de = de - ga * b; ga = 0.0; }
+    }
+  }
 };
 
 // Chunk elimination.  Rows s..s+m-1 (2 <= m <= M) of a system with R rows.  On return, for
@@ -84,29 +113,33 @@ struct LdsDst {
 // reduced rows are
 //   F row:  AF * E_prev + F + CF * E      = DF
 //   E row:  AE * F      + E + CE * F_next = DE.
-template <typename T, int M, typename Src>
+// IN_PLACE: de[j] holds row j's old state value on entry (read just before de[j] is overwritten).
+template <typename T, int M, bool IN_PLACE = false, typename Src>
 __device__ __forceinline__ void chunk_eliminate(const Src& src, int s, int m, int R, T (&al)[M],
                                                 T (&ga)[M], T (&de)[M], T& AF, T& CF, T& DF, T& AE,
                                                 T& CE, T& DE) {
   T a0, b0, c0, d0;
-  src.row(s, R, a0, b0, c0, d0);
+  if constexpr (IN_PLACE) src.row_value(de[0], s, R, a0, b0, c0, d0);
+  else src.row(0, s, R, a0, b0, c0, d0);
   // forward: x_j + al[j] x_0 + ga[j] x_{j+1} = de[j]
 #pragma unroll
   for (int j = 1; j < M; ++j) {
     if (j < m) {
       T aj, bj, cj, dj;
-      src.row(s + j, R, aj, bj, cj, dj);
-      // Each coefficient is divided separately: scaling all three by one rounded reciprocal biases
-      // the row, and in FP32 that bias accumulates over many steps.
+      if constexpr (IN_PLACE) src.row_value(de[j], s + j, R, aj, bj, cj, dj);
+      else src.row(j, s + j, R, aj, bj, cj, dj);
+      // (binary64 only: one reciprocal per pivot; in binary32, scaling all three coefficients by one
+      // rounded reciprocal biases the row enough to accumulate over many steps)
       if (j == 1) {
-        al[1] = aj / bj;
-        ga[1] = cj / bj;
-        de[1] = dj / bj;
+        const T inv = recip(bj);
+        al[1] = aj * inv;
+        ga[1] = cj * inv;
+        de[1] = dj * inv;
       } else {
-        const T den = bj - aj * ga[j - 1];
-        al[j] = -(aj * al[j - 1]) / den;
-        ga[j] = cj / den;
-        de[j] = (dj - aj * de[j - 1]) / den;
+        const T inv = recip(bj - aj * ga[j - 1]);
+        al[j] = -(aj * al[j - 1]) * inv;
+        ga[j] = cj * inv;
+        de[j] = (dj - aj * de[j - 1]) * inv;
       }
       if (j == m - 1) {
         AE = al[j];
@@ -132,28 +165,41 @@ __device__ __forceinline__ void chunk_eliminate(const Src& src, int s, int m, in
     g1 = ga[1];
     d1 = de[1];
   }
-  const T den0 = b0 - c0 * a1;
-  AF = a0 / den0;
-  CF = -(c0 * g1) / den0;
-  DF = (d0 - c0 * d1) / den0;
+  const T inv0 = recip(b0 - c0 * a1);
+  AF = a0 * inv0;
+  CF = -(c0 * g1) * inv0;
+  DF = (d0 - c0 * d1) * inv0;
 }
 
 // Interior rows from the chunk's end values.
 template <typename T, int M, typename Dst>
 __device__ __forceinline__ void chunk_recover(const Dst& dst, int s, int m, const T (&al)[M],
                                               const T (&ga)[M], const T (&de)[M], T F, T E) {
-  dst.write(s, F);
+  dst.write(0, s, F);
 #pragma unroll
   for (int j = 1; j < M; ++j) {
-    if (j < m - 1) dst.write(s + j, de[j] - al[j] * F - ga[j] * E);
+    if (j < m - 1) dst.write(j, s + j, de[j] - al[j] * F - ga[j] * E);
+    if (j == m - 1) dst.write(j, s + j, E);
   }
-  dst.write(s + m - 1, E);
+}
+
+// In-place recovery for the resident solver: de[j] becomes row j's new value, rounded through the
+// state type S exactly as a store to and reload from the state buffer would round it.
+template <typename S, typename T, int M>
+__device__ __forceinline__ void chunk_recover_in_place(int m, const T (&al)[M], const T (&ga)[M], T (&de)[M],
+                                                       T F, T E) {
+  de[0] = static_cast<T>(static_cast<S>(F));
+#pragma unroll
+  for (int j = 1; j < M; ++j) {
+    if (j < m - 1) de[j] = static_cast<T>(static_cast<S>(de[j] - al[j] * F - ga[j] * E));
+    if (j == m - 1) de[j] = static_cast<T>(static_cast<S>(E));
+  }
 }
 
 template <typename S>
 struct PtrDst {
   S* __restrict__ x;
-  __device__ __forceinline__ void write(int k, double v) const { x[k] = static_cast<S>(v); }
+  __device__ __forceinline__ void write(int, int k, double v) const { x[k] = static_cast<S>(v); }
 };
 
 // Chunk layout of a system of R rows split into P chunks: sizes q or q+1, the longer ones first.
@@ -163,26 +209,32 @@ __device__ __forceinline__ void chunk_span(int k, int R, int P, int& s, int& m) 
   m = q + (k < rho ? 1 : 0);
 }
 
-// Cyclic PCR on R2 (a power of two, <= 2 NT) rows with coefficients in LDS.  Indices wrap modulo R2;
-// a non-cyclic system simply carries zero corner couplings.  After log2(R2) steps every row couples
-// only to itself and the solution is D / (A + B + C); it is left in sD.
+// Cyclic PCR on R2 (a power of two, <= 2 NT) rows with coefficients in LDS; sI holds 1/B.  Indices
+// wrap modulo R2; a non-cyclic system simply carries zero corner couplings.  After log2(R2) steps every
+// row couples only to itself and the solution is D / (A + B + C).  The reduction stops earlier once
+// every remaining coupling is negligible against its diagonal; the solution is then D / B.  The result
+// is left in sD.
 template <typename T, int NT>
-__device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, int R2) {
+__device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, T* sI, int R2) {
   const int tid = threadIdx.x;
-  for (int s = 1; s < R2; s <<= 1) {
+  bool done = false;
+  int s = 1;
+  for (; s < R2 && !done; s <<= 1) {
     T nA[2], nB[2], nC[2], nD[2];
+    int live = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int i = tid + h * NT;
       if (i < R2) {
         const int im = (i - s) & (R2 - 1);
         const int ip = (i + s) & (R2 - 1);
-        const T k1 = sA[i] / sB[im];
-        const T k2 = sC[i] / sB[ip];
+        const T k1 = sA[i] * sI[im];
+        const T k2 = sC[i] * sI[ip];
         nB[h] = (sB[i] - k1 * sC[im]) - k2 * sA[ip];
         nD[h] = (sD[i] - k1 * sD[im]) - k2 * sD[ip];
         nA[h] = -(k1 * sA[im]);
         nC[h] = -(k2 * sC[ip]);
+        live |= (__builtin_fabs(nA[h]) + __builtin_fabs(nC[h])) > kNegligible * __builtin_fabs(nB[h]);
       }
     }
     __syncthreads();
@@ -194,14 +246,16 @@ __device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, int R2) {
         sB[i] = nB[h];
         sC[i] = nC[h];
         sD[i] = nD[h];
+        sI[i] = recip(nB[h]);
       }
     }
-    __syncthreads();
+    done = !__syncthreads_or(live);
   }
+  const bool folded = !done;   // ran all log2(R2) steps: the remaining couplings point at the row itself
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int i = tid + h * NT;
-    if (i < R2) sD[i] = sD[i] / ((sB[i] + sA[i]) + sC[i]);
+    if (i < R2) sD[i] = folded ? sD[i] / ((sB[i] + sA[i]) + sC[i]) : sD[i] * sI[i];
   }
   __syncthreads();
 }
@@ -210,20 +264,22 @@ __device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, int R2) {
 // (coalesced loads), eliminate chunks from LDS, solve the reduced system by PCR in the same LDS, write
 // the new values back into the staging buffer and store them coalesced, with the Dirichlet boundary
 // nodes.  Reduced systems of the partition levels read (A, C, D) and write X in HBM directly.
-template <typename S, bool FromState>
-__global__ __launch_bounds__(kWgThreads, 4) void btcs_wg_kernel(
+template <typename S, bool FromState, int NT>
+__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, const S* __restrict__ u,
     S* __restrict__ out, const double* __restrict__ LA, const double* __restrict__ LC,
     const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
-  constexpr int kPcrBytes = 4 * 2 * kWgThreads * static_cast<int>(sizeof(T));
+  constexpr int MC = kWgRows / NT;
+  constexpr int kPcrBytes = 5 * 2 * NT * static_cast<int>(sizeof(T));
   constexpr int kStageBytes = FromState ? padded_size(kWgRows) * static_cast<int>(sizeof(S)) : 0;
   constexpr int kBytes = kStageBytes > kPcrBytes ? kStageBytes : kPcrBytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
   T* sA = reinterpret_cast<T*>(smem);
-  T* sB = sA + 2 * kWgThreads;
-  T* sC = sB + 2 * kWgThreads;
-  T* sD = sC + 2 * kWgThreads;
+  T* sB = sA + 2 * NT;
+  T* sC = sB + 2 * NT;
+  T* sD = sC + 2 * NT;
+  T* sI = sD + 2 * NT;
   S* stage = reinterpret_cast<S*>(smem);
 
   const SysDesc sys = systems[blockIdx.x];
@@ -239,7 +295,7 @@ __global__ __launch_bounds__(kWgThreads, 4) void btcs_wg_kernel(
     d = inst[sys.inst];
     const bool dir = d.bc == kDirichlet;
     const S* src = u + d.off + (dir ? 1 : 0);
-    for (int i = tid; i < R; i += kWgThreads) stage[padded(i)] = src[i];
+    for (int i = tid; i < R; i += NT) stage[padded(i)] = src[i];
     ssrc = LdsRows<S>{stage, 0, d.r, d.D, d.a, d.b, dir};
     sdst = LdsDst<S>{stage, 0};
     if (dir && tid == 0) {
@@ -256,34 +312,35 @@ __global__ __launch_bounds__(kWgThreads, 4) void btcs_wg_kernel(
     if (tid == 0) {
       T al, be, ga, de;
       if constexpr (FromState) {
-        ssrc.row(0, 1, al, be, ga, de);
+        ssrc.row(0, 0, 1, al, be, ga, de);
         out[d.off + 1] = static_cast<S>(de / be);
       } else {
-        asrc.row(0, 1, al, be, ga, de);
-        adst.write(0, de / be);
+        asrc.row(0, 0, 1, al, be, ga, de);
+        adst.write(0, 0, de / be);
       }
     }
     return;
   }
 
-  T al[kWgChunk], ga[kWgChunk], de[kWgChunk];
+  T al[MC], ga[MC], de[MC];
   T AF, CF, DF, AE, CE, DE;
   int s = 0, m = 0;
   if (tid < P) {
     chunk_span(tid, R, P, s, m);
     if constexpr (FromState) {
-      chunk_eliminate<T, kWgChunk>(ssrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+      chunk_eliminate<T, MC>(ssrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
     } else {
-      chunk_eliminate<T, kWgChunk>(asrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+      chunk_eliminate<T, MC>(asrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
     }
   }
   if constexpr (FromState) __syncthreads();   // the PCR arrays overlay the staged rows
   if (tid < P) {
-    sA[2 * tid] = AF; sB[2 * tid] = T(1); sC[2 * tid] = CF; sD[2 * tid] = DF;
+    sA[2 * tid] = AF; sB[2 * tid] = T(1); sC[2 * tid] = CF; sD[2 * tid] = DF; sI[2 * tid] = T(1);
     sA[2 * tid + 1] = AE; sB[2 * tid + 1] = T(1); sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
+    sI[2 * tid + 1] = T(1);
   }
   __syncthreads();
-  pcr_cyclic<T, kWgThreads>(sA, sB, sC, sD, 2 * P);
+  pcr_cyclic<T, NT>(sA, sB, sC, sD, sI, 2 * P);
   T F = T(0), E = T(0);
   if (tid < P) {
     F = sD[2 * tid];
@@ -291,12 +348,84 @@ __global__ __launch_bounds__(kWgThreads, 4) void btcs_wg_kernel(
   }
   if constexpr (FromState) {
     __syncthreads();                           // all ends read before the staging buffer is reused
-    if (tid < P) chunk_recover<T, kWgChunk>(sdst, s, m, al, ga, de, F, E);
+    if (tid < P) chunk_recover<T, MC>(sdst, s, m, al, ga, de, F, E);
     __syncthreads();
     S* dst = out + d.off + (d.bc == kDirichlet ? 1 : 0);
-    for (int i = tid; i < R; i += kWgThreads) dst[i] = stage[padded(i)];
+    for (int i = tid; i < R; i += NT) dst[i] = stage[padded(i)];
   } else {
-    if (tid < P) chunk_recover<T, kWgChunk>(adst, s, m, al, ga, de, F, E);
+    if (tid < P) chunk_recover<T, MC>(adst, s, m, al, ga, de, F, E);
+  }
+}
+
+// Resident solver: one workgroup keeps one system (<= 8192 rows) in registers, MC rows per lane (NT
+// lanes x MC = 8192), for all steps of a launch.  Each step is the whole-system solver's step without the trips to HBM; the
+// state is rounded through S once per step as the per-step kernel's store would, so both solvers agree
+// bitwise.  The state buffer is read once and written once per launch (in place).
+template <typename S, int NT, int MC>
+__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_resident_kernel(
+    const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, S* __restrict__ u,
+    int steps) {
+  using T = double;
+  __shared__ T pcr[5 * 2 * NT];
+  T* sA = pcr;
+  T* sB = sA + 2 * NT;
+  T* sC = sB + 2 * NT;
+  T* sD = sC + 2 * NT;
+  T* sI = sD + 2 * NT;
+  const SysDesc sys = systems[blockIdx.x];
+  const InstDesc d = inst[sys.inst];
+  const bool dir = d.bc == kDirichlet;
+  const int R = sys.rows, P = sys.chunks;
+  const int tid = threadIdx.x;
+  S* __restrict__ x = u + d.off + (dir ? 1 : 0);
+  if (dir && tid == 0) {
+    u[d.off] = static_cast<S>(d.a);
+    u[d.off + d.n - 1] = static_cast<S>(d.b);
+  }
+  if (R == 1) {   // a single Dirichlet unknown
+    if (tid == 0) {
+      T v = static_cast<T>(x[0]);
+      for (int step = 0; step < steps; ++step) {
+        T al, be, ga;
+        btcs_row(v, d.r, d.D, al, be, ga);
+        const T de = (v - al * d.a) - ga * d.b;
+        v = static_cast<T>(static_cast<S>(de / be));
+      }
+      x[0] = static_cast<S>(v);
+    }
+    return;
+  }
+  int s = 0, m = 0;
+  T al[MC], ga[MC], de[MC];   // de carries the state between steps
+  if (tid < P) {
+    chunk_span(tid, R, P, s, m);
+#pragma unroll
+    for (int j = 0; j < MC; ++j)
+      if (j < m) de[j] = static_cast<T>(x[s + j]);
+  }
+  const ValueRows src{d.r, d.D, d.a, d.b, dir};
+  for (int step = 0; step < steps; ++step) {
+    T AF, CF, DF, AE, CE, DE;
+    if (tid < P) {
+      chunk_eliminate<T, MC, true>(src, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+      sA[2 * tid] = AF; sB[2 * tid] = T(1); sC[2 * tid] = CF; sD[2 * tid] = DF; sI[2 * tid] = T(1);
+      sA[2 * tid + 1] = AE; sB[2 * tid + 1] = T(1); sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
+      sI[2 * tid + 1] = T(1);
+    }
+    __syncthreads();
+    pcr_cyclic<T, NT>(sA, sB, sC, sD, sI, 2 * P);
+    T F = T(0), E = T(0);
+    if (tid < P) {
+      F = sD[2 * tid];
+      E = sD[2 * tid + 1];
+    }
+    __syncthreads();                           // ends read before the next step rewrites the arrays
+    if (tid < P) chunk_recover_in_place<S>(m, al, ga, de, F, E);
+  }
+  if (tid < P) {
+#pragma unroll
+    for (int j = 0; j < MC; ++j)
+      if (j < m) x[s + j] = static_cast<S>(de[j]);
   }
 }
 
@@ -430,8 +559,8 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   for (int l = L - 1; l >= 1; --l) {
     const auto& lv = plan.levels[l];
     if (lv.n_wg) {
-      btcs_wg_kernel<S, false><<<lv.n_wg, kWgThreads, 0, st>>>(inst, lv.wg->as<SysDesc>(), u, out, LA,
-                                                               LC, LD, LX);
+      btcs_wg_kernel<S, false, kWgThreads><<<lv.n_wg, kWgThreads, 0, st>>>(inst, lv.wg->as<SysDesc>(), u,
+                                                                           out, LA, LC, LD, LX);
     }
     if (lv.n_blocks) {
       btcs_backsub_kernel<S, false><<<lv.n_blocks, kReduceBlock, 0, st>>>(
@@ -439,8 +568,13 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
     }
   }
   if (plan.n_wg_state) {
-    btcs_wg_kernel<S, true><<<plan.n_wg_state, kWgThreads, 0, st>>>(
-        inst, plan.wg_state->as<SysDesc>(), u, out, LA, LC, LD, LX);
+    if (plan.threads == 1024) {
+      btcs_wg_kernel<S, true, 1024><<<plan.n_wg_state, 1024, 0, st>>>(
+          inst, plan.wg_state->as<SysDesc>(), u, out, LA, LC, LD, LX);
+    } else {
+      btcs_wg_kernel<S, true, kWgThreads><<<plan.n_wg_state, kWgThreads, 0, st>>>(
+          inst, plan.wg_state->as<SysDesc>(), u, out, LA, LC, LD, LX);
+    }
   }
   if (L > 0 && plan.levels[0].n_blocks) {
     const auto& lv = plan.levels[0];
@@ -452,6 +586,34 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
 
 }  // namespace
 
+template <typename S, int NT>
+void resident_launch(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u, int steps) {
+  btcs_resident_kernel<S, NT, kWgRows / NT><<<static_cast<unsigned>(n_sys), NT, 0, ctx->stream>>>(
+      ctx->inst.as<InstDesc>(), systems, static_cast<S*>(u), steps);
+}
+
+hipError_t launch_btcs_resident(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u,
+                                int steps, int threads) {
+  if (n_sys <= 0 || steps <= 0) return hipSuccess;
+  const bool f64 = ctx->dtype == BURGERS_F64;
+  if (threads == 512) {
+    if (f64) resident_launch<double, 512>(ctx, systems, n_sys, u, steps);
+    else resident_launch<float, 512>(ctx, systems, n_sys, u, steps);
+  } else {
+    if (f64) resident_launch<double, 1024>(ctx, systems, n_sys, u, steps);
+    else resident_launch<float, 1024>(ctx, systems, n_sys, u, steps);
+  }
+  return hipGetLastError();
+}
+
+// Chunk count of the whole-system and on-chip solvers with `threads` lanes: the largest power of two P <= threads with
+// two rows or more per chunk; systems of up to 8192 rows then have chunks of at most 8192 / threads.
+int btcs_chunks(int rows, int threads) {
+  int P = 1;
+  while (2 * P <= threads && 2 * (2 * P) <= rows) P *= 2;
+  return P;
+}
+
 int btcs_wg_capacity() { return kWgRows; }
 
 int btcs_wg_chunks(int rows) {
@@ -462,6 +624,33 @@ int btcs_wg_chunks(int rows) {
 }
 
 int btcs_reduce_chunk() { return kRedChunk; }
+
+// Solve systems stored in (A, C, D) arrays with unit diagonal (all levels array-sourced); the solution
+// lands in X at each root system's offset.  levels[0] holds the roots that need partitioning.
+hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
+                              double* LD, double* LX) {
+  const InstDesc* inst = ctx->inst.as<InstDesc>();
+  hipStream_t st = ctx->stream;
+  const double* none = nullptr;
+  double* none_out = nullptr;
+  const int L = static_cast<int>(plan.levels.size());
+  for (int l = 0; l < L; ++l) {
+    const auto& lv = plan.levels[l];
+    if (lv.n_blocks)
+      btcs_reduce_kernel<double, false><<<lv.n_blocks, kReduceBlock, 0, st>>>(
+          inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), none, LA, LC, LD);
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    const auto& lv = plan.levels[l];
+    if (lv.n_wg)
+      btcs_wg_kernel<double, false, kWgThreads><<<lv.n_wg, kWgThreads, 0, st>>>(
+          inst, lv.wg->as<SysDesc>(), none, none_out, LA, LC, LD, LX);
+    if (lv.n_blocks)
+      btcs_backsub_kernel<double, false><<<lv.n_blocks, kReduceBlock, 0, st>>>(
+          inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), none, none_out, LA, LC, LD, LX);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out) {
   if (ctx->dtype == BURGERS_F64) return launch_step<double>(ctx, plan, u, out);

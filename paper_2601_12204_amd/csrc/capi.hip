@@ -158,21 +158,41 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
   return BURGERS_OK;
 }
 
-// BTCS launch plan of one instance subset: whole-system solves for short systems, partition levels for
-// long ones.  Reduced-system rows are carved from the context's level arrays.
-hipError_t ensure_btcs(burgers_ctx* ctx, int set) {
-  if (ctx->btcs.count(set)) return hipSuccess;
+// BTCS launch plan of one instance subset under the context's forced path (0 = automatic).
+//   path 1: every step through HBM; whole-system solves for systems of up to 8192 rows, partition
+//           levels for longer ones.
+//   path 2: systems of up to 8192 rows stay on chip for all steps of a launch (every system must fit).
+//   path 3: partition levels for every system of at least 32 rows (shorter ones solved whole).
+//   automatic: on chip for systems that fit, partition levels for longer ones.
+// Reduced-system rows are carved from the context's level arrays.
+burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
+  const int want = ctx->plan.btcs_path;
+  const int threads = ctx->plan.btcs_block ? ctx->plan.btcs_block : burgers::kResidentThreadsDefault;
+  auto found = ctx->btcs.find(set);
+  if (found != ctx->btcs.end() && found->second->path == want && found->second->threads == threads)
+    return BURGERS_OK;
   auto plan = std::make_unique<burgers::BtcsPlan>();
+  plan->path = want;
+  plan->threads = threads;
   const int cap = burgers::btcs_wg_capacity();
   const int chunk = burgers::btcs_reduce_chunk();
-  std::vector<SysDesc> wg_state;
+  std::vector<SysDesc> wg_state, resident;
+  std::vector<int32_t> stepped;
   std::vector<std::vector<SysDesc>> red_sys, wg_sys;
   int64_t rows_used = 0;
   for (int32_t i : set_members(ctx, set)) {
     const burgers_problem& p = ctx->probs[i];
     const int32_t R0 = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
-    if (R0 <= cap) {
-      wg_state.push_back(SysDesc{0, -1, R0, burgers::btcs_wg_chunks(R0), i, 0});
+    const bool fits = R0 <= cap;
+    if (want == 2 && !fits) return BURGERS_E_UNSUPPORTED;
+    if ((want == 0 || want == 2) && fits) {
+      resident.push_back(SysDesc{0, -1, R0, burgers::btcs_chunks(R0, threads), i, 0});
+      continue;
+    }
+    stepped.push_back(i);
+    const bool partition = want == 3 ? R0 >= 32 : !fits;
+    if (!partition) {
+      wg_state.push_back(SysDesc{0, -1, R0, burgers::btcs_chunks(R0, threads), i, 0});
       continue;
     }
     int32_t R = R0;
@@ -194,12 +214,19 @@ hipError_t ensure_btcs(burgers_ctx* ctx, int set) {
       R = 2 * P;
     }
   }
-  if (rows_used > ctx->level_capacity) return hipErrorOutOfMemory;   // sized at create
+  if (rows_used > ctx->level_capacity) return BURGERS_E_NOMEM;   // sized at create for every path
   plan->level_rows = rows_used;
+  hipError_t e;
   plan->n_wg_state = static_cast<int32_t>(wg_state.size());
+  plan->n_resident = static_cast<int32_t>(resident.size());
   plan->wg_state = std::make_unique<DevBuf>();
-  hipError_t e = upload(*plan->wg_state, wg_state);
-  if (e != hipSuccess) return e;
+  plan->resident = std::make_unique<DevBuf>();
+  plan->copy = std::make_unique<DevBuf>();
+  auto ct = stream_tiles(ctx, stepped);
+  plan->n_copy = static_cast<int64_t>(ct.size());
+  if ((e = upload(*plan->wg_state, wg_state)) != hipSuccess || (e = upload(*plan->resident, resident)) != hipSuccess ||
+      (e = upload(*plan->copy, ct)) != hipSuccess)
+    return from_hip(e);
   plan->levels.resize(red_sys.size());
   for (size_t l = 0; l < red_sys.size(); ++l) {
     auto& lv = plan->levels[l];
@@ -210,24 +237,24 @@ hipError_t ensure_btcs(burgers_ctx* ctx, int set) {
     lv.sys = std::make_unique<DevBuf>();
     lv.blocks = std::make_unique<DevBuf>();
     lv.wg = std::make_unique<DevBuf>();
-    if ((e = upload(*lv.sys, red_sys[l])) != hipSuccess) return e;
-    if ((e = upload(*lv.blocks, blocks)) != hipSuccess) return e;
-    if ((e = upload(*lv.wg, wg_sys[l])) != hipSuccess) return e;
+    if ((e = upload(*lv.sys, red_sys[l])) != hipSuccess || (e = upload(*lv.blocks, blocks)) != hipSuccess ||
+        (e = upload(*lv.wg, wg_sys[l])) != hipSuccess)
+      return from_hip(e);
     lv.n_blocks = static_cast<int32_t>(blocks.size());
     lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
   }
   ctx->btcs[set] = std::move(plan);
-  return hipSuccess;
+  return BURGERS_OK;
 }
 
-// Rows of the partition levels all long instances need (upper bound used to size the level arrays).
+// Rows of the partition levels the instances can need on any path (sizes the level arrays).
 int64_t level_rows_needed(const burgers_ctx* ctx) {
   const int cap = burgers::btcs_wg_capacity();
   const int chunk = burgers::btcs_reduce_chunk();
   int64_t rows = 0;
   for (const auto& p : ctx->probs) {
     int64_t R = p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2;
-    if (R <= cap) continue;
+    if (R < 32) continue;                      // partition levels serve systems of >= 32 rows
     for (int level = 0;; ++level) {
       if (level > 0 && R <= cap) break;
       const int64_t P = (R + chunk - 1) / chunk;
@@ -284,17 +311,22 @@ hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) 
 
 // Enqueue nsteps BTCS steps of one subset; the final state lands in u.
 hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
+  const burgers::BtcsPlan& pl = *ctx->btcs[set];
+  hipError_t e = hipSuccess;
+  for (int64_t done = 0; done < nsteps;) {   // on-chip systems, in place
+    const int k = static_cast<int>(std::min<int64_t>(nsteps - done, int64_t{1} << 30));
+    if ((e = burgers::launch_btcs_resident(ctx, pl.resident->as<SysDesc>(), pl.n_resident, u, k, pl.threads)) != hipSuccess)
+      return e;
+    done += k;
+  }
+  if (pl.n_copy == 0) return e;
   void* bufs[2] = {u, ctx->work.ptr};
   int cur = 0;
-  hipError_t e = hipSuccess;
   for (int64_t s = 0; s < nsteps; ++s) {
-    if ((e = burgers::launch_btcs_step(ctx, *ctx->btcs[set], bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+    if ((e = burgers::launch_btcs_step(ctx, pl, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
     cur ^= 1;
   }
-  if (cur) {
-    auto& ct = ctx->copy_tiles[set];
-    e = burgers::launch_copy_tiles(ctx, ct.first->as<Tile>(), ct.second, ctx->work.ptr, u);
-  }
+  if (cur) e = burgers::launch_copy_tiles(ctx, pl.copy->as<Tile>(), pl.n_copy, ctx->work.ptr, u);
   return e;
 }
 
@@ -315,10 +347,8 @@ burgers_status prepare(burgers_ctx* ctx, int set, int scheme) {
   const int es = scheme < 0 ? kSetExplicit : set;
   const int bs = scheme < 0 ? kSetBtcs : set;
   if (need_explicit && (st = ensure_explicit(ctx, es)) != BURGERS_OK) return st;
-  if (need_btcs) {
-    if ((e = ensure_btcs(ctx, bs)) != hipSuccess) return from_hip(e);
-    if ((e = ensure_copy(ctx, bs)) != hipSuccess) return from_hip(e);
-  }
+  if (need_btcs && (st = ensure_btcs(ctx, bs)) != BURGERS_OK) return st;
+  (void)e;
   return BURGERS_OK;
 }
 
@@ -365,6 +395,121 @@ burgers_status advance(burgers_ctx* ctx, void* u, int64_t nsteps, int set, int s
   else e = enqueue_all(ctx, set, scheme, u, nsteps);
   if (e != hipSuccess) return note(ctx, e);
   return BURGERS_OK;
+}
+
+
+// Adjoint launch lists: 256-node tiles of every instance (explicit and BTCS lists), one dJ/dD slot per
+// tile, and the partition hierarchy over the transposed BTCS systems, which sit at the start of the
+// adjoint arrays followed by their reduced rows.
+burgers_status ensure_adjoint(burgers_ctx* ctx) {
+  if (ctx->adjoint) return BURGERS_OK;
+  auto ap = std::make_unique<burgers::AdjointPlan>();
+  const int tile = burgers::adjoint_tile_nodes();
+  const int cap = burgers::btcs_wg_capacity();
+  const int chunk = burgers::btcs_reduce_chunk();
+  std::vector<burgers::AdjTile> et, bt;
+  std::vector<int32_t> slot_begin(ctx->count + 1, 0);
+  int32_t slot = 0;
+  int64_t sys_rows = 0;
+  std::vector<int64_t> sys_off(ctx->count, -1);
+  for (int32_t i = 0; i < ctx->count; ++i) {
+    const burgers_problem& p = ctx->probs[i];
+    if (p.scheme == BURGERS_BTCS) {
+      sys_off[i] = sys_rows;
+      sys_rows += p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2;
+    }
+  }
+  std::vector<std::vector<SysDesc>> red_sys(1), wg_sys(1);
+  int64_t rows_used = sys_rows;
+  for (int32_t i = 0; i < ctx->count; ++i) {
+    const burgers_problem& p = ctx->probs[i];
+    const int32_t n = static_cast<int32_t>(p.n);
+    slot_begin[i] = slot;
+    for (int32_t s = 0; s < n; s += tile)
+      (p.scheme == BURGERS_BTCS ? bt : et).push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, s, slot++, 0});
+    if (p.scheme != BURGERS_BTCS) continue;
+    int32_t R = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
+    int64_t in_off = sys_off[i];
+    for (int level = 0;; ++level) {
+      if (static_cast<int>(red_sys.size()) <= level) {
+        red_sys.resize(level + 1);
+        wg_sys.resize(level + 1);
+      }
+      if (R <= cap) {
+        wg_sys[level].push_back(SysDesc{in_off, -1, R, burgers::btcs_chunks(R, 512), i, level});
+        break;
+      }
+      const int32_t P = (R + chunk - 1) / chunk;
+      const int64_t red = rows_used;
+      rows_used += 2 * static_cast<int64_t>(P);
+      red_sys[level].push_back(SysDesc{in_off, red, R, P, i, level});
+      in_off = red;
+      R = 2 * P;
+    }
+  }
+  slot_begin[ctx->count] = slot;
+  hipError_t e;
+  ap->exp_tiles = std::make_unique<DevBuf>();
+  ap->btcs_tiles = std::make_unique<DevBuf>();
+  ap->slot_begin = std::make_unique<DevBuf>();
+  if ((e = upload(*ap->exp_tiles, et)) != hipSuccess || (e = upload(*ap->btcs_tiles, bt)) != hipSuccess ||
+      (e = upload(*ap->slot_begin, slot_begin)) != hipSuccess)
+    return from_hip(e);
+  ap->n_exp_tiles = static_cast<int64_t>(et.size());
+  ap->n_btcs_tiles = static_cast<int64_t>(bt.size());
+  ap->n_slots = slot;
+  ap->solve.levels.resize(red_sys.size());
+  for (size_t l = 0; l < red_sys.size(); ++l) {
+    auto& lv = ap->solve.levels[l];
+    std::vector<ChunkBlock> blocks;
+    for (size_t si = 0; si < red_sys[l].size(); ++si)
+      for (int32_t c = 0; c < red_sys[l][si].chunks; c += burgers::kReduceBlock)
+        blocks.push_back(ChunkBlock{static_cast<int32_t>(si), c});
+    lv.sys = std::make_unique<DevBuf>();
+    lv.blocks = std::make_unique<DevBuf>();
+    lv.wg = std::make_unique<DevBuf>();
+    if ((e = upload(*lv.sys, red_sys[l])) != hipSuccess || (e = upload(*lv.blocks, blocks)) != hipSuccess ||
+        (e = upload(*lv.wg, wg_sys[l])) != hipSuccess)
+      return from_hip(e);
+    lv.n_blocks = static_cast<int32_t>(blocks.size());
+    lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
+  }
+  const size_t lb = static_cast<size_t>(rows_used) * sizeof(double);
+  if ((e = ap->LA.alloc(lb)) != hipSuccess || (e = ap->LC.alloc(lb)) != hipSuccess ||
+      (e = ap->LD.alloc(lb)) != hipSuccess || (e = ap->LX.alloc(lb)) != hipSuccess ||
+      (e = ap->gslot.alloc(static_cast<size_t>(std::max<int64_t>(slot, 1)) * sizeof(double))) != hipSuccess)
+    return from_hip(e);
+  ctx->adjoint = std::move(ap);
+  return BURGERS_OK;
+}
+
+hipError_t grow(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.ptr) return hipSuccess;
+  if (b.ptr) {
+    (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  return b.alloc(bytes);
+}
+
+// One adjoint step: lam_out from lam_in at the forward pair (y = u^k, x = u^{k+1}).
+hipError_t enqueue_adjoint_step(burgers_ctx* ctx, const double* y, const double* x, const double* lam_in,
+                                double* lam_out) {
+  burgers::AdjointPlan& ap = *ctx->adjoint;
+  double* g = ap.gslot.as<double>();
+  hipError_t e = burgers::launch_adj_explicit(ctx, ap.exp_tiles->as<burgers::AdjTile>(), ap.n_exp_tiles, y,
+                                              lam_in, lam_out, g);
+  if (e != hipSuccess || ap.n_btcs_tiles == 0) return e;
+  if ((e = burgers::launch_adj_btcs_assemble(ctx, ap.btcs_tiles->as<burgers::AdjTile>(), ap.n_btcs_tiles, y,
+                                             lam_in, ap.LA.as<double>(), ap.LC.as<double>(),
+                                             ap.LD.as<double>())) != hipSuccess)
+    return e;
+  if ((e = burgers::launch_array_solve(ctx, ap.solve, ap.LA.as<double>(), ap.LC.as<double>(), ap.LD.as<double>(),
+                                       ap.LX.as<double>())) != hipSuccess)
+    return e;
+  return burgers::launch_adj_btcs_finish(ctx, ap.btcs_tiles->as<burgers::AdjTile>(), ap.n_btcs_tiles, y, x,
+                                         ap.LX.as<double>(), lam_out, g);
 }
 
 }  // namespace
@@ -438,6 +583,10 @@ burgers_status burgers_create(const burgers_problem* problems, int64_t count, bu
     d.n = static_cast<int32_t>(p.n);
     d.bc = p.bc;
     burgers_ratios(&p, &d.r, &d.D);
+    {
+      const double dxv = grid_dx(p);
+      d.dtdx2 = p.dt / (dxv * dxv);
+    }
     d.a = p.bc == BURGERS_BC_DIRICHLET ? p.left : 0.0;
     d.b = p.bc == BURGERS_BC_DIRICHLET ? p.right : 0.0;
     ctx->set_all.push_back(static_cast<int32_t>(i));
@@ -495,7 +644,61 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
                                int64_t ckpt_every, void* grad_u0, void* grad_nu) {
   if (!ctx || !u0 || !lambda_T || !grad_u0 || !grad_nu || nsteps < 0 || ckpt_every < 1)
     return BURGERS_E_INVALID;
-  return BURGERS_E_UNSUPPORTED;
+  if (ctx->dtype != BURGERS_F64) return BURGERS_E_UNSUPPORTED;
+  if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return note(ctx, e);
+  burgers_status st = prepare(ctx, kSetAll, -1);
+  if (st != BURGERS_OK) return st;
+  if ((st = ensure_adjoint(ctx)) != BURGERS_OK) return st;
+  burgers::AdjointPlan& ap = *ctx->adjoint;
+  const size_t state_bytes = static_cast<size_t>(ctx->total) * sizeof(double);
+  const int64_t K = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
+  const int64_t ncp = (nsteps + K - 1) / K;   // checkpoints at steps 0, K, 2K, ...
+  if ((e = grow(ap.ckpt, state_bytes * static_cast<size_t>(std::max<int64_t>(ncp, 1)))) != hipSuccess ||
+      (e = grow(ap.seg, state_bytes * static_cast<size_t>(K + 1))) != hipSuccess ||
+      (e = grow(ap.lam0, state_bytes)) != hipSuccess || (e = grow(ap.lam1, state_bytes)) != hipSuccess)
+    return from_hip(e);
+  auto state = [&](DevBuf& b, int64_t k) { return static_cast<char*>(b.ptr) + static_cast<size_t>(k) * state_bytes; };
+  const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;
+  // forward sweep, keeping checkpoints
+  if (ncp > 0 && (e = hipMemcpyAsync(state(ap.ckpt, 0), u0, state_bytes, d2d, ctx->stream)) != hipSuccess)
+    return note(ctx, e);
+  for (int64_t c = 1; c < ncp; ++c) {
+    if ((e = hipMemcpyAsync(state(ap.ckpt, c), state(ap.ckpt, c - 1), state_bytes, d2d, ctx->stream)) != hipSuccess ||
+        (e = enqueue_all(ctx, kSetAll, -1, state(ap.ckpt, c), K)) != hipSuccess)
+      return note(ctx, e);
+  }
+  // reverse sweep: recompute each segment's states one step at a time, then step the adjoint back
+  double* lam = ap.lam0.as<double>();
+  double* lam_next = ap.lam1.as<double>();
+  if ((e = hipMemcpyAsync(lam, lambda_T, state_bytes, d2d, ctx->stream)) != hipSuccess ||
+      (e = burgers::launch_fill(ctx, ap.gslot.as<double>(), ap.n_slots, 0.0)) != hipSuccess)
+    return note(ctx, e);
+  for (int64_t c = ncp - 1; c >= 0; --c) {
+    const int64_t len = std::min(K, nsteps - c * K);
+    if ((e = hipMemcpyAsync(state(ap.seg, 0), state(ap.ckpt, c), state_bytes, d2d, ctx->stream)) != hipSuccess)
+      return note(ctx, e);
+    for (int64_t k = 1; k <= len; ++k) {
+      if ((e = hipMemcpyAsync(state(ap.seg, k), state(ap.seg, k - 1), state_bytes, d2d, ctx->stream)) != hipSuccess ||
+          (e = enqueue_all(ctx, kSetAll, -1, state(ap.seg, k), 1)) != hipSuccess)
+        return note(ctx, e);
+    }
+    for (int64_t k = len - 1; k >= 0; --k) {
+      if ((e = enqueue_adjoint_step(ctx, reinterpret_cast<const double*>(state(ap.seg, k)),
+                                    reinterpret_cast<const double*>(state(ap.seg, k + 1)), lam, lam_next)) != hipSuccess)
+        return note(ctx, e);
+      std::swap(lam, lam_next);
+    }
+  }
+  if ((e = ensure_copy(ctx, kSetAll)) != hipSuccess) return from_hip(e);
+  auto& all_tiles = ctx->copy_tiles[kSetAll];
+  if ((e = burgers::launch_copy_tiles(ctx, all_tiles.first->as<Tile>(), all_tiles.second, lam, grad_u0)) != hipSuccess ||
+      (e = burgers::launch_zero_dirichlet_ends(ctx, static_cast<double*>(grad_u0))) != hipSuccess ||
+      (e = burgers::launch_adj_nu(ctx, ap.slot_begin->as<int32_t>(), ap.gslot.as<double>(),
+                                  static_cast<double*>(grad_nu))) != hipSuccess)
+    return note(ctx, e);
+  return BURGERS_OK;
 }
 
 burgers_status burgers_sync(burgers_ctx* ctx) {
@@ -516,12 +719,15 @@ burgers_status burgers_get_plan(const burgers_ctx* ctx, burgers_plan* out) {
 burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan) {
   if (!ctx || !plan) return BURGERS_E_INVALID;
   if (plan->explicit_path < 0 || plan->explicit_path > 3 || plan->btcs_path < 0 || plan->btcs_path > 3 ||
-      plan->tblock_depth < 0 || plan->tblock_depth > 32 || plan->use_graph < -1 || plan->use_graph > 1)
+      plan->tblock_depth < 0 || plan->tblock_depth > 32 || plan->use_graph < -1 || plan->use_graph > 1 ||
+      (plan->btcs_block != 0 && plan->btcs_block != 512 && plan->btcs_block != 1024))
     return BURGERS_E_INVALID;
   const bool explicit_changed = plan->explicit_path != ctx->plan.explicit_path ||
                                 plan->tblock_depth != ctx->plan.tblock_depth;
+  const bool btcs_changed = plan->btcs_path != ctx->plan.btcs_path || plan->btcs_block != ctx->plan.btcs_block;
   ctx->plan = *plan;
   if (explicit_changed) ctx->explicit_plans.clear();
+  if (btcs_changed) ctx->btcs.clear();
   for (auto& kv : ctx->graph_cache) (void)hipGraphExecDestroy(kv.second);
   ctx->graph_cache.clear();
   return BURGERS_OK;

@@ -26,6 +26,7 @@ struct InstDesc {
   double D;     // nu dt / dx^2
   double a;     // Dirichlet left value
   double b;     // Dirichlet right value
+  double dtdx2; // dt / dx^2 = dD / dnu
 };
 
 // A run of consecutive nodes of one instance handled by one workgroup of a streaming kernel.  It
@@ -48,6 +49,19 @@ struct BlockTile {
   int32_t lo;
   int32_t count;
   int32_t wrap;   // 1: the window is a whole periodic instance and its ends are neighbours
+};
+
+// A run of 256 nodes of one instance in the adjoint sweep; `slot` indexes the tile's accumulator of
+// dJ/dD and `sys_off` the instance's transposed system in the adjoint arrays (BTCS instances).
+struct AdjTile {
+  int64_t off;
+  int64_t sys_off;
+  int32_t n;
+  int32_t bc;
+  int32_t inst;
+  int32_t start;
+  int32_t slot;
+  int32_t pad;
 };
 
 // One tridiagonal system of the BTCS solve at some level of the partition hierarchy.
@@ -83,6 +97,13 @@ struct DevBuf {
 
 // Launch list of the BTCS solve for a set of instances, built once per context and set.
 struct BtcsPlan {
+  int path = 0;                              // 0 automatic, 1 per-step, 2 resident, 3 partition levels
+  int threads = 0;                           // lanes per system of the on-chip solver (512 or 1024)
+  // systems kept on chip for all steps of a launch (in place)
+  std::unique_ptr<DevBuf> resident;          // SysDesc[]
+  int32_t n_resident = 0;
+  std::unique_ptr<DevBuf> copy;              // Tile[] of the instances stepped through HBM (copy-back)
+  int64_t n_copy = 0;
   // small systems solved whole by one workgroup each, straight from and to the state
   std::unique_ptr<DevBuf> wg_state;          // SysDesc[]
   int32_t n_wg_state = 0;
@@ -111,6 +132,17 @@ struct ExplicitPlan {
   int depth = 0;                             // steps per launch of the windows (and whole tiles, path 3)
 };
 
+// Launch lists and buffers of the adjoint sweep (built on the first burgers_adjoint call).
+struct AdjointPlan {
+  std::unique_ptr<DevBuf> exp_tiles, btcs_tiles;   // AdjTile[]
+  int64_t n_exp_tiles = 0, n_btcs_tiles = 0;
+  std::unique_ptr<DevBuf> slot_begin;               // int32[count + 1]
+  int64_t n_slots = 0;
+  BtcsPlan solve;                                   // partition hierarchy over the transposed systems
+  DevBuf LA, LC, LD, LX, gslot;
+  DevBuf ckpt, seg, lam0, lam1;                     // grown on demand
+};
+
 }  // namespace burgers
 
 struct burgers_ctx {
@@ -137,6 +169,7 @@ struct burgers_ctx {
   // launch sequences captured as graphs, keyed by (subset, scheme, steps, state buffer)
   std::map<std::tuple<int, int, int64_t, void*>, hipGraphExec_t> graph_cache;
   hipStream_t capture_stream = nullptr;      // private non-blocking stream used only for capture
+  std::unique_ptr<burgers::AdjointPlan> adjoint;
   hipError_t sticky = hipSuccess;
 };
 
@@ -152,11 +185,31 @@ hipError_t launch_copy_tiles(const burgers_ctx* ctx, const Tile* tiles, int64_t 
 int explicit_tile_nodes(burgers_dtype dt);
 int explicit_block_capacity();
 
+// adjoint.hip
+int adjoint_tile_nodes();
+hipError_t launch_adj_explicit(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const double* u,
+                               const double* lamp, double* lam, double* gslot);
+hipError_t launch_adj_btcs_assemble(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles,
+                                    const double* u, const double* lamp, double* LA, double* LC, double* LD);
+hipError_t launch_adj_btcs_finish(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles,
+                                  const double* u, const double* x, const double* X, double* lam,
+                                  double* gslot);
+hipError_t launch_adj_nu(const burgers_ctx* ctx, const int32_t* slot_begin, const double* gslot,
+                         double* grad_nu);
+hipError_t launch_fill(const burgers_ctx* ctx, double* p, int64_t n, double v);
+hipError_t launch_zero_dirichlet_ends(const burgers_ctx* ctx, double* g);
+
 // btcs.hip
 int btcs_wg_capacity();                 // longest system one workgroup solves whole
 int btcs_wg_chunks(int rows);           // chunk count the workgroup solver uses for `rows` rows
 int btcs_reduce_chunk();                // target rows per chunk in the partition levels
 constexpr int kReduceBlock = 256;       // chunks per workgroup in the partition kernels
 hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out);
+hipError_t launch_btcs_resident(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u,
+                                int steps, int threads);
+int btcs_chunks(int rows, int threads);
+hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
+                              double* LD, double* LX);
+constexpr int kResidentThreadsDefault = 512;
 
 }  // namespace burgers

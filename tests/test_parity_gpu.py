@@ -241,3 +241,50 @@ def test_run_mixed_odd_even_steps(nsteps):
     announce(f"mixed run {nsteps} steps")
     got = device_run(batch, nsteps, "f64", how="run")
     check_batch(batch, got, nsteps, "f64")
+
+
+def _btcs_mix_batch(seed):
+    sizes = [3, 4, 5, 33, 64, 255, 511, 1000, 4099, 8190, 8192, 8193, 8194, 20000]
+    problems, states = [], []
+    for k, n in enumerate(sizes):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            b = W.random_batch(seed + 13 * k + bc, 1, n, n, bc=bc, amplitude=3.0)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    return set_cfl_steps(W._pack(problems, states), scheme=W.BTCS)
+
+
+@pytest.mark.parametrize("block", [512, 1024])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_btcs_resident_bitwise_equals_per_step(dtype, block):
+    """The on-chip solver runs the per-step solver's arithmetic without the trips to HBM, rounding a
+    binary32 state once per step as the per-step store does: results agree bitwise."""
+    sizes_fit = [3, 4, 5, 33, 64, 255, 511, 1000, 4099, 8190, 8192]
+    problems, states = [], []
+    for k, n in enumerate(sizes_fit):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            b = W.random_batch(400 + 7 * k + bc, 1, n, n, bc=bc, amplitude=3.0)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    batch = set_cfl_steps(W._pack(problems, states), scheme=W.BTCS)
+    announce(f"btcs resident vs per-step {dtype} block={block} 25 steps")
+    res = device_run(batch, 25, dtype, how="step_btcs", plan=dict(btcs_path=2, btcs_block=block))
+    per = device_run(batch, 25, dtype, how="step_btcs", plan=dict(btcs_path=1, btcs_block=block))
+    assert np.array_equal(res, per)
+    check_batch(batch, res, 25, dtype, scheme=W.BTCS)
+
+
+@pytest.mark.parametrize("path", [1, 2, 3, 0])
+def test_btcs_paths_against_oracle(path):
+    """Per-step whole-system solves, the on-chip solver, partition levels for every system of >= 32 rows,
+    and the automatic mix all match the oracle (the on-chip path rejects systems that do not fit)."""
+    import paper_2601_12204_amd as B
+    batch = _btcs_mix_batch(41)
+    announce(f"btcs path={path} 9 steps")
+    if path == 2:
+        with pytest.raises(B.BurgersError) as err:
+            device_run(batch, 9, "f64", how="step_btcs", plan=dict(btcs_path=2))
+        assert err.value.status == -2
+        return
+    got = device_run(batch, 9, "f64", how="step_btcs", plan=dict(btcs_path=path))
+    check_batch(batch, got, 9, "f64", scheme=W.BTCS)
