@@ -202,6 +202,70 @@ def dominant_roofline(c2):
             "launches": c2["btcs_launches"], "algorithmic_bytes_per_launch": bytes_}
 
 
+def bench_c4(B, torch, dtype, graph, batch, n_exp=1_000, n_btcs=100):
+    """Ragged batch: 10^4 instances, N log-uniform in [64, 65536], half periodic / half Dirichlet, half
+    explicit / half BTCS; explicit instances 10^3 steps at CFL 0.5, BTCS 10^2 steps at 10x, in one call."""
+    import workloads as W
+    count = batch.count
+    for i, p in enumerate(batch.problems):
+        f = 1.0 if p.scheme == W.EXPLICIT else 10.0
+        p.dt = f * B.burgers_cfl_dt(p, float(batch.umax[i]), 0.5)
+    s = B.Solver(batch.problems, dtype=dtype)
+    s.set_plan(use_graph=1 if graph else 0)
+    u0 = s.pack_flat(batch.u0, batch.offsets)
+    u = torch.empty_like(u0)
+    u.copy_(u0)
+    s.run_mixed(u, n_exp, n_btcs)                # warm-up (plans, graph capture)
+    s.sync()
+    timer = PhaseTimer()
+    reps = 2
+    for _ in range(reps):
+        u.copy_(u0)
+        timer.mark("run")
+        s.run_mixed(u, n_exp, n_btcs)
+        timer.mark("copy")
+    spans = timer.spans()
+    s.close()
+    ms = float(np.mean(spans["run"]))
+    upd_exp = sum((p.n if p.bc == W.BC_PERIODIC else p.n - 2) for p in batch.problems if p.scheme == W.EXPLICIT)
+    upd_btcs = sum((p.n if p.bc == W.BC_PERIODIC else p.n - 2) for p in batch.problems if p.scheme == W.BTCS)
+    updates = upd_exp * n_exp + upd_btcs * n_btcs
+    return {"ms": ms, "glups": updates / (ms * 1e-3) / 1e9, "instances": count,
+            "nodes": int(batch.offsets[-1]), "updates": int(updates), "graph": bool(graph)}
+
+
+def bench_c5_adjoint(B, torch, scheme, count=256, n=16384, nsteps=2000, ckpt=100):
+    """Gradient of 1/2 |u_T - target|^2 w.r.t. u0 and nu for 256 periodic instances of N=16384 (FP64),
+    2000 steps, checkpoints every 100 steps: forward, checkpointed recompute and reverse sweep."""
+    import workloads as W
+    first, second = W.adjoint_batch(count, n, scheme=scheme)
+    f = 1.0 if scheme == W.EXPLICIT else 10.0
+    for i, (p, q) in enumerate(zip(first.problems, second.problems)):
+        p.dt = f * B.burgers_cfl_dt(p, float(first.umax[i]), 0.5)
+        q.dt = p.dt
+    s = B.Solver(first.problems, dtype=torch.float64)
+    u0 = s.pack_flat(first.u0, first.offsets)
+    target = s.pack_flat(second.u0, second.offsets)
+    s2 = B.Solver(second.problems, dtype=torch.float64)
+    s2.run(target, nsteps)
+    uT = u0.clone()
+    s.run(uT, nsteps)
+    lam = uT - target
+    g = torch.zeros_like(u0)
+    gn = torch.zeros(count, dtype=torch.float64, device="cuda")
+    B.adjoint_into(s, u0, lam, nsteps, ckpt, g, gn)   # warm-up (buffers)
+    s.sync()
+    timer = PhaseTimer()
+    timer.mark("adjoint")
+    B.adjoint_into(s, u0, lam, nsteps, ckpt, g, gn)
+    timer.mark("end")
+    ms = timer.spans()["adjoint"][0]
+    s.close()
+    s2.close()
+    return {"ms": ms, "point_steps_per_s": count * n * nsteps / (ms * 1e-3),
+            "steps": nsteps, "ckpt_every": ckpt, "instances": count, "n": n}
+
+
 def cpu_baseline(target_s=12.0):
     """The oracle as it stands on the host cores, on a bounded sample of the same workload."""
     import oracle
@@ -273,6 +337,16 @@ def main():
         extra["c1_latency"] = bench_c1_latency(B, torch)
         log("C3")
         extra["c3_f64"] = bench_c3(B, torch)
+        log("C4 ragged")
+        import workloads as W
+        c4 = W.ragged_batch(10_000)
+        extra["c4_f64_graph"] = bench_c4(B, torch, torch.float64, True, c4)
+        extra["c4_f64_eager"] = bench_c4(B, torch, torch.float64, False, c4)
+        extra["c4_f32_graph"] = bench_c4(B, torch, torch.float32, True, c4)
+        log("C5 adjoint")
+        import workloads as W
+        extra["c5_adjoint_explicit"] = bench_c5_adjoint(B, torch, W.EXPLICIT)
+        extra["c5_adjoint_btcs"] = bench_c5_adjoint(B, torch, W.BTCS)
 
     roofline = dominant_roofline(c2)
     cpu = None

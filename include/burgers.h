@@ -148,6 +148,15 @@ burgers_status burgers_step_btcs(burgers_ctx* ctx, void* u, int64_t nsteps);
 burgers_status burgers_run(burgers_ctx* ctx, void* u, int64_t nsteps);
 
 /*
+ * As burgers_run, with separate step counts for the two schemes: instances whose `scheme` is
+ * BURGERS_EXPLICIT advance explicit_steps steps and BTCS instances btcs_steps steps (both >= 0), in one
+ * launch sequence (one graph launch when use_graph is 1).  Ragged batches mixing schemes with
+ * scheme-specific step budgets (explicit steps at the CFL limit, BTCS steps at a multiple of it) run
+ * this way.  Errors as for burgers_step_explicit.
+ */
+burgers_status burgers_run_mixed(burgers_ctx* ctx, void* u, int64_t explicit_steps, int64_t btcs_steps);
+
+/*
  * Discrete adjoint of burgers_run (the paper differentiates its solvers by reverse-mode AD, Sec. 2.7.1
  * and 2.7.3).  Given the initial state u0 and lambda_T = dJ/du(t_T) after nsteps steps of each
  * instance's scheme, write grad_u0 = dJ/du0 (packed layout) and grad_nu[b] = dJ/dnu_b (count values,

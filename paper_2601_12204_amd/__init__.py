@@ -47,7 +47,8 @@ class CPlan(ctypes.Structure):
 
 _lib = None
 EXPORTS = ["burgers_create", "burgers_destroy", "burgers_offsets", "burgers_state_elems",
-           "burgers_step_explicit", "burgers_step_btcs", "burgers_run", "burgers_adjoint", "burgers_sync",
+           "burgers_step_explicit", "burgers_step_btcs", "burgers_run", "burgers_run_mixed",
+           "burgers_adjoint", "burgers_sync",
            "burgers_get_plan", "burgers_set_plan", "burgers_status_string", "burgers_cfl_dt",
            "burgers_ratios", "burgers_abi_version"]
 
@@ -79,6 +80,8 @@ def load() -> ctypes.CDLL:
         f = getattr(lib, name)
         f.argtypes = [vp, vp, i64]
         f.restype = ctypes.c_int
+    lib.burgers_run_mixed.argtypes = [vp, vp, i64, i64]
+    lib.burgers_run_mixed.restype = ctypes.c_int
     lib.burgers_adjoint.argtypes = [vp, vp, vp, i64, i64, vp, vp]
     lib.burgers_adjoint.restype = ctypes.c_int
     lib.burgers_sync.argtypes = [vp]
@@ -179,6 +182,10 @@ def burgers_run(ctx, u, nsteps: int) -> None:
     _check(load().burgers_run(ctx, _ptr(u), int(nsteps)), "burgers_run")
 
 
+def burgers_run_mixed(ctx, u, explicit_steps: int, btcs_steps: int) -> None:
+    _check(load().burgers_run_mixed(ctx, _ptr(u), int(explicit_steps), int(btcs_steps)), "burgers_run_mixed")
+
+
 def burgers_adjoint(ctx, u0, lambda_T, nsteps: int, ckpt_every: int, grad_u0, grad_nu) -> None:
     _check(load().burgers_adjoint(ctx, _ptr(u0), _ptr(lambda_T), int(nsteps), int(ckpt_every),
                                   _ptr(grad_u0), _ptr(grad_nu)), "burgers_adjoint")
@@ -275,6 +282,10 @@ class Solver:
     def run(self, u, nsteps: int) -> None:
         self._check_state(u)
         burgers_run(self.ctx, u, nsteps)
+
+    def run_mixed(self, u, explicit_steps: int, btcs_steps: int) -> None:
+        self._check_state(u)
+        burgers_run_mixed(self.ctx, u, explicit_steps, btcs_steps)
 
     def sync(self) -> None:
         burgers_sync(self.ctx)

@@ -330,12 +330,15 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
   return e;
 }
 
-hipError_t enqueue_all(burgers_ctx* ctx, int set, int scheme, void* u, int64_t nsteps) {
+// scheme -1: each instance's own scheme, explicit instances nsteps steps and BTCS ones nsteps_btcs.
+hipError_t enqueue_all(burgers_ctx* ctx, int set, int scheme, void* u, int64_t nsteps, int64_t nsteps_btcs = -1) {
   hipError_t e = hipSuccess;
   if (scheme == BURGERS_EXPLICIT) return enqueue_explicit(ctx, set, u, nsteps);
   if (scheme == BURGERS_BTCS) return enqueue_btcs(ctx, set, u, nsteps);
-  if (!ctx->set_explicit.empty() && (e = enqueue_explicit(ctx, kSetExplicit, u, nsteps)) != hipSuccess) return e;
-  if (!ctx->set_btcs.empty()) e = enqueue_btcs(ctx, kSetBtcs, u, nsteps);
+  if (nsteps_btcs < 0) nsteps_btcs = nsteps;
+  if (!ctx->set_explicit.empty() && nsteps > 0 && (e = enqueue_explicit(ctx, kSetExplicit, u, nsteps)) != hipSuccess)
+    return e;
+  if (!ctx->set_btcs.empty() && nsteps_btcs > 0) e = enqueue_btcs(ctx, kSetBtcs, u, nsteps_btcs);
   return e;
 }
 
@@ -352,9 +355,9 @@ burgers_status prepare(burgers_ctx* ctx, int set, int scheme) {
   return BURGERS_OK;
 }
 
-// Replay the launch sequence of (set, scheme, nsteps, u) from a captured graph, capturing it on first use.
-hipError_t enqueue_graph(burgers_ctx* ctx, int set, int scheme, void* u, int64_t nsteps) {
-  const auto key = std::make_tuple(set, scheme, nsteps, u);
+// Replay the launch sequence of (set, scheme, steps, u) from a captured graph, capturing it on first use.
+hipError_t enqueue_graph(burgers_ctx* ctx, int set, int scheme, void* u, int64_t nsteps, int64_t nsteps_btcs) {
+  const auto key = std::make_tuple(set, scheme, nsteps, nsteps_btcs, u);
   auto it = ctx->graph_cache.find(key);
   if (it == ctx->graph_cache.end()) {
     hipError_t e;
@@ -367,7 +370,7 @@ hipError_t enqueue_graph(burgers_ctx* ctx, int set, int scheme, void* u, int64_t
       ctx->stream = user;
       return e;
     }
-    hipError_t le = enqueue_all(ctx, set, scheme, u, nsteps);
+    hipError_t le = enqueue_all(ctx, set, scheme, u, nsteps, nsteps_btcs);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(ctx->capture_stream, &graph);
     ctx->stream = user;
@@ -382,17 +385,19 @@ hipError_t enqueue_graph(burgers_ctx* ctx, int set, int scheme, void* u, int64_t
   return hipGraphLaunch(it->second, ctx->stream);
 }
 
-// nsteps steps of `set` with `scheme` (-1: each instance's own); the final state lands in u.
-burgers_status advance(burgers_ctx* ctx, void* u, int64_t nsteps, int set, int scheme) {
+// nsteps steps of `set` with `scheme` (-1: each instance's own; BTCS instances then take nsteps_btcs
+// steps); the final state lands in u.
+burgers_status advance(burgers_ctx* ctx, void* u, int64_t nsteps, int set, int scheme, int64_t nsteps_btcs = -1) {
+  if (nsteps_btcs < 0) nsteps_btcs = nsteps;
   if (!ctx || !u || nsteps < 0) return BURGERS_E_INVALID;
   if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
-  if (nsteps == 0) return BURGERS_OK;
+  if (nsteps == 0 && (scheme >= 0 || nsteps_btcs == 0)) return BURGERS_OK;
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return note(ctx, e);
   burgers_status st = prepare(ctx, set, scheme);
   if (st != BURGERS_OK) return st == BURGERS_E_UNSUPPORTED || st == BURGERS_E_INVALID ? st : note(ctx, hipErrorOutOfMemory);
-  if (ctx->plan.use_graph == 1) e = enqueue_graph(ctx, set, scheme, u, nsteps);
-  else e = enqueue_all(ctx, set, scheme, u, nsteps);
+  if (ctx->plan.use_graph == 1) e = enqueue_graph(ctx, set, scheme, u, nsteps, nsteps_btcs);
+  else e = enqueue_all(ctx, set, scheme, u, nsteps, nsteps_btcs);
   if (e != hipSuccess) return note(ctx, e);
   return BURGERS_OK;
 }
@@ -638,6 +643,11 @@ burgers_status burgers_step_btcs(burgers_ctx* ctx, void* u, int64_t nsteps) {
 
 burgers_status burgers_run(burgers_ctx* ctx, void* u, int64_t nsteps) {
   return advance(ctx, u, nsteps, kSetAll, -1);
+}
+
+burgers_status burgers_run_mixed(burgers_ctx* ctx, void* u, int64_t explicit_steps, int64_t btcs_steps) {
+  if (btcs_steps < 0) return BURGERS_E_INVALID;
+  return advance(ctx, u, explicit_steps, kSetAll, -1, btcs_steps);
 }
 
 burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lambda_T, int64_t nsteps,

@@ -166,8 +166,8 @@ struct burgers_ctx {
   std::map<int, std::unique_ptr<burgers::ExplicitPlan>> explicit_plans;
   std::map<int, std::unique_ptr<burgers::BtcsPlan>> btcs;
   std::map<int, std::pair<std::unique_ptr<burgers::DevBuf>, int64_t>> copy_tiles;   // per subset
-  // launch sequences captured as graphs, keyed by (subset, scheme, steps, state buffer)
-  std::map<std::tuple<int, int, int64_t, void*>, hipGraphExec_t> graph_cache;
+  // launch sequences captured as graphs, keyed by (subset, scheme, steps, BTCS steps, state buffer)
+  std::map<std::tuple<int, int, int64_t, int64_t, void*>, hipGraphExec_t> graph_cache;
   hipStream_t capture_stream = nullptr;      // private non-blocking stream used only for capture
   std::unique_ptr<burgers::AdjointPlan> adjoint;
   hipError_t sticky = hipSuccess;

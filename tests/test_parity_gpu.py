@@ -288,3 +288,27 @@ def test_btcs_paths_against_oracle(path):
         return
     got = device_run(batch, 9, "f64", how="step_btcs", plan=dict(btcs_path=path))
     check_batch(batch, got, 9, "f64", scheme=W.BTCS)
+
+
+@pytest.mark.parametrize("graph", [0, 1])
+def test_run_mixed_step_counts(graph):
+    """Explicit instances take 13 steps and BTCS instances 5 in one call (and one graph)."""
+    batch = set_cfl_steps(W.random_batch(35, 30, 3, 20000, amplitude=2.0))
+    announce(f"run_mixed 13/5 graph={graph}")
+    import torch
+    import paper_2601_12204_amd as B
+    s = B.Solver(batch.problems, dtype=torch.float64)
+    s.set_plan(use_graph=graph)
+    u = s.pack_flat(batch.u0, batch.offsets)
+    s.run_mixed(u, 13, 5)
+    s.sync()
+    got = s.unpack_flat(u)
+    s.close()
+    exp = oracle_run(batch, 13, "f64", scheme=W.EXPLICIT)
+    imp = oracle_run(batch, 5, "f64", scheme=W.BTCS)
+    for b, p in enumerate(batch.problems):
+        lo, hi = batch.offsets[b], batch.offsets[b + 1]
+        if p.scheme == W.EXPLICIT:
+            assert np.array_equal(got[lo:hi], exp[lo:hi]), b
+        else:
+            assert rel_err(got[lo:hi], imp[lo:hi]) <= TOL_F64, b
