@@ -176,6 +176,20 @@ burgers_status burgers_sync(burgers_ctx* ctx);
 burgers_status burgers_get_plan(const burgers_ctx* ctx, burgers_plan* out);
 burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan);
 
+/*
+ * Autotuner.  Times candidate plans on a scratch copy of the device state u (u itself is not modified)
+ * for explicit_steps / btcs_steps steps (as burgers_run_mixed), with HIP events on the context's
+ * stream, and keeps the fastest plan in the context.  Only the knobs that matter for the context's
+ * instances are searched: the explicit path and temporal-blocking depth (4, 8, 16, 32) when explicit
+ * instances exist (the depth only when some exceed the on-chip limit), lanes per BTCS system (512,
+ * 1024) when BTCS instances exist, and graph replay on or off.  *best (optional) receives the chosen
+ * plan and *best_ms (optional) its time.  The call synchronises the stream and allocates one scratch
+ * state, released before it returns.
+ * Errors: BURGERS_E_INVALID, BURGERS_E_NOMEM, BURGERS_E_DEVICE.
+ */
+burgers_status burgers_autotune(burgers_ctx* ctx, const void* u, int64_t explicit_steps, int64_t btcs_steps,
+                                burgers_plan* best, double* best_ms);
+
 /* Static text for a status code. */
 const char* burgers_status_string(burgers_status status);
 

@@ -50,7 +50,7 @@ EXPORTS = ["burgers_create", "burgers_destroy", "burgers_offsets", "burgers_stat
            "burgers_step_explicit", "burgers_step_btcs", "burgers_run", "burgers_run_mixed",
            "burgers_adjoint", "burgers_sync",
            "burgers_get_plan", "burgers_set_plan", "burgers_status_string", "burgers_cfl_dt",
-           "burgers_ratios", "burgers_abi_version"]
+           "burgers_ratios", "burgers_abi_version", "burgers_autotune"]
 
 
 def load() -> ctypes.CDLL:
@@ -96,6 +96,8 @@ def load() -> ctypes.CDLL:
     lib.burgers_cfl_dt.restype = dbl
     lib.burgers_ratios.argtypes = [P(CProblem), P(dbl), P(dbl)]
     lib.burgers_ratios.restype = ctypes.c_int
+    lib.burgers_autotune.argtypes = [vp, vp, i64, i64, P(CPlan), P(dbl)]
+    lib.burgers_autotune.restype = ctypes.c_int
     lib.burgers_abi_version.argtypes = []
     lib.burgers_abi_version.restype = i32
     _lib = lib
@@ -122,6 +124,16 @@ def burgers_ratios(p):
     _check(load().burgers_ratios(ctypes.byref(to_cproblem(p)), ctypes.byref(r), ctypes.byref(D)),
            "burgers_ratios")
     return r.value, D.value
+
+
+def burgers_autotune(ctx, u, explicit_steps: int, btcs_steps: int):
+    """Time candidate plans on a scratch copy of u; the context keeps the fastest. Returns (plan, ms)."""
+    plan = CPlan()
+    ms = ctypes.c_double()
+    _check(load().burgers_autotune(ctx, _ptr(u), int(explicit_steps), int(btcs_steps), ctypes.byref(plan),
+                                   ctypes.byref(ms)), "burgers_autotune")
+    return ({"explicit_path": plan.explicit_path, "tblock_depth": plan.tblock_depth, "btcs_path": plan.btcs_path,
+             "use_graph": plan.use_graph, "btcs_block": plan.btcs_block}, ms.value)
 
 
 def burgers_status_string(status: int) -> str:
@@ -289,6 +301,28 @@ class Solver:
 
     def sync(self) -> None:
         burgers_sync(self.ctx)
+
+    def autotune(self, u, explicit_steps: int, btcs_steps: int, cache: Optional[str] = None):
+        """Pick the fastest plan for this workload (burgers_autotune); with `cache`, a JSON file keyed by a
+        signature of the batch (sizes, boundary types, schemes, dtype) stores and reuses the choice."""
+        import hashlib
+        import json
+        key = hashlib.sha1(json.dumps([self.torch_dtype == __import__("torch").float64, explicit_steps, btcs_steps,
+                                       sorted((int(p.n), int(p.bc), int(p.scheme)) for p in self.problems)]
+                                      ).encode()).hexdigest()
+        store = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                store = json.load(f)
+            if key in store:
+                self.set_plan(**store[key]["plan"])
+                return store[key]["plan"], store[key]["ms"], True
+        plan, ms = burgers_autotune(self.ctx, u, explicit_steps, btcs_steps)
+        if cache:
+            store[key] = {"plan": plan, "ms": ms}
+            with open(cache, "w") as f:
+                json.dump(store, f, indent=1)
+        return plan, ms, False
 
     def set_plan(self, **kw) -> None:
         burgers_set_plan(self.ctx, **kw)

@@ -209,18 +209,18 @@ __device__ __forceinline__ void chunk_span(int k, int R, int P, int& s, int& m) 
   m = q + (k < rho ? 1 : 0);
 }
 
-// Cyclic PCR on R2 (a power of two, <= 2 NT) rows with coefficients in LDS; sI holds 1/B.  Indices
-// wrap modulo R2; a non-cyclic system simply carries zero corner couplings.  After log2(R2) steps every
-// row couples only to itself and the solution is D / (A + B + C).  The reduction stops earlier once
-// every remaining coupling is negligible against its diagonal; the solution is then D / B.  The result
-// is left in sD.
+// Cyclic PCR on R2 (a power of two, <= 2 NT) rows with coefficients in LDS, every row kept normalised
+// to a unit diagonal:  A_i x_{i-s} + x_i + C_i x_{i+s} = D_i.  One step combines row i with rows i-s and
+// i+s and renormalises.  Indices wrap modulo R2; a non-cyclic system simply carries zero corner
+// couplings.  After log2(R2) steps every row couples only to itself and the solution is D / (1 + A + C).
+// The reduction stops earlier once every remaining coupling is negligible; the solution is then D.  The
+// result is left in sD.
 template <typename T, int NT>
-__device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, T* sI, int R2) {
+__device__ __forceinline__ void pcr_cyclic(T* sA, T* sC, T* sD, int R2) {
   const int tid = threadIdx.x;
   bool done = false;
-  int s = 1;
-  for (; s < R2 && !done; s <<= 1) {
-    T nA[2], nB[2], nC[2], nD[2];
+  for (int s = 1; s < R2 && !done; s <<= 1) {
+    T nA[2], nC[2], nD[2];
     int live = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -228,13 +228,12 @@ __device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, T* sI, in
       if (i < R2) {
         const int im = (i - s) & (R2 - 1);
         const int ip = (i + s) & (R2 - 1);
-        const T k1 = sA[i] * sI[im];
-        const T k2 = sC[i] * sI[ip];
-        nB[h] = (sB[i] - k1 * sC[im]) - k2 * sA[ip];
-        nD[h] = (sD[i] - k1 * sD[im]) - k2 * sD[ip];
-        nA[h] = -(k1 * sA[im]);
-        nC[h] = -(k2 * sC[ip]);
-        live |= (__builtin_fabs(nA[h]) + __builtin_fabs(nC[h])) > kNegligible * __builtin_fabs(nB[h]);
+        const T a = sA[i], c = sC[i];
+        const T inv = recip((T(1) - a * sC[im]) - c * sA[ip]);
+        nA[h] = -(a * sA[im]) * inv;
+        nC[h] = -(c * sC[ip]) * inv;
+        nD[h] = ((sD[i] - a * sD[im]) - c * sD[ip]) * inv;
+        live |= (__builtin_fabs(nA[h]) + __builtin_fabs(nC[h])) > kNegligible;
       }
     }
     __syncthreads();
@@ -243,19 +242,18 @@ __device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, T* sI, in
       const int i = tid + h * NT;
       if (i < R2) {
         sA[i] = nA[h];
-        sB[i] = nB[h];
         sC[i] = nC[h];
         sD[i] = nD[h];
-        sI[i] = recip(nB[h]);
       }
     }
     done = !__syncthreads_or(live);
   }
-  const bool folded = !done;   // ran all log2(R2) steps: the remaining couplings point at the row itself
+  if (!done) {   // ran all log2(R2) steps: the remaining couplings point at the row itself
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int i = tid + h * NT;
-    if (i < R2) sD[i] = folded ? sD[i] / ((sB[i] + sA[i]) + sC[i]) : sD[i] * sI[i];
+    for (int h = 0; h < 2; ++h) {
+      const int i = tid + h * NT;
+      if (i < R2) sD[i] = sD[i] / ((T(1) + sA[i]) + sC[i]);
+    }
   }
   __syncthreads();
 }
@@ -264,22 +262,20 @@ __device__ __forceinline__ void pcr_cyclic(T* sA, T* sB, T* sC, T* sD, T* sI, in
 // (coalesced loads), eliminate chunks from LDS, solve the reduced system by PCR in the same LDS, write
 // the new values back into the staging buffer and store them coalesced, with the Dirichlet boundary
 // nodes.  Reduced systems of the partition levels read (A, C, D) and write X in HBM directly.
-template <typename S, bool FromState, int NT>
+template <typename S, bool FromState, int NT, bool EXACT = false>
 __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, const S* __restrict__ u,
     S* __restrict__ out, const double* __restrict__ LA, const double* __restrict__ LC,
     const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
   constexpr int MC = kWgRows / NT;
-  constexpr int kPcrBytes = 5 * 2 * NT * static_cast<int>(sizeof(T));
+  constexpr int kPcrBytes = 3 * 2 * NT * static_cast<int>(sizeof(T));
   constexpr int kStageBytes = FromState ? padded_size(kWgRows) * static_cast<int>(sizeof(S)) : 0;
   constexpr int kBytes = kStageBytes > kPcrBytes ? kStageBytes : kPcrBytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
   T* sA = reinterpret_cast<T*>(smem);
-  T* sB = sA + 2 * NT;
-  T* sC = sB + 2 * NT;
+  T* sC = sA + 2 * NT;
   T* sD = sC + 2 * NT;
-  T* sI = sD + 2 * NT;
   S* stage = reinterpret_cast<S*>(smem);
 
   const SysDesc sys = systems[blockIdx.x];
@@ -327,6 +323,10 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
   int s = 0, m = 0;
   if (tid < P) {
     chunk_span(tid, R, P, s, m);
+    if constexpr (EXACT) {
+      s = tid * MC;
+      m = MC;
+    }
     if constexpr (FromState) {
       chunk_eliminate<T, MC>(ssrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
     } else {
@@ -335,12 +335,11 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
   }
   if constexpr (FromState) __syncthreads();   // the PCR arrays overlay the staged rows
   if (tid < P) {
-    sA[2 * tid] = AF; sB[2 * tid] = T(1); sC[2 * tid] = CF; sD[2 * tid] = DF; sI[2 * tid] = T(1);
-    sA[2 * tid + 1] = AE; sB[2 * tid + 1] = T(1); sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
-    sI[2 * tid + 1] = T(1);
+    sA[2 * tid] = AF; sC[2 * tid] = CF; sD[2 * tid] = DF;
+    sA[2 * tid + 1] = AE; sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
   }
   __syncthreads();
-  pcr_cyclic<T, NT>(sA, sB, sC, sD, sI, 2 * P);
+  pcr_cyclic<T, NT>(sA, sC, sD, 2 * P);
   T F = T(0), E = T(0);
   if (tid < P) {
     F = sD[2 * tid];
@@ -361,17 +360,15 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
 // lanes x MC = 8192), for all steps of a launch.  Each step is the whole-system solver's step without the trips to HBM; the
 // state is rounded through S once per step as the per-step kernel's store would, so both solvers agree
 // bitwise.  The state buffer is read once and written once per launch (in place).
-template <typename S, int NT, int MC>
+template <typename S, int NT, int MC, bool EXACT = false>
 __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_resident_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, S* __restrict__ u,
     int steps) {
   using T = double;
-  __shared__ T pcr[5 * 2 * NT];
+  __shared__ T pcr[3 * 2 * NT];
   T* sA = pcr;
-  T* sB = sA + 2 * NT;
-  T* sC = sB + 2 * NT;
+  T* sC = sA + 2 * NT;
   T* sD = sC + 2 * NT;
-  T* sI = sD + 2 * NT;
   const SysDesc sys = systems[blockIdx.x];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
@@ -399,6 +396,10 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_resident_kernel(
   T al[MC], ga[MC], de[MC];   // de carries the state between steps
   if (tid < P) {
     chunk_span(tid, R, P, s, m);
+    if constexpr (EXACT) {
+      s = tid * MC;
+      m = MC;
+    }
 #pragma unroll
     for (int j = 0; j < MC; ++j)
       if (j < m) de[j] = static_cast<T>(x[s + j]);
@@ -407,20 +408,19 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_resident_kernel(
   for (int step = 0; step < steps; ++step) {
     T AF, CF, DF, AE, CE, DE;
     if (tid < P) {
-      chunk_eliminate<T, MC, true>(src, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
-      sA[2 * tid] = AF; sB[2 * tid] = T(1); sC[2 * tid] = CF; sD[2 * tid] = DF; sI[2 * tid] = T(1);
-      sA[2 * tid + 1] = AE; sB[2 * tid + 1] = T(1); sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
-      sI[2 * tid + 1] = T(1);
+      chunk_eliminate<T, MC, true>(src, s, EXACT ? MC : m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+      sA[2 * tid] = AF; sC[2 * tid] = CF; sD[2 * tid] = DF;
+      sA[2 * tid + 1] = AE; sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
     }
     __syncthreads();
-    pcr_cyclic<T, NT>(sA, sB, sC, sD, sI, 2 * P);
+    pcr_cyclic<T, NT>(sA, sC, sD, 2 * P);
     T F = T(0), E = T(0);
     if (tid < P) {
       F = sD[2 * tid];
       E = sD[2 * tid + 1];
     }
     __syncthreads();                           // ends read before the next step rewrites the arrays
-    if (tid < P) chunk_recover_in_place<S>(m, al, ga, de, F, E);
+    if (tid < P) chunk_recover_in_place<S>(EXACT ? MC : m, al, ga, de, F, E);
   }
   if (tid < P) {
 #pragma unroll
@@ -587,21 +587,27 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
 }  // namespace
 
 template <typename S, int NT>
-void resident_launch(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u, int steps) {
-  btcs_resident_kernel<S, NT, kWgRows / NT><<<static_cast<unsigned>(n_sys), NT, 0, ctx->stream>>>(
-      ctx->inst.as<InstDesc>(), systems, static_cast<S*>(u), steps);
+void resident_launch(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u, int steps,
+                     bool exact) {
+  if (exact) {
+    btcs_resident_kernel<S, NT, kWgRows / NT, true><<<static_cast<unsigned>(n_sys), NT, 0, ctx->stream>>>(
+        ctx->inst.as<InstDesc>(), systems, static_cast<S*>(u), steps);
+  } else {
+    btcs_resident_kernel<S, NT, kWgRows / NT><<<static_cast<unsigned>(n_sys), NT, 0, ctx->stream>>>(
+        ctx->inst.as<InstDesc>(), systems, static_cast<S*>(u), steps);
+  }
 }
 
 hipError_t launch_btcs_resident(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u,
-                                int steps, int threads) {
+                                int steps, int threads, bool exact) {
   if (n_sys <= 0 || steps <= 0) return hipSuccess;
   const bool f64 = ctx->dtype == BURGERS_F64;
   if (threads == 512) {
-    if (f64) resident_launch<double, 512>(ctx, systems, n_sys, u, steps);
-    else resident_launch<float, 512>(ctx, systems, n_sys, u, steps);
+    if (f64) resident_launch<double, 512>(ctx, systems, n_sys, u, steps, exact);
+    else resident_launch<float, 512>(ctx, systems, n_sys, u, steps, exact);
   } else {
-    if (f64) resident_launch<double, 1024>(ctx, systems, n_sys, u, steps);
-    else resident_launch<float, 1024>(ctx, systems, n_sys, u, steps);
+    if (f64) resident_launch<double, 1024>(ctx, systems, n_sys, u, steps, exact);
+    else resident_launch<float, 1024>(ctx, systems, n_sys, u, steps, exact);
   }
   return hipGetLastError();
 }

@@ -53,12 +53,14 @@ const std::vector<int32_t>& set_members(const burgers_ctx* ctx, int set) {
   return set == kSetAll ? ctx->set_all : (set == kSetExplicit ? ctx->set_explicit : ctx->set_btcs);
 }
 
+// Copy a host table to a new device buffer, in stream order (a pageable source may be released as soon
+// as the call returns).
 template <typename T>
-hipError_t upload(DevBuf& buf, const std::vector<T>& v) {
-  hipError_t e = buf.alloc(v.size() * sizeof(T));
+hipError_t upload_on(hipStream_t stream, DevBuf& buf, const std::vector<T>& v) {
+  hipError_t e = buf.alloc(v.size() * sizeof(T), stream);
   if (e != hipSuccess) return e;
   if (v.empty()) return hipSuccess;
-  return hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return hipMemcpyAsync(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, stream);
 }
 
 // Streaming tiles covering every node of the members of one subset.
@@ -78,7 +80,7 @@ hipError_t ensure_copy(burgers_ctx* ctx, int set) {
   if (ctx->copy_tiles.count(set)) return hipSuccess;
   auto tiles = stream_tiles(ctx, set_members(ctx, set));
   auto buf = std::make_unique<DevBuf>();
-  hipError_t e = upload(*buf, tiles);
+  hipError_t e = upload_on(ctx->stream, *buf, tiles);
   if (e != hipSuccess) return e;
   ctx->copy_tiles[set] = {std::move(buf), static_cast<int64_t>(tiles.size())};
   return hipSuccess;
@@ -105,19 +107,19 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
   hipError_t e;
   auto st = stream_tiles(ctx, members);
   plan->stream = std::make_unique<DevBuf>();
-  if ((e = upload(*plan->stream, st)) != hipSuccess) return from_hip(e);
+  if ((e = upload_on(ctx->stream, *plan->stream, st)) != hipSuccess) return from_hip(e);
   plan->n_stream = static_cast<int64_t>(st.size());
   if (plan->path != 1) {
     const int cap = burgers::explicit_block_capacity();
     const int T = plan->depth;
-    std::vector<BlockTile> we, wg, ne, ng;
+    std::vector<BlockTile> whole, win;
     std::vector<int32_t> windowed;
     for (int32_t i : members) {
       const burgers_problem& p = ctx->probs[i];
       const int32_t n = static_cast<int32_t>(p.n);
       const bool periodic = p.bc == BURGERS_BC_PERIODIC;
       if (n <= cap) {
-        (n == cap ? we : wg).push_back(BlockTile{i, 0, n, 0, n, periodic ? 1 : 0});
+        whole.push_back(BlockTile{i, 0, n, 0, n, periodic ? 1 : 0});
         continue;
       }
       if (plan->path == 2) return BURGERS_E_UNSUPPORTED;
@@ -135,23 +137,18 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
           bt.width = std::min(n, hi + T) - bt.first;
           bt.lo = lo - bt.first;
         }
-        (bt.width == cap ? ne : ng).push_back(bt);
+        win.push_back(bt);
       }
     }
-    plan->whole_exact = std::make_unique<DevBuf>();
-    plan->whole_generic = std::make_unique<DevBuf>();
-    plan->win_exact = std::make_unique<DevBuf>();
-    plan->win_generic = std::make_unique<DevBuf>();
+    plan->whole = std::make_unique<DevBuf>();
+    plan->win = std::make_unique<DevBuf>();
     plan->win_copy = std::make_unique<DevBuf>();
     auto wc = stream_tiles(ctx, windowed);
-    if ((e = upload(*plan->whole_exact, we)) != hipSuccess || (e = upload(*plan->whole_generic, wg)) != hipSuccess ||
-        (e = upload(*plan->win_exact, ne)) != hipSuccess || (e = upload(*plan->win_generic, ng)) != hipSuccess ||
-        (e = upload(*plan->win_copy, wc)) != hipSuccess)
+    if ((e = upload_on(ctx->stream, *plan->whole, whole)) != hipSuccess || (e = upload_on(ctx->stream, *plan->win, win)) != hipSuccess ||
+        (e = upload_on(ctx->stream, *plan->win_copy, wc)) != hipSuccess)
       return from_hip(e);
-    plan->n_whole_exact = static_cast<int64_t>(we.size());
-    plan->n_whole_generic = static_cast<int64_t>(wg.size());
-    plan->n_win_exact = static_cast<int64_t>(ne.size());
-    plan->n_win_generic = static_cast<int64_t>(ng.size());
+    plan->n_whole = static_cast<int64_t>(whole.size());
+    plan->n_win = static_cast<int64_t>(win.size());
     plan->n_win_copy = static_cast<int64_t>(wc.size());
   }
   ctx->explicit_plans[set] = std::move(plan);
@@ -176,7 +173,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   plan->threads = threads;
   const int cap = burgers::btcs_wg_capacity();
   const int chunk = burgers::btcs_reduce_chunk();
-  std::vector<SysDesc> wg_state, resident;
+  std::vector<SysDesc> wg_state, resident, resident_exact;
   std::vector<int32_t> stepped;
   std::vector<std::vector<SysDesc>> red_sys, wg_sys;
   int64_t rows_used = 0;
@@ -186,7 +183,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     const bool fits = R0 <= cap;
     if (want == 2 && !fits) return BURGERS_E_UNSUPPORTED;
     if ((want == 0 || want == 2) && fits) {
-      resident.push_back(SysDesc{0, -1, R0, burgers::btcs_chunks(R0, threads), i, 0});
+      (R0 == cap ? resident_exact : resident).push_back(SysDesc{0, -1, R0, burgers::btcs_chunks(R0, threads), i, 0});
       continue;
     }
     stepped.push_back(i);
@@ -219,13 +216,16 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   hipError_t e;
   plan->n_wg_state = static_cast<int32_t>(wg_state.size());
   plan->n_resident = static_cast<int32_t>(resident.size());
+  plan->n_resident_exact = static_cast<int32_t>(resident_exact.size());
   plan->wg_state = std::make_unique<DevBuf>();
   plan->resident = std::make_unique<DevBuf>();
+  plan->resident_exact = std::make_unique<DevBuf>();
   plan->copy = std::make_unique<DevBuf>();
   auto ct = stream_tiles(ctx, stepped);
   plan->n_copy = static_cast<int64_t>(ct.size());
-  if ((e = upload(*plan->wg_state, wg_state)) != hipSuccess || (e = upload(*plan->resident, resident)) != hipSuccess ||
-      (e = upload(*plan->copy, ct)) != hipSuccess)
+  if ((e = upload_on(ctx->stream, *plan->wg_state, wg_state)) != hipSuccess || (e = upload_on(ctx->stream, *plan->resident, resident)) != hipSuccess ||
+      (e = upload_on(ctx->stream, *plan->resident_exact, resident_exact)) != hipSuccess ||
+      (e = upload_on(ctx->stream, *plan->copy, ct)) != hipSuccess)
     return from_hip(e);
   plan->levels.resize(red_sys.size());
   for (size_t l = 0; l < red_sys.size(); ++l) {
@@ -237,8 +237,8 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     lv.sys = std::make_unique<DevBuf>();
     lv.blocks = std::make_unique<DevBuf>();
     lv.wg = std::make_unique<DevBuf>();
-    if ((e = upload(*lv.sys, red_sys[l])) != hipSuccess || (e = upload(*lv.blocks, blocks)) != hipSuccess ||
-        (e = upload(*lv.wg, wg_sys[l])) != hipSuccess)
+    if ((e = upload_on(ctx->stream, *lv.sys, red_sys[l])) != hipSuccess || (e = upload_on(ctx->stream, *lv.blocks, blocks)) != hipSuccess ||
+        (e = upload_on(ctx->stream, *lv.wg, wg_sys[l])) != hipSuccess)
       return from_hip(e);
     lv.n_blocks = static_cast<int32_t>(blocks.size());
     lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
@@ -285,21 +285,17 @@ hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) 
   const int64_t whole_chunk = pl.path == 3 ? pl.depth : (int64_t{1} << 30);
   for (int64_t done = 0; done < nsteps;) {
     const int k = static_cast<int>(std::min(whole_chunk, nsteps - done));
-    if ((e = burgers::launch_explicit_block(ctx, pl.whole_exact->as<BlockTile>(), pl.n_whole_exact, true, u, u, k)) != hipSuccess)
-      return e;
-    if ((e = burgers::launch_explicit_block(ctx, pl.whole_generic->as<BlockTile>(), pl.n_whole_generic, false, u, u, k)) != hipSuccess)
+    if ((e = burgers::launch_explicit_block(ctx, pl.whole->as<BlockTile>(), pl.n_whole, u, u, k)) != hipSuccess)
       return e;
     done += k;
   }
   // windows of long instances: `depth` steps per launch, ping-pong
-  if (pl.n_win_exact + pl.n_win_generic > 0) {
+  if (pl.n_win > 0) {
     void* bufs[2] = {u, work};
     int cur = 0;
     for (int64_t done = 0; done < nsteps;) {
       const int k = static_cast<int>(std::min<int64_t>(pl.depth, nsteps - done));
-      if ((e = burgers::launch_explicit_block(ctx, pl.win_exact->as<BlockTile>(), pl.n_win_exact, true, bufs[cur], bufs[cur ^ 1], k)) != hipSuccess)
-        return e;
-      if ((e = burgers::launch_explicit_block(ctx, pl.win_generic->as<BlockTile>(), pl.n_win_generic, false, bufs[cur], bufs[cur ^ 1], k)) != hipSuccess)
+      if ((e = burgers::launch_explicit_block(ctx, pl.win->as<BlockTile>(), pl.n_win, bufs[cur], bufs[cur ^ 1], k)) != hipSuccess)
         return e;
       cur ^= 1;
       done += k;
@@ -315,7 +311,10 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
   hipError_t e = hipSuccess;
   for (int64_t done = 0; done < nsteps;) {   // on-chip systems, in place
     const int k = static_cast<int>(std::min<int64_t>(nsteps - done, int64_t{1} << 30));
-    if ((e = burgers::launch_btcs_resident(ctx, pl.resident->as<SysDesc>(), pl.n_resident, u, k, pl.threads)) != hipSuccess)
+    if ((e = burgers::launch_btcs_resident(ctx, pl.resident_exact->as<SysDesc>(), pl.n_resident_exact, u, k,
+                                           pl.threads, true)) != hipSuccess ||
+        (e = burgers::launch_btcs_resident(ctx, pl.resident->as<SysDesc>(), pl.n_resident, u, k, pl.threads,
+                                           false)) != hipSuccess)
       return e;
     done += k;
   }
@@ -457,8 +456,8 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   ap->exp_tiles = std::make_unique<DevBuf>();
   ap->btcs_tiles = std::make_unique<DevBuf>();
   ap->slot_begin = std::make_unique<DevBuf>();
-  if ((e = upload(*ap->exp_tiles, et)) != hipSuccess || (e = upload(*ap->btcs_tiles, bt)) != hipSuccess ||
-      (e = upload(*ap->slot_begin, slot_begin)) != hipSuccess)
+  if ((e = upload_on(ctx->stream, *ap->exp_tiles, et)) != hipSuccess || (e = upload_on(ctx->stream, *ap->btcs_tiles, bt)) != hipSuccess ||
+      (e = upload_on(ctx->stream, *ap->slot_begin, slot_begin)) != hipSuccess)
     return from_hip(e);
   ap->n_exp_tiles = static_cast<int64_t>(et.size());
   ap->n_btcs_tiles = static_cast<int64_t>(bt.size());
@@ -473,29 +472,24 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
     lv.sys = std::make_unique<DevBuf>();
     lv.blocks = std::make_unique<DevBuf>();
     lv.wg = std::make_unique<DevBuf>();
-    if ((e = upload(*lv.sys, red_sys[l])) != hipSuccess || (e = upload(*lv.blocks, blocks)) != hipSuccess ||
-        (e = upload(*lv.wg, wg_sys[l])) != hipSuccess)
+    if ((e = upload_on(ctx->stream, *lv.sys, red_sys[l])) != hipSuccess || (e = upload_on(ctx->stream, *lv.blocks, blocks)) != hipSuccess ||
+        (e = upload_on(ctx->stream, *lv.wg, wg_sys[l])) != hipSuccess)
       return from_hip(e);
     lv.n_blocks = static_cast<int32_t>(blocks.size());
     lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
   }
   const size_t lb = static_cast<size_t>(rows_used) * sizeof(double);
-  if ((e = ap->LA.alloc(lb)) != hipSuccess || (e = ap->LC.alloc(lb)) != hipSuccess ||
-      (e = ap->LD.alloc(lb)) != hipSuccess || (e = ap->LX.alloc(lb)) != hipSuccess ||
-      (e = ap->gslot.alloc(static_cast<size_t>(std::max<int64_t>(slot, 1)) * sizeof(double))) != hipSuccess)
+  if ((e = ap->LA.alloc(lb, ctx->stream)) != hipSuccess || (e = ap->LC.alloc(lb, ctx->stream)) != hipSuccess ||
+      (e = ap->LD.alloc(lb, ctx->stream)) != hipSuccess || (e = ap->LX.alloc(lb, ctx->stream)) != hipSuccess ||
+      (e = ap->gslot.alloc(static_cast<size_t>(std::max<int64_t>(slot, 1)) * sizeof(double), ctx->stream)) != hipSuccess)
     return from_hip(e);
   ctx->adjoint = std::move(ap);
   return BURGERS_OK;
 }
 
-hipError_t grow(DevBuf& b, size_t bytes) {
+hipError_t grow(DevBuf& b, size_t bytes, hipStream_t stream) {
   if (b.bytes >= bytes && b.ptr) return hipSuccess;
-  if (b.ptr) {
-    (void)hipFree(b.ptr);
-    b.ptr = nullptr;
-    b.bytes = 0;
-  }
-  return b.alloc(bytes);
+  return b.alloc(bytes, stream);
 }
 
 // One adjoint step: lam_out from lam_in at the forward pair (y = u^k, x = u^{k+1}).
@@ -598,14 +592,14 @@ burgers_status burgers_create(const burgers_problem* problems, int64_t count, bu
     (p.scheme == BURGERS_EXPLICIT ? ctx->set_explicit : ctx->set_btcs).push_back(static_cast<int32_t>(i));
   }
   burgers_status st = BURGERS_OK;
-  if ((e = upload(ctx->inst, ctx->inst_host)) != hipSuccess) st = from_hip(e);
-  if (st == BURGERS_OK && (e = ctx->work.alloc(static_cast<size_t>(ctx->total) * ctx->word)) != hipSuccess)
+  if ((e = upload_on(ctx->stream, ctx->inst, ctx->inst_host)) != hipSuccess) st = from_hip(e);
+  if (st == BURGERS_OK && (e = ctx->work.alloc(static_cast<size_t>(ctx->total) * ctx->word, ctx->stream)) != hipSuccess)
     st = from_hip(e);
   if (st == BURGERS_OK) {
     ctx->level_capacity = level_rows_needed(ctx);
     const size_t lb = static_cast<size_t>(ctx->level_capacity) * sizeof(double);   // binary64 solve
-    if ((e = ctx->level_a.alloc(lb)) != hipSuccess || (e = ctx->level_c.alloc(lb)) != hipSuccess ||
-        (e = ctx->level_d.alloc(lb)) != hipSuccess || (e = ctx->level_x.alloc(lb)) != hipSuccess)
+    if ((e = ctx->level_a.alloc(lb, ctx->stream)) != hipSuccess || (e = ctx->level_c.alloc(lb, ctx->stream)) != hipSuccess ||
+        (e = ctx->level_d.alloc(lb, ctx->stream)) != hipSuccess || (e = ctx->level_x.alloc(lb, ctx->stream)) != hipSuccess)
       st = from_hip(e);
   }
   if (st != BURGERS_OK) {
@@ -650,6 +644,83 @@ burgers_status burgers_run_mixed(burgers_ctx* ctx, void* u, int64_t explicit_ste
   return advance(ctx, u, explicit_steps, kSetAll, -1, btcs_steps);
 }
 
+burgers_status burgers_autotune(burgers_ctx* ctx, const void* u, int64_t explicit_steps, int64_t btcs_steps,
+                                burgers_plan* best, double* best_ms) {
+  if (!ctx || !u || explicit_steps < 0 || btcs_steps < 0 || explicit_steps + btcs_steps == 0)
+    return BURGERS_E_INVALID;
+  if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return note(ctx, e);
+  const bool has_exp = !ctx->set_explicit.empty() && explicit_steps > 0;
+  const bool has_btcs = !ctx->set_btcs.empty() && btcs_steps > 0;
+  bool long_exp = false;
+  for (int32_t i : ctx->set_explicit)
+    if (ctx->probs[i].n > burgers::explicit_block_capacity()) long_exp = true;
+  std::vector<burgers_plan> cands;
+  const burgers_plan base = ctx->plan;
+  std::vector<std::pair<int, int>> exp_opts = {{0, 0}};            // (path, depth)
+  if (has_exp) {
+    exp_opts.clear();
+    if (long_exp) for (int d : {4, 8, 16, 32}) exp_opts.push_back({0, d});
+    else exp_opts.push_back({0, 0});
+    exp_opts.push_back({1, 0});
+  }
+  std::vector<int> blocks = {0};
+  if (has_btcs) blocks = {512, 1024};
+  for (auto eo : exp_opts)
+    for (int bl : blocks)
+      for (int g : {0, 1}) {
+        burgers_plan p = base;
+        p.explicit_path = eo.first;
+        p.tblock_depth = eo.second;
+        p.btcs_path = 0;
+        p.btcs_block = bl;
+        p.use_graph = g;
+        cands.push_back(p);
+      }
+  DevBuf scratch;
+  if ((e = scratch.alloc(static_cast<size_t>(ctx->total) * ctx->word, ctx->stream)) != hipSuccess) return from_hip(e);
+  hipEvent_t t0, t1;
+  if ((e = hipEventCreate(&t0)) != hipSuccess) return from_hip(e);
+  if ((e = hipEventCreate(&t1)) != hipSuccess) { (void)hipEventDestroy(t0); return from_hip(e); }
+  const size_t bytes = static_cast<size_t>(ctx->total) * ctx->word;
+  double best_t = INFINITY;
+  burgers_plan best_p = base;
+  burgers_status st = BURGERS_OK;
+  for (const burgers_plan& p : cands) {
+    if ((st = burgers_set_plan(ctx, &p)) != BURGERS_OK) break;
+    float ms = 0.0f;
+    for (int rep = 0; rep < 2; ++rep) {      // first run builds plans and graphs
+      if ((e = hipMemcpyAsync(scratch.ptr, u, bytes, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess) break;
+      if ((e = hipEventRecord(t0, ctx->stream)) != hipSuccess) break;
+      st = advance(ctx, scratch.ptr, explicit_steps, kSetAll, -1, btcs_steps);
+      if (st != BURGERS_OK) break;
+      if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess) break;
+      if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+    }
+    if (st == BURGERS_E_UNSUPPORTED) { st = BURGERS_OK; continue; }
+    if (e != hipSuccess || st != BURGERS_OK) break;
+    if (ms < best_t) {
+      best_t = ms;
+      best_p = p;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (e != hipSuccess) {
+    (void)burgers_set_plan(ctx, &base);
+    return note(ctx, e);
+  }
+  if (st != BURGERS_OK) {
+    (void)burgers_set_plan(ctx, &base);
+    return st;
+  }
+  (void)burgers_set_plan(ctx, &best_p);
+  if (best) *best = best_p;
+  if (best_ms) *best_ms = best_t;
+  return BURGERS_OK;
+}
+
 burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lambda_T, int64_t nsteps,
                                int64_t ckpt_every, void* grad_u0, void* grad_nu) {
   if (!ctx || !u0 || !lambda_T || !grad_u0 || !grad_nu || nsteps < 0 || ckpt_every < 1)
@@ -665,9 +736,9 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   const size_t state_bytes = static_cast<size_t>(ctx->total) * sizeof(double);
   const int64_t K = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
   const int64_t ncp = (nsteps + K - 1) / K;   // checkpoints at steps 0, K, 2K, ...
-  if ((e = grow(ap.ckpt, state_bytes * static_cast<size_t>(std::max<int64_t>(ncp, 1)))) != hipSuccess ||
-      (e = grow(ap.seg, state_bytes * static_cast<size_t>(K + 1))) != hipSuccess ||
-      (e = grow(ap.lam0, state_bytes)) != hipSuccess || (e = grow(ap.lam1, state_bytes)) != hipSuccess)
+  if ((e = grow(ap.ckpt, state_bytes * static_cast<size_t>(std::max<int64_t>(ncp, 1)), ctx->stream)) != hipSuccess ||
+      (e = grow(ap.seg, state_bytes * static_cast<size_t>(K + 1), ctx->stream)) != hipSuccess ||
+      (e = grow(ap.lam0, state_bytes, ctx->stream)) != hipSuccess || (e = grow(ap.lam1, state_bytes, ctx->stream)) != hipSuccess)
     return from_hip(e);
   auto state = [&](DevBuf& b, int64_t k) { return static_cast<char*>(b.ptr) + static_cast<size_t>(k) * state_bytes; };
   const hipMemcpyKind d2d = hipMemcpyDeviceToDevice;

@@ -14,7 +14,8 @@
 //    to address it, so the vector load issues after a single scalar load.
 //  * explicit_block_kernel: temporal blocking.  A workgroup holds a window of up to 8192 nodes in
 //    registers (32 per lane), exchanges only the chunk end values through LDS each step (double
-//    buffered, one barrier per step) and advances many steps per pass over HBM.  A whole instance that
+//    buffered, one barrier per step) and advances many steps per pass over HBM.  The window is loaded
+//    and stored through LDS so that HBM sees coalesced accesses.  A whole instance that
 //    fits is advanced for all its steps in one launch with exact boundaries; longer grids are cut into
 //    windows with a halo of T nodes per side that are recomputed redundantly, so that after T steps the
 //    window's interior is exact.  Every node goes through the same arithmetic as in the streaming
@@ -97,17 +98,18 @@ __device__ __forceinline__ void lane_span(int t, int W, int P, int& s, int& m) {
   m = q + (t < rho ? 1 : 0);
 }
 
-// Temporal blocking.  EXACT: the window has exactly kBlockThreads * kBlockChunk nodes, so every lane
+// LDS staging of window I/O: half the lanes' chunks at a time (at most 4096 nodes), padded by one element
+// every 32 nodes so that lanes reading their 32-node chunks hit distinct banks.
+constexpr int kStageNodes = kBlockThreads * kBlockChunk / 2;
+__device__ __forceinline__ int spad(int i) { return i + (i >> 5); }
+
+// Temporal-blocking body.  EXACT: the window has exactly kBlockThreads * kBlockChunk nodes, so every lane
 // holds a full chunk and the guards below fold away.
 template <typename T, bool EXACT>
-__global__ __launch_bounds__(kBlockThreads) void explicit_block_kernel(
-    const InstDesc* __restrict__ inst, const BlockTile* __restrict__ tiles, const T* __restrict__ u,
-    T* __restrict__ out, int steps) {
+__device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& d, const T* __restrict__ src,
+                                           T* __restrict__ dst, int steps, T* stage,
+                                           T (*s_first)[kBlockThreads], T (*s_last)[kBlockThreads]) {
   constexpr int M = kBlockChunk;
-  __shared__ T s_first[2][kBlockThreads];
-  __shared__ T s_last[2][kBlockThreads];
-  const BlockTile bt = tiles[blockIdx.x];
-  const InstDesc d = inst[bt.inst];
   const T r = static_cast<T>(d.r), D = static_cast<T>(d.D);
   const int n = d.n;
   const bool periodic = d.bc == kPeriodic;
@@ -118,16 +120,25 @@ __global__ __launch_bounds__(kBlockThreads) void explicit_block_kernel(
   int s = 0, m = 0;
   if (active) lane_span(t, W, P, s, m);
   if (EXACT) m = M;
-  // window node w is instance node (bt.first + w) mod n; the window wraps only for periodic instances
-  const T* __restrict__ src = u + d.off;
+  const int half = P / 2;                       // lanes [0, half) and [half, P) are staged in turn
   T v[M];
-#pragma unroll
-  for (int j = 0; j < M; ++j) {
-    if (active && j < m) {
-      int g = bt.first + s + j;
+  // window node w is instance node (bt.first + w) mod n; the window wraps only for periodic instances
+  for (int h = 0; h < 2; ++h) {
+    int r0, r1, mm;
+    lane_span(h == 0 ? 0 : half, W, P, r0, mm);
+    if (h == 0) lane_span(half, W, P, r1, mm); else r1 = W;
+    for (int w = r0 + t; w < r1; w += kBlockThreads) {
+      int g = bt.first + w;
       if (g >= n) g -= n;
-      v[j] = src[g];
+      stage[spad(w - r0)] = src[g];
     }
+    __syncthreads();
+    if (active && (h == 0) == (t < half)) {
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        if (EXACT || j < m) v[j] = stage[spad(s + j - r0)];
+    }
+    __syncthreads();
   }
   // Window ends that are not periodic neighbours are held fixed: at a Dirichlet boundary they carry
   // a or b (and node 1 then reads a exactly as the streaming kernel does); at an interior window edge
@@ -179,18 +190,44 @@ __global__ __launch_bounds__(kBlockThreads) void explicit_block_kernel(
     }
   }
 
-  // store the window's output nodes [bt.lo, bt.lo + bt.count)
-  T* __restrict__ dst = out + d.off;
-  if (active) {
+  // store the window's output nodes [bt.lo, bt.lo + bt.count), staged like the load
+  for (int h = 0; h < 2; ++h) {
+    int r0, r1, mm;
+    lane_span(h == 0 ? 0 : half, W, P, r0, mm);
+    if (h == 0) lane_span(half, W, P, r1, mm); else r1 = W;
+    if (active && (h == 0) == (t < half)) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const int w = s + j;
-      if ((EXACT || j < m) && w >= bt.lo && w < bt.lo + bt.count) {
-        int g = bt.first + w;
-        if (g >= n) g -= n;
-        dst[g] = v[j];
-      }
+      for (int j = 0; j < M; ++j)
+        if (EXACT || j < m) stage[spad(s + j - r0)] = v[j];
     }
+    __syncthreads();
+    const int o0 = r0 > bt.lo ? r0 : bt.lo;
+    const int o1 = r1 < bt.lo + bt.count ? r1 : bt.lo + bt.count;
+    for (int w = o0 + t; w < o1; w += kBlockThreads) {
+      int g = bt.first + w;
+      if (g >= n) g -= n;
+      dst[g] = stage[spad(w - r0)];
+    }
+    __syncthreads();
+  }
+}
+
+// One workgroup per window; full-size windows take the specialised body.
+template <typename T>
+__global__ __launch_bounds__(kBlockThreads) void explicit_block_kernel(
+    const InstDesc* __restrict__ inst, const BlockTile* __restrict__ tiles, const T* __restrict__ u,
+    T* __restrict__ out, int steps) {
+  __shared__ T s_first[2][kBlockThreads];
+  __shared__ T s_last[2][kBlockThreads];
+  __shared__ T stage[kStageNodes + kStageNodes / 32 + 1];
+  const BlockTile bt = tiles[blockIdx.x];
+  const InstDesc d = inst[bt.inst];
+  const T* src = u + d.off;
+  T* dst = out + d.off;
+  if (bt.width == kBlockThreads * kBlockChunk) {
+    block_body<T, true>(bt, d, src, dst, steps, stage, s_first, s_last);
+  } else {
+    block_body<T, false>(bt, d, src, dst, steps, stage, s_first, s_last);
   }
 }
 
@@ -253,20 +290,16 @@ hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int
 }
 
 hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_tiles,
-                                 bool exact, const void* u, void* out, int steps) {
+                                 const void* u, void* out, int steps) {
   if (n_tiles <= 0 || steps <= 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(n_tiles)), block(kBlockThreads);
   const InstDesc* inst = ctx->inst.as<InstDesc>();
   if (ctx->dtype == BURGERS_F64) {
-    const double* uu = static_cast<const double*>(u);
-    double* oo = static_cast<double*>(out);
-    if (exact) explicit_block_kernel<double, true><<<grid, block, 0, ctx->stream>>>(inst, tiles, uu, oo, steps);
-    else explicit_block_kernel<double, false><<<grid, block, 0, ctx->stream>>>(inst, tiles, uu, oo, steps);
+    explicit_block_kernel<double><<<grid, block, 0, ctx->stream>>>(inst, tiles, static_cast<const double*>(u),
+                                                                  static_cast<double*>(out), steps);
   } else {
-    const float* uu = static_cast<const float*>(u);
-    float* oo = static_cast<float*>(out);
-    if (exact) explicit_block_kernel<float, true><<<grid, block, 0, ctx->stream>>>(inst, tiles, uu, oo, steps);
-    else explicit_block_kernel<float, false><<<grid, block, 0, ctx->stream>>>(inst, tiles, uu, oo, steps);
+    explicit_block_kernel<float><<<grid, block, 0, ctx->stream>>>(inst, tiles, static_cast<const float*>(u),
+                                                                 static_cast<float*>(out), steps);
   }
   return hipGetLastError();
 }

@@ -83,14 +83,32 @@ struct ChunkBlock {
   int32_t chunk0;
 };
 
-// Device buffer owned by a context.
+// Device buffer owned by a context, allocated and released in stream order on the context's stream:
+// hipFree would synchronise the whole device and stall every other context's work in flight.
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
-  ~DevBuf() { if (ptr) (void)hipFree(ptr); }
-  hipError_t alloc(size_t n) {
+  hipStream_t stream = nullptr;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (ptr) (void)hipFreeAsync(ptr, stream);
+    ptr = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t n, hipStream_t s) {
+    release();
+    stream = s;
+    if (!n) return hipSuccess;
+    hipError_t e = hipMallocAsync(&ptr, n, s);
+    if (e != hipSuccess) {
+      ptr = nullptr;
+      return e;
+    }
     bytes = n;
-    return n ? hipMalloc(&ptr, n) : hipSuccess;
+    return hipSuccess;
   }
   template <typename T> T* as() const { return static_cast<T*>(ptr); }
 };
@@ -100,8 +118,8 @@ struct BtcsPlan {
   int path = 0;                              // 0 automatic, 1 per-step, 2 resident, 3 partition levels
   int threads = 0;                           // lanes per system of the on-chip solver (512 or 1024)
   // systems kept on chip for all steps of a launch (in place)
-  std::unique_ptr<DevBuf> resident;          // SysDesc[]
-  int32_t n_resident = 0;
+  std::unique_ptr<DevBuf> resident, resident_exact;   // SysDesc[]; exact: rows == 8192
+  int32_t n_resident = 0, n_resident_exact = 0;
   std::unique_ptr<DevBuf> copy;              // Tile[] of the instances stepped through HBM (copy-back)
   int64_t n_copy = 0;
   // small systems solved whole by one workgroup each, straight from and to the state
@@ -124,8 +142,8 @@ struct ExplicitPlan {
   std::unique_ptr<DevBuf> stream;            // Tile[] covering every node of the set
   int64_t n_stream = 0;
   // temporal blocking: whole instances (all steps in place) and windows of long instances
-  std::unique_ptr<DevBuf> whole_exact, whole_generic, win_exact, win_generic;   // BlockTile[]
-  int64_t n_whole_exact = 0, n_whole_generic = 0, n_win_exact = 0, n_win_generic = 0;
+  std::unique_ptr<DevBuf> whole, win;        // BlockTile[]
+  int64_t n_whole = 0, n_win = 0;
   std::unique_ptr<DevBuf> win_copy;          // Tile[] of the windowed instances (copy-back)
   int64_t n_win_copy = 0;
   int path = 1;                              // 1 stream, 2 resident, 3 tiled
@@ -179,7 +197,7 @@ namespace burgers {
 hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles,
                                   const void* u, void* out);
 hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_tiles,
-                                 bool exact, const void* u, void* out, int steps);
+                                 const void* u, void* out, int steps);
 hipError_t launch_copy_tiles(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* src,
                              void* dst);
 int explicit_tile_nodes(burgers_dtype dt);
@@ -206,7 +224,7 @@ int btcs_reduce_chunk();                // target rows per chunk in the partitio
 constexpr int kReduceBlock = 256;       // chunks per workgroup in the partition kernels
 hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out);
 hipError_t launch_btcs_resident(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u,
-                                int steps, int threads);
+                                int steps, int threads, bool exact);
 int btcs_chunks(int rows, int threads);
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
                               double* LD, double* LX);

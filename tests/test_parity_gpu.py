@@ -312,3 +312,35 @@ def test_run_mixed_step_counts(graph):
             assert np.array_equal(got[lo:hi], exp[lo:hi]), b
         else:
             assert rel_err(got[lo:hi], imp[lo:hi]) <= TOL_F64, b
+
+
+def test_autotune_keeps_state_and_results(tmp_path):
+    """The autotuner times candidates on a scratch copy: u is untouched, the chosen plan still matches
+    the oracle, and a cached choice is reused."""
+    import torch
+    import paper_2601_12204_amd as B
+    batch = set_cfl_steps(W.random_batch(36, 30, 3, 30000, amplitude=2.0))
+    announce("autotune ragged mix")
+    s = B.Solver(batch.problems, dtype=torch.float64)
+    u = s.pack_flat(batch.u0, batch.offsets)
+    before = u.clone()
+    cache = str(tmp_path / "tune.json")
+    plan, ms, cached = s.autotune(u, 20, 5, cache=cache)
+    assert not cached and ms > 0
+    assert torch.equal(u, before)
+    s.run_mixed(u, 20, 5)
+    s.sync()
+    got = s.unpack_flat(u)
+    s.close()
+    exp = oracle_run(batch, 20, "f64", scheme=W.EXPLICIT)
+    imp = oracle_run(batch, 5, "f64", scheme=W.BTCS)
+    for b, p in enumerate(batch.problems):
+        lo, hi = batch.offsets[b], batch.offsets[b + 1]
+        if p.scheme == W.EXPLICIT:
+            assert np.array_equal(got[lo:hi], exp[lo:hi]), (b, plan)
+        else:
+            assert rel_err(got[lo:hi], imp[lo:hi]) <= TOL_F64, (b, plan)
+    s2 = B.Solver(batch.problems, dtype=torch.float64)
+    plan2, ms2, cached2 = s2.autotune(s2.pack_flat(batch.u0, batch.offsets), 20, 5, cache=cache)
+    assert cached2 and plan2 == plan and s2.get_plan() == plan
+    s2.close()
