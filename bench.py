@@ -266,6 +266,32 @@ def bench_c5_adjoint(B, torch, scheme, count=256, n=16384, nsteps=2000, ckpt=100
             "steps": nsteps, "ckpt_every": ckpt, "instances": count, "n": n}
 
 
+def bench_serve(B, torch, duration=2.0, rate=2000.0, pool=800, budget=8 << 30):
+    """Poisson request stream (rate 2000/s) over the ragged mix (N log-uniform in [64, 65536], half
+    periodic / half Dirichlet, half explicit (10^3 steps) / half BTCS (10^2 steps), half FP32 / half FP64),
+    admitted by HBM budget into batched cohorts; latency = completion - arrival."""
+    import workloads as W
+    from paper_2601_12204_amd.serve import Request, Server
+    batch, dtypes = W.ragged_batch(pool, seed=W.SEED_BASE + 4, dtype_mix=True)
+    for i, p in enumerate(batch.problems):
+        f = 1.0 if p.scheme == W.EXPLICIT else 10.0
+        p.dt = f * B.burgers_cfl_dt(p, float(batch.umax[i]), 0.5)
+    arrivals = W.poisson_arrivals(rate, duration)
+
+    def make(k, rid):
+        p = batch.problems[k]
+        return Request(rid=rid, problem=p, u0=batch.instance(k), dtype="f64" if dtypes[k] else "f32",
+                       nsteps=1000 if p.scheme == W.EXPLICIT else 100)
+
+    warm = [make(k, k) for k in range(min(pool, 64))]
+    Server(hbm_budget=budget).run(warm, np.zeros(len(warm)))
+    reqs = [make(k % pool, k) for k in range(len(arrivals))]
+    srv = Server(hbm_budget=budget, batch_window=0.001)
+    stats = srv.run(reqs, arrivals)
+    stats.update({"rate_per_s": rate, "duration_s": duration, "pool": pool})
+    return stats
+
+
 def cpu_baseline(target_s=12.0):
     """The oracle as it stands on the host cores, on a bounded sample of the same workload."""
     import oracle
@@ -310,6 +336,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
+    ap.add_argument("--legs", default="c2,c2f32,c1,c3,c4,c5,serve",
+                    help="comma-separated side measurements to run (profiling runs select one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--exp-steps", type=int, default=10_000, help="explicit steps per step (profiling runs)")
     ap.add_argument("--btcs-steps", type=int, default=1_000, help="BTCS steps per step (profiling runs)")
@@ -326,34 +354,52 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
 
-    log("C2 FP64")
-    c2 = bench_c2(B, torch, torch.float64, args.steps, args.warmup, args.exp_steps, args.btcs_steps,
-                  args.explicit_path, args.btcs_path, args.btcs_block)
-    extra = {"c2_f64": c2}
-    if not args.quick:
+    import workloads as W
+    legs = set() if args.quick else set(args.legs.split(","))
+    extra = {}
+    c2 = None
+    if "c2" in legs or args.quick:
+        log("C2 FP64")
+        c2 = bench_c2(B, torch, torch.float64, args.steps, args.warmup, args.exp_steps, args.btcs_steps,
+                      args.explicit_path, args.btcs_path, args.btcs_block)
+        extra["c2_f64"] = c2
+    if "c2f32" in legs:
         log("C2 FP32")
         extra["c2_f32"] = bench_c2(B, torch, torch.float32, 1, 1)
+    if "c1" in legs:
         log("C1 latency")
         extra["c1_latency"] = bench_c1_latency(B, torch)
+    if "c3" in legs:
         log("C3")
         extra["c3_f64"] = bench_c3(B, torch)
+    if "c4" in legs:
         log("C4 ragged")
-        import workloads as W
         c4 = W.ragged_batch(10_000)
         extra["c4_f64_graph"] = bench_c4(B, torch, torch.float64, True, c4)
         extra["c4_f64_eager"] = bench_c4(B, torch, torch.float64, False, c4)
         extra["c4_f32_graph"] = bench_c4(B, torch, torch.float32, True, c4)
+    if "c5" in legs:
         log("C5 adjoint")
-        import workloads as W
         extra["c5_adjoint_explicit"] = bench_c5_adjoint(B, torch, W.EXPLICIT)
         extra["c5_adjoint_btcs"] = bench_c5_adjoint(B, torch, W.BTCS)
+    if "serve" in legs:
+        log("serving")
+        extra["serve"] = bench_serve(B, torch)
+    if c2 is None:
+        print(json.dumps({"metric": METRIC, "partial": True, "extra": extra}), flush=True)
+        return
 
     roofline = dominant_roofline(c2)
     cpu = None
     if not args.no_cpu:
         log("CPU oracle baseline")
         cpu = cpu_baseline()
+    if "serve" in extra:
+        line_latency = {"p50_ms": extra["serve"]["p50_ms"], "p99_ms": extra["serve"]["p99_ms"]}
+    else:
+        line_latency = None
     line = {
+        "served_latency": line_latency,
         "metric": METRIC, "value": c2["glups"], "unit": "GLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": c2["step_ms"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
