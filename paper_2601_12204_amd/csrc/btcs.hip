@@ -429,6 +429,116 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_resident_kernel(
   }
 }
 
+// Rows of a reduced system held in LDS with unit diagonal, row k at padded(k).
+template <typename T>
+struct LdsArrayRows {
+  const T* A;
+  const T* C;
+  const T* Dv;
+  __device__ __forceinline__ void row(int, int k, int, T& al, T& be, T& ga, T& de) const {
+    const int i = padded(k);
+    al = A[i];
+    be = T(1);
+    ga = C[i];
+    de = Dv[i];
+  }
+};
+
+// In-block reduction of the block partition kernels.  A workgroup's 256 chunk pairs form a segment of
+// at most 512 reduced rows whose first row couples to the previous block's last unknown and whose last
+// row couples to the next block's first unknown.  The segment is reduced by the same chunk elimination,
+// 16 rows per chunk, level by level (512 -> 64 -> 8 -> 2 rows), to the two rows that tie the block's
+// first and last unknowns to its neighbours.  Level l's rows sit at kLvlBase(l) of the level arrays.
+constexpr int kLvlLevels = 4;                   // rows: <= 512, <= 64, <= 8, 2
+__device__ __forceinline__ int lvl_base(int l) {
+  return l == 0 ? 0 : l == 1 ? padded_size(512) : l == 2 ? padded_size(512) + padded_size(64)
+                                                        : padded_size(512) + padded_size(64) + padded_size(8);
+}
+constexpr int kLvlSpan = padded_size(512) + padded_size(64) + padded_size(8) + padded_size(2);
+
+struct LvlArrays {
+  double* A;
+  double* C;
+  double* D;
+  double* X;
+};
+
+__device__ __forceinline__ int lvl_chunks(int R) { return (R + kRedChunk - 1) / kRedChunk; }
+
+// One level forward: rows of level l (R of them) -> 2 * lvl_chunks(R) rows of level l + 1.
+__device__ __forceinline__ int lvl_reduce(const LvlArrays& L, int l, int R) {
+  using T = double;
+  const int P = lvl_chunks(R);
+  const int tid = threadIdx.x;
+  if (tid < P) {
+    int s, m;
+    chunk_span(tid, R, P, s, m);
+    const int b = lvl_base(l);
+    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
+    T AF, CF, DF, AE, CE, DE;
+    chunk_eliminate<T, kRedChunk>(LdsArrayRows<T>{L.A + b, L.C + b, L.D + b}, s, m, R, al, ga, de, AF, CF, DF,
+                                  AE, CE, DE);
+    const int o = lvl_base(l + 1);
+    L.A[o + padded(2 * tid)] = AF; L.C[o + padded(2 * tid)] = CF; L.D[o + padded(2 * tid)] = DF;
+    L.A[o + padded(2 * tid + 1)] = AE; L.C[o + padded(2 * tid + 1)] = CE; L.D[o + padded(2 * tid + 1)] = DE;
+  }
+  __syncthreads();
+  return 2 * P;
+}
+
+// One level backward: level l's unknowns from level l + 1's solution (re-eliminating the chunks).
+__device__ __forceinline__ void lvl_recover(const LvlArrays& L, int l, int R) {
+  using T = double;
+  const int P = lvl_chunks(R);
+  const int tid = threadIdx.x;
+  if (tid < P) {
+    int s, m;
+    chunk_span(tid, R, P, s, m);
+    const int b = lvl_base(l);
+    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
+    T AF, CF, DF, AE, CE, DE;
+    chunk_eliminate<T, kRedChunk>(LdsArrayRows<T>{L.A + b, L.C + b, L.D + b}, s, m, R, al, ga, de, AF, CF, DF,
+                                  AE, CE, DE);
+    const int o = lvl_base(l + 1);
+    const T F = L.X[o + padded(2 * tid)];
+    const T E = L.X[o + padded(2 * tid + 1)];
+    T* x = L.X + b;
+    x[padded(s)] = F;
+#pragma unroll
+    for (int j = 1; j < kRedChunk; ++j) {
+      if (j < m - 1) x[padded(s + j)] = de[j] - al[j] * F - ga[j] * E;
+      if (j == m - 1) x[padded(s + j)] = E;
+    }
+  }
+  __syncthreads();
+}
+
+// Coalesced copies of a block's rows between HBM and LDS: all loads are issued before the first LDS
+// store, so a wave has its whole share of the block in flight at once.
+template <typename S>
+__device__ __forceinline__ void stage_in(S* stage, const S* __restrict__ src, int cnt) {
+  S v[kRedChunk];
+#pragma unroll
+  for (int j = 0; j < kRedChunk; ++j) {
+    const int i = static_cast<int>(threadIdx.x) + j * kReduceBlock;
+    v[j] = i < cnt ? src[i] : S(0);
+  }
+#pragma unroll
+  for (int j = 0; j < kRedChunk; ++j) {
+    const int i = static_cast<int>(threadIdx.x) + j * kReduceBlock;
+    if (i < cnt) stage[padded(i)] = v[j];
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void stage_out(const S* stage, S* __restrict__ dst, int cnt) {
+#pragma unroll
+  for (int j = 0; j < kRedChunk; ++j) {
+    const int i = static_cast<int>(threadIdx.x) + j * kReduceBlock;
+    if (i < cnt) dst[i] = stage[padded(i)];
+  }
+}
+
 // Rows [rs, re) of the chunks a partition workgroup owns: chunk k spans chunk_span(k).
 __device__ __forceinline__ void block_rows(const SysDesc& sys, int c0, int& rs, int& re) {
   int m;
@@ -441,94 +551,160 @@ __device__ __forceinline__ void block_rows(const SysDesc& sys, int c0, int& rs, 
   }
 }
 
-// Partition level, forward half: every thread eliminates one chunk and stores its two reduced rows.
-// At level 0 the workgroup's rows are staged through LDS first (coalesced loads).
-template <typename S, bool FromState>
-__global__ __launch_bounds__(kReduceBlock) void btcs_reduce_kernel(
-    const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
-    const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, double* __restrict__ LA,
+// Partition level of a reduced system held in (A, C, D) arrays, forward half: every thread eliminates
+// one chunk and stores its two reduced rows.
+__global__ __launch_bounds__(kReduceBlock) void btcs_array_reduce_kernel(
+    const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, double* __restrict__ LA,
     double* __restrict__ LC, double* __restrict__ LD) {
   using T = double;
-  __shared__ S stage[FromState ? padded_size(kRedRows) : 1];
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
+  if (k >= sys.chunks) return;
   T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
   T AF, CF, DF, AE, CE, DE;
-  int s = 0, m = 0;
-  if constexpr (FromState) {
-    const InstDesc d = inst[sys.inst];
-    const bool dir = d.bc == kDirichlet;
-    int rs, re;
-    block_rows(sys, cb.chunk0, rs, re);
-    const S* src = u + d.off + (dir ? 1 : 0);
-    for (int i = rs + static_cast<int>(threadIdx.x); i < re; i += kReduceBlock) stage[padded(i - rs)] = src[i];
-    __syncthreads();
-    if (k >= sys.chunks) return;
-    chunk_span(k, sys.rows, sys.chunks, s, m);
-    const LdsRows<S> rows{stage, rs, d.r, d.D, d.a, d.b, dir};
-    chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-  } else {
-    if (k >= sys.chunks) return;
-    chunk_span(k, sys.rows, sys.chunks, s, m);
-    const ArrayRows<T> rows{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
-    chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-  }
+  int s, m;
+  chunk_span(k, sys.rows, sys.chunks, s, m);
+  const ArrayRows<T> rows{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
+  chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
   LA[o] = AF; LC[o] = CF; LD[o] = DF;
   LA[o + 1] = AE; LC[o + 1] = CE; LD[o + 1] = DE;
 }
 
-// Partition level, backward half: re-eliminate the chunk and recover its rows from the solved
-// reduced unknowns.  At level 0 the rows are staged through LDS both ways.
-template <typename S, bool FromState>
-__global__ __launch_bounds__(kReduceBlock) void btcs_backsub_kernel(
-    const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
-    const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, S* __restrict__ out,
-    const double* __restrict__ LA, const double* __restrict__ LC, const double* __restrict__ LD,
-    double* __restrict__ LX) {
+// Backward half: re-eliminate the chunk and recover its rows from the solved reduced unknowns.
+__global__ __launch_bounds__(kReduceBlock) void btcs_array_backsub_kernel(
+    const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, const double* __restrict__ LA,
+    const double* __restrict__ LC, const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
-  __shared__ S stage[FromState ? padded_size(kRedRows) : 1];
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
-  const bool active = k < sys.chunks;
+  if (k >= sys.chunks) return;
   T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
   T AF, CF, DF, AE, CE, DE;
-  int s = 0, m = 0;
-  T F = T(0), E = T(0);
-  if (active) {
+  int s, m;
+  chunk_span(k, sys.rows, sys.chunks, s, m);
+  const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
+  const T F = LX[o];
+  const T E = LX[o + 1];
+  const ArrayRows<T> rows{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
+  chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
+  chunk_recover<T, kRedChunk>(PtrDst<T>{LX + sys.in_off}, s, m, al, ga, de, F, E);
+}
+
+// Block partition, forward half (level 0 of a long system): a workgroup stages its 256 chunks' rows
+// (<= 4096) through LDS, eliminates every chunk, reduces the block's chunk pairs in LDS down to two rows
+// and stores those at red_off + 2 * (block index within the system).
+template <typename S>
+__global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
+    const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
+    const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, double* __restrict__ LA,
+    double* __restrict__ LC, double* __restrict__ LD) {
+  using T = double;
+  constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
+  constexpr int kLvlBytes = 3 * kLvlSpan * static_cast<int>(sizeof(T));
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kStageBytes > kLvlBytes ? kStageBytes : kLvlBytes];
+  S* stage = reinterpret_cast<S*>(smem);
+  const LvlArrays L{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + kLvlSpan,
+                    reinterpret_cast<T*>(smem) + 2 * kLvlSpan, nullptr};
+  const ChunkBlock cb = blocks[blockIdx.x];
+  const SysDesc sys = systems[cb.sys];
+  const InstDesc d = inst[sys.inst];
+  const bool dir = d.bc == kDirichlet;
+  const int tid = threadIdx.x;
+  const int k = cb.chunk0 + tid;
+  const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
+  int rs, re;
+  block_rows(sys, cb.chunk0, rs, re);
+  stage_in(stage, u + d.off + (dir ? 1 : 0) + rs, re - rs);
+  __syncthreads();
+  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
+  if (tid < Pb) {
+    int s, m;
     chunk_span(k, sys.rows, sys.chunks, s, m);
-    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
-    F = LX[o];
-    E = LX[o + 1];
+    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
+    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, d.a, d.b, dir}, s, m, sys.rows, al, ga, de,
+                                  AF, CF, DF, AE, CE, DE);
   }
-  if constexpr (FromState) {
-    const InstDesc d = inst[sys.inst];
-    const bool dir = d.bc == kDirichlet;
-    int rs, re;
-    block_rows(sys, cb.chunk0, rs, re);
-    const S* src = u + d.off + (dir ? 1 : 0);
-    for (int i = rs + static_cast<int>(threadIdx.x); i < re; i += kReduceBlock) stage[padded(i - rs)] = src[i];
-    __syncthreads();
-    if (active) {
-      const LdsRows<S> rows{stage, rs, d.r, d.D, d.a, d.b, dir};
-      chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-    }
-    __syncthreads();                           // every chunk read before the buffer is overwritten
-    if (active) chunk_recover<T, kRedChunk>(LdsDst<S>{stage, rs}, s, m, al, ga, de, F, E);
-    __syncthreads();
-    S* dst = out + d.off + (dir ? 1 : 0);
-    for (int i = rs + static_cast<int>(threadIdx.x); i < re; i += kReduceBlock) dst[i] = stage[padded(i - rs)];
-    if (dir && threadIdx.x == 0) {
-      if (cb.chunk0 == 0) out[d.off] = static_cast<S>(d.a);
-      if (cb.chunk0 + kReduceBlock >= sys.chunks) out[d.off + d.n - 1] = static_cast<S>(d.b);
-    }
-  } else {
-    if (!active) return;
-    const ArrayRows<T> rows{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
+  __syncthreads();                             // every chunk read before the level arrays overlay the stage
+  if (tid < Pb) {
+    L.A[padded(2 * tid)] = AF; L.C[padded(2 * tid)] = CF; L.D[padded(2 * tid)] = DF;
+    L.A[padded(2 * tid + 1)] = AE; L.C[padded(2 * tid + 1)] = CE; L.D[padded(2 * tid + 1)] = DE;
+  }
+  __syncthreads();
+  int R = 2 * Pb, l = 0;
+  while (R > 2) R = lvl_reduce(L, l++, R);
+  if (tid < 2) {
+    const int i = lvl_base(l) + padded(tid);
+    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock) + tid;
+    LA[o] = L.A[i];
+    LC[o] = L.C[i];
+    LD[o] = L.D[i];
+  }
+}
+
+// Block partition, backward half: the block's first and last unknowns come from the solved reduced
+// system; the block re-stages its rows, repeats the forward reduction, recovers the in-block levels top
+// down, then every chunk and stores the new state coalesced (with the Dirichlet boundary nodes).
+template <typename S>
+__global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
+    const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
+    const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, S* __restrict__ out,
+    const double* __restrict__ LX) {
+  using T = double;
+  __shared__ S stage[padded_size(kRedRows)];
+  __shared__ T lvl[4 * kLvlSpan];
+  const LvlArrays L{lvl, lvl + kLvlSpan, lvl + 2 * kLvlSpan, lvl + 3 * kLvlSpan};
+  const ChunkBlock cb = blocks[blockIdx.x];
+  const SysDesc sys = systems[cb.sys];
+  const InstDesc d = inst[sys.inst];
+  const bool dir = d.bc == kDirichlet;
+  const int tid = threadIdx.x;
+  const int k = cb.chunk0 + tid;
+  const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
+  int rs, re;
+  block_rows(sys, cb.chunk0, rs, re);
+  const S* src = u + d.off + (dir ? 1 : 0) + rs;
+  stage_in(stage, src, re - rs);
+  __syncthreads();
+  const LdsRows<S> rows{stage, rs, d.r, d.D, d.a, d.b, dir};
+  int s = 0, m = 0;
+  if (tid < Pb) {
+    chunk_span(k, sys.rows, sys.chunks, s, m);
+    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
+    T AF, CF, DF, AE, CE, DE;
     chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-    chunk_recover<T, kRedChunk>(PtrDst<T>{LX + sys.in_off}, s, m, al, ga, de, F, E);
+    L.A[padded(2 * tid)] = AF; L.C[padded(2 * tid)] = CF; L.D[padded(2 * tid)] = DF;
+    L.A[padded(2 * tid + 1)] = AE; L.C[padded(2 * tid + 1)] = CE; L.D[padded(2 * tid + 1)] = DE;
+  }
+  __syncthreads();
+  int Rl[kLvlLevels];
+  int R = 2 * Pb, l = 0;
+  Rl[0] = R;
+  while (R > 2) {
+    R = lvl_reduce(L, l, R);
+    Rl[++l] = R;
+  }
+  if (tid < 2) {
+    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock) + tid;
+    L.X[lvl_base(l) + padded(tid)] = LX[o];
+  }
+  __syncthreads();
+  for (int j = l - 1; j >= 0; --j) lvl_recover(L, j, Rl[j]);
+  if (tid < Pb) {
+    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
+    T AF, CF, DF, AE, CE, DE;
+    chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
+    // a chunk's rows depend only on its own old values, so it may overwrite them in place
+    chunk_recover<T, kRedChunk>(LdsDst<S>{stage, rs}, s, m, al, ga, de, L.X[padded(2 * tid)],
+                                L.X[padded(2 * tid + 1)]);
+  }
+  __syncthreads();
+  stage_out(stage, out + d.off + (dir ? 1 : 0) + rs, re - rs);
+  if (dir && tid == 0) {
+    if (cb.chunk0 == 0) out[d.off] = static_cast<S>(d.a);
+    if (cb.chunk0 + kReduceBlock >= sys.chunks) out[d.off + d.n - 1] = static_cast<S>(d.b);
   }
 }
 
@@ -548,11 +724,11 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
     const auto& lv = plan.levels[l];
     if (lv.n_blocks == 0) continue;
     if (l == 0) {
-      btcs_reduce_kernel<S, true><<<lv.n_blocks, kReduceBlock, 0, st>>>(
+      btcs_block_reduce_kernel<S><<<lv.n_blocks, kReduceBlock, 0, st>>>(
           inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, LA, LC, LD);
     } else {
-      btcs_reduce_kernel<S, false><<<lv.n_blocks, kReduceBlock, 0, st>>>(
-          inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, LA, LC, LD);
+      btcs_array_reduce_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
+                                                                     lv.blocks->as<ChunkBlock>(), LA, LC, LD);
     }
   }
   // backward: whole-system solves of each level, then back-substitution of the reduced systems
@@ -563,8 +739,8 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
                                                                            out, LA, LC, LD, LX);
     }
     if (lv.n_blocks) {
-      btcs_backsub_kernel<S, false><<<lv.n_blocks, kReduceBlock, 0, st>>>(
-          inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, out, LA, LC, LD, LX);
+      btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
+                                                                      lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);
     }
   }
   if (plan.n_wg_state) {
@@ -578,8 +754,8 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   }
   if (L > 0 && plan.levels[0].n_blocks) {
     const auto& lv = plan.levels[0];
-    btcs_backsub_kernel<S, true><<<lv.n_blocks, kReduceBlock, 0, st>>>(
-        inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, out, LA, LC, LD, LX);
+    btcs_block_backsub_kernel<S><<<lv.n_blocks, kReduceBlock, 0, st>>>(
+        inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, out, LX);
   }
   return hipGetLastError();
 }
@@ -643,8 +819,8 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
   for (int l = 0; l < L; ++l) {
     const auto& lv = plan.levels[l];
     if (lv.n_blocks)
-      btcs_reduce_kernel<double, false><<<lv.n_blocks, kReduceBlock, 0, st>>>(
-          inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), none, LA, LC, LD);
+      btcs_array_reduce_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
+                                                                     lv.blocks->as<ChunkBlock>(), LA, LC, LD);
   }
   for (int l = L - 1; l >= 0; --l) {
     const auto& lv = plan.levels[l];
@@ -652,8 +828,8 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
       btcs_wg_kernel<double, false, kWgThreads><<<lv.n_wg, kWgThreads, 0, st>>>(
           inst, lv.wg->as<SysDesc>(), none, none_out, LA, LC, LD, LX);
     if (lv.n_blocks)
-      btcs_backsub_kernel<double, false><<<lv.n_blocks, kReduceBlock, 0, st>>>(
-          inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), none, none_out, LA, LC, LD, LX);
+      btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
+                                                                      lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);
   }
   return hipGetLastError();
 }

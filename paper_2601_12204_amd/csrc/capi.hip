@@ -162,6 +162,13 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
 //   path 3: partition levels for every system of at least 32 rows (shorter ones solved whole).
 //   automatic: on chip for systems that fit, partition levels for longer ones.
 // Reduced-system rows are carved from the context's level arrays.
+// Rows a partition level leaves for the next one.  Level 0 (from the state) runs the block partition,
+// which reduces each workgroup's 256 chunks to two rows; deeper levels leave two rows per chunk.
+int32_t reduced_rows(int level, int32_t chunks) {
+  if (level == 0) return 2 * ((chunks + burgers::kReduceBlock - 1) / burgers::kReduceBlock);
+  return 2 * chunks;
+}
+
 burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   const int want = ctx->plan.btcs_path;
   const int threads = ctx->plan.btcs_block ? ctx->plan.btcs_block : burgers::kResidentThreadsDefault;
@@ -204,11 +211,12 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
         break;
       }
       const int32_t P = (R + chunk - 1) / chunk;
+      const int32_t out_rows = reduced_rows(level, P);
       const int64_t red = rows_used;
-      rows_used += 2 * static_cast<int64_t>(P);
+      rows_used += out_rows;
       red_sys[level].push_back(SysDesc{in_off, red, R, P, i, level});
       in_off = red;
-      R = 2 * P;
+      R = out_rows;
     }
   }
   if (rows_used > ctx->level_capacity) return BURGERS_E_NOMEM;   // sized at create for every path
@@ -258,8 +266,9 @@ int64_t level_rows_needed(const burgers_ctx* ctx) {
     for (int level = 0;; ++level) {
       if (level > 0 && R <= cap) break;
       const int64_t P = (R + chunk - 1) / chunk;
-      rows += 2 * P;
-      R = 2 * P;
+      const int64_t out_rows = reduced_rows(level, static_cast<int32_t>(P));
+      rows += out_rows;
+      R = out_rows;
     }
   }
   return rows;

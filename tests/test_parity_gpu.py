@@ -159,6 +159,20 @@ def test_c3_btcs_full_size():
     assert np.max(np.abs(inc - inc_ref)) <= 4 * 64 * np.finfo(np.float64).eps
 
 
+@pytest.mark.parametrize("n", [4096 * 4096 + 4096, 3 * 4096 * 16 + 40])
+def test_btcs_block_partition_beyond_one_level(n):
+    """Periodic systems whose block-partition level leaves more than one workgroup's worth of rows
+    (n = 2^24 + 4096: 8194 reduced rows, so one array level follows) and a multi-block system with a
+    ragged last block, 3 BTCS steps at 10x dt against the oracle."""
+    b = W.random_batch(91, 1, n, n, bc=W.BC_PERIODIC, scheme=W.BTCS, amplitude=2.0)
+    p = b.problems[0]
+    p.dt = 10 * oracle.cfl_dt(p.n, p.length, p.nu, p.bc, b.umax[0], 0.5)
+    announce(f"btcs block partition periodic n={n} 3 steps")
+    got = device_run(b, 3, "f64", how="step_btcs")
+    ref = oracle_run(b, 3, "f64", scheme=W.BTCS)
+    assert rel_err(got, ref) <= TOL_F64
+
+
 def test_repeatable_and_resumable():
     """Identical runs are bitwise identical (no races); run(n1) then run(n2) equals run(n1 + n2)."""
     batch = set_cfl_steps(W.random_batch(25, 20, 3, 20000, amplitude=2.0))
