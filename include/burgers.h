@@ -91,7 +91,9 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *                  3 multilevel: recursive partition across workgroups (any n).
  *   use_graph      1 replays the launch sequence of a stepping call from a captured HIP graph,
  *                  0 launches eagerly, -1 automatic.
- *   btcs_block     lanes per system of the on-chip BTCS solver (512 or 1024; 0 automatic).
+ *   btcs_block     lanes per system for BTCS systems of exactly 8192 rows (512 lanes of 16 rows or
+ *                  1024 of 8; 0 automatic = 512).  Other whole systems take the narrowest of 128, 256,
+ *                  512 or 1024 lanes that holds them at <= 8 rows per lane.
  * burgers_set_plan rejects values outside these ranges with BURGERS_E_INVALID.
  */
 typedef struct {
@@ -99,7 +101,7 @@ typedef struct {
   int32_t tblock_depth;
   int32_t btcs_path;
   int32_t use_graph;
-  int32_t btcs_block;      /* lanes per system of the on-chip BTCS solver: 512, 1024, or 0 = automatic */
+  int32_t btcs_block;      /* lanes for 8192-row BTCS systems: 512, 1024, or 0 = automatic */
   int32_t reserved[3];
 } burgers_plan;
 

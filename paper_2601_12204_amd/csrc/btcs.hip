@@ -52,6 +52,10 @@ __device__ __forceinline__ double recip(double x) {
 // Couplings below this fraction of a row's diagonal are below binary64 rounding of the solution.
 constexpr double kNegligible = 0x1p-60;
 
+// Row sources of the chunk elimination.  row() returns row k as assembled; boundary() then folds the
+// Dirichlet values into the reduced rows of the chunk that holds the first or last row of the system
+// (only level-0 systems of Dirichlet instances have such values; every other source has none).
+
 // Rows of a reduced system stored with unit diagonal.
 template <typename T>
 struct ArrayRows {
@@ -64,6 +68,27 @@ struct ArrayRows {
     ga = C[k];
     de = Dv[k];
   }
+  __device__ __forceinline__ void boundary(int, int, int, T&, T&, T&, T&) const {}
+};
+
+// Dirichlet values of a level-0 system: row 0 reads x_{-1} = a, row R-1 reads x_R = b.  In the reduced
+// rows, x_{-1} enters only the chunk's F row (coefficient AF) and x_R only its E row (coefficient CE),
+// so moving the known values to the right-hand side is DF -= AF a, AF = 0 and DE -= CE b, CE = 0.
+struct DirichletEnds {
+  double a, b;
+  bool dirichlet;
+  __device__ __forceinline__ void apply(int s, int m, int R, double& AF, double& DF, double& CE,
+                                        double& DE) const {
+    if (!dirichlet) return;
+    if (s == 0) {
+      DF = __builtin_fma(-AF, a, DF);
+      AF = 0.0;
+    }
+    if (s + m == R) {
+      DE = __builtin_fma(-CE, b, DE);
+      CE = 0.0;
+    }
+  }
 };
 
 // Rows of a level-0 system whose old values sit in LDS (staged coalesced from HBM); row k is held at
@@ -72,17 +97,16 @@ template <typename S>
 struct LdsRows {
   const S* st;
   int base;
-  double r, D, a, b;
-  bool dirichlet;
-  __device__ __forceinline__ void row(int, int k, int R, double& al, double& be, double& ga,
-                                      double& de) const {
+  double r, D;
+  DirichletEnds ends;
+  __device__ __forceinline__ void row(int, int k, int, double& al, double& be, double& ga, double& de) const {
     const double ui = static_cast<double>(st[padded(k - base)]);
     btcs_row(ui, r, D, al, be, ga);
     de = ui;
-    if (dirichlet) {
-      if (k == 0) { de = de - al * a; al = 0.0; }
-      if (k == R - 1) { de = de - ga * b; ga = 0.0; }
-    }
+  }
+  __device__ __forceinline__ void boundary(int s, int m, int R, double& AF, double& DF, double& CE,
+                                           double& DE) const {
+    ends.apply(s, m, R, AF, DF, CE, DE);
   }
 };
 
@@ -95,16 +119,16 @@ struct LdsDst {
 
 // Row k of a level-0 system from its old value ui (resident solver, where the values live in registers).
 struct ValueRows {
-  double r, D, a, b;
-  bool dirichlet;
-  __device__ __forceinline__ void row_value(double ui, int k, int R, double& al, double& be, double& ga,
+  double r, D;
+  DirichletEnds ends;
+  __device__ __forceinline__ void row_value(double ui, int, int, double& al, double& be, double& ga,
                                             double& de) const {
     btcs_row(ui, r, D, al, be, ga);
     de = ui;
-    if (dirichlet) {
-      if (k == 0) { de = de - al * a; al = 0.0; }
-      if (k == R - 1) { de = de - ga * b; ga = 0.0; }
-    }
+  }
+  __device__ __forceinline__ void boundary(int s, int m, int R, double& AF, double& DF, double& CE,
+                                           double& DE) const {
+    ends.apply(s, m, R, AF, DF, CE, DE);
   }
 };
 
@@ -136,10 +160,11 @@ __device__ __forceinline__ void chunk_eliminate(const Src& src, int s, int m, in
         ga[1] = cj * inv;
         de[1] = dj * inv;
       } else {
-        const T inv = recip(bj - aj * ga[j - 1]);
-        al[j] = -(aj * al[j - 1]) * inv;
+        const T inv = recip(__builtin_fma(-aj, ga[j - 1], bj));
+        const T ai = aj * inv;
+        al[j] = -(ai * al[j - 1]);
         ga[j] = cj * inv;
-        de[j] = (dj - aj * de[j - 1]) * inv;
+        de[j] = __builtin_fma(-ai, de[j - 1], dj * inv);
       }
       if (j == m - 1) {
         AE = al[j];
@@ -153,8 +178,8 @@ __device__ __forceinline__ void chunk_eliminate(const Src& src, int s, int m, in
   for (int j = M - 3; j >= 1; --j) {
     if (j <= m - 3) {
       const T g = ga[j];
-      de[j] = de[j] - g * de[j + 1];
-      al[j] = al[j] - g * al[j + 1];
+      de[j] = __builtin_fma(-g, de[j + 1], de[j]);
+      al[j] = __builtin_fma(-g, al[j + 1], al[j]);
       ga[j] = -(g * ga[j + 1]);
     }
   }
@@ -165,10 +190,12 @@ __device__ __forceinline__ void chunk_eliminate(const Src& src, int s, int m, in
     g1 = ga[1];
     d1 = de[1];
   }
-  const T inv0 = recip(b0 - c0 * a1);
+  const T inv0 = recip(__builtin_fma(-c0, a1, b0));
+  const T ci = c0 * inv0;
   AF = a0 * inv0;
-  CF = -(c0 * g1) * inv0;
-  DF = (d0 - c0 * d1) * inv0;
+  CF = -(ci * g1);
+  DF = __builtin_fma(-ci, d1, d0 * inv0);
+  src.boundary(s, m, R, AF, DF, CE, DE);
 }
 
 // Interior rows from the chunk's end values.
@@ -178,7 +205,7 @@ __device__ __forceinline__ void chunk_recover(const Dst& dst, int s, int m, cons
   dst.write(0, s, F);
 #pragma unroll
   for (int j = 1; j < M; ++j) {
-    if (j < m - 1) dst.write(j, s + j, de[j] - al[j] * F - ga[j] * E);
+    if (j < m - 1) dst.write(j, s + j, __builtin_fma(-ga[j], E, __builtin_fma(-al[j], F, de[j])));
     if (j == m - 1) dst.write(j, s + j, E);
   }
 }
@@ -191,7 +218,7 @@ __device__ __forceinline__ void chunk_recover_in_place(int m, const T (&al)[M], 
   de[0] = static_cast<T>(static_cast<S>(F));
 #pragma unroll
   for (int j = 1; j < M; ++j) {
-    if (j < m - 1) de[j] = static_cast<T>(static_cast<S>(de[j] - al[j] * F - ga[j] * E));
+    if (j < m - 1) de[j] = static_cast<T>(static_cast<S>(__builtin_fma(-ga[j], E, __builtin_fma(-al[j], F, de[j]))));
     if (j == m - 1) de[j] = static_cast<T>(static_cast<S>(E));
   }
 }
@@ -228,11 +255,11 @@ __device__ __forceinline__ void pcr_cyclic(T* sA, T* sC, T* sD, int R2) {
       if (i < R2) {
         const int im = (i - s) & (R2 - 1);
         const int ip = (i + s) & (R2 - 1);
-        const T a = sA[i], c = sC[i];
-        const T inv = recip((T(1) - a * sC[im]) - c * sA[ip]);
-        nA[h] = -(a * sA[im]) * inv;
-        nC[h] = -(c * sC[ip]) * inv;
-        nD[h] = ((sD[i] - a * sD[im]) - c * sD[ip]) * inv;
+        const T inv = recip(__builtin_fma(-sC[i], sA[ip], __builtin_fma(-sA[i], sC[im], T(1))));
+        const T a = sA[i] * inv, c = sC[i] * inv;
+        nA[h] = -(a * sA[im]);
+        nC[h] = -(c * sC[ip]);
+        nD[h] = __builtin_fma(-c, sD[ip], __builtin_fma(-a, sD[im], sD[i] * inv));
         live |= (__builtin_fabs(nA[h]) + __builtin_fabs(nC[h])) > kNegligible;
       }
     }
@@ -258,19 +285,44 @@ __device__ __forceinline__ void pcr_cyclic(T* sA, T* sC, T* sD, int R2) {
   __syncthreads();
 }
 
+// Coalesced copies of a block's rows between HBM and LDS: all loads are issued before the first LDS
+// store, so a wave has its whole share of the block in flight at once.
+template <typename S, int NT = kReduceBlock, int J = kRedChunk>
+__device__ __forceinline__ void stage_in(S* stage, const S* __restrict__ src, int cnt) {
+  S v[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = static_cast<int>(threadIdx.x) + j * NT;
+    v[j] = i < cnt ? src[i] : S(0);
+  }
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = static_cast<int>(threadIdx.x) + j * NT;
+    if (i < cnt) stage[padded(i)] = v[j];
+  }
+}
+
+template <typename S, int NT = kReduceBlock, int J = kRedChunk>
+__device__ __forceinline__ void stage_out(const S* stage, S* __restrict__ dst, int cnt) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = static_cast<int>(threadIdx.x) + j * NT;
+    if (i < cnt) dst[i] = stage[padded(i)];
+  }
+}
+
 // Whole-system solver: one workgroup per system.  Level-0 systems stage the old state through LDS
 // (coalesced loads), eliminate chunks from LDS, solve the reduced system by PCR in the same LDS, write
 // the new values back into the staging buffer and store them coalesced, with the Dirichlet boundary
 // nodes.  Reduced systems of the partition levels read (A, C, D) and write X in HBM directly.
-template <typename S, bool FromState, int NT, bool EXACT = false>
-__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
+template <typename S, bool FromState, int NT, int MC, bool EXACT = false>
+__global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, const S* __restrict__ u,
     S* __restrict__ out, const double* __restrict__ LA, const double* __restrict__ LC,
     const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
-  constexpr int MC = kWgRows / NT;
   constexpr int kPcrBytes = 3 * 2 * NT * static_cast<int>(sizeof(T));
-  constexpr int kStageBytes = FromState ? padded_size(kWgRows) * static_cast<int>(sizeof(S)) : 0;
+  constexpr int kStageBytes = FromState ? padded_size(NT * MC) * static_cast<int>(sizeof(S)) : 0;
   constexpr int kBytes = kStageBytes > kPcrBytes ? kStageBytes : kPcrBytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
   T* sA = reinterpret_cast<T*>(smem);
@@ -290,9 +342,8 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
   if constexpr (FromState) {
     d = inst[sys.inst];
     const bool dir = d.bc == kDirichlet;
-    const S* src = u + d.off + (dir ? 1 : 0);
-    for (int i = tid; i < R; i += NT) stage[padded(i)] = src[i];
-    ssrc = LdsRows<S>{stage, 0, d.r, d.D, d.a, d.b, dir};
+    stage_in<S, NT, MC>(stage, u + d.off + (dir ? 1 : 0), R);
+    ssrc = LdsRows<S>{stage, 0, d.r, d.D, DirichletEnds{d.a, d.b, dir}};
     sdst = LdsDst<S>{stage, 0};
     if (dir && tid == 0) {
       out[d.off] = static_cast<S>(d.a);
@@ -309,7 +360,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
       T al, be, ga, de;
       if constexpr (FromState) {
         ssrc.row(0, 0, 1, al, be, ga, de);
-        out[d.off + 1] = static_cast<S>(de / be);
+        out[d.off + 1] = static_cast<S>(((de - al * d.a) - ga * d.b) / be);
       } else {
         asrc.row(0, 0, 1, al, be, ga, de);
         adst.write(0, 0, de / be);
@@ -349,8 +400,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
     __syncthreads();                           // all ends read before the staging buffer is reused
     if (tid < P) chunk_recover<T, MC>(sdst, s, m, al, ga, de, F, E);
     __syncthreads();
-    S* dst = out + d.off + (d.bc == kDirichlet ? 1 : 0);
-    for (int i = tid; i < R; i += NT) dst[i] = stage[padded(i)];
+    stage_out<S, NT, MC>(stage, out + d.off + (d.bc == kDirichlet ? 1 : 0), R);
   } else {
     if (tid < P) chunk_recover<T, MC>(adst, s, m, al, ga, de, F, E);
   }
@@ -361,7 +411,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_wg_kernel(
 // state is rounded through S once per step as the per-step kernel's store would, so both solvers agree
 // bitwise.  The state buffer is read once and written once per launch (in place).
 template <typename S, int NT, int MC, bool EXACT = false>
-__global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_resident_kernel(
+__global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, S* __restrict__ u,
     int steps) {
   using T = double;
@@ -404,7 +454,7 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_resident_kernel(
     for (int j = 0; j < MC; ++j)
       if (j < m) de[j] = static_cast<T>(x[s + j]);
   }
-  const ValueRows src{d.r, d.D, d.a, d.b, dir};
+  const ValueRows src{d.r, d.D, DirichletEnds{d.a, d.b, dir}};
   for (int step = 0; step < steps; ++step) {
     T AF, CF, DF, AE, CE, DE;
     if (tid < P) {
@@ -429,114 +479,100 @@ __global__ __launch_bounds__(NT, NT == 512 ? 4 : 1) void btcs_resident_kernel(
   }
 }
 
-// Rows of a reduced system held in LDS with unit diagonal, row k at padded(k).
-template <typename T>
-struct LdsArrayRows {
-  const T* A;
-  const T* C;
-  const T* Dv;
-  __device__ __forceinline__ void row(int, int k, int, T& al, T& be, T& ga, T& de) const {
-    const int i = padded(k);
-    al = A[i];
-    be = T(1);
-    ga = C[i];
-    de = Dv[i];
-  }
-};
-
-// In-block reduction of the block partition kernels.  A workgroup's 256 chunk pairs form a segment of
-// at most 512 reduced rows whose first row couples to the previous block's last unknown and whose last
-// row couples to the next block's first unknown.  The segment is reduced by the same chunk elimination,
-// 16 rows per chunk, level by level (512 -> 64 -> 8 -> 2 rows), to the two rows that tie the block's
-// first and last unknowns to its neighbours.  Level l's rows sit at kLvlBase(l) of the level arrays.
-constexpr int kLvlLevels = 4;                   // rows: <= 512, <= 64, <= 8, 2
-__device__ __forceinline__ int lvl_base(int l) {
-  return l == 0 ? 0 : l == 1 ? padded_size(512) : l == 2 ? padded_size(512) + padded_size(64)
-                                                        : padded_size(512) + padded_size(64) + padded_size(8);
-}
-constexpr int kLvlSpan = padded_size(512) + padded_size(64) + padded_size(8) + padded_size(2);
-
-struct LvlArrays {
+// In-block reduction of the block partition kernels.  A workgroup's chunk pairs form a segment of
+// Rb <= 512 reduced rows (unit diagonal) whose first row couples to the previous block's last unknown L
+// and whose last row couples to the next block's first unknown Rt.  Those two couplings are moved into
+// two extra columns (P for L, Q for Rt), and PCR over the segment, with out-of-segment rows taken as
+// zero, removes every in-segment coupling, leaving
+//     x_i + P_i L + Q_i Rt = D_i        (the segment's solution as a function of its two neighbours).
+// Each sweep combines row i with rows i - s and i + s and renormalises; the loop stops early once all
+// remaining in-segment couplings are negligible.  Arrays are indexed by row, five of them in LDS.
+struct SpikeRows {
   double* A;
   double* C;
   double* D;
-  double* X;
+  double* P;
+  double* Q;
 };
+constexpr int kSpikeRows = 2 * kReduceBlock;
 
-__device__ __forceinline__ int lvl_chunks(int R) { return (R + kRedChunk - 1) / kRedChunk; }
-
-// One level forward: rows of level l (R of them) -> 2 * lvl_chunks(R) rows of level l + 1.
-__device__ __forceinline__ int lvl_reduce(const LvlArrays& L, int l, int R) {
+__device__ __forceinline__ void spike_pcr(const SpikeRows& S, int Rb) {
   using T = double;
-  const int P = lvl_chunks(R);
   const int tid = threadIdx.x;
-  if (tid < P) {
-    int s, m;
-    chunk_span(tid, R, P, s, m);
-    const int b = lvl_base(l);
-    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-    T AF, CF, DF, AE, CE, DE;
-    chunk_eliminate<T, kRedChunk>(LdsArrayRows<T>{L.A + b, L.C + b, L.D + b}, s, m, R, al, ga, de, AF, CF, DF,
-                                  AE, CE, DE);
-    const int o = lvl_base(l + 1);
-    L.A[o + padded(2 * tid)] = AF; L.C[o + padded(2 * tid)] = CF; L.D[o + padded(2 * tid)] = DF;
-    L.A[o + padded(2 * tid + 1)] = AE; L.C[o + padded(2 * tid + 1)] = CE; L.D[o + padded(2 * tid + 1)] = DE;
-  }
-  __syncthreads();
-  return 2 * P;
-}
-
-// One level backward: level l's unknowns from level l + 1's solution (re-eliminating the chunks).
-__device__ __forceinline__ void lvl_recover(const LvlArrays& L, int l, int R) {
-  using T = double;
-  const int P = lvl_chunks(R);
-  const int tid = threadIdx.x;
-  if (tid < P) {
-    int s, m;
-    chunk_span(tid, R, P, s, m);
-    const int b = lvl_base(l);
-    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-    T AF, CF, DF, AE, CE, DE;
-    chunk_eliminate<T, kRedChunk>(LdsArrayRows<T>{L.A + b, L.C + b, L.D + b}, s, m, R, al, ga, de, AF, CF, DF,
-                                  AE, CE, DE);
-    const int o = lvl_base(l + 1);
-    const T F = L.X[o + padded(2 * tid)];
-    const T E = L.X[o + padded(2 * tid + 1)];
-    T* x = L.X + b;
-    x[padded(s)] = F;
+  bool done = false;
+  for (int s = 1; s < Rb && !done; s <<= 1) {
+    T nA[2], nC[2], nD[2], nP[2], nQ[2];
+    int live = 0;
 #pragma unroll
-    for (int j = 1; j < kRedChunk; ++j) {
-      if (j < m - 1) x[padded(s + j)] = de[j] - al[j] * F - ga[j] * E;
-      if (j == m - 1) x[padded(s + j)] = E;
+    for (int h = 0; h < 2; ++h) {
+      const int i = tid + h * kReduceBlock;
+      if (i < Rb) {
+        const int im = i - s, ip = i + s;
+        const T Am = im >= 0 ? S.A[im] : T(0), Cm = im >= 0 ? S.C[im] : T(0);
+        const T Dm = im >= 0 ? S.D[im] : T(0), Pm = im >= 0 ? S.P[im] : T(0), Qm = im >= 0 ? S.Q[im] : T(0);
+        const T Ap = ip < Rb ? S.A[ip] : T(0), Cp = ip < Rb ? S.C[ip] : T(0);
+        const T Dp = ip < Rb ? S.D[ip] : T(0), Pp = ip < Rb ? S.P[ip] : T(0), Qp = ip < Rb ? S.Q[ip] : T(0);
+        const T inv = recip(__builtin_fma(-S.C[i], Ap, __builtin_fma(-S.A[i], Cm, T(1))));
+        const T a = S.A[i] * inv, c = S.C[i] * inv;
+        nA[h] = -(a * Am);
+        nC[h] = -(c * Cp);
+        nD[h] = __builtin_fma(-c, Dp, __builtin_fma(-a, Dm, S.D[i] * inv));
+        nP[h] = __builtin_fma(-c, Pp, __builtin_fma(-a, Pm, S.P[i] * inv));
+        nQ[h] = __builtin_fma(-c, Qp, __builtin_fma(-a, Qm, S.Q[i] * inv));
+        live |= (__builtin_fabs(nA[h]) + __builtin_fabs(nC[h])) > kNegligible;
+      }
     }
-  }
-  __syncthreads();
-}
-
-// Coalesced copies of a block's rows between HBM and LDS: all loads are issued before the first LDS
-// store, so a wave has its whole share of the block in flight at once.
-template <typename S>
-__device__ __forceinline__ void stage_in(S* stage, const S* __restrict__ src, int cnt) {
-  S v[kRedChunk];
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kRedChunk; ++j) {
-    const int i = static_cast<int>(threadIdx.x) + j * kReduceBlock;
-    v[j] = i < cnt ? src[i] : S(0);
-  }
-#pragma unroll
-  for (int j = 0; j < kRedChunk; ++j) {
-    const int i = static_cast<int>(threadIdx.x) + j * kReduceBlock;
-    if (i < cnt) stage[padded(i)] = v[j];
+    for (int h = 0; h < 2; ++h) {
+      const int i = tid + h * kReduceBlock;
+      if (i < Rb) {
+        S.A[i] = nA[h];
+        S.C[i] = nC[h];
+        S.D[i] = nD[h];
+        S.P[i] = nP[h];
+        S.Q[i] = nQ[h];
+      }
+    }
+    done = !__syncthreads_or(live);
   }
 }
 
-template <typename S>
-__device__ __forceinline__ void stage_out(const S* stage, S* __restrict__ dst, int cnt) {
-#pragma unroll
-  for (int j = 0; j < kRedChunk; ++j) {
-    const int i = static_cast<int>(threadIdx.x) + j * kReduceBlock;
-    if (i < cnt) dst[i] = stage[padded(i)];
-  }
+// Chunk pair t of the block into the spike rows (row 2t: F row, row 2t + 1: E row); the segment's outer
+// couplings go to the P and Q columns.
+__device__ __forceinline__ void spike_put(const SpikeRows& S, int t, int Rb, double AF, double CF, double DF,
+                                          double AE, double CE, double DE) {
+  const int f = 2 * t, e = 2 * t + 1;
+  S.A[f] = f == 0 ? 0.0 : AF;
+  S.P[f] = f == 0 ? AF : 0.0;
+  S.C[f] = CF;
+  S.Q[f] = 0.0;
+  S.D[f] = DF;
+  S.A[e] = AE;
+  S.P[e] = 0.0;
+  S.C[e] = e == Rb - 1 ? 0.0 : CE;
+  S.Q[e] = e == Rb - 1 ? CE : 0.0;
+  S.D[e] = DE;
+}
+
+// The block's two rows in the partition form (tridiagonal over first/last unknowns of all blocks),
+// from the end rows of the spike form:  x_0 + P_0 L + Q_0 Rt = D_0,  x_e + P_e L + Q_e Rt = D_e.
+//   F row:  (P_0 - k P_e) L + x_0 - k x_e = D_0 - k D_e,        k = Q_0 / Q_e
+//   E row:  -h x_0 + x_e + (Q_e - h Q_0) Rt = D_e - h D_0,     h = P_e / P_0
+// A block with no left (right) neighbour coupling has P = 0 (Q = 0) throughout; then h = 0 (k = 0).
+__device__ __forceinline__ void spike_ends(const SpikeRows& S, int Rb, double& AF, double& CF, double& DF,
+                                           double& AE, double& CE, double& DE) {
+  const int e = Rb - 1;
+  const double P0 = S.P[0], Q0 = S.Q[0], D0 = S.D[0];
+  const double Pe = S.P[e], Qe = S.Q[e], De = S.D[e];
+  const double k = Qe != 0.0 ? Q0 / Qe : 0.0;
+  const double h = P0 != 0.0 ? Pe / P0 : 0.0;
+  AF = __builtin_fma(-k, Pe, P0);
+  CF = -k;
+  DF = __builtin_fma(-k, De, D0);
+  AE = -h;
+  CE = __builtin_fma(-h, Q0, Qe);
+  DE = __builtin_fma(-h, D0, De);
 }
 
 // Rows [rs, re) of the chunks a partition workgroup owns: chunk k spans chunk_span(k).
@@ -594,8 +630,8 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_array_backsub_kernel(
 }
 
 // Block partition, forward half (level 0 of a long system): a workgroup stages its 256 chunks' rows
-// (<= 4096) through LDS, eliminates every chunk, reduces the block's chunk pairs in LDS down to two rows
-// and stores those at red_off + 2 * (block index within the system).
+// (<= 4096) through LDS, eliminates every chunk, reduces the block's chunk pairs to the spike form by
+// PCR and stores the block's two partition rows at red_off + 2 * (block index within the system).
 template <typename S>
 __global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
@@ -603,18 +639,18 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
     double* __restrict__ LC, double* __restrict__ LD) {
   using T = double;
   constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
-  constexpr int kLvlBytes = 3 * kLvlSpan * static_cast<int>(sizeof(T));
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kStageBytes > kLvlBytes ? kStageBytes : kLvlBytes];
+  constexpr int kSpikeBytes = 5 * kSpikeRows * static_cast<int>(sizeof(T));
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kStageBytes > kSpikeBytes ? kStageBytes : kSpikeBytes];
   S* stage = reinterpret_cast<S*>(smem);
-  const LvlArrays L{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + kLvlSpan,
-                    reinterpret_cast<T*>(smem) + 2 * kLvlSpan, nullptr};
+  T* sp = reinterpret_cast<T*>(smem);
+  const SpikeRows SR{sp, sp + kSpikeRows, sp + 2 * kSpikeRows, sp + 3 * kSpikeRows, sp + 4 * kSpikeRows};
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
   const int tid = threadIdx.x;
-  const int k = cb.chunk0 + tid;
   const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
+  const int Rb = 2 * Pb;
   int rs, re;
   block_rows(sys, cb.chunk0, rs, re);
   stage_in(stage, u + d.off + (dir ? 1 : 0) + rs, re - rs);
@@ -622,84 +658,77 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
   T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
   if (tid < Pb) {
     int s, m;
-    chunk_span(k, sys.rows, sys.chunks, s, m);
+    chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
     T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, d.a, d.b, dir}, s, m, sys.rows, al, ga, de,
-                                  AF, CF, DF, AE, CE, DE);
+    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
+                                  sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
-  __syncthreads();                             // every chunk read before the level arrays overlay the stage
-  if (tid < Pb) {
-    L.A[padded(2 * tid)] = AF; L.C[padded(2 * tid)] = CF; L.D[padded(2 * tid)] = DF;
-    L.A[padded(2 * tid + 1)] = AE; L.C[padded(2 * tid + 1)] = CE; L.D[padded(2 * tid + 1)] = DE;
-  }
+  __syncthreads();                             // every chunk read before the spike rows overlay the stage
+  if (tid < Pb) spike_put(SR, tid, Rb, AF, CF, DF, AE, CE, DE);
   __syncthreads();
-  int R = 2 * Pb, l = 0;
-  while (R > 2) R = lvl_reduce(L, l++, R);
-  if (tid < 2) {
-    const int i = lvl_base(l) + padded(tid);
-    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock) + tid;
-    LA[o] = L.A[i];
-    LC[o] = L.C[i];
-    LD[o] = L.D[i];
+  spike_pcr(SR, Rb);
+  if (tid == 0) {
+    spike_ends(SR, Rb, AF, CF, DF, AE, CE, DE);
+    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock);
+    LA[o] = AF; LC[o] = CF; LD[o] = DF;
+    LA[o + 1] = AE; LC[o + 1] = CE; LD[o + 1] = DE;
   }
 }
 
-// Block partition, backward half: the block's first and last unknowns come from the solved reduced
-// system; the block re-stages its rows, repeats the forward reduction, recovers the in-block levels top
-// down, then every chunk and stores the new state coalesced (with the Dirichlet boundary nodes).
+// Block partition, backward half: the block repeats the forward reduction (keeping its chunks'
+// elimination in registers), takes its neighbours' solved end unknowns L = E of the previous block and
+// Rt = F of the next block (cyclically for periodic systems), evaluates x_i = D_i - P_i L - Q_i Rt for
+// its chunk ends, recovers every chunk and stores the new state coalesced (with the Dirichlet nodes).
 template <typename S>
 __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
     const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, S* __restrict__ out,
     const double* __restrict__ LX) {
   using T = double;
-  __shared__ S stage[padded_size(kRedRows)];
-  __shared__ T lvl[4 * kLvlSpan];
-  const LvlArrays L{lvl, lvl + kLvlSpan, lvl + 2 * kLvlSpan, lvl + 3 * kLvlSpan};
+  constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
+  constexpr int kSpikeBytes = 5 * kSpikeRows * static_cast<int>(sizeof(T));
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kStageBytes > kSpikeBytes ? kStageBytes : kSpikeBytes];
+  S* stage = reinterpret_cast<S*>(smem);
+  T* sp = reinterpret_cast<T*>(smem);
+  const SpikeRows SR{sp, sp + kSpikeRows, sp + 2 * kSpikeRows, sp + 3 * kSpikeRows, sp + 4 * kSpikeRows};
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
   const int tid = threadIdx.x;
-  const int k = cb.chunk0 + tid;
   const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
+  const int Rb = 2 * Pb;
+  const int blk = cb.chunk0 / kReduceBlock;
+  const int nblk = (sys.chunks + kReduceBlock - 1) / kReduceBlock;
   int rs, re;
   block_rows(sys, cb.chunk0, rs, re);
-  const S* src = u + d.off + (dir ? 1 : 0) + rs;
-  stage_in(stage, src, re - rs);
+  stage_in(stage, u + d.off + (dir ? 1 : 0) + rs, re - rs);
   __syncthreads();
-  const LdsRows<S> rows{stage, rs, d.r, d.D, d.a, d.b, dir};
   int s = 0, m = 0;
+  T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
+  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
   if (tid < Pb) {
-    chunk_span(k, sys.rows, sys.chunks, s, m);
-    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-    T AF, CF, DF, AE, CE, DE;
-    chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-    L.A[padded(2 * tid)] = AF; L.C[padded(2 * tid)] = CF; L.D[padded(2 * tid)] = DF;
-    L.A[padded(2 * tid + 1)] = AE; L.C[padded(2 * tid + 1)] = CE; L.D[padded(2 * tid + 1)] = DE;
+    chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
+    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
+                                  sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
   __syncthreads();
-  int Rl[kLvlLevels];
-  int R = 2 * Pb, l = 0;
-  Rl[0] = R;
-  while (R > 2) {
-    R = lvl_reduce(L, l, R);
-    Rl[++l] = R;
-  }
-  if (tid < 2) {
-    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock) + tid;
-    L.X[lvl_base(l) + padded(tid)] = LX[o];
-  }
+  if (tid < Pb) spike_put(SR, tid, Rb, AF, CF, DF, AE, CE, DE);
   __syncthreads();
-  for (int j = l - 1; j >= 0; --j) lvl_recover(L, j, Rl[j]);
+  spike_pcr(SR, Rb);
+  // neighbours' end unknowns; a Dirichlet system's outer blocks have P = 0 or Q = 0 and ignore them
+  const T* X = LX + sys.red_off;
+  const bool periodic = !dir;
+  const T L = blk > 0 ? X[2 * blk - 1] : (periodic ? X[2 * nblk - 1] : T(0));
+  const T Rt = blk + 1 < nblk ? X[2 * blk + 2] : (periodic ? X[0] : T(0));
+  T F = T(0), E = T(0);
   if (tid < Pb) {
-    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-    T AF, CF, DF, AE, CE, DE;
-    chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-    // a chunk's rows depend only on its own old values, so it may overwrite them in place
-    chunk_recover<T, kRedChunk>(LdsDst<S>{stage, rs}, s, m, al, ga, de, L.X[padded(2 * tid)],
-                                L.X[padded(2 * tid + 1)]);
+    const int f = 2 * tid, e = 2 * tid + 1;
+    F = __builtin_fma(-SR.Q[f], Rt, __builtin_fma(-SR.P[f], L, SR.D[f]));
+    E = __builtin_fma(-SR.Q[e], Rt, __builtin_fma(-SR.P[e], L, SR.D[e]));
   }
+  __syncthreads();                             // spike rows read before the stage is rewritten
+  if (tid < Pb) chunk_recover<T, kRedChunk>(LdsDst<S>{stage, rs}, s, m, al, ga, de, F, E);
   __syncthreads();
   stage_out(stage, out + d.off + (dir ? 1 : 0) + rs, re - rs);
   if (dir && tid == 0) {
@@ -735,21 +764,30 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   for (int l = L - 1; l >= 1; --l) {
     const auto& lv = plan.levels[l];
     if (lv.n_wg) {
-      btcs_wg_kernel<S, false, kWgThreads><<<lv.n_wg, kWgThreads, 0, st>>>(inst, lv.wg->as<SysDesc>(), u,
-                                                                           out, LA, LC, LD, LX);
+      btcs_wg_kernel<S, false, kWgThreads, kWgChunk><<<lv.n_wg, kWgThreads, 0, st>>>(
+          inst, lv.wg->as<SysDesc>(), u, out, LA, LC, LD, LX);
     }
     if (lv.n_blocks) {
       btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
                                                                       lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);
     }
   }
-  if (plan.n_wg_state) {
-    if (plan.threads == 1024) {
-      btcs_wg_kernel<S, true, 1024><<<plan.n_wg_state, 1024, 0, st>>>(
-          inst, plan.wg_state->as<SysDesc>(), u, out, LA, LC, LD, LX);
-    } else {
-      btcs_wg_kernel<S, true, kWgThreads><<<plan.n_wg_state, kWgThreads, 0, st>>>(
-          inst, plan.wg_state->as<SysDesc>(), u, out, LA, LC, LD, LX);
+  for (const WgGroup& g : plan.wg_state) {
+    if (!g.n) continue;
+    const SysDesc* sys = g.sys->as<SysDesc>();
+    const unsigned n = static_cast<unsigned>(g.n);
+    if (g.shape.exact) {
+      if (g.shape.lanes == 1024)
+        btcs_wg_kernel<S, true, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX);
+      else
+        btcs_wg_kernel<S, true, 512, 16, true><<<n, 512, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX);
+      continue;
+    }
+    switch (g.shape.lanes) {
+      case 128: btcs_wg_kernel<S, true, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
+      case 256: btcs_wg_kernel<S, true, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
+      case 512: btcs_wg_kernel<S, true, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
+      default: btcs_wg_kernel<S, true, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
     }
   }
   if (L > 0 && plan.levels[0].n_blocks) {
@@ -762,30 +800,42 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
 
 }  // namespace
 
-template <typename S, int NT>
-void resident_launch(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u, int steps,
-                     bool exact) {
-  if (exact) {
-    btcs_resident_kernel<S, NT, kWgRows / NT, true><<<static_cast<unsigned>(n_sys), NT, 0, ctx->stream>>>(
-        ctx->inst.as<InstDesc>(), systems, static_cast<S*>(u), steps);
-  } else {
-    btcs_resident_kernel<S, NT, kWgRows / NT><<<static_cast<unsigned>(n_sys), NT, 0, ctx->stream>>>(
-        ctx->inst.as<InstDesc>(), systems, static_cast<S*>(u), steps);
+template <typename S>
+void resident_launch(const burgers_ctx* ctx, const WgGroup& g, S* u, int steps) {
+  const InstDesc* inst = ctx->inst.as<InstDesc>();
+  const SysDesc* sys = g.sys->as<SysDesc>();
+  const unsigned n = static_cast<unsigned>(g.n);
+  hipStream_t st = ctx->stream;
+  if (g.shape.exact) {
+    if (g.shape.lanes == 1024)
+      btcs_resident_kernel<S, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, steps);
+    else
+      btcs_resident_kernel<S, 512, 16, true><<<n, 512, 0, st>>>(inst, sys, u, steps);
+    return;
+  }
+  switch (g.shape.lanes) {
+    case 128: btcs_resident_kernel<S, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, steps); break;
+    case 256: btcs_resident_kernel<S, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, steps); break;
+    case 512: btcs_resident_kernel<S, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, steps); break;
+    default: btcs_resident_kernel<S, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, steps); break;
   }
 }
 
-hipError_t launch_btcs_resident(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u,
-                                int steps, int threads, bool exact) {
-  if (n_sys <= 0 || steps <= 0) return hipSuccess;
-  const bool f64 = ctx->dtype == BURGERS_F64;
-  if (threads == 512) {
-    if (f64) resident_launch<double, 512>(ctx, systems, n_sys, u, steps, exact);
-    else resident_launch<float, 512>(ctx, systems, n_sys, u, steps, exact);
-  } else {
-    if (f64) resident_launch<double, 1024>(ctx, systems, n_sys, u, steps, exact);
-    else resident_launch<float, 1024>(ctx, systems, n_sys, u, steps, exact);
-  }
+hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, void* u, int steps) {
+  if (group.n <= 0 || steps <= 0) return hipSuccess;
+  if (ctx->dtype == BURGERS_F64) resident_launch<double>(ctx, group, static_cast<double*>(u), steps);
+  else resident_launch<float>(ctx, group, static_cast<float*>(u), steps);
   return hipGetLastError();
+}
+
+// Width class of a system of up to 8192 rows.  A system of exactly 8192 rows runs the exact kernels
+// (`threads` = 512 lanes of 16 rows, or 1024 of 8); any other size takes the narrowest workgroup whose
+// lanes hold at most 8 rows each, so ragged chunks never need more than 8 registers per row array.
+WidthClass btcs_width_class(int rows, int threads) {
+  if (rows == kWgRows) return threads == 1024 ? WidthClass{1024, 8, true} : WidthClass{512, 16, true};
+  int lanes = 128;
+  while (lanes * 8 < rows) lanes *= 2;
+  return WidthClass{lanes, 8, false};
 }
 
 // Chunk count of the whole-system and on-chip solvers with `threads` lanes: the largest power of two P <= threads with
@@ -825,7 +875,7 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
   for (int l = L - 1; l >= 0; --l) {
     const auto& lv = plan.levels[l];
     if (lv.n_wg)
-      btcs_wg_kernel<double, false, kWgThreads><<<lv.n_wg, kWgThreads, 0, st>>>(
+      btcs_wg_kernel<double, false, kWgThreads, kWgChunk><<<lv.n_wg, kWgThreads, 0, st>>>(
           inst, lv.wg->as<SysDesc>(), none, none_out, LA, LC, LD, LX);
     if (lv.n_blocks)
       btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),

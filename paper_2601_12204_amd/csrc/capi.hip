@@ -180,7 +180,13 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   plan->threads = threads;
   const int cap = burgers::btcs_wg_capacity();
   const int chunk = burgers::btcs_reduce_chunk();
-  std::vector<SysDesc> wg_state, resident, resident_exact;
+  // whole-system systems grouped by width class (lanes, chunk, exact)
+  std::map<std::tuple<int, int, bool>, std::vector<SysDesc>> wg_state, resident;
+  auto whole = [&](std::map<std::tuple<int, int, bool>, std::vector<SysDesc>>& groups, int32_t rows, int32_t i) {
+    const burgers::WidthClass w = burgers::btcs_width_class(rows, threads);
+    groups[std::make_tuple(w.lanes, w.chunk, w.exact)].push_back(
+        SysDesc{0, -1, rows, burgers::btcs_chunks(rows, w.lanes), i, 0});
+  };
   std::vector<int32_t> stepped;
   std::vector<std::vector<SysDesc>> red_sys, wg_sys;
   int64_t rows_used = 0;
@@ -190,13 +196,13 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     const bool fits = R0 <= cap;
     if (want == 2 && !fits) return BURGERS_E_UNSUPPORTED;
     if ((want == 0 || want == 2) && fits) {
-      (R0 == cap ? resident_exact : resident).push_back(SysDesc{0, -1, R0, burgers::btcs_chunks(R0, threads), i, 0});
+      whole(resident, R0, i);
       continue;
     }
     stepped.push_back(i);
     const bool partition = want == 3 ? R0 >= 32 : !fits;
     if (!partition) {
-      wg_state.push_back(SysDesc{0, -1, R0, burgers::btcs_chunks(R0, threads), i, 0});
+      whole(wg_state, R0, i);
       continue;
     }
     int32_t R = R0;
@@ -222,17 +228,24 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   if (rows_used > ctx->level_capacity) return BURGERS_E_NOMEM;   // sized at create for every path
   plan->level_rows = rows_used;
   hipError_t e;
-  plan->n_wg_state = static_cast<int32_t>(wg_state.size());
-  plan->n_resident = static_cast<int32_t>(resident.size());
-  plan->n_resident_exact = static_cast<int32_t>(resident_exact.size());
-  plan->wg_state = std::make_unique<DevBuf>();
-  plan->resident = std::make_unique<DevBuf>();
-  plan->resident_exact = std::make_unique<DevBuf>();
+  auto upload_groups = [&](std::map<std::tuple<int, int, bool>, std::vector<SysDesc>>& groups,
+                           std::vector<burgers::WgGroup>& out) -> hipError_t {
+    for (auto& kv : groups) {
+      burgers::WgGroup g;
+      g.shape = burgers::WidthClass{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first)};
+      g.sys = std::make_unique<DevBuf>();
+      g.n = static_cast<int32_t>(kv.second.size());
+      hipError_t err = upload_on(ctx->stream, *g.sys, kv.second);
+      if (err != hipSuccess) return err;
+      out.push_back(std::move(g));
+    }
+    return hipSuccess;
+  };
   plan->copy = std::make_unique<DevBuf>();
   auto ct = stream_tiles(ctx, stepped);
   plan->n_copy = static_cast<int64_t>(ct.size());
-  if ((e = upload_on(ctx->stream, *plan->wg_state, wg_state)) != hipSuccess || (e = upload_on(ctx->stream, *plan->resident, resident)) != hipSuccess ||
-      (e = upload_on(ctx->stream, *plan->resident_exact, resident_exact)) != hipSuccess ||
+  if ((e = upload_groups(wg_state, plan->wg_state)) != hipSuccess ||
+      (e = upload_groups(resident, plan->resident)) != hipSuccess ||
       (e = upload_on(ctx->stream, *plan->copy, ct)) != hipSuccess)
     return from_hip(e);
   plan->levels.resize(red_sys.size());
@@ -320,11 +333,8 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
   hipError_t e = hipSuccess;
   for (int64_t done = 0; done < nsteps;) {   // on-chip systems, in place
     const int k = static_cast<int>(std::min<int64_t>(nsteps - done, int64_t{1} << 30));
-    if ((e = burgers::launch_btcs_resident(ctx, pl.resident_exact->as<SysDesc>(), pl.n_resident_exact, u, k,
-                                           pl.threads, true)) != hipSuccess ||
-        (e = burgers::launch_btcs_resident(ctx, pl.resident->as<SysDesc>(), pl.n_resident, u, k, pl.threads,
-                                           false)) != hipSuccess)
-      return e;
+    for (const burgers::WgGroup& g : pl.resident)
+      if ((e = burgers::launch_btcs_resident(ctx, g, u, k)) != hipSuccess) return e;
     done += k;
   }
   if (pl.n_copy == 0) return e;

@@ -113,18 +113,29 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(ptr); }
 };
 
+// Shape of the workgroup that solves a system of up to 8192 rows whole: `lanes` threads with chunks of
+// at most `chunk` rows; `exact` when the system has exactly lanes x chunk rows (no ragged chunks).
+struct WidthClass {
+  int lanes = 0;
+  int chunk = 0;
+  bool exact = false;
+};
+
+// Systems of one width class, one workgroup each.
+struct WgGroup {
+  WidthClass shape;
+  std::unique_ptr<DevBuf> sys;               // SysDesc[]
+  int32_t n = 0;
+};
+
 // Launch list of the BTCS solve for a set of instances, built once per context and set.
 struct BtcsPlan {
   int path = 0;                              // 0 automatic, 1 per-step, 2 resident, 3 partition levels
-  int threads = 0;                           // lanes per system of the on-chip solver (512 or 1024)
-  // systems kept on chip for all steps of a launch (in place)
-  std::unique_ptr<DevBuf> resident, resident_exact;   // SysDesc[]; exact: rows == 8192
-  int32_t n_resident = 0, n_resident_exact = 0;
+  int threads = 0;                           // lanes for systems of exactly 8192 rows (512 or 1024)
+  std::vector<WgGroup> resident;             // kept on chip for all steps of a launch (in place)
   std::unique_ptr<DevBuf> copy;              // Tile[] of the instances stepped through HBM (copy-back)
   int64_t n_copy = 0;
-  // small systems solved whole by one workgroup each, straight from and to the state
-  std::unique_ptr<DevBuf> wg_state;          // SysDesc[]
-  int32_t n_wg_state = 0;
+  std::vector<WgGroup> wg_state;             // solved whole per step, straight from and to the state
   // partition hierarchy for the long systems
   struct Level {
     std::unique_ptr<DevBuf> sys;             // SysDesc[] of the systems reduced at this level
@@ -223,8 +234,8 @@ int btcs_wg_chunks(int rows);           // chunk count the workgroup solver uses
 int btcs_reduce_chunk();                // target rows per chunk in the partition levels
 constexpr int kReduceBlock = 256;       // chunks per workgroup in the partition kernels
 hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out);
-hipError_t launch_btcs_resident(const burgers_ctx* ctx, const SysDesc* systems, int64_t n_sys, void* u,
-                                int steps, int threads, bool exact);
+hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, void* u, int steps);
+WidthClass btcs_width_class(int rows, int threads);
 int btcs_chunks(int rows, int threads);
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
                               double* LD, double* LX);

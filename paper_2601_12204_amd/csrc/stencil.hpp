@@ -27,7 +27,7 @@ __device__ __forceinline__ void btcs_row(T ui, T r, T D, T& sub, T& diag, T& sup
   const T c = r * ui;
   const T cpos = c > T(0) ? c : T(0);
   const T cneg = c < T(0) ? c : T(0);
-  const T cabs = c < T(0) ? -c : c;
+  const T cabs = __builtin_fabs(c);
   sub = -(D + cpos);
   diag = (T(1) + T(2) * D) + cabs;
   sup = cneg - D;
