@@ -144,7 +144,7 @@ def bench_c1_latency(B, torch, solves=200):
     return out
 
 
-def bench_c3(B, torch, n_exp=1024, n_btcs=32):
+def bench_c3(B, torch, n_exp=1024, n_btcs=128):
     import workloads as W
     b = W.c3_problem()
     p = b.problems[0]

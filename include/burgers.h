@@ -85,7 +85,7 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *   explicit_path  1 stream: one step per pass over HBM;
  *                  2 resident: a whole instance held on chip for many steps (n <= resident limit);
  *                  3 tiled: temporal blocking, tblock_depth steps per pass over HBM tiles.
- *   tblock_depth   steps per HBM pass for path 3 (1..32), 0 = automatic.
+ *   tblock_depth   steps per HBM pass of temporal blocking (1..512), 0 = automatic (128).
  *   btcs_path      1 workgroup: one workgroup solves one system per step (n <= workgroup limit);
  *                  2 resident: one workgroup per system for many steps;
  *                  3 multilevel: recursive partition across workgroups (any n).

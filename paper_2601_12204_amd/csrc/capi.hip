@@ -86,7 +86,10 @@ hipError_t ensure_copy(burgers_ctx* ctx, int set) {
   return hipSuccess;
 }
 
-constexpr int kDefaultDepth = 16;
+// Steps per launch of the explicit windows.  Each launch moves a window through HBM once (load and
+// store) and recomputes 2 T halo nodes of its 8192 per step; T = 128 balances the two (3% halo work).
+constexpr int kDefaultDepth = 128;
+constexpr int kMaxDepth = 512;
 
 // Explicit launch plan of one subset under the context's forced path (0 = automatic).
 //   path 1: streaming kernel, one step per launch.
@@ -680,7 +683,7 @@ burgers_status burgers_autotune(burgers_ctx* ctx, const void* u, int64_t explici
   std::vector<std::pair<int, int>> exp_opts = {{0, 0}};            // (path, depth)
   if (has_exp) {
     exp_opts.clear();
-    if (long_exp) for (int d : {4, 8, 16, 32}) exp_opts.push_back({0, d});
+    if (long_exp) for (int d : {32, 64, 128, 256}) exp_opts.push_back({0, d});
     else exp_opts.push_back({0, 0});
     exp_opts.push_back({1, 0});
   }
@@ -819,7 +822,7 @@ burgers_status burgers_get_plan(const burgers_ctx* ctx, burgers_plan* out) {
 burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan) {
   if (!ctx || !plan) return BURGERS_E_INVALID;
   if (plan->explicit_path < 0 || plan->explicit_path > 3 || plan->btcs_path < 0 || plan->btcs_path > 3 ||
-      plan->tblock_depth < 0 || plan->tblock_depth > 32 || plan->use_graph < -1 || plan->use_graph > 1 ||
+      plan->tblock_depth < 0 || plan->tblock_depth > kMaxDepth || plan->use_graph < -1 || plan->use_graph > 1 ||
       (plan->btcs_block != 0 && plan->btcs_block != 512 && plan->btcs_block != 1024))
     return BURGERS_E_INVALID;
   const bool explicit_changed = plan->explicit_path != ctx->plan.explicit_path ||

@@ -204,7 +204,7 @@ def _ragged_long_batch(seed):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("path,depth", [(1, 0), (3, 1), (3, 5), (3, 16), (3, 32), (0, 0), (0, 7)])
+@pytest.mark.parametrize("path,depth", [(1, 0), (3, 1), (3, 5), (3, 16), (3, 32), (3, 200), (0, 0), (0, 7), (0, 300)])
 def test_explicit_paths_bitwise(dtype, path, depth):
     """Streaming, whole-instance and windowed temporal blocking at several depths, including step counts
     that are not multiples of the depth, are all bitwise equal to the oracle."""
@@ -212,6 +212,17 @@ def test_explicit_paths_bitwise(dtype, path, depth):
     announce(f"explicit path={path} depth={depth} {dtype} 37 steps")
     got = device_run(batch, 37, dtype, how="step_explicit", plan=dict(explicit_path=path, tblock_depth=depth))
     ref = oracle_run(batch, 37, dtype, scheme=W.EXPLICIT)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("depth", [200, 0])
+def test_explicit_deep_windows_bitwise(depth):
+    """Deep temporal blocking (200 steps per launch, and the default) over 450 steps: several launches
+    with a partial last one, windows whose halos span hundreds of nodes, bitwise equal to the oracle."""
+    batch = _ragged_long_batch(47)
+    announce(f"explicit deep windows depth={depth} 450 steps")
+    got = device_run(batch, 450, "f64", how="step_explicit", plan=dict(explicit_path=0, tblock_depth=depth))
+    ref = oracle_run(batch, 450, "f64", scheme=W.EXPLICIT)
     assert np.array_equal(got, ref)
 
 
