@@ -12,8 +12,9 @@
 //    flops, far below the machine balance, so it is bound by HBM: each workgroup streams one tile of
 //    256 lanes x 16 bytes with vector loads and stores; a tile's descriptor carries everything needed
 //    to address it, so the vector load issues after a single scalar load.
-//  * explicit_block_kernel: temporal blocking.  A workgroup holds a window of up to 8192 nodes in
-//    registers (32 per lane), exchanges only the chunk end values through LDS each step (double
+//  * explicit_block_kernel: temporal blocking.  A workgroup of 512 lanes holds a window of up to 8192
+//    nodes in registers (16 per lane, in two arrays that alternate as old and new state, so no value is
+//    copied between registers), exchanges only the chunk end values through LDS each step (double
 //    buffered, one barrier per step) and advances many steps per pass over HBM.  The window is loaded
 //    and stored through LDS so that HBM sees coalesced accesses.  A whole instance that
 //    fits is advanced for all its steps in one launch with exact boundaries; longer grids are cut into
@@ -29,8 +30,8 @@ namespace burgers {
 namespace {
 
 constexpr int kStreamThreads = 256;
-constexpr int kBlockThreads = 256;
-constexpr int kBlockChunk = 32;
+constexpr int kBlockThreads = 512;
+constexpr int kBlockChunk = 16;
 
 template <typename T> struct Vec;
 template <> struct Vec<double> { using type = double2; static constexpr int n = 2; };
@@ -99,9 +100,56 @@ __device__ __forceinline__ void lane_span(int t, int W, int P, int& s, int& m) {
 }
 
 // LDS staging of window I/O: half the lanes' chunks at a time (at most 4096 nodes), padded by one element
-// every 32 nodes so that lanes reading their 32-node chunks hit distinct banks.
+// every 16 nodes so that lanes reading their 16-node chunks (a stride of 17 elements) hit distinct banks.
 constexpr int kStageNodes = kBlockThreads * kBlockChunk / 2;
-__device__ __forceinline__ int spad(int i) { return i + (i >> 5); }
+__device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
+
+// One step of a lane's chunk: out[j] from in[j-1], in[j], in[j+1], with the neighbours' end values
+// `left` and `right`; fixed nodes keep their value.
+template <typename T, bool EXACT>
+__device__ __forceinline__ void chunk_step(const T (&in)[kBlockChunk], T (&out)[kBlockChunk], T left, T right,
+                                           int m, bool fix_first, bool fix_last, T r, T D) {
+  constexpr int M = kBlockChunk;
+  T prev = left;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (EXACT || j < m) {
+      T up;
+      if (EXACT) {
+        up = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
+      } else {
+        up = right;
+        if (j + 1 < M && j + 1 < m) up = in[j + 1 < M ? j + 1 : j];
+      }
+      const bool fixed = (j == 0 && fix_first) || (EXACT ? (j == M - 1 && fix_last) : (j == m - 1 && fix_last));
+      out[j] = fixed ? in[j] : upwind_central(in[j], prev, up, r, D);
+      prev = in[j];
+    }
+  }
+}
+
+// Publish a lane's chunk end values in exchange buffer `buf`, wait, and read the neighbours' ends.
+template <typename T, bool EXACT>
+__device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf, int t, int P, int m, bool active,
+                                              T (*s_first)[kBlockThreads], T (*s_last)[kBlockThreads], T& left,
+                                              T& right) {
+  constexpr int M = kBlockChunk;
+  if (active) {
+    s_first[buf][t] = x[0];
+    T last = x[M - 1];
+    if (!EXACT) {
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        if (j == m - 1) last = x[j];
+    }
+    s_last[buf][t] = last;
+  }
+  __syncthreads();
+  if (active) {
+    left = t > 0 ? s_last[buf][t - 1] : s_last[buf][P - 1];
+    right = t < P - 1 ? s_first[buf][t + 1] : s_first[buf][0];
+  }
+}
 
 // Temporal-blocking body.  EXACT: the window has exactly kBlockThreads * kBlockChunk nodes, so every lane
 // holds a full chunk and the guards below fold away.
@@ -153,40 +201,22 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
       if (j == m - 1 && bt.first + s + j == n - 1) v[j] = static_cast<T>(d.b);
   }
 
-  for (int step = 0; step < steps; ++step) {
-    const int buf = step & 1;
+  // two steps per iteration: v -> w, then w -> v (exchange buffers 0 and 1 alternate)
+  T w[M];
+  T left = T(0), right = T(0);
+  int step = 0;
+  for (; step + 2 <= steps; step += 2) {
+    exchange_ends<T, EXACT>(v, 0, t, P, m, active, s_first, s_last, left, right);
+    if (active) chunk_step<T, EXACT>(v, w, left, right, m, fix_first, fix_last, r, D);
+    exchange_ends<T, EXACT>(w, 1, t, P, m, active, s_first, s_last, left, right);
+    if (active) chunk_step<T, EXACT>(w, v, left, right, m, fix_first, fix_last, r, D);
+  }
+  if (step < steps) {
+    exchange_ends<T, EXACT>(v, 0, t, P, m, active, s_first, s_last, left, right);
     if (active) {
-      s_first[buf][t] = v[0];
-      T last = v[M - 1];
-      if (!EXACT) {
+      chunk_step<T, EXACT>(v, w, left, right, m, fix_first, fix_last, r, D);
 #pragma unroll
-        for (int j = 0; j < M; ++j)
-          if (j == m - 1) last = v[j];
-      }
-      s_last[buf][t] = last;
-    }
-    __syncthreads();
-    if (active) {
-      const T left = t > 0 ? s_last[buf][t - 1] : s_last[buf][P - 1];
-      const T right = t < P - 1 ? s_first[buf][t + 1] : s_first[buf][0];
-      T prev = left;
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        if (EXACT || j < m) {
-          const T old = v[j];
-          T up;
-          if (EXACT) {
-            up = j + 1 < M ? v[j + 1 < M ? j + 1 : j] : right;
-          } else {
-            up = right;
-            if (j + 1 < M && j + 1 < m) up = v[j + 1 < M ? j + 1 : j];
-          }
-          const bool fixed = (j == 0 && fix_first) || (EXACT ? (j == M - 1 && fix_last)
-                                                              : (j == m - 1 && fix_last));
-          if (!fixed) v[j] = upwind_central(old, prev, up, r, D);
-          prev = old;
-        }
-      }
+      for (int j = 0; j < M; ++j) v[j] = w[j];
     }
   }
 

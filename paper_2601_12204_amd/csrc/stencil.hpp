@@ -9,14 +9,17 @@
 namespace burgers {
 
 // Explicit forward-Euler update of one node (Sec. 2.3, eq. 21): first-order upwind convection whose
-// side follows the sign of c = r u_i (eq. 3 and the text after it), central diffusion (eq. 4).
+// side follows the sign of c = r u_i (eq. 3 and the text after it), central diffusion (eq. 4):
+//   u' = ((u - max(c,0) (u - u_m)) - min(c,0) (u_p - u)) + D ((u_p + u_m) - 2u).
+// At most one of max(c,0), min(c,0) is nonzero; the other one's product is a zero, and subtracting a
+// zero leaves a value unchanged, so selecting the upwind difference by the sign of c and subtracting
+// c times it rounds exactly like the formula above (up to the sign of a zero result).
 template <typename T>
 __device__ __forceinline__ T upwind_central(T ui, T um, T up, T r, T D) {
   const T c = r * ui;
-  const T cpos = c > T(0) ? c : T(0);
-  const T cneg = c < T(0) ? c : T(0);
+  const T diff = c > T(0) ? ui - um : up - ui;
   const T lap = (up + um) - T(2) * ui;
-  return ((ui - cpos * (ui - um)) - cneg * (up - ui)) + D * lap;
+  return (ui - c * diff) + D * lap;
 }
 
 // Row of the BTCS matrix (Sec. 2.4, eq. 23) at a node with old value ui, convective coefficient
