@@ -34,7 +34,7 @@
 namespace {
 
 enum { PERIODIC = 0, DIRICHLET = 1 };
-enum { SCHEME_EXPLICIT = 0, SCHEME_BTCS = 1 };
+enum { SCHEME_EXPLICIT = 0, SCHEME_BTCS = 1, SCHEME_RK4 = 2 };
 
 // Sec. 2.2: grid spacing for N stored nodes.
 double grid_dx(int64_t n, double length, int bc) {
@@ -75,6 +75,57 @@ void explicit_range(int64_t n, int bc, T a, T b, T r, T D, const T* u, T* out, i
 template <typename T>
 void explicit_step(int64_t n, int bc, T a, T b, T r, T D, const T* u, T* out) {
   explicit_range(n, bc, a, b, r, D, u, out, 0, n);
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Classical fourth-order Runge-Kutta step (Sec. 2.7.1, eq. 22) over the spatial operator of eq. 21.
+// K(v) = dt L(v) is the increment eq. 21 adds to v in one forward-Euler step:
+//   K_i(v) = D ((v_{i+1} + v_{i-1}) - 2 v_i) - (max(c,0) (v_i - v_{i-1}) + min(c,0) (v_{i+1} - v_i)),
+// c = r v_i, upwinded as in the explicit step.  The stages are the classical ones,
+//   K1 = K(u), K2 = K(u + K1/2), K3 = K(u + K2/2), K4 = K(u + K3),
+// and u' = u + (K1 + 2 K2 + 2 K3 + K4) / 6, summed left to right (eq. 22 with dt folded into K).
+// Dirichlet nodes carry a and b in every stage and have K = 0.
+template <typename T>
+void rk4_increment(int64_t n, int bc, T a, T b, T r, T D, const T* v, T* K) {
+  const T zero = 0, two = 2;
+  for (int64_t i = 0; i < n; ++i) {
+    if (bc == DIRICHLET && (i == 0 || i == n - 1)) {
+      K[i] = zero;
+      continue;
+    }
+    T um, up;
+    if (bc == PERIODIC) {
+      um = v[i == 0 ? n - 1 : i - 1];
+      up = v[i == n - 1 ? 0 : i + 1];
+    } else {
+      um = (i == 1) ? a : v[i - 1];
+      up = (i == n - 2) ? b : v[i + 1];
+    }
+    T vi = v[i];
+    T c = r * vi;
+    T cpos = c > zero ? c : zero;
+    T cneg = c < zero ? c : zero;
+    T lap = (up + um) - two * vi;
+    K[i] = D * lap - (cpos * (vi - um) + cneg * (up - vi));
+  }
+}
+
+template <typename T>
+void rk4_step(int64_t n, int bc, T a, T b, T r, T D, const T* u, T* out) {
+  const T half = (T)0.5, two = 2, six = 6;
+  std::vector<T> K1(n), K2(n), K3(n), K4(n), v(n);
+  rk4_increment(n, bc, a, b, r, D, u, K1.data());
+  for (int64_t i = 0; i < n; ++i) v[i] = u[i] + half * K1[i];
+  rk4_increment(n, bc, a, b, r, D, v.data(), K2.data());
+  for (int64_t i = 0; i < n; ++i) v[i] = u[i] + half * K2[i];
+  rk4_increment(n, bc, a, b, r, D, v.data(), K3.data());
+  for (int64_t i = 0; i < n; ++i) v[i] = u[i] + K3[i];
+  rk4_increment(n, bc, a, b, r, D, v.data(), K4.data());
+  for (int64_t i = 0; i < n; ++i) out[i] = u[i] + (((K1[i] + two * K2[i]) + two * K3[i]) + K4[i]) / six;
+  if (bc == DIRICHLET) {
+    out[0] = a;
+    out[n - 1] = b;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------------
@@ -168,6 +219,7 @@ void run_one(int64_t n, int bc, int scheme, T a, T b, T r, T D, T* u, int64_t ns
   std::vector<T> tmp(n);
   for (int64_t s = 0; s < nsteps; ++s) {
     if (scheme == SCHEME_EXPLICIT) explicit_step(n, bc, a, b, r, D, u, tmp.data());
+    else if (scheme == SCHEME_RK4) rk4_step(n, bc, a, b, r, D, u, tmp.data());
     else btcs_step(n, bc, a, b, r, D, u, tmp.data());
     std::memcpy(u, tmp.data(), sizeof(T) * (size_t)n);
   }
@@ -427,6 +479,14 @@ double oracle_cfl_dt(int64_t n, double length, double nu, int bc, double umax, d
 void oracle_explicit_step_f64(int64_t n, int bc, double a, double b, double r, double D,
                               const double* u, double* out) {
   explicit_step<double>(n, bc, a, b, r, D, u, out);
+}
+void oracle_rk4_step_f64(int64_t n, int bc, double a, double b, double r, double D, const double* u,
+                         double* out) {
+  rk4_step<double>(n, bc, a, b, r, D, u, out);
+}
+void oracle_rk4_step_f32(int64_t n, int bc, double a, double b, double r, double D, const float* u,
+                         float* out) {
+  rk4_step<float>(n, bc, (float)a, (float)b, (float)r, (float)D, u, out);
 }
 void oracle_explicit_step_f32(int64_t n, int bc, double a, double b, double r, double D,
                               const float* u, float* out) {

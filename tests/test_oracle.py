@@ -198,6 +198,76 @@ def test_explicit_first_order_in_time(oracle_lib):
     assert 1.8 <= ratio <= 2.2, ratio
 
 
+# ------------------------------------------------------------------------------------ RK4 (eq. 22)
+def test_rk4_constant_state_bitwise(oracle_lib):
+    for U in (1.7, -0.3, 0.0):
+        p = _with_ratios(37, 0.4, 0.3, U=1.0)
+        u = np.full(37, U)
+        assert np.array_equal(oracle_lib.rk4_step(p, u), u)
+        q = _problem(37, 1.0, 0.01, 1e-4, W.BC_DIRICHLET, a=U, b=U)
+        assert np.array_equal(oracle_lib.rk4_step(q, u), u)
+
+
+@pytest.mark.parametrize("U,C", [(1.0, 0.3), (-1.0, -0.45), (2.5, 0.05)])
+@pytest.mark.parametrize("k", [1, 3, 11])
+def test_rk4_von_neumann_symbol(oracle_lib, U, C, k):
+    """A small perturbation of a constant state is multiplied by the RK4 polynomial
+    1 + z + z^2/2 + z^3/6 + z^4/24 of the forward-Euler increment symbol z (eq. 22 over eq. 21)."""
+    n, D, eps = 64, 0.2, 1e-6
+    p = _with_ratios(n, C, D, U=U)
+    theta = 2 * np.pi * k / n
+    j = np.arange(n)
+    u = U + eps * np.sin(j * theta)
+    if C >= 0:
+        z = -C * (1 - np.exp(-1j * theta)) - 4 * D * np.sin(theta / 2) ** 2
+    else:
+        z = -C * (np.exp(1j * theta) - 1) - 4 * D * np.sin(theta / 2) ** 2
+    g = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    pred = g.real * np.sin(j * theta) + g.imag * np.cos(j * theta)
+    got = (oracle_lib.rk4_step(p, u) - U) / eps
+    assert np.max(np.abs(got - pred)) < 2e-5
+
+
+def test_rk4_fourth_order_in_time(oracle_lib):
+    """At fixed N on a smooth solution, halving dt divides the change of the solution by 2^4."""
+    n, nu, T = 128, 0.05, 0.4
+    x = W.node_coordinates(n, 2 * np.pi, W.BC_PERIODIC)
+    u0 = 1.0 + 0.5 * np.sin(x)
+    sols = []
+    for steps in (20, 40, 80):
+        p = _problem(n, 2 * np.pi, nu, T / steps, scheme=W.RK4)
+        sols.append(oracle_lib.run([p], u0, np.array([0, n]), steps))
+    ratio = np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[1] - sols[2])
+    assert 14.0 <= ratio <= 18.0, ratio
+
+
+def test_rk4_first_stage_is_forward_euler(oracle_lib):
+    """With the later stages removed (u' = u + K1), eq. 22 is eq. 21: checks that K is eq. 21's increment
+    by comparing RK4 against forward Euler to second order in dt."""
+    b = W.random_batch(3, 1, 60, 60, bc=W.BC_PERIODIC, amplitude=2.0)
+    p = b.problems[0]
+    u = b.instance(0)
+    diffs = []
+    for f in (1.0, 0.5, 0.25):
+        p.dt = f * oracle_lib.cfl_dt(p.n, p.length, p.nu, p.bc, float(b.umax[0]), 0.5)
+        diffs.append(np.max(np.abs(oracle_lib.rk4_step(p, u) - oracle_lib.explicit_step(p, u))))
+    # one step differs by O(dt^2): the ratio for halved dt is ~4
+    assert 3.5 <= diffs[0] / diffs[1] <= 4.5 and 3.5 <= diffs[1] / diffs[2] <= 4.5, diffs
+
+
+def test_rk4_dirichlet_ends_held_and_translation_equivariant(oracle_lib):
+    b = W.random_batch(5, 1, 41, 41, bc=W.BC_DIRICHLET, amplitude=2.0)
+    p = b.problems[0]
+    p.dt = oracle_lib.cfl_dt(p.n, p.length, p.nu, p.bc, float(b.umax[0]), 0.5)
+    out = oracle_lib.rk4_step(p, b.instance(0))
+    assert out[0] == p.left and out[-1] == p.right
+    c = W.random_batch(6, 1, 50, 50, bc=W.BC_PERIODIC, amplitude=3.0)
+    q = c.problems[0]
+    q.dt = oracle_lib.cfl_dt(q.n, q.length, q.nu, q.bc, float(c.umax[0]), 0.5)
+    u = c.instance(0)
+    assert np.array_equal(np.roll(oracle_lib.rk4_step(q, u), 7), oracle_lib.rk4_step(q, np.roll(u, 7)))
+
+
 # ------------------------------------------------------------------------------------ tridiagonal
 def _dense(l, d, p, cyclic):
     m = len(d)

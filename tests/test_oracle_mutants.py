@@ -47,6 +47,15 @@ MUTANTS = {
     "adj_g_upwind_side": ("G[i] = y[i] >= 0 ? r * (x[i] - xm) : r * (xp - x[i]);",
                           "G[i] = y[i] >= 0 ? r * (xp - x[i]) : r * (x[i] - xm);"),
     "tangent_drops_nu": ("dout[i] = v + D * dlap + dD * lap;", "dout[i] = v + D * dlap;"),
+    "rk4_weights": ("(((K1[i] + two * K2[i]) + two * K3[i]) + K4[i]) / six", "(((K1[i] + K2[i]) + K3[i]) + K4[i]) / six"),
+    "rk4_half_stage": ("for (int64_t i = 0; i < n; ++i) v[i] = u[i] + half * K1[i];",
+                       "for (int64_t i = 0; i < n; ++i) v[i] = u[i] + K1[i];"),
+    "rk4_last_stage": ("for (int64_t i = 0; i < n; ++i) v[i] = u[i] + K3[i];",
+                       "for (int64_t i = 0; i < n; ++i) v[i] = u[i] + half * K3[i];"),
+    "rk4_increment_sign": ("K[i] = D * lap - (cpos * (vi - um) + cneg * (up - vi));",
+                           "K[i] = D * lap + (cpos * (vi - um) + cneg * (up - vi));"),
+    "rk4_upwind_side": ("K[i] = D * lap - (cpos * (vi - um) + cneg * (up - vi));",
+                        "K[i] = D * lap - (cpos * (up - vi) + cneg * (vi - um));"),
 }
 
 PINS = [name for name in dir(T) if name.startswith("test_")]

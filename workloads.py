@@ -33,6 +33,7 @@ BC_PERIODIC = 0
 BC_DIRICHLET = 1
 EXPLICIT = 0
 BTCS = 1
+RK4 = 2
 
 SEED_BASE = 12204
 TWO_PI = 2.0 * math.pi
