@@ -19,6 +19,7 @@ BC_PERIODIC = 0
 BC_DIRICHLET = 1
 EXPLICIT = 0
 BTCS = 1
+RK4 = 2
 F32 = 0
 F64 = 1
 ALIGN = 64

@@ -32,7 +32,7 @@ bool valid_problem(const burgers_problem& p) {
   if (!is_finite(p.nu) || p.nu < 0) return false;
   if (!is_finite(p.dt) || p.dt <= 0) return false;
   if (p.bc != BURGERS_BC_PERIODIC && p.bc != BURGERS_BC_DIRICHLET) return false;
-  if (p.scheme != BURGERS_EXPLICIT && p.scheme != BURGERS_BTCS) return false;
+  if (p.scheme != BURGERS_EXPLICIT && p.scheme != BURGERS_BTCS && p.scheme != BURGERS_RK4) return false;
   if (!is_finite(p.left) || !is_finite(p.right)) return false;
   return true;
 }
@@ -107,6 +107,12 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
   plan->path = want_path ? want_path : 0;
   plan->depth = want_depth;
   const auto& members = set_members(ctx, set);
+  // instances advanced by their own scheme (burgers_run) take RK4 where they ask for it; a forward-Euler
+  // call (burgers_step_explicit) steps every instance with forward Euler
+  auto is_rk4 = [&](int32_t i) { return set == kSetExplicit && ctx->probs[i].scheme == BURGERS_RK4; };
+  bool any_rk4 = false;
+  for (int32_t i : members) any_rk4 = any_rk4 || is_rk4(i);
+  if (plan->path == 1 && any_rk4) return BURGERS_E_UNSUPPORTED;   // the streaming kernel is forward Euler only
   hipError_t e;
   auto st = stream_tiles(ctx, members);
   plan->stream = std::make_unique<DevBuf>();
@@ -121,28 +127,35 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
       const burgers_problem& p = ctx->probs[i];
       const int32_t n = static_cast<int32_t>(p.n);
       const bool periodic = p.bc == BURGERS_BC_PERIODIC;
+      const int32_t rk4 = is_rk4(i) ? 1 : 0;
       if (n <= cap) {
-        whole.push_back(BlockTile{i, 0, n, 0, n, periodic ? 1 : 0});
+        whole.push_back(BlockTile{i, 0, n, 0, n, periodic ? 1 : 0, rk4});
         continue;
       }
       if (plan->path == 2) return BURGERS_E_UNSUPPORTED;
       windowed.push_back(i);
-      const int32_t wout = cap - 2 * T;
+      // each step consumes one halo node per side per stage
+      const int32_t halo = T * (rk4 ? 4 : 1);
+      const int32_t wout = cap - 2 * halo;
+      if (wout < 1) return BURGERS_E_UNSUPPORTED;
       for (int32_t lo = 0; lo < n; lo += wout) {
         const int32_t hi = std::min(n, lo + wout);
-        BlockTile bt{i, 0, 0, 0, hi - lo, 0};
+        BlockTile bt{i, 0, 0, 0, hi - lo, 0, rk4};
         if (periodic) {
-          bt.first = ((lo - T) % n + n) % n;
-          bt.width = (hi - lo) + 2 * T;
-          bt.lo = T;
+          bt.first = ((lo - halo) % n + n) % n;
+          bt.width = (hi - lo) + 2 * halo;
+          bt.lo = halo;
         } else {
-          bt.first = std::max(0, lo - T);
-          bt.width = std::min(n, hi + T) - bt.first;
+          bt.first = std::max(0, lo - halo);
+          bt.width = std::min(n, hi + halo) - bt.first;
           bt.lo = lo - bt.first;
         }
         win.push_back(bt);
       }
     }
+    auto fe_first = [](const BlockTile& x, const BlockTile& y) { return x.rk4 < y.rk4; };
+    std::stable_sort(whole.begin(), whole.end(), fe_first);
+    std::stable_sort(win.begin(), win.end(), fe_first);
     plan->whole = std::make_unique<DevBuf>();
     plan->win = std::make_unique<DevBuf>();
     plan->win_copy = std::make_unique<DevBuf>();
@@ -152,6 +165,8 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
       return from_hip(e);
     plan->n_whole = static_cast<int64_t>(whole.size());
     plan->n_win = static_cast<int64_t>(win.size());
+    plan->n_whole_rk4 = std::count_if(whole.begin(), whole.end(), [](const BlockTile& b) { return b.rk4 != 0; });
+    plan->n_win_rk4 = std::count_if(win.begin(), win.end(), [](const BlockTile& b) { return b.rk4 != 0; });
     plan->n_win_copy = static_cast<int64_t>(wc.size());
   }
   ctx->explicit_plans[set] = std::move(plan);
@@ -310,7 +325,8 @@ hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) 
   const int64_t whole_chunk = pl.path == 3 ? pl.depth : (int64_t{1} << 30);
   for (int64_t done = 0; done < nsteps;) {
     const int k = static_cast<int>(std::min(whole_chunk, nsteps - done));
-    if ((e = burgers::launch_explicit_block(ctx, pl.whole->as<BlockTile>(), pl.n_whole, u, u, k)) != hipSuccess)
+    if ((e = burgers::launch_explicit_block(ctx, pl.whole->as<BlockTile>(), pl.n_whole - pl.n_whole_rk4,
+                                            pl.n_whole_rk4, u, u, k)) != hipSuccess)
       return e;
     done += k;
   }
@@ -320,7 +336,8 @@ hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) 
     int cur = 0;
     for (int64_t done = 0; done < nsteps;) {
       const int k = static_cast<int>(std::min<int64_t>(pl.depth, nsteps - done));
-      if ((e = burgers::launch_explicit_block(ctx, pl.win->as<BlockTile>(), pl.n_win, bufs[cur], bufs[cur ^ 1], k)) != hipSuccess)
+      if ((e = burgers::launch_explicit_block(ctx, pl.win->as<BlockTile>(), pl.n_win - pl.n_win_rk4, pl.n_win_rk4,
+                                              bufs[cur], bufs[cur ^ 1], k)) != hipSuccess)
         return e;
       cur ^= 1;
       done += k;
@@ -611,7 +628,7 @@ burgers_status burgers_create(const burgers_problem* problems, int64_t count, bu
     d.a = p.bc == BURGERS_BC_DIRICHLET ? p.left : 0.0;
     d.b = p.bc == BURGERS_BC_DIRICHLET ? p.right : 0.0;
     ctx->set_all.push_back(static_cast<int32_t>(i));
-    (p.scheme == BURGERS_EXPLICIT ? ctx->set_explicit : ctx->set_btcs).push_back(static_cast<int32_t>(i));
+    (p.scheme == BURGERS_BTCS ? ctx->set_btcs : ctx->set_explicit).push_back(static_cast<int32_t>(i));
   }
   burgers_status st = BURGERS_OK;
   if ((e = upload_on(ctx->stream, ctx->inst, ctx->inst_host)) != hipSuccess) st = from_hip(e);
@@ -748,6 +765,8 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   if (!ctx || !u0 || !lambda_T || !grad_u0 || !grad_nu || nsteps < 0 || ckpt_every < 1)
     return BURGERS_E_INVALID;
   if (ctx->dtype != BURGERS_F64) return BURGERS_E_UNSUPPORTED;
+  for (const auto& p : ctx->probs)
+    if (p.scheme == BURGERS_RK4) return BURGERS_E_UNSUPPORTED;   // adjoint of forward Euler and BTCS only
   if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return note(ctx, e);

@@ -128,6 +128,50 @@ __device__ __forceinline__ void chunk_step(const T (&in)[kBlockChunk], T (&out)[
   }
 }
 
+// One RK4 stage of a lane's chunk (Sec. 2.7.1, eq. 22): K = increment of the stage input `in` (with
+// the neighbours' end values `left`, `right`; fixed nodes have K = 0), then by stage
+//   1: acc = K,             out = v + K/2
+//   2: acc = acc + 2K,      out = v + K/2
+//   3: acc = acc + 2K,      out = v + K
+//   4: v = v + (acc + K)/6  (out unused)
+// `in` and `out` may be the same array: node j reads in[j-1] from a register kept before it is
+// overwritten.
+template <typename T, bool EXACT, int STAGE>
+__device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBlockChunk], T (&out)[kBlockChunk],
+                                          T (&acc)[kBlockChunk], T left, T right, int m, bool fix_first,
+                                          bool fix_last, T r, T D) {
+  constexpr int M = kBlockChunk;
+  T prev = left;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (EXACT || j < m) {
+      T up;
+      if (EXACT) {
+        up = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
+      } else {
+        up = right;
+        if (j + 1 < M && j + 1 < m) up = in[j + 1 < M ? j + 1 : j];
+      }
+      const bool fixed = (j == 0 && fix_first) || (EXACT ? (j == M - 1 && fix_last) : (j == m - 1 && fix_last));
+      const T cur = in[j];
+      const T K = fixed ? T(0) : rk4_increment(cur, prev, up, r, D);
+      prev = cur;
+      if constexpr (STAGE == 1) {
+        acc[j] = K;
+        out[j] = v[j] + T(0.5) * K;
+      } else if constexpr (STAGE == 2) {
+        acc[j] = acc[j] + T(2) * K;
+        out[j] = v[j] + T(0.5) * K;
+      } else if constexpr (STAGE == 3) {
+        acc[j] = acc[j] + T(2) * K;
+        out[j] = v[j] + K;
+      } else {
+        v[j] = v[j] + (acc[j] + K) / T(6);
+      }
+    }
+  }
+}
+
 // Publish a lane's chunk end values in exchange buffer `buf`, wait, and read the neighbours' ends.
 template <typename T, bool EXACT>
 __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf, int t, int P, int m, bool active,
@@ -153,7 +197,7 @@ __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf
 
 // Temporal-blocking body.  EXACT: the window has exactly kBlockThreads * kBlockChunk nodes, so every lane
 // holds a full chunk and the guards below fold away.
-template <typename T, bool EXACT>
+template <typename T, bool EXACT, bool RK4>
 __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& d, const T* __restrict__ src,
                                            T* __restrict__ dst, int steps, T* stage,
                                            T (*s_first)[kBlockThreads], T (*s_last)[kBlockThreads]) {
@@ -201,9 +245,23 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
       if (j == m - 1 && bt.first + s + j == n - 1) v[j] = static_cast<T>(d.b);
   }
 
-  // two steps per iteration: v -> w, then w -> v (exchange buffers 0 and 1 alternate)
   T w[M];
   T left = T(0), right = T(0);
+  if constexpr (RK4) {
+    // four stages per step, each after an exchange of the stage's end values (buffers alternate)
+    T acc[M];
+    for (int step = 0; step < steps; ++step) {
+      exchange_ends<T, EXACT>(v, 0, t, P, m, active, s_first, s_last, left, right);
+      if (active) rk4_stage<T, EXACT, 1>(v, v, w, acc, left, right, m, fix_first, fix_last, r, D);
+      exchange_ends<T, EXACT>(w, 1, t, P, m, active, s_first, s_last, left, right);
+      if (active) rk4_stage<T, EXACT, 2>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
+      exchange_ends<T, EXACT>(w, 0, t, P, m, active, s_first, s_last, left, right);
+      if (active) rk4_stage<T, EXACT, 3>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
+      exchange_ends<T, EXACT>(w, 1, t, P, m, active, s_first, s_last, left, right);
+      if (active) rk4_stage<T, EXACT, 4>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
+    }
+  } else {
+  // two steps per iteration: v -> w, then w -> v (exchange buffers 0 and 1 alternate)
   int step = 0;
   for (; step + 2 <= steps; step += 2) {
     exchange_ends<T, EXACT>(v, 0, t, P, m, active, s_first, s_last, left, right);
@@ -218,6 +276,7 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
 #pragma unroll
       for (int j = 0; j < M; ++j) v[j] = w[j];
     }
+  }
   }
 
   // store the window's output nodes [bt.lo, bt.lo + bt.count), staged like the load
@@ -242,22 +301,23 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   }
 }
 
-// One workgroup per window; full-size windows take the specialised body.
-template <typename T>
+// One workgroup per window; full-size windows take the specialised body.  RK4 windows run in a kernel
+// of their own, so that the forward-Euler kernel keeps its smaller register footprint.
+template <typename T, bool RK4>
 __global__ __launch_bounds__(kBlockThreads) void explicit_block_kernel(
     const InstDesc* __restrict__ inst, const BlockTile* __restrict__ tiles, const T* __restrict__ u,
     T* __restrict__ out, int steps) {
   __shared__ T s_first[2][kBlockThreads];
   __shared__ T s_last[2][kBlockThreads];
-  __shared__ T stage[kStageNodes + kStageNodes / 32 + 1];
+  __shared__ T stage[kStageNodes + kStageNodes / 16 + 1];
   const BlockTile bt = tiles[blockIdx.x];
   const InstDesc d = inst[bt.inst];
   const T* src = u + d.off;
   T* dst = out + d.off;
   if (bt.width == kBlockThreads * kBlockChunk) {
-    block_body<T, true>(bt, d, src, dst, steps, stage, s_first, s_last);
+    block_body<T, true, RK4>(bt, d, src, dst, steps, stage, s_first, s_last);
   } else {
-    block_body<T, false>(bt, d, src, dst, steps, stage, s_first, s_last);
+    block_body<T, false, RK4>(bt, d, src, dst, steps, stage, s_first, s_last);
   }
 }
 
@@ -319,18 +379,25 @@ hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int
   return hipGetLastError();
 }
 
-hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_tiles,
-                                 const void* u, void* out, int steps) {
-  if (n_tiles <= 0 || steps <= 0) return hipSuccess;
-  const dim3 grid(static_cast<unsigned>(n_tiles)), block(kBlockThreads);
+template <typename T>
+void block_launch(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4, const void* u,
+                  void* out, int steps) {
   const InstDesc* inst = ctx->inst.as<InstDesc>();
-  if (ctx->dtype == BURGERS_F64) {
-    explicit_block_kernel<double><<<grid, block, 0, ctx->stream>>>(inst, tiles, static_cast<const double*>(u),
-                                                                  static_cast<double*>(out), steps);
-  } else {
-    explicit_block_kernel<float><<<grid, block, 0, ctx->stream>>>(inst, tiles, static_cast<const float*>(u),
-                                                                 static_cast<float*>(out), steps);
-  }
+  const T* src = static_cast<const T*>(u);
+  T* dst = static_cast<T*>(out);
+  if (n_fe > 0)
+    explicit_block_kernel<T, false><<<static_cast<unsigned>(n_fe), kBlockThreads, 0, ctx->stream>>>(
+        inst, tiles, src, dst, steps);
+  if (n_rk4 > 0)
+    explicit_block_kernel<T, true><<<static_cast<unsigned>(n_rk4), kBlockThreads, 0, ctx->stream>>>(
+        inst, tiles + n_fe, src, dst, steps);
+}
+
+hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4,
+                                 const void* u, void* out, int steps) {
+  if (n_fe + n_rk4 <= 0 || steps <= 0) return hipSuccess;
+  if (ctx->dtype == BURGERS_F64) block_launch<double>(ctx, tiles, n_fe, n_rk4, u, out, steps);
+  else block_launch<float>(ctx, tiles, n_fe, n_rk4, u, out, steps);
   return hipGetLastError();
 }
 

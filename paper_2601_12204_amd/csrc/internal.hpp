@@ -49,6 +49,7 @@ struct BlockTile {
   int32_t lo;
   int32_t count;
   int32_t wrap;   // 1: the window is a whole periodic instance and its ends are neighbours
+  int32_t rk4;    // 1: classical RK4 steps (4 stages) instead of forward Euler
 };
 
 // A run of 256 nodes of one instance in the adjoint sweep; `slot` indexes the tile's accumulator of
@@ -154,7 +155,8 @@ struct ExplicitPlan {
   int64_t n_stream = 0;
   // temporal blocking: whole instances (all steps in place) and windows of long instances
   std::unique_ptr<DevBuf> whole, win;        // BlockTile[]
-  int64_t n_whole = 0, n_win = 0;
+  int64_t n_whole = 0, n_win = 0;            // of which the last n_*_rk4 take RK4 steps
+  int64_t n_whole_rk4 = 0, n_win_rk4 = 0;
   std::unique_ptr<DevBuf> win_copy;          // Tile[] of the windowed instances (copy-back)
   int64_t n_win_copy = 0;
   int path = 1;                              // 1 stream, 2 resident, 3 tiled
@@ -207,7 +209,8 @@ namespace burgers {
 // explicit.hip
 hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles,
                                   const void* u, void* out);
-hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_tiles,
+// Windows tiles[0, n_fe) advance by forward Euler and tiles[n_fe, n_fe + n_rk4) by RK4.
+hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4,
                                  const void* u, void* out, int steps);
 hipError_t launch_copy_tiles(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* src,
                              void* dst);

@@ -22,6 +22,17 @@ __device__ __forceinline__ T upwind_central(T ui, T um, T up, T r, T D) {
   return (ui - c * diff) + D * lap;
 }
 
+// Increment dt L(v) of one node for the classical RK4 step (Sec. 2.7.1, eq. 22) over eq. 21's spatial
+// operator:  K = D ((v_p + v_m) - 2v) - (max(c,0) (v - v_m) + min(c,0) (v_p - v)),  c = r v.  As in
+// upwind_central, one of the two products is a zero, so selecting the upwind difference rounds the same.
+template <typename T>
+__device__ __forceinline__ T rk4_increment(T vi, T vm, T vp, T r, T D) {
+  const T c = r * vi;
+  const T diff = c > T(0) ? vi - vm : vp - vi;
+  const T lap = (vp + vm) - T(2) * vi;
+  return D * lap - c * diff;
+}
+
 // Row of the BTCS matrix (Sec. 2.4, eq. 23) at a node with old value ui, convective coefficient
 // c = r u_i lagged at u^n:  sub = -(D + max(c,0)), diag = 1 + 2D + |c|, super = min(c,0) - D.
 // Every row sums to one, and the matrix is a strictly diagonally dominant M-matrix.

@@ -23,7 +23,7 @@ def set_cfl_steps(batch, sigma=0.5, explicit_factor=1.0, btcs_factor=10.0, schem
     import paper_2601_12204_amd as B
     for i, p in enumerate(batch.problems):
         s = p.scheme if scheme is None else scheme
-        f = explicit_factor if s == W.EXPLICIT else btcs_factor
+        f = btcs_factor if s == W.BTCS else explicit_factor
         d0 = oracle.cfl_dt(p.n, p.length, p.nu, p.bc, float(batch.umax[i]), sigma)
         d1 = B.burgers_cfl_dt(p, float(batch.umax[i]), sigma)
         assert d0 == d1

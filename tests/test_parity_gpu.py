@@ -369,3 +369,70 @@ def test_autotune_keeps_state_and_results(tmp_path):
     plan2, ms2, cached2 = s2.autotune(s2.pack_flat(batch.u0, batch.offsets), 20, 5, cache=cache)
     assert cached2 and plan2 == plan and s2.get_plan() == plan
     s2.close()
+
+
+# ----------------------------------------------------------------------------- RK4 (eq. 22)
+def _rk4_batch(seed):
+    batch = _ragged_long_batch(seed)
+    for p in batch.problems:
+        p.scheme = W.RK4
+    return batch
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("depth", [0, 5, 16])
+def test_rk4_bitwise(dtype, depth):
+    """RK4 instances (whole on chip and windows with 4 halo nodes per step) bitwise equal to the oracle's
+    RK4, over 37 steps (several launches with a partial last one at depths 5 and 16)."""
+    batch = _rk4_batch(61)
+    announce(f"rk4 {dtype} depth={depth} 37 steps")
+    got = device_run(batch, 37, dtype, how="run", plan=dict(tblock_depth=depth))
+    ref = oracle_run(batch, 37, dtype)
+    assert np.array_equal(got, ref)
+
+
+def test_rk4_mixed_with_euler_and_btcs():
+    """Forward-Euler, RK4 and BTCS instances in one context: run_mixed gives each its own integrator."""
+    import torch
+    import paper_2601_12204_amd as B
+    batch = W.random_batch(71, 30, 3, 20000, amplitude=2.0)
+    for k, p in enumerate(batch.problems):
+        p.scheme = (W.EXPLICIT, W.RK4, W.BTCS)[k % 3]
+    set_cfl_steps(batch)
+    announce("rk4 + euler + btcs run_mixed 11/4")
+    s = B.Solver(batch.problems, dtype=torch.float64)
+    u = s.pack_flat(batch.u0, batch.offsets)
+    s.run_mixed(u, 11, 4)
+    s.sync()
+    got = s.unpack_flat(u)
+    s.close()
+    exp = oracle_run(batch, 11, "f64")
+    imp = oracle_run(batch, 4, "f64")
+    for b, p in enumerate(batch.problems):
+        lo, hi = batch.offsets[b], batch.offsets[b + 1]
+        if p.scheme == W.BTCS:
+            assert rel_err(got[lo:hi], imp[lo:hi]) <= TOL_F64, b
+        else:
+            assert np.array_equal(got[lo:hi], exp[lo:hi]), b
+
+
+def test_rk4_unsupported_paths():
+    """The streaming kernel and the adjoint reject RK4 instances with BURGERS_E_UNSUPPORTED; a
+    forward-Euler call steps RK4-scheme instances with forward Euler."""
+    import torch
+    import paper_2601_12204_amd as B
+    batch = _rk4_batch(83)
+    announce("rk4 unsupported paths")
+    with pytest.raises(B.BurgersError) as err:
+        device_run(batch, 3, "f64", how="run", plan=dict(explicit_path=1))
+    assert err.value.status == -2
+    s = B.Solver(batch.problems, dtype=torch.float64)
+    u = s.pack_flat(batch.u0, batch.offsets)
+    g = torch.zeros_like(u)
+    gn = torch.zeros(s.count, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.BurgersError) as err:
+        B.adjoint_into(s, u, u.clone(), 3, 2, g, gn)
+    assert err.value.status == -2
+    s.close()
+    got = device_run(batch, 9, "f64", how="step_explicit")
+    assert np.array_equal(got, oracle_run(batch, 9, "f64", scheme=W.EXPLICIT))
