@@ -10,6 +10,7 @@ Functions and the passages they follow (Potluri et al., arXiv 2601.12204):
   cfl_dt            eqs. 7-8
   explicit_step     eq. 21, upwind direction by sign of u_i (text after eq. 3)
   rk4_step          eq. 22: classical RK4 over eq. 21's spatial operator
+  cn_step           Crank-Nicolson (Sec. 2.2) with the BTCS lagged operator
   btcs_assemble     Sec. 2.4 / eq. 23 with the convective coefficient lagged at u^n
   thomas, cyclic    tridiagonal and cyclic (Sherman-Morrison) solves of eq. 23
   btcs_step         assemble + solve
@@ -57,9 +58,10 @@ def configure(lib):
     lib.oracle_cfl_dt.restype = dbl
     lib.oracle_cfl_dt.argtypes = [i64, dbl, dbl, c_int, dbl, dbl]
     for name, ptr in (("f64", _dp), ("f32", _fp)):
-        f = getattr(lib, f"oracle_rk4_step_{name}")
-        f.restype = None
-        f.argtypes = [i64, c_int, dbl, dbl, dbl, dbl, ptr, ptr]
+        for fn in ("rk4", "cn"):
+            f = getattr(lib, f"oracle_{fn}_step_{name}")
+            f.restype = None
+            f.argtypes = [i64, c_int, dbl, dbl, dbl, dbl, ptr, ptr]
         f = getattr(lib, f"oracle_explicit_step_{name}")
         f.restype = None
         f.argtypes = [i64, c_int, dbl, dbl, dbl, dbl, ptr, ptr]
@@ -133,6 +135,14 @@ def rk4_step(p, u: np.ndarray) -> np.ndarray:
     out = np.empty_like(u)
     r, D = ratios(p)
     getattr(_load(), f"oracle_rk4_step_{_tag(u.dtype)}")(p.n, p.bc, p.left, p.right, r, D, _ptr(u), _ptr(out))
+    return out
+
+
+def cn_step(p, u: np.ndarray) -> np.ndarray:
+    u = np.ascontiguousarray(u)
+    out = np.empty_like(u)
+    r, D = ratios(p)
+    getattr(_load(), f"oracle_cn_step_{_tag(u.dtype)}")(p.n, p.bc, p.left, p.right, r, D, _ptr(u), _ptr(out))
     return out
 
 

@@ -34,7 +34,7 @@
 namespace {
 
 enum { PERIODIC = 0, DIRICHLET = 1 };
-enum { SCHEME_EXPLICIT = 0, SCHEME_BTCS = 1, SCHEME_RK4 = 2 };
+enum { SCHEME_EXPLICIT = 0, SCHEME_BTCS = 1, SCHEME_RK4 = 2, SCHEME_CN = 3 };
 
 // Sec. 2.2: grid spacing for N stored nodes.
 double grid_dx(int64_t n, double length, int bc) {
@@ -213,6 +213,52 @@ void btcs_step(int64_t n, int bc, T a, T b, T r, T D, const T* u, T* out) {
   }
 }
 
+// One Crank-Nicolson step (the paper names Crank-Nicolson beside BTCS among its implicit schemes,
+// Sec. 2.2), with the same lagged upwind/central operator as BTCS:  write the BTCS matrix as A = I + N,
+// N's row i = (-(D + max(c_i,0)), 2D + |c_i|, min(c_i,0) - D), c_i = r u_i^n; then
+//   (I + N/2) u^{n+1} = (I - N/2) u^n,
+// i.e. rows (N_sub/2, 1 + N_diag/2, N_sup/2) and right-hand side u_i - (N u^n)_i / 2, cyclic for
+// periodic instances; Dirichlet values enter both sides as in BTCS.
+template <typename T>
+void cn_step(int64_t n, int bc, T a, T b, T r, T D, const T* u, T* out) {
+  const T zero = 0, one = 1, two = 2, half = (T)0.5;
+  std::vector<T> l(n), d(n), p(n), rhs(n), cw(n), yw(n);
+  const int64_t first = bc == PERIODIC ? 0 : 1;
+  const int64_t m = bc == PERIODIC ? n : n - 2;
+  for (int64_t k = 0; k < m; ++k) {
+    const int64_t i = first + k;
+    T um, up;
+    if (bc == PERIODIC) {
+      um = u[i == 0 ? n - 1 : i - 1];
+      up = u[i == n - 1 ? 0 : i + 1];
+    } else {
+      um = (i == 1) ? a : u[i - 1];
+      up = (i == n - 2) ? b : u[i + 1];
+    }
+    const T ui = u[i];
+    const T c = r * ui;
+    const T cpos = c > zero ? c : zero;
+    const T cneg = c < zero ? c : zero;
+    const T cabs = c < zero ? -c : c;
+    const T nl = -(D + cpos);
+    const T nd = two * D + cabs;
+    const T np = cneg - D;
+    l[k] = half * nl;
+    d[k] = one + half * nd;
+    p[k] = half * np;
+    rhs[k] = ui - half * ((nl * um + nd * ui) + np * up);
+  }
+  if (bc == PERIODIC) {
+    cyclic_solve(m, l.data(), d.data(), p.data(), rhs.data(), out);
+  } else {
+    rhs[0] = rhs[0] - l[0] * a;
+    rhs[m - 1] = rhs[m - 1] - p[m - 1] * b;
+    thomas(m, l.data(), d.data(), p.data(), rhs.data(), out + 1, cw.data(), yw.data());
+    out[0] = a;
+    out[n - 1] = b;
+  }
+}
+
 // Advance one instance nsteps times with fixed dt.
 template <typename T>
 void run_one(int64_t n, int bc, int scheme, T a, T b, T r, T D, T* u, int64_t nsteps) {
@@ -220,6 +266,7 @@ void run_one(int64_t n, int bc, int scheme, T a, T b, T r, T D, T* u, int64_t ns
   for (int64_t s = 0; s < nsteps; ++s) {
     if (scheme == SCHEME_EXPLICIT) explicit_step(n, bc, a, b, r, D, u, tmp.data());
     else if (scheme == SCHEME_RK4) rk4_step(n, bc, a, b, r, D, u, tmp.data());
+    else if (scheme == SCHEME_CN) cn_step(n, bc, a, b, r, D, u, tmp.data());
     else btcs_step(n, bc, a, b, r, D, u, tmp.data());
     std::memcpy(u, tmp.data(), sizeof(T) * (size_t)n);
   }
@@ -479,6 +526,14 @@ double oracle_cfl_dt(int64_t n, double length, double nu, int bc, double umax, d
 void oracle_explicit_step_f64(int64_t n, int bc, double a, double b, double r, double D,
                               const double* u, double* out) {
   explicit_step<double>(n, bc, a, b, r, D, u, out);
+}
+void oracle_cn_step_f64(int64_t n, int bc, double a, double b, double r, double D, const double* u,
+                        double* out) {
+  cn_step<double>(n, bc, a, b, r, D, u, out);
+}
+void oracle_cn_step_f32(int64_t n, int bc, double a, double b, double r, double D, const float* u,
+                        float* out) {
+  cn_step<float>(n, bc, (float)a, (float)b, (float)r, (float)D, u, out);
 }
 void oracle_rk4_step_f64(int64_t n, int bc, double a, double b, double r, double D, const double* u,
                          double* out) {

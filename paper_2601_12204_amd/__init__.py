@@ -20,6 +20,7 @@ BC_DIRICHLET = 1
 EXPLICIT = 0
 BTCS = 1
 RK4 = 2
+CN = 3
 F32 = 0
 F64 = 1
 ALIGN = 64

@@ -352,6 +352,71 @@ def test_btcs_von_neumann_symbol(oracle_lib, U, C):
     assert np.max(np.abs(got - pred)) < 2e-5
 
 
+# ------------------------------------------------------------------------------------ Crank-Nicolson
+def test_cn_constant_state(oracle_lib):
+    for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+        for U in (1.3, -0.7):
+            p = _with_ratios(33, 6.0, 3.0, U=1.0, bc=bc)
+            p.left = p.right = U
+            u = np.full(33, U)
+            assert np.max(np.abs(oracle_lib.cn_step(p, u) - U)) < 1e-14
+
+
+@pytest.mark.parametrize("U,C", [(1.0, 3.0), (-1.0, -7.0), (2.0, 0.4)])
+@pytest.mark.parametrize("k", [2, 5, 17])
+def test_cn_von_neumann_symbol(oracle_lib, U, C, k):
+    """Linearised, a mode is multiplied by (1 - z/2) / (1 + z/2) with z the symbol of the BTCS operator
+    minus the identity (the convective coefficient's own perturbation drops out: N's rows sum to zero)."""
+    n, D, eps = 64, 2.0, 1e-6
+    p = _with_ratios(n, C, D, U=U)
+    theta = 2 * np.pi * k / n
+    j = np.arange(n)
+    u = U + eps * np.sin(j * theta)
+    if C >= 0:
+        z = C * (1 - np.exp(-1j * theta)) + 4 * D * np.sin(theta / 2) ** 2
+    else:
+        z = C * (np.exp(1j * theta) - 1) + 4 * D * np.sin(theta / 2) ** 2
+    g = (1 - z / 2) / (1 + z / 2)
+    assert abs(g) <= 1 + 1e-12
+    pred = g.real * np.sin(j * theta) + g.imag * np.cos(j * theta)
+    got = (oracle_lib.cn_step(p, u) - U) / eps
+    assert np.max(np.abs(got - pred)) < 2e-5
+
+
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_DIRICHLET])
+def test_cn_is_twice_half_step_btcs_minus_identity(oracle_lib, bc):
+    """(I + N/2)^{-1} (I - N/2) u = 2 (I + N/2)^{-1} u - u, and I + N/2 is the BTCS matrix of dt/2: one
+    Crank-Nicolson step equals twice a half-dt BTCS step minus the old state."""
+    b = W.random_batch(8 + bc, 1, 300, 300, bc=bc, amplitude=2.0)
+    p = b.problems[0]
+    p.dt = 12 * oracle_lib.cfl_dt(p.n, p.length, p.nu, p.bc, float(b.umax[0]), 0.5)
+    u = b.instance(0)
+    half = W.Problem(n=p.n, length=p.length, nu=p.nu, dt=p.dt / 2, bc=p.bc, scheme=W.BTCS, left=p.left,
+                     right=p.right)
+    ref = 2 * oracle_lib.btcs_step(half, u) - u
+    got = oracle_lib.cn_step(p, u)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(u))
+    if bc == W.BC_DIRICHLET:
+        assert got[0] == p.left and got[-1] == p.right
+
+
+def test_cn_second_order_in_time_linear_limit(oracle_lib):
+    """In the linear (small-amplitude, diffusion-dominated) limit halving dt divides the change by 4,
+    against 2 for BTCS: Crank-Nicolson's time weighting.  (With the convective coefficient lagged at
+    t^n the nonlinear scheme is first order, like BTCS; that reading is listed in the design notes.)"""
+    n, nu, T, eps = 64, 0.5, 1.0, 1e-3
+    x = W.node_coordinates(n, 2 * np.pi, W.BC_PERIODIC)
+    ratios = {}
+    for scheme in (W.CN, W.BTCS):
+        sols = []
+        for steps in (10, 20, 40):
+            p = _problem(n, 2 * np.pi, nu, T / steps, scheme=scheme)
+            sols.append(oracle_lib.run([p], eps * np.sin(x), np.array([0, n]), steps))
+        ratios[scheme] = np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[1] - sols[2])
+    assert 3.7 <= ratios[W.CN] <= 4.3, ratios
+    assert 1.8 <= ratios[W.BTCS] <= 2.2, ratios
+
+
 def test_btcs_equivariance(oracle_lib):
     b = W.random_batch(9, 1, 48, 48, bc=W.BC_PERIODIC, amplitude=3.0)
     u = b.instance(0)

@@ -47,6 +47,14 @@ MUTANTS = {
     "adj_g_upwind_side": ("G[i] = y[i] >= 0 ? r * (x[i] - xm) : r * (xp - x[i]);",
                           "G[i] = y[i] >= 0 ? r * (xp - x[i]) : r * (x[i] - xm);"),
     "tangent_drops_nu": ("dout[i] = v + D * dlap + dD * lap;", "dout[i] = v + D * dlap;"),
+    "cn_diag_half": ("d[k] = one + half * nd;", "d[k] = one + nd;"),
+    "cn_rhs_sign": ("rhs[k] = ui - half * ((nl * um + nd * ui) + np * up);",
+                    "rhs[k] = ui + half * ((nl * um + nd * ui) + np * up);"),
+    "cn_rhs_neighbours_swapped": ("rhs[k] = ui - half * ((nl * um + nd * ui) + np * up);",
+                                  "rhs[k] = ui - half * ((nl * up + nd * ui) + np * um);"),
+    "cn_dirichlet_rhs": ("    rhs[0] = rhs[0] - l[0] * a;\n    rhs[m - 1] = rhs[m - 1] - p[m - 1] * b;\n    thomas",
+                         "    rhs[0] = rhs[0] + l[0] * a;\n    rhs[m - 1] = rhs[m - 1] - p[m - 1] * b;\n    thomas"),
+    "cn_sub_uses_half_twice": ("l[k] = half * nl;", "l[k] = half * half * nl;"),
     "rk4_weights": ("(((K1[i] + two * K2[i]) + two * K3[i]) + K4[i]) / six", "(((K1[i] + K2[i]) + K3[i]) + K4[i]) / six"),
     "rk4_half_stage": ("for (int64_t i = 0; i < n; ++i) v[i] = u[i] + half * K1[i];",
                        "for (int64_t i = 0; i < n; ++i) v[i] = u[i] + K1[i];"),

@@ -34,6 +34,7 @@ BC_DIRICHLET = 1
 EXPLICIT = 0
 BTCS = 1
 RK4 = 2
+CN = 3
 
 SEED_BASE = 12204
 TWO_PI = 2.0 * math.pi
