@@ -145,6 +145,31 @@ def bench_c2_rk4(B, torch, nsteps=2500, reps=2):
             "stage_glups": 4 * nodes * nsteps / (ms * 1e-3) / 1e9}
 
 
+def bench_c2_cn(B, torch, nsteps=1000, reps=2):
+    """The C2 batch advanced by Crank-Nicolson at 10x the explicit dt: each step one half-dt BTCS solve
+    through HBM (the whole-system workgroup solver) and the combination u' = 2y - u."""
+    import workloads as W
+    batch = W.c2_batch()
+    cfl_batch(B, batch, 10.0)
+    for p in batch.problems:
+        p.scheme = W.CN
+    s = B.Solver(batch.problems, dtype=torch.float64)
+    u0 = s.pack_flat(batch.u0, batch.offsets)
+    u = torch.empty_like(u0)
+    u.copy_(u0)
+    s.run(u, 2)                                  # warm-up (plans)
+    timer = PhaseTimer()
+    for _ in range(reps):
+        u.copy_(u0)
+        timer.mark("run")
+        s.run(u, nsteps)
+        timer.mark("copy")
+    ms = float(np.mean(timer.spans()["run"]))
+    s.close()
+    nodes = 4096 * 8192
+    return {"ms": ms, "steps": nsteps, "glups": nodes * nsteps / (ms * 1e-3) / 1e9}
+
+
 def bench_c1_latency(B, torch, solves=200):
     """Single periodic N=101 sawtooth to t=0.5: latency of one whole solve (explicit 113 steps, BTCS 12)."""
     import workloads as W
@@ -403,7 +428,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
-    ap.add_argument("--legs", default="c2,c2f32,c2rk4,c1,c3,c4,c5,serve",
+    ap.add_argument("--legs", default="c2,c2f32,c2rk4,c2cn,c1,c3,c4,c5,serve",
                     help="comma-separated side measurements to run (profiling runs select one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--exp-steps", type=int, default=10_000, help="explicit steps per step (profiling runs)")
@@ -436,6 +461,9 @@ def main():
     if "c2rk4" in legs:
         log("C2 RK4")
         extra["c2_rk4_f64"] = bench_c2_rk4(B, torch)
+    if "c2cn" in legs:
+        log("C2 Crank-Nicolson")
+        extra["c2_cn_f64"] = bench_c2_cn(B, torch)
     if "c1" in legs:
         log("C1 latency")
         extra["c1_latency"] = bench_c1_latency(B, torch)

@@ -745,7 +745,8 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   double* LC = ctx->level_c.as<double>();
   double* LD = ctx->level_d.as<double>();
   double* LX = ctx->level_x.as<double>();
-  const InstDesc* inst = ctx->inst.as<InstDesc>();
+  const InstDesc* inst = plan.inst_half && plan.inst_half->ptr ? plan.inst_half->as<InstDesc>()
+                                                               : ctx->inst.as<InstDesc>();
   hipStream_t st = ctx->stream;
   const int L = static_cast<int>(plan.levels.size());
   // forward: reduce level by level
@@ -881,6 +882,39 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
       btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
                                                                       lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);
   }
+  return hipGetLastError();
+}
+
+namespace {
+
+// Crank-Nicolson from a half-dt BTCS solution (see the plan): one 256-node tile per workgroup.
+template <typename S>
+__global__ __launch_bounds__(256) void cn_combine_kernel(const InstDesc* __restrict__ inst,
+                                                         const Tile* __restrict__ tiles,
+                                                         const S* __restrict__ u, S* __restrict__ y) {
+  const Tile t = tiles[blockIdx.x];
+  const int j = t.start + static_cast<int>(threadIdx.x);
+  if (j >= t.n) return;
+  const int64_t k = t.off + j;
+  if (t.bc == kDirichlet && (j == 0 || j == t.n - 1)) {
+    const InstDesc d = inst[t.inst];
+    y[k] = static_cast<S>(j == 0 ? d.a : d.b);
+    return;
+  }
+  y[k] = static_cast<S>(2.0 * static_cast<double>(y[k]) - static_cast<double>(u[k]));
+}
+
+}  // namespace
+
+hipError_t launch_cn_combine(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* u, void* y) {
+  if (n_tiles <= 0) return hipSuccess;
+  const InstDesc* inst = ctx->inst.as<InstDesc>();
+  if (ctx->dtype == BURGERS_F64)
+    cn_combine_kernel<double><<<static_cast<unsigned>(n_tiles), 256, 0, ctx->stream>>>(
+        inst, tiles, static_cast<const double*>(u), static_cast<double*>(y));
+  else
+    cn_combine_kernel<float><<<static_cast<unsigned>(n_tiles), 256, 0, ctx->stream>>>(
+        inst, tiles, static_cast<const float*>(u), static_cast<float*>(y));
   return hipGetLastError();
 }
 

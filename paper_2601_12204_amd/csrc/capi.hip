@@ -32,7 +32,7 @@ bool valid_problem(const burgers_problem& p) {
   if (!is_finite(p.nu) || p.nu < 0) return false;
   if (!is_finite(p.dt) || p.dt <= 0) return false;
   if (p.bc != BURGERS_BC_PERIODIC && p.bc != BURGERS_BC_DIRICHLET) return false;
-  if (p.scheme != BURGERS_EXPLICIT && p.scheme != BURGERS_BTCS && p.scheme != BURGERS_RK4) return false;
+  if (p.scheme < BURGERS_EXPLICIT || p.scheme > BURGERS_CN) return false;
   if (!is_finite(p.left) || !is_finite(p.right)) return false;
   return true;
 }
@@ -205,15 +205,19 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     groups[std::make_tuple(w.lanes, w.chunk, w.exact)].push_back(
         SysDesc{0, -1, rows, burgers::btcs_chunks(rows, w.lanes), i, 0});
   };
-  std::vector<int32_t> stepped;
+  std::vector<int32_t> stepped, cn;
   std::vector<std::vector<SysDesc>> red_sys, wg_sys;
   int64_t rows_used = 0;
   for (int32_t i : set_members(ctx, set)) {
     const burgers_problem& p = ctx->probs[i];
     const int32_t R0 = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
     const bool fits = R0 <= cap;
-    if (want == 2 && !fits) return BURGERS_E_UNSUPPORTED;
-    if ((want == 0 || want == 2) && fits) {
+    // Crank-Nicolson instances (advanced by their own scheme) need the old state after each solve, so
+    // they always step through HBM
+    const bool is_cn = set == kSetBtcs && p.scheme == BURGERS_CN;
+    if (is_cn) cn.push_back(i);
+    if (want == 2 && (!fits || is_cn)) return BURGERS_E_UNSUPPORTED;
+    if ((want == 0 || want == 2) && fits && !is_cn) {
       whole(resident, R0, i);
       continue;
     }
@@ -262,6 +266,22 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   plan->copy = std::make_unique<DevBuf>();
   auto ct = stream_tiles(ctx, stepped);
   plan->n_copy = static_cast<int64_t>(ct.size());
+  plan->inst_half = std::make_unique<DevBuf>();
+  plan->cn_tiles = std::make_unique<DevBuf>();
+  if (!cn.empty()) {
+    std::vector<burgers::InstDesc> half = ctx->inst_host;
+    std::vector<Tile> tiles;
+    for (int32_t i : cn) {
+      half[i].r = 0.5 * half[i].r;               // the BTCS rows of dt/2 (exact: a power of two)
+      half[i].D = 0.5 * half[i].D;
+      const int32_t n = static_cast<int32_t>(ctx->probs[i].n);
+      for (int32_t s0 = 0; s0 < n; s0 += 256) tiles.push_back(Tile{ctx->offsets[i], n, ctx->probs[i].bc, i, s0});
+    }
+    plan->n_cn_tiles = static_cast<int64_t>(tiles.size());
+    if ((e = upload_on(ctx->stream, *plan->inst_half, half)) != hipSuccess ||
+        (e = upload_on(ctx->stream, *plan->cn_tiles, tiles)) != hipSuccess)
+      return from_hip(e);
+  }
   if ((e = upload_groups(wg_state, plan->wg_state)) != hipSuccess ||
       (e = upload_groups(resident, plan->resident)) != hipSuccess ||
       (e = upload_on(ctx->stream, *plan->copy, ct)) != hipSuccess)
@@ -362,6 +382,9 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
   int cur = 0;
   for (int64_t s = 0; s < nsteps; ++s) {
     if ((e = burgers::launch_btcs_step(ctx, pl, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+    if (pl.n_cn_tiles &&
+        (e = burgers::launch_cn_combine(ctx, pl.cn_tiles->as<Tile>(), pl.n_cn_tiles, bufs[cur], bufs[cur ^ 1])) != hipSuccess)
+      return e;
     cur ^= 1;
   }
   if (cur) e = burgers::launch_copy_tiles(ctx, pl.copy->as<Tile>(), pl.n_copy, ctx->work.ptr, u);
@@ -628,7 +651,8 @@ burgers_status burgers_create(const burgers_problem* problems, int64_t count, bu
     d.a = p.bc == BURGERS_BC_DIRICHLET ? p.left : 0.0;
     d.b = p.bc == BURGERS_BC_DIRICHLET ? p.right : 0.0;
     ctx->set_all.push_back(static_cast<int32_t>(i));
-    (p.scheme == BURGERS_BTCS ? ctx->set_btcs : ctx->set_explicit).push_back(static_cast<int32_t>(i));
+    (p.scheme == BURGERS_BTCS || p.scheme == BURGERS_CN ? ctx->set_btcs : ctx->set_explicit)
+        .push_back(static_cast<int32_t>(i));
   }
   burgers_status st = BURGERS_OK;
   if ((e = upload_on(ctx->stream, ctx->inst, ctx->inst_host)) != hipSuccess) st = from_hip(e);
@@ -765,8 +789,8 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   if (!ctx || !u0 || !lambda_T || !grad_u0 || !grad_nu || nsteps < 0 || ckpt_every < 1)
     return BURGERS_E_INVALID;
   if (ctx->dtype != BURGERS_F64) return BURGERS_E_UNSUPPORTED;
-  for (const auto& p : ctx->probs)
-    if (p.scheme == BURGERS_RK4) return BURGERS_E_UNSUPPORTED;   // adjoint of forward Euler and BTCS only
+  for (const auto& p : ctx->probs)   // adjoint of forward Euler and BTCS only
+    if (p.scheme == BURGERS_RK4 || p.scheme == BURGERS_CN) return BURGERS_E_UNSUPPORTED;
   if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return note(ctx, e);

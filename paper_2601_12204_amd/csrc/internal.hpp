@@ -137,6 +137,11 @@ struct BtcsPlan {
   std::unique_ptr<DevBuf> copy;              // Tile[] of the instances stepped through HBM (copy-back)
   int64_t n_copy = 0;
   std::vector<WgGroup> wg_state;             // solved whole per step, straight from and to the state
+  // Crank-Nicolson instances: solved per step with the coefficients of dt/2 (a copy of the instance
+  // table with r and D halved), then combined as u' = 2 y - u over their tiles
+  std::unique_ptr<DevBuf> inst_half;         // InstDesc[count], or empty: the context's table
+  std::unique_ptr<DevBuf> cn_tiles;          // Tile[] of the Crank-Nicolson instances
+  int64_t n_cn_tiles = 0;
   // partition hierarchy for the long systems
   struct Level {
     std::unique_ptr<DevBuf> sys;             // SysDesc[] of the systems reduced at this level
@@ -242,6 +247,8 @@ WidthClass btcs_width_class(int rows, int threads);
 int btcs_chunks(int rows, int threads);
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
                               double* LD, double* LX);
+// y = 2 y - u over the tiles (Crank-Nicolson from a half-dt BTCS solve y); Dirichlet ends get a and b.
+hipError_t launch_cn_combine(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* u, void* y);
 constexpr int kResidentThreadsDefault = 512;
 
 }  // namespace burgers

@@ -436,3 +436,45 @@ def test_rk4_unsupported_paths():
     s.close()
     got = device_run(batch, 9, "f64", how="step_explicit")
     assert np.array_equal(got, oracle_run(batch, 9, "f64", scheme=W.EXPLICIT))
+
+
+# ----------------------------------------------------------------------------- Crank-Nicolson
+def _cn_batch(seed):
+    sizes = [3, 4, 33, 1000, 8190, 8192, 8193, 20000, 300001]
+    problems, states = [], []
+    for k, n in enumerate(sizes):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            b = W.random_batch(seed + 13 * k + bc, 1, n, n, bc=bc, scheme=W.CN, amplitude=3.0)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    return set_cfl_steps(W._pack(problems, states))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_cn_parity(dtype):
+    """Crank-Nicolson instances (whole systems and block-partitioned long ones, both BCs) at 10x the
+    explicit dt against the oracle's direct (I + N/2) u' = (I - N/2) u solve."""
+    batch = _cn_batch(97)
+    announce(f"cn {dtype} 9 steps")
+    got = device_run(batch, 9, dtype, how="run")
+    check_batch(batch, got, 9, dtype)
+
+
+def test_cn_mixed_and_unsupported():
+    """BTCS and Crank-Nicolson instances in one context each get their own scheme; btcs_step steps every
+    instance with BTCS; a plan forcing the on-chip BTCS path rejects Crank-Nicolson instances."""
+    import paper_2601_12204_amd as B
+    batch = W.random_batch(101, 24, 3, 30000, amplitude=2.0)
+    for k, p in enumerate(batch.problems):
+        p.scheme = (W.BTCS, W.CN, W.EXPLICIT)[k % 3]
+    set_cfl_steps(batch)
+    announce("cn + btcs + euler run, btcs_step, forced resident")
+    got = device_run(batch, 7, "f64", how="run")
+    check_batch(batch, got, 7, "f64")
+    got = device_run(batch, 5, "f64", how="step_btcs")
+    check_batch(batch, got, 5, "f64", scheme=W.BTCS)
+    fit = W.random_batch(103, 6, 3, 8000, scheme=W.CN, amplitude=2.0)
+    set_cfl_steps(fit)
+    with pytest.raises(B.BurgersError) as err:
+        device_run(fit, 2, "f64", how="run", plan=dict(btcs_path=2))
+    assert err.value.status == -2
