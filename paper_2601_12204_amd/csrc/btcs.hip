@@ -311,6 +311,19 @@ __device__ __forceinline__ void stage_out(const S* stage, S* __restrict__ dst, i
   }
 }
 
+// Crank-Nicolson store: the staged rows hold the half-dt BTCS solution y; write 2 y - u, with u re-read
+// (coalesced) from the old state.
+template <typename S, int NT = kReduceBlock, int J = kRedChunk>
+__device__ __forceinline__ void stage_out_cn(const S* stage, const S* __restrict__ old, S* __restrict__ dst,
+                                             int cnt) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = static_cast<int>(threadIdx.x) + j * NT;
+    if (i < cnt)
+      dst[i] = static_cast<S>(2.0 * static_cast<double>(stage[padded(i)]) - static_cast<double>(old[i]));
+  }
+}
+
 // Whole-system solver: one workgroup per system.  Level-0 systems stage the old state through LDS
 // (coalesced loads), eliminate chunks from LDS, solve the reduced system by PCR in the same LDS, write
 // the new values back into the staging buffer and store them coalesced, with the Dirichlet boundary
@@ -360,7 +373,10 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
       T al, be, ga, de;
       if constexpr (FromState) {
         ssrc.row(0, 0, 1, al, be, ga, de);
-        out[d.off + 1] = static_cast<S>(((de - al * d.a) - ga * d.b) / be);
+        const T y = ((de - al * d.a) - ga * d.b) / be;
+        out[d.off + 1] = sys.cn ? static_cast<S>(2.0 * static_cast<double>(static_cast<S>(y)) -
+                                                 static_cast<double>(u[d.off + 1]))
+                                : static_cast<S>(y);
       } else {
         asrc.row(0, 0, 1, al, be, ga, de);
         adst.write(0, 0, de / be);
@@ -400,7 +416,9 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
     __syncthreads();                           // all ends read before the staging buffer is reused
     if (tid < P) chunk_recover<T, MC>(sdst, s, m, al, ga, de, F, E);
     __syncthreads();
-    stage_out<S, NT, MC>(stage, out + d.off + (d.bc == kDirichlet ? 1 : 0), R);
+    const int64_t o = d.off + (d.bc == kDirichlet ? 1 : 0);
+    if (sys.cn) stage_out_cn<S, NT, MC>(stage, u + o, out + o, R);
+    else stage_out<S, NT, MC>(stage, out + o, R);
   } else {
     if (tid < P) chunk_recover<T, MC>(adst, s, m, al, ga, de, F, E);
   }
@@ -730,7 +748,9 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   __syncthreads();                             // spike rows read before the stage is rewritten
   if (tid < Pb) chunk_recover<T, kRedChunk>(LdsDst<S>{stage, rs}, s, m, al, ga, de, F, E);
   __syncthreads();
-  stage_out(stage, out + d.off + (dir ? 1 : 0) + rs, re - rs);
+  const int64_t o = d.off + (dir ? 1 : 0) + rs;
+  if (sys.cn) stage_out_cn(stage, u + o, out + o, re - rs);
+  else stage_out(stage, out + o, re - rs);
   if (dir && tid == 0) {
     if (cb.chunk0 == 0) out[d.off] = static_cast<S>(d.a);
     if (cb.chunk0 + kReduceBlock >= sys.chunks) out[d.off + d.n - 1] = static_cast<S>(d.b);
@@ -882,39 +902,6 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
       btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
                                                                       lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);
   }
-  return hipGetLastError();
-}
-
-namespace {
-
-// Crank-Nicolson from a half-dt BTCS solution (see the plan): one 256-node tile per workgroup.
-template <typename S>
-__global__ __launch_bounds__(256) void cn_combine_kernel(const InstDesc* __restrict__ inst,
-                                                         const Tile* __restrict__ tiles,
-                                                         const S* __restrict__ u, S* __restrict__ y) {
-  const Tile t = tiles[blockIdx.x];
-  const int j = t.start + static_cast<int>(threadIdx.x);
-  if (j >= t.n) return;
-  const int64_t k = t.off + j;
-  if (t.bc == kDirichlet && (j == 0 || j == t.n - 1)) {
-    const InstDesc d = inst[t.inst];
-    y[k] = static_cast<S>(j == 0 ? d.a : d.b);
-    return;
-  }
-  y[k] = static_cast<S>(2.0 * static_cast<double>(y[k]) - static_cast<double>(u[k]));
-}
-
-}  // namespace
-
-hipError_t launch_cn_combine(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* u, void* y) {
-  if (n_tiles <= 0) return hipSuccess;
-  const InstDesc* inst = ctx->inst.as<InstDesc>();
-  if (ctx->dtype == BURGERS_F64)
-    cn_combine_kernel<double><<<static_cast<unsigned>(n_tiles), 256, 0, ctx->stream>>>(
-        inst, tiles, static_cast<const double*>(u), static_cast<double*>(y));
-  else
-    cn_combine_kernel<float><<<static_cast<unsigned>(n_tiles), 256, 0, ctx->stream>>>(
-        inst, tiles, static_cast<const float*>(u), static_cast<float*>(y));
   return hipGetLastError();
 }
 

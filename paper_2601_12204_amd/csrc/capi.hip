@@ -200,10 +200,11 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   const int chunk = burgers::btcs_reduce_chunk();
   // whole-system systems grouped by width class (lanes, chunk, exact)
   std::map<std::tuple<int, int, bool>, std::vector<SysDesc>> wg_state, resident;
-  auto whole = [&](std::map<std::tuple<int, int, bool>, std::vector<SysDesc>>& groups, int32_t rows, int32_t i) {
+  auto whole = [&](std::map<std::tuple<int, int, bool>, std::vector<SysDesc>>& groups, int32_t rows, int32_t i,
+                   bool is_cn) {
     const burgers::WidthClass w = burgers::btcs_width_class(rows, threads);
     groups[std::make_tuple(w.lanes, w.chunk, w.exact)].push_back(
-        SysDesc{0, -1, rows, burgers::btcs_chunks(rows, w.lanes), i, 0});
+        SysDesc{0, -1, rows, burgers::btcs_chunks(rows, w.lanes), i, 0, is_cn ? 1 : 0});
   };
   std::vector<int32_t> stepped, cn;
   std::vector<std::vector<SysDesc>> red_sys, wg_sys;
@@ -218,13 +219,13 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     if (is_cn) cn.push_back(i);
     if (want == 2 && (!fits || is_cn)) return BURGERS_E_UNSUPPORTED;
     if ((want == 0 || want == 2) && fits && !is_cn) {
-      whole(resident, R0, i);
+      whole(resident, R0, i, false);
       continue;
     }
     stepped.push_back(i);
     const bool partition = want == 3 ? R0 >= 32 : !fits;
     if (!partition) {
-      whole(wg_state, R0, i);
+      whole(wg_state, R0, i, is_cn);
       continue;
     }
     int32_t R = R0;
@@ -242,7 +243,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
       const int32_t out_rows = reduced_rows(level, P);
       const int64_t red = rows_used;
       rows_used += out_rows;
-      red_sys[level].push_back(SysDesc{in_off, red, R, P, i, level});
+      red_sys[level].push_back(SysDesc{in_off, red, R, P, i, level, (level == 0 && is_cn) ? 1 : 0});
       in_off = red;
       R = out_rows;
     }
@@ -267,20 +268,13 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   auto ct = stream_tiles(ctx, stepped);
   plan->n_copy = static_cast<int64_t>(ct.size());
   plan->inst_half = std::make_unique<DevBuf>();
-  plan->cn_tiles = std::make_unique<DevBuf>();
   if (!cn.empty()) {
     std::vector<burgers::InstDesc> half = ctx->inst_host;
-    std::vector<Tile> tiles;
     for (int32_t i : cn) {
       half[i].r = 0.5 * half[i].r;               // the BTCS rows of dt/2 (exact: a power of two)
       half[i].D = 0.5 * half[i].D;
-      const int32_t n = static_cast<int32_t>(ctx->probs[i].n);
-      for (int32_t s0 = 0; s0 < n; s0 += 256) tiles.push_back(Tile{ctx->offsets[i], n, ctx->probs[i].bc, i, s0});
     }
-    plan->n_cn_tiles = static_cast<int64_t>(tiles.size());
-    if ((e = upload_on(ctx->stream, *plan->inst_half, half)) != hipSuccess ||
-        (e = upload_on(ctx->stream, *plan->cn_tiles, tiles)) != hipSuccess)
-      return from_hip(e);
+    if ((e = upload_on(ctx->stream, *plan->inst_half, half)) != hipSuccess) return from_hip(e);
   }
   if ((e = upload_groups(wg_state, plan->wg_state)) != hipSuccess ||
       (e = upload_groups(resident, plan->resident)) != hipSuccess ||
@@ -382,9 +376,6 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
   int cur = 0;
   for (int64_t s = 0; s < nsteps; ++s) {
     if ((e = burgers::launch_btcs_step(ctx, pl, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
-    if (pl.n_cn_tiles &&
-        (e = burgers::launch_cn_combine(ctx, pl.cn_tiles->as<Tile>(), pl.n_cn_tiles, bufs[cur], bufs[cur ^ 1])) != hipSuccess)
-      return e;
     cur ^= 1;
   }
   if (cur) e = burgers::launch_copy_tiles(ctx, pl.copy->as<Tile>(), pl.n_copy, ctx->work.ptr, u);

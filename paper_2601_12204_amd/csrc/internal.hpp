@@ -76,6 +76,8 @@ struct SysDesc {
   int32_t chunks;
   int32_t inst;
   int32_t level;
+  int32_t cn = 0;   // level-0 Crank-Nicolson system: the solve is the half-dt BTCS one, stored as 2y - u
+  int32_t pad = 0;
 };
 
 // A block of consecutive chunks of one system (reduce and back-substitution kernels).
@@ -138,10 +140,8 @@ struct BtcsPlan {
   int64_t n_copy = 0;
   std::vector<WgGroup> wg_state;             // solved whole per step, straight from and to the state
   // Crank-Nicolson instances: solved per step with the coefficients of dt/2 (a copy of the instance
-  // table with r and D halved), then combined as u' = 2 y - u over their tiles
+  // table with r and D halved); their systems carry the `cn` flag and store u' = 2 y - u
   std::unique_ptr<DevBuf> inst_half;         // InstDesc[count], or empty: the context's table
-  std::unique_ptr<DevBuf> cn_tiles;          // Tile[] of the Crank-Nicolson instances
-  int64_t n_cn_tiles = 0;
   // partition hierarchy for the long systems
   struct Level {
     std::unique_ptr<DevBuf> sys;             // SysDesc[] of the systems reduced at this level
@@ -247,8 +247,6 @@ WidthClass btcs_width_class(int rows, int threads);
 int btcs_chunks(int rows, int threads);
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
                               double* LD, double* LX);
-// y = 2 y - u over the tiles (Crank-Nicolson from a half-dt BTCS solve y); Dirichlet ends get a and b.
-hipError_t launch_cn_combine(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* u, void* y);
 constexpr int kResidentThreadsDefault = 512;
 
 }  // namespace burgers
