@@ -11,6 +11,7 @@ Functions and the passages they follow (Potluri et al., arXiv 2601.12204):
   explicit_step     eq. 21, upwind direction by sign of u_i (text after eq. 3)
   rk4_step          eq. 22: classical RK4 over eq. 21's spatial operator
   cn_step           Crank-Nicolson (Sec. 2.2) with the BTCS lagged operator
+  newton_step       fully implicit central-convection step by Newton-Raphson (eqs. 10-14)
   btcs_assemble     Sec. 2.4 / eq. 23 with the convective coefficient lagged at u^n
   thomas, cyclic    tridiagonal and cyclic (Sherman-Morrison) solves of eq. 23
   btcs_step         assemble + solve
@@ -62,6 +63,9 @@ def configure(lib):
             f = getattr(lib, f"oracle_{fn}_step_{name}")
             f.restype = None
             f.argtypes = [i64, c_int, dbl, dbl, dbl, dbl, ptr, ptr]
+        f = getattr(lib, f"oracle_newton_step_{name}")
+        f.restype = None
+        f.argtypes = [i64, c_int, dbl, dbl, dbl, dbl, ptr, ptr, c_int]
         f = getattr(lib, f"oracle_explicit_step_{name}")
         f.restype = None
         f.argtypes = [i64, c_int, dbl, dbl, dbl, dbl, ptr, ptr]
@@ -71,6 +75,8 @@ def configure(lib):
         f = getattr(lib, f"oracle_run_{name}")
         f.restype = None
         f.argtypes = [i64, _i64p, _i32p, _i32p, _dp, _dp, _dp, _dp, ptr, i64, c_int]
+    lib.oracle_newton_iters.restype = c_int
+    lib.oracle_newton_iters.argtypes = []
     lib.oracle_btcs_assemble_f64.restype = i64
     lib.oracle_btcs_assemble_f64.argtypes = [i64, c_int, dbl, dbl, dbl, dbl, _dp, _dp, _dp, _dp, _dp]
     lib.oracle_thomas_f64.restype = None
@@ -136,6 +142,20 @@ def rk4_step(p, u: np.ndarray) -> np.ndarray:
     r, D = ratios(p)
     getattr(_load(), f"oracle_rk4_step_{_tag(u.dtype)}")(p.n, p.bc, p.left, p.right, r, D, _ptr(u), _ptr(out))
     return out
+
+
+def newton_step(p, u: np.ndarray, iters: Optional[int] = None) -> np.ndarray:
+    u = np.ascontiguousarray(u)
+    out = np.empty_like(u)
+    r, D = ratios(p)
+    it = _load().oracle_newton_iters() if iters is None else iters
+    getattr(_load(), f"oracle_newton_step_{_tag(u.dtype)}")(p.n, p.bc, p.left, p.right, r, D, _ptr(u), _ptr(out),
+                                                          it)
+    return out
+
+
+def newton_iters() -> int:
+    return _load().oracle_newton_iters()
 
 
 def cn_step(p, u: np.ndarray) -> np.ndarray:

@@ -34,7 +34,10 @@
 namespace {
 
 enum { PERIODIC = 0, DIRICHLET = 1 };
-enum { SCHEME_EXPLICIT = 0, SCHEME_BTCS = 1, SCHEME_RK4 = 2, SCHEME_CN = 3 };
+enum { SCHEME_EXPLICIT = 0, SCHEME_BTCS = 1, SCHEME_RK4 = 2, SCHEME_CN = 3, SCHEME_NEWTON = 4 };
+
+// Newton-Raphson iterations per implicit central-convection step (a fixed count; see newton_step).
+constexpr int kNewtonIters = 4;
 
 // Sec. 2.2: grid spacing for N stored nodes.
 double grid_dx(int64_t n, double length, int bc) {
@@ -259,6 +262,46 @@ void cn_step(int64_t n, int bc, T a, T b, T r, T D, const T* u, T* out) {
   }
 }
 
+// Fully implicit step with central convection (Sec. 2.4, eqs. 10-14): solve F(x) = 0 with
+//   F_i(x) = (x_i - u_i) + ((r/2) x_i (x_{i+1} - x_{i-1}) - D ((x_{i+1} + x_{i-1}) - 2 x_i)),
+// r = dt/dx, D = nu dt/dx^2 (eq. 11 with dt folded in), by Newton-Raphson from x = u: J(x) delta = -F(x),
+// x = x + delta (eqs. 12-13).  J is tridiagonal (eq. 14), cyclic for periodic instances:
+//   J_{i,i-1} = -(r/2) x_i - D,  J_{i,i} = (1 + 2D) + (r/2)(x_{i+1} - x_{i-1}),  J_{i,i+1} = (r/2) x_i - D
+// (eq. 15 is garbled; these are the derivatives of eq. 11).  Dirichlet values are fixed and enter F.
+// `iters` iterations, no pivoting (the Jacobian is diagonally dominant while the cell Peclet number
+// (r/2)|x_i| / D stays below 1 and the step is moderate).
+template <typename T>
+void newton_step(int64_t n, int bc, T a, T b, T r, T D, const T* u, T* out, int iters) {
+  const T one = 1, two = 2, half_r = r / two;
+  std::vector<T> x(u, u + n), l(n), d(n), p(n), rhs(n), dx(n), cw(n), yw(n);
+  if (bc == DIRICHLET) {
+    x[0] = a;
+    x[n - 1] = b;
+  }
+  const int64_t first = bc == PERIODIC ? 0 : 1;
+  const int64_t m = bc == PERIODIC ? n : n - 2;
+  for (int it = 0; it < iters; ++it) {
+    for (int64_t k = 0; k < m; ++k) {
+      const int64_t i = first + k;
+      const T xm = x[i == 0 ? n - 1 : i - 1];
+      const T xp = x[i == n - 1 ? 0 : i + 1];
+      const T xi = x[i];
+      const T F = (xi - u[i]) + (half_r * xi * (xp - xm) - D * ((xp + xm) - two * xi));
+      l[k] = -(half_r * xi) - D;
+      d[k] = (one + two * D) + half_r * (xp - xm);
+      p[k] = half_r * xi - D;
+      rhs[k] = -F;
+    }
+    if (bc == PERIODIC) {
+      cyclic_solve(m, l.data(), d.data(), p.data(), rhs.data(), dx.data());
+    } else {
+      thomas(m, l.data(), d.data(), p.data(), rhs.data(), dx.data(), cw.data(), yw.data());
+    }
+    for (int64_t k = 0; k < m; ++k) x[first + k] = x[first + k] + dx[k];
+  }
+  std::copy(x.begin(), x.end(), out);
+}
+
 // Advance one instance nsteps times with fixed dt.
 template <typename T>
 void run_one(int64_t n, int bc, int scheme, T a, T b, T r, T D, T* u, int64_t nsteps) {
@@ -267,6 +310,7 @@ void run_one(int64_t n, int bc, int scheme, T a, T b, T r, T D, T* u, int64_t ns
     if (scheme == SCHEME_EXPLICIT) explicit_step(n, bc, a, b, r, D, u, tmp.data());
     else if (scheme == SCHEME_RK4) rk4_step(n, bc, a, b, r, D, u, tmp.data());
     else if (scheme == SCHEME_CN) cn_step(n, bc, a, b, r, D, u, tmp.data());
+    else if (scheme == SCHEME_NEWTON) newton_step(n, bc, a, b, r, D, u, tmp.data(), kNewtonIters);
     else btcs_step(n, bc, a, b, r, D, u, tmp.data());
     std::memcpy(u, tmp.data(), sizeof(T) * (size_t)n);
   }
@@ -527,6 +571,15 @@ void oracle_explicit_step_f64(int64_t n, int bc, double a, double b, double r, d
                               const double* u, double* out) {
   explicit_step<double>(n, bc, a, b, r, D, u, out);
 }
+void oracle_newton_step_f64(int64_t n, int bc, double a, double b, double r, double D, const double* u,
+                            double* out, int iters) {
+  newton_step<double>(n, bc, a, b, r, D, u, out, iters);
+}
+void oracle_newton_step_f32(int64_t n, int bc, double a, double b, double r, double D, const float* u,
+                            float* out, int iters) {
+  newton_step<float>(n, bc, (float)a, (float)b, (float)r, (float)D, u, out, iters);
+}
+int oracle_newton_iters() { return kNewtonIters; }
 void oracle_cn_step_f64(int64_t n, int bc, double a, double b, double r, double D, const double* u,
                         double* out) {
   cn_step<double>(n, bc, a, b, r, D, u, out);

@@ -21,6 +21,7 @@ EXPLICIT = 0
 BTCS = 1
 RK4 = 2
 CN = 3
+NEWTON = 4
 F32 = 0
 F64 = 1
 ALIGN = 64

@@ -13,6 +13,7 @@ import os
 import numpy as np
 import pytest
 
+import oracle
 import workloads as W
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_statements.json")))
@@ -415,6 +416,63 @@ def test_cn_second_order_in_time_linear_limit(oracle_lib):
         ratios[scheme] = np.linalg.norm(sols[0] - sols[1]) / np.linalg.norm(sols[1] - sols[2])
     assert 3.7 <= ratios[W.CN] <= 4.3, ratios
     assert 1.8 <= ratios[W.BTCS] <= 2.2, ratios
+
+
+# ------------------------------------------------------------------------------------ Newton (eqs. 10-15)
+def _newton_case(seed, bc, factor=1.0, amplitude=1.5, n=160):
+    b = W.random_batch(seed, 1, n, n, bc=bc, amplitude=amplitude)
+    p = b.problems[0]
+    p.scheme = W.NEWTON
+    p.dt = factor * oracle.cfl_dt(p.n, p.length, p.nu, p.bc, float(b.umax[0]), 0.5)
+    return p, b.instance(0)
+
+
+def test_newton_constant_state(oracle_lib):
+    for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+        p = _with_ratios(40, 0.5, 0.4, U=1.0, bc=bc)
+        p.left = p.right = 0.8
+        u = np.full(40, 0.8)
+        assert np.array_equal(oracle_lib.newton_step(p, u), u)
+
+
+@pytest.mark.parametrize("bc", [W.BC_PERIODIC, W.BC_DIRICHLET])
+@pytest.mark.parametrize("factor", [1.0, 4.0])
+def test_newton_converges_quadratically(oracle_lib, bc, factor):
+    """Errors of successive Newton iterates against the converged root fall quadratically (eq. 12 with
+    the exact Jacobian of eq. 11), and the fixed iteration count reaches rounding level."""
+    p, u = _newton_case(21 + bc, bc, factor)
+    ref = oracle_lib.newton_step(p, u, 12)
+    errs = [np.max(np.abs(oracle_lib.newton_step(p, u, k) - ref)) for k in (1, 2, 3)]
+    assert errs[1] <= 50 * errs[0] ** 2 and errs[2] <= 50 * errs[1] ** 2 + 1e-15, errs
+    assert np.max(np.abs(oracle_lib.newton_step(p, u) - ref)) <= 4e-15 * np.max(np.abs(u))
+
+
+@pytest.mark.parametrize("U,C", [(1.0, 0.4), (-1.0, -0.8), (2.0, 0.1)])
+@pytest.mark.parametrize("k", [2, 7, 19])
+def test_newton_von_neumann_symbol(oracle_lib, U, C, k):
+    """Linearised about a constant state the fully implicit central step multiplies a mode by
+    1 / (1 + i C sin(theta) + 4 D sin^2(theta/2)), C = r U (central convection, eq. 11)."""
+    n, D, eps = 64, 1.5, 1e-6
+    p = _with_ratios(n, C, D, U=U)
+    theta = 2 * np.pi * k / n
+    j = np.arange(n)
+    u = U + eps * np.sin(j * theta)
+    g = 1 / (1 + 1j * C * np.sin(theta) + 4 * D * np.sin(theta / 2) ** 2)
+    pred = g.real * np.sin(j * theta) + g.imag * np.cos(j * theta)
+    got = (oracle_lib.newton_step(p, u) - U) / eps
+    assert np.max(np.abs(got - pred)) < 2e-5
+
+
+def test_newton_symmetries(oracle_lib):
+    """Translation equivariance (periodic) and the Burgers reflection u(x) -> -u(-x), which the central
+    scheme keeps exactly; Dirichlet ends are held."""
+    p, u = _newton_case(31, W.BC_PERIODIC)
+    assert np.array_equal(np.roll(oracle_lib.newton_step(p, u), 5), oracle_lib.newton_step(p, np.roll(u, 5)))
+    refl = lambda v: -np.roll(v[::-1], 1)
+    assert np.max(np.abs(oracle_lib.newton_step(p, refl(u)) - refl(oracle_lib.newton_step(p, u)))) < 1e-14
+    q, v = _newton_case(33, W.BC_DIRICHLET)
+    out = oracle_lib.newton_step(q, v)
+    assert out[0] == q.left and out[-1] == q.right
 
 
 def test_btcs_equivariance(oracle_lib):

@@ -47,6 +47,14 @@ MUTANTS = {
     "adj_g_upwind_side": ("G[i] = y[i] >= 0 ? r * (x[i] - xm) : r * (xp - x[i]);",
                           "G[i] = y[i] >= 0 ? r * (xp - x[i]) : r * (x[i] - xm);"),
     "tangent_drops_nu": ("dout[i] = v + D * dlap + dD * lap;", "dout[i] = v + D * dlap;"),
+    "newton_convection_sign": ("const T F = (xi - u[i]) + (half_r * xi * (xp - xm) - D * ((xp + xm) - two * xi));",
+                               "const T F = (xi - u[i]) + (-half_r * xi * (xp - xm) - D * ((xp + xm) - two * xi));"),
+    "newton_jacobian_diag": ("d[k] = (one + two * D) + half_r * (xp - xm);", "d[k] = one + two * D;"),
+    "newton_jacobian_sub": ("l[k] = -(half_r * xi) - D;", "l[k] = (half_r * xi) - D;"),
+    "newton_upwinded": ("const T F = (xi - u[i]) + (half_r * xi * (xp - xm) - D * ((xp + xm) - two * xi));",
+                        "const T F = (xi - u[i]) + (two * half_r * xi * (xi - xm) - D * ((xp + xm) - two * xi));"),
+    "newton_diffusion_sign": ("const T F = (xi - u[i]) + (half_r * xi * (xp - xm) - D * ((xp + xm) - two * xi));",
+                              "const T F = (xi - u[i]) + (half_r * xi * (xp - xm) + D * ((xp + xm) - two * xi));"),
     "cn_diag_half": ("d[k] = one + half * nd;", "d[k] = one + nd;"),
     "cn_rhs_sign": ("rhs[k] = ui - half * ((nl * um + nd * ui) + np * up);",
                     "rhs[k] = ui + half * ((nl * um + nd * ui) + np * up);"),

@@ -35,6 +35,7 @@ EXPLICIT = 0
 BTCS = 1
 RK4 = 2
 CN = 3
+NEWTON = 4
 
 SEED_BASE = 12204
 TWO_PI = 2.0 * math.pi
