@@ -170,6 +170,31 @@ def bench_c2_cn(B, torch, nsteps=1000, reps=2):
     return {"ms": ms, "steps": nsteps, "glups": nodes * nsteps / (ms * 1e-3) / 1e9}
 
 
+def bench_c2_newton(B, torch, nsteps=100, reps=2):
+    """The C2 batch advanced by the fully implicit central-convection step at twice the CFL dt: four
+    Newton iterations per step, each an assembly, a Jacobian solve (array path) and an update."""
+    import workloads as W
+    batch = W.c2_batch()
+    cfl_batch(B, batch, 2.0)
+    for p in batch.problems:
+        p.scheme = W.NEWTON
+    s = B.Solver(batch.problems, dtype=torch.float64)
+    u0 = s.pack_flat(batch.u0, batch.offsets)
+    u = torch.empty_like(u0)
+    u.copy_(u0)
+    s.run(u, 2)                                  # warm-up (plans)
+    timer = PhaseTimer()
+    for _ in range(reps):
+        u.copy_(u0)
+        timer.mark("run")
+        s.run(u, nsteps)
+        timer.mark("copy")
+    ms = float(np.mean(timer.spans()["run"]))
+    s.close()
+    nodes = 4096 * 8192
+    return {"ms": ms, "steps": nsteps, "newton_iters": 4, "glups": nodes * nsteps / (ms * 1e-3) / 1e9}
+
+
 def bench_c1_latency(B, torch, solves=200):
     """Single periodic N=101 sawtooth to t=0.5: latency of one whole solve (explicit 113 steps, BTCS 12)."""
     import workloads as W
@@ -428,7 +453,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
-    ap.add_argument("--legs", default="c2,c2f32,c2rk4,c2cn,c1,c3,c4,c5,serve",
+    ap.add_argument("--legs", default="c2,c2f32,c2rk4,c2cn,c2newton,c1,c3,c4,c5,serve",
                     help="comma-separated side measurements to run (profiling runs select one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--exp-steps", type=int, default=10_000, help="explicit steps per step (profiling runs)")
@@ -464,6 +489,9 @@ def main():
     if "c2cn" in legs:
         log("C2 Crank-Nicolson")
         extra["c2_cn_f64"] = bench_c2_cn(B, torch)
+    if "c2newton" in legs:
+        log("C2 Newton")
+        extra["c2_newton_f64"] = bench_c2_newton(B, torch)
     if "c1" in legs:
         log("C1 latency")
         extra["c1_latency"] = bench_c1_latency(B, torch)

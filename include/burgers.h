@@ -52,8 +52,12 @@ typedef enum { BURGERS_BC_PERIODIC = 0, BURGERS_BC_DIRICHLET = 1 } burgers_bc; /
 /* Sec. 2.3 (forward Euler, eq. 21); Sec. 2.4 (BTCS, eq. 23); Sec. 2.7.1 (classical RK4, eq. 22, over
    eq. 21's spatial operator with the stages k1 = L(u), k2 = L(u + dt k1/2), k3 = L(u + dt k2/2),
    k4 = L(u + dt k3)); Crank-Nicolson, which Sec. 2.2 names beside BTCS: with the BTCS matrix written
-   A = I + N (coefficients lagged at u^n), (I + N/2) u^{n+1} = (I - N/2) u^n. */
-typedef enum { BURGERS_EXPLICIT = 0, BURGERS_BTCS = 1, BURGERS_RK4 = 2, BURGERS_CN = 3 } burgers_scheme;
+   A = I + N (coefficients lagged at u^n), (I + N/2) u^{n+1} = (I - N/2) u^n; the fully implicit step
+   with central convection of eqs. 10-14, F(u^{n+1}) = 0 solved by four Newton-Raphson iterations from
+   u^n with the tridiagonal Jacobian of eq. 11 (no pivoting: meant for steps whose Jacobian stays
+   diagonally dominant, e.g. up to a few times the CFL step). */
+typedef enum { BURGERS_EXPLICIT = 0, BURGERS_BTCS = 1, BURGERS_RK4 = 2, BURGERS_CN = 3,
+               BURGERS_NEWTON = 4 } burgers_scheme;
 typedef enum { BURGERS_F32 = 0, BURGERS_F64 = 1 } burgers_dtype;
 
 /*
@@ -151,15 +155,16 @@ burgers_status burgers_step_btcs(burgers_ctx* ctx, void* u, int64_t nsteps);
  * Advance every instance nsteps >= 0 steps of its own `scheme` (forward-Euler, RK4 and BTCS instances
  * may be mixed in one context).  u as for burgers_step_explicit.  Errors as for burgers_step_explicit;
  * BURGERS_E_UNSUPPORTED also when RK4 instances meet a plan forcing explicit_path 1 (the one-step
- * streaming kernel is forward Euler only) or Crank-Nicolson instances meet btcs_path 2 (they are
- * solved per step through HBM: each step is a BTCS solve with dt/2, y, followed by u' = 2y - u).
+ * streaming kernel is forward Euler only) or Crank-Nicolson or Newton instances meet btcs_path 2 (they
+ * are solved per step through HBM: a Crank-Nicolson step is a BTCS solve with dt/2, y, followed by
+ * u' = 2y - u; a Newton step is four assemble-solve-update iterations).
  */
 burgers_status burgers_run(burgers_ctx* ctx, void* u, int64_t nsteps);
 
 /*
  * As burgers_run, with separate step counts for the two kinds of scheme: instances whose `scheme` is
- * BURGERS_EXPLICIT or BURGERS_RK4 advance explicit_steps steps and BURGERS_BTCS or BURGERS_CN instances
- * btcs_steps steps (both >= 0), in one
+ * BURGERS_EXPLICIT or BURGERS_RK4 advance explicit_steps steps and the implicit ones (BURGERS_BTCS,
+ * BURGERS_CN, BURGERS_NEWTON) btcs_steps steps (both >= 0), in one
  * launch sequence (one graph launch when use_graph is 1).  Ragged batches mixing schemes with
  * scheme-specific step budgets (explicit steps at the CFL limit, BTCS steps at a multiple of it) run
  * this way.  Errors as for burgers_step_explicit.
@@ -175,8 +180,8 @@ burgers_status burgers_run_mixed(burgers_ctx* ctx, void* u, int64_t explicit_ste
  * Dirichlet boundary nodes are constants, so their entries of grad_u0 are zero.  The upwind switch is
  * differentiated on its u_i >= 0 branch at u_i = 0.
  * Errors: BURGERS_E_INVALID, BURGERS_E_NOMEM (checkpoint storage), BURGERS_E_DEVICE,
- * BURGERS_E_UNSUPPORTED (an FP32 context, or an RK4 or Crank-Nicolson instance: the adjoint covers
- * forward Euler and BTCS).
+ * BURGERS_E_UNSUPPORTED (an FP32 context, or an RK4, Crank-Nicolson or Newton instance: the adjoint
+ * covers forward Euler and BTCS).
  */
 burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lambda_T, int64_t nsteps,
                                int64_t ckpt_every, void* grad_u0, void* grad_nu);

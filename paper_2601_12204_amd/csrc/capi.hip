@@ -32,7 +32,7 @@ bool valid_problem(const burgers_problem& p) {
   if (!is_finite(p.nu) || p.nu < 0) return false;
   if (!is_finite(p.dt) || p.dt <= 0) return false;
   if (p.bc != BURGERS_BC_PERIODIC && p.bc != BURGERS_BC_DIRICHLET) return false;
-  if (p.scheme < BURGERS_EXPLICIT || p.scheme > BURGERS_CN) return false;
+  if (p.scheme < BURGERS_EXPLICIT || p.scheme > BURGERS_NEWTON) return false;
   if (!is_finite(p.left) || !is_finite(p.right)) return false;
   return true;
 }
@@ -180,6 +180,8 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
 //   path 3: partition levels for every system of at least 32 rows (shorter ones solved whole).
 //   automatic: on chip for systems that fit, partition levels for longer ones.
 // Reduced-system rows are carved from the context's level arrays.
+burgers_status ensure_newton(burgers_ctx* ctx, const std::vector<int32_t>& members);
+
 // Rows a partition level leaves for the next one.  Level 0 (from the state) runs the block partition,
 // which reduces each workgroup's 256 chunks to two rows; deeper levels leave two rows per chunk.
 int32_t reduced_rows(int level, int32_t chunks) {
@@ -206,7 +208,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     groups[std::make_tuple(w.lanes, w.chunk, w.exact)].push_back(
         SysDesc{0, -1, rows, burgers::btcs_chunks(rows, w.lanes), i, 0, is_cn ? 1 : 0});
   };
-  std::vector<int32_t> stepped, cn;
+  std::vector<int32_t> stepped, cn, newton;
   std::vector<std::vector<SysDesc>> red_sys, wg_sys;
   int64_t rows_used = 0;
   for (int32_t i : set_members(ctx, set)) {
@@ -217,7 +219,13 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     // they always step through HBM
     const bool is_cn = set == kSetBtcs && p.scheme == BURGERS_CN;
     if (is_cn) cn.push_back(i);
-    if (want == 2 && (!fits || is_cn)) return BURGERS_E_UNSUPPORTED;
+    const bool is_newton = set == kSetBtcs && p.scheme == BURGERS_NEWTON;
+    if (want == 2 && (!fits || is_cn || is_newton)) return BURGERS_E_UNSUPPORTED;
+    if (is_newton) {            // Newton iterations of their own, through HBM every step
+      stepped.push_back(i);
+      newton.push_back(i);
+      continue;
+    }
     if ((want == 0 || want == 2) && fits && !is_cn) {
       whole(resident, R0, i, false);
       continue;
@@ -267,6 +275,11 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   plan->copy = std::make_unique<DevBuf>();
   auto ct = stream_tiles(ctx, stepped);
   plan->n_copy = static_cast<int64_t>(ct.size());
+  if (!newton.empty()) {
+    burgers_status nst = ensure_newton(ctx, newton);
+    if (nst != BURGERS_OK) return nst;
+    plan->newton = true;
+  }
   plan->inst_half = std::make_unique<DevBuf>();
   if (!cn.empty()) {
     std::vector<burgers::InstDesc> half = ctx->inst_host;
@@ -376,6 +389,19 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
   int cur = 0;
   for (int64_t s = 0; s < nsteps; ++s) {
     if ((e = burgers::launch_btcs_step(ctx, pl, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+    if (pl.newton) {
+      burgers::NewtonPlan& np = *ctx->newton;
+      const burgers::AdjTile* nt = np.tiles->as<burgers::AdjTile>();
+      if ((e = burgers::launch_newton_init(ctx, nt, np.n_tiles, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+      for (int it = 0; it < burgers::kNewtonIters; ++it) {
+        if ((e = burgers::launch_newton_assemble(ctx, nt, np.n_tiles, bufs[cur], bufs[cur ^ 1], np.NA.as<double>(),
+                                                 np.NC.as<double>(), np.ND.as<double>())) != hipSuccess ||
+            (e = burgers::launch_array_solve(ctx, np.solve, np.NA.as<double>(), np.NC.as<double>(), np.ND.as<double>(),
+                                             np.NX.as<double>())) != hipSuccess ||
+            (e = burgers::launch_newton_update(ctx, nt, np.n_tiles, bufs[cur ^ 1], np.NX.as<double>())) != hipSuccess)
+          return e;
+      }
+    }
     cur ^= 1;
   }
   if (cur) e = burgers::launch_copy_tiles(ctx, pl.copy->as<Tile>(), pl.n_copy, ctx->work.ptr, u);
@@ -458,35 +484,18 @@ burgers_status advance(burgers_ctx* ctx, void* u, int64_t nsteps, int set, int s
 // Adjoint launch lists: 256-node tiles of every instance (explicit and BTCS lists), one dJ/dD slot per
 // tile, and the partition hierarchy over the transposed BTCS systems, which sit at the start of the
 // adjoint arrays followed by their reduced rows.
-burgers_status ensure_adjoint(burgers_ctx* ctx) {
-  if (ctx->adjoint) return BURGERS_OK;
-  auto ap = std::make_unique<burgers::AdjointPlan>();
-  const int tile = burgers::adjoint_tile_nodes();
+// Partition hierarchy for systems stored as unit-diagonal rows in binary64 arrays: root (instance, row
+// offset, rows) triples; systems of up to 8192 rows are solved whole, longer ones reduced by chunk-
+// partition levels whose reduced rows are appended after `rows_used` (updated).
+hipError_t build_array_solve(burgers_ctx* ctx, const std::vector<std::tuple<int32_t, int64_t, int32_t>>& roots,
+                             burgers::BtcsPlan& plan, int64_t& rows_used) {
   const int cap = burgers::btcs_wg_capacity();
   const int chunk = burgers::btcs_reduce_chunk();
-  std::vector<burgers::AdjTile> et, bt;
-  std::vector<int32_t> slot_begin(ctx->count + 1, 0);
-  int32_t slot = 0;
-  int64_t sys_rows = 0;
-  std::vector<int64_t> sys_off(ctx->count, -1);
-  for (int32_t i = 0; i < ctx->count; ++i) {
-    const burgers_problem& p = ctx->probs[i];
-    if (p.scheme == BURGERS_BTCS) {
-      sys_off[i] = sys_rows;
-      sys_rows += p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2;
-    }
-  }
   std::vector<std::vector<SysDesc>> red_sys(1), wg_sys(1);
-  int64_t rows_used = sys_rows;
-  for (int32_t i = 0; i < ctx->count; ++i) {
-    const burgers_problem& p = ctx->probs[i];
-    const int32_t n = static_cast<int32_t>(p.n);
-    slot_begin[i] = slot;
-    for (int32_t s = 0; s < n; s += tile)
-      (p.scheme == BURGERS_BTCS ? bt : et).push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, s, slot++, 0});
-    if (p.scheme != BURGERS_BTCS) continue;
-    int32_t R = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
-    int64_t in_off = sys_off[i];
+  for (const auto& root : roots) {
+    const int32_t i = std::get<0>(root);
+    int64_t in_off = std::get<1>(root);
+    int32_t R = std::get<2>(root);
     for (int level = 0;; ++level) {
       if (static_cast<int>(red_sys.size()) <= level) {
         red_sys.resize(level + 1);
@@ -504,6 +513,83 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
       R = 2 * P;
     }
   }
+  hipError_t e;
+  plan.levels.resize(red_sys.size());
+  for (size_t l = 0; l < red_sys.size(); ++l) {
+    auto& lv = plan.levels[l];
+    std::vector<ChunkBlock> blocks;
+    for (size_t si = 0; si < red_sys[l].size(); ++si)
+      for (int32_t c = 0; c < red_sys[l][si].chunks; c += burgers::kReduceBlock)
+        blocks.push_back(ChunkBlock{static_cast<int32_t>(si), c});
+    lv.sys = std::make_unique<DevBuf>();
+    lv.blocks = std::make_unique<DevBuf>();
+    lv.wg = std::make_unique<DevBuf>();
+    if ((e = upload_on(ctx->stream, *lv.sys, red_sys[l])) != hipSuccess ||
+        (e = upload_on(ctx->stream, *lv.blocks, blocks)) != hipSuccess ||
+        (e = upload_on(ctx->stream, *lv.wg, wg_sys[l])) != hipSuccess)
+      return e;
+    lv.n_blocks = static_cast<int32_t>(blocks.size());
+    lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
+  }
+  return hipSuccess;
+}
+
+// Newton plan over the given instances (built once per context).
+burgers_status ensure_newton(burgers_ctx* ctx, const std::vector<int32_t>& members) {
+  if (ctx->newton) return BURGERS_OK;
+  auto np = std::make_unique<burgers::NewtonPlan>();
+  std::vector<burgers::AdjTile> tiles;
+  std::vector<std::tuple<int32_t, int64_t, int32_t>> roots;
+  int64_t rows = 0;
+  for (int32_t i : members) {
+    const burgers_problem& p = ctx->probs[i];
+    const int32_t n = static_cast<int32_t>(p.n);
+    const int32_t R = p.bc == BURGERS_BC_PERIODIC ? n : n - 2;
+    for (int32_t s0 = 0; s0 < n; s0 += 256) tiles.push_back(burgers::AdjTile{ctx->offsets[i], rows, n, p.bc, i, s0, 0, 0});
+    roots.emplace_back(i, rows, R);
+    rows += R;
+  }
+  int64_t rows_used = rows;
+  hipError_t e;
+  np->tiles = std::make_unique<DevBuf>();
+  if ((e = upload_on(ctx->stream, *np->tiles, tiles)) != hipSuccess) return from_hip(e);
+  np->n_tiles = static_cast<int64_t>(tiles.size());
+  if ((e = build_array_solve(ctx, roots, np->solve, rows_used)) != hipSuccess) return from_hip(e);
+  const size_t lb = static_cast<size_t>(std::max<int64_t>(rows_used, 1)) * sizeof(double);
+  if ((e = np->NA.alloc(lb, ctx->stream)) != hipSuccess || (e = np->NC.alloc(lb, ctx->stream)) != hipSuccess ||
+      (e = np->ND.alloc(lb, ctx->stream)) != hipSuccess || (e = np->NX.alloc(lb, ctx->stream)) != hipSuccess)
+    return from_hip(e);
+  ctx->newton = std::move(np);
+  return BURGERS_OK;
+}
+
+burgers_status ensure_adjoint(burgers_ctx* ctx) {
+  if (ctx->adjoint) return BURGERS_OK;
+  auto ap = std::make_unique<burgers::AdjointPlan>();
+  const int tile = burgers::adjoint_tile_nodes();
+  std::vector<burgers::AdjTile> et, bt;
+  std::vector<int32_t> slot_begin(ctx->count + 1, 0);
+  int32_t slot = 0;
+  int64_t sys_rows = 0;
+  std::vector<int64_t> sys_off(ctx->count, -1);
+  for (int32_t i = 0; i < ctx->count; ++i) {
+    const burgers_problem& p = ctx->probs[i];
+    if (p.scheme == BURGERS_BTCS) {
+      sys_off[i] = sys_rows;
+      sys_rows += p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2;
+    }
+  }
+  std::vector<std::tuple<int32_t, int64_t, int32_t>> roots;
+  int64_t rows_used = sys_rows;
+  for (int32_t i = 0; i < ctx->count; ++i) {
+    const burgers_problem& p = ctx->probs[i];
+    const int32_t n = static_cast<int32_t>(p.n);
+    slot_begin[i] = slot;
+    for (int32_t s = 0; s < n; s += tile)
+      (p.scheme == BURGERS_BTCS ? bt : et).push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, s, slot++, 0});
+    if (p.scheme == BURGERS_BTCS)
+      roots.emplace_back(i, sys_off[i], static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2));
+  }
   slot_begin[ctx->count] = slot;
   hipError_t e;
   ap->exp_tiles = std::make_unique<DevBuf>();
@@ -515,22 +601,7 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   ap->n_exp_tiles = static_cast<int64_t>(et.size());
   ap->n_btcs_tiles = static_cast<int64_t>(bt.size());
   ap->n_slots = slot;
-  ap->solve.levels.resize(red_sys.size());
-  for (size_t l = 0; l < red_sys.size(); ++l) {
-    auto& lv = ap->solve.levels[l];
-    std::vector<ChunkBlock> blocks;
-    for (size_t si = 0; si < red_sys[l].size(); ++si)
-      for (int32_t c = 0; c < red_sys[l][si].chunks; c += burgers::kReduceBlock)
-        blocks.push_back(ChunkBlock{static_cast<int32_t>(si), c});
-    lv.sys = std::make_unique<DevBuf>();
-    lv.blocks = std::make_unique<DevBuf>();
-    lv.wg = std::make_unique<DevBuf>();
-    if ((e = upload_on(ctx->stream, *lv.sys, red_sys[l])) != hipSuccess || (e = upload_on(ctx->stream, *lv.blocks, blocks)) != hipSuccess ||
-        (e = upload_on(ctx->stream, *lv.wg, wg_sys[l])) != hipSuccess)
-      return from_hip(e);
-    lv.n_blocks = static_cast<int32_t>(blocks.size());
-    lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
-  }
+  if ((e = build_array_solve(ctx, roots, ap->solve, rows_used)) != hipSuccess) return from_hip(e);
   const size_t lb = static_cast<size_t>(rows_used) * sizeof(double);
   if ((e = ap->LA.alloc(lb, ctx->stream)) != hipSuccess || (e = ap->LC.alloc(lb, ctx->stream)) != hipSuccess ||
       (e = ap->LD.alloc(lb, ctx->stream)) != hipSuccess || (e = ap->LX.alloc(lb, ctx->stream)) != hipSuccess ||
@@ -642,7 +713,7 @@ burgers_status burgers_create(const burgers_problem* problems, int64_t count, bu
     d.a = p.bc == BURGERS_BC_DIRICHLET ? p.left : 0.0;
     d.b = p.bc == BURGERS_BC_DIRICHLET ? p.right : 0.0;
     ctx->set_all.push_back(static_cast<int32_t>(i));
-    (p.scheme == BURGERS_BTCS || p.scheme == BURGERS_CN ? ctx->set_btcs : ctx->set_explicit)
+    (p.scheme == BURGERS_EXPLICIT || p.scheme == BURGERS_RK4 ? ctx->set_explicit : ctx->set_btcs)
         .push_back(static_cast<int32_t>(i));
   }
   burgers_status st = BURGERS_OK;
@@ -781,7 +852,7 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
     return BURGERS_E_INVALID;
   if (ctx->dtype != BURGERS_F64) return BURGERS_E_UNSUPPORTED;
   for (const auto& p : ctx->probs)   // adjoint of forward Euler and BTCS only
-    if (p.scheme == BURGERS_RK4 || p.scheme == BURGERS_CN) return BURGERS_E_UNSUPPORTED;
+    if (p.scheme != BURGERS_EXPLICIT && p.scheme != BURGERS_BTCS) return BURGERS_E_UNSUPPORTED;
   if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return note(ctx, e);

@@ -142,6 +142,7 @@ struct BtcsPlan {
   // Crank-Nicolson instances: solved per step with the coefficients of dt/2 (a copy of the instance
   // table with r and D halved); their systems carry the `cn` flag and store u' = 2 y - u
   std::unique_ptr<DevBuf> inst_half;         // InstDesc[count], or empty: the context's table
+  bool newton = false;                       // the context's Newton instances step with this plan
   // partition hierarchy for the long systems
   struct Level {
     std::unique_ptr<DevBuf> sys;             // SysDesc[] of the systems reduced at this level
@@ -179,6 +180,17 @@ struct AdjointPlan {
   DevBuf ckpt, seg, lam0, lam1;                     // grown on demand
 };
 
+// Fully implicit central-convection instances (Newton-Raphson, a fixed number of iterations per step):
+// per iteration the Jacobian rows and the residual are assembled, normalised to unit diagonal, into
+// binary64 arrays and solved by the partition solver's array path.
+constexpr int kNewtonIters = 4;
+struct NewtonPlan {
+  std::unique_ptr<DevBuf> tiles;                    // AdjTile[] (256 nodes each) of the Newton instances
+  int64_t n_tiles = 0;
+  BtcsPlan solve;                                   // partition hierarchy over their systems
+  DevBuf NA, NC, ND, NX;
+};
+
 }  // namespace burgers
 
 struct burgers_ctx {
@@ -206,6 +218,7 @@ struct burgers_ctx {
   std::map<std::tuple<int, int, int64_t, int64_t, void*>, hipGraphExec_t> graph_cache;
   hipStream_t capture_stream = nullptr;      // private non-blocking stream used only for capture
   std::unique_ptr<burgers::AdjointPlan> adjoint;
+  std::unique_ptr<burgers::NewtonPlan> newton;
   hipError_t sticky = hipSuccess;
 };
 
@@ -235,6 +248,13 @@ hipError_t launch_adj_nu(const burgers_ctx* ctx, const int32_t* slot_begin, cons
                          double* grad_nu);
 hipError_t launch_fill(const burgers_ctx* ctx, double* p, int64_t n, double v);
 hipError_t launch_zero_dirichlet_ends(const burgers_ctx* ctx, double* g);
+
+// newton.hip
+hipError_t launch_newton_init(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const void* u, void* x);
+hipError_t launch_newton_assemble(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const void* u,
+                                  const void* x, double* NA, double* NC, double* ND);
+hipError_t launch_newton_update(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, void* x,
+                                const double* NX);
 
 // btcs.hip
 int btcs_wg_capacity();                 // longest system one workgroup solves whole

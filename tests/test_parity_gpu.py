@@ -478,3 +478,56 @@ def test_cn_mixed_and_unsupported():
     with pytest.raises(B.BurgersError) as err:
         device_run(fit, 2, "f64", how="run", plan=dict(btcs_path=2))
     assert err.value.status == -2
+
+
+# ----------------------------------------------------------------------------- Newton (eqs. 10-15)
+def _newton_batch(seed, tiny=True):
+    sizes = ([3, 4] if tiny else []) + [33, 1000, 8190, 8192, 8193, 20000, 150001]
+    problems, states = [], []
+    for k, n in enumerate(sizes):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            b = W.random_batch(seed + 11 * k + bc, 1, n, n, bc=bc, scheme=W.NEWTON, amplitude=1.5)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    # at the CFL step (sigma = 0.5) the Jacobian is strictly diagonally dominant whatever the grid, as
+    # the unpivoted solves require
+    return set_cfl_steps(W._pack(problems, states))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_newton_parity(dtype):
+    """Fully implicit central-convection instances (four Newton iterations per step, whole-system and
+    partitioned Jacobian solves, both BCs) at the CFL step against the oracle."""
+    # 3- and 4-node grids at cell Peclet numbers ~30 amplify rounding (the central scheme grows the state
+    # several-fold in six steps), so binary32 runs them only in the mixed test's binary64 context
+    batch = _newton_batch(109, tiny=dtype == "f64")
+    announce(f"newton {dtype} 6 steps")
+    got = device_run(batch, 6, dtype, how="run")
+    check_batch(batch, got, 6, dtype)
+
+
+def test_newton_mixed_and_unsupported():
+    """Newton, Crank-Nicolson, BTCS and RK4 instances in one context each take their own scheme; the
+    adjoint and a forced on-chip BTCS plan reject Newton instances."""
+    import torch
+    import paper_2601_12204_amd as B
+    batch = W.random_batch(113, 24, 3, 30000, amplitude=1.5)
+    for k, p in enumerate(batch.problems):
+        p.scheme = (W.NEWTON, W.CN, W.BTCS, W.RK4)[k % 4]
+    set_cfl_steps(batch, btcs_factor=2.0)
+    announce("newton + cn + btcs + rk4 run")
+    got = device_run(batch, 5, "f64", how="run")
+    check_batch(batch, got, 5, "f64")
+    fit = W.random_batch(117, 5, 3, 8000, scheme=W.NEWTON, amplitude=1.5)
+    set_cfl_steps(fit)
+    with pytest.raises(B.BurgersError) as err:
+        device_run(fit, 2, "f64", how="run", plan=dict(btcs_path=2))
+    assert err.value.status == -2
+    s = B.Solver(fit.problems, dtype=torch.float64)
+    u = s.pack_flat(fit.u0, fit.offsets)
+    g = torch.zeros_like(u)
+    gn = torch.zeros(s.count, dtype=torch.float64, device="cuda")
+    with pytest.raises(B.BurgersError) as err:
+        B.adjoint_into(s, u, u.clone(), 3, 2, g, gn)
+    assert err.value.status == -2
+    s.close()
