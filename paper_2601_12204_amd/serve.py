@@ -107,7 +107,7 @@ class GpuBackend:
 
 
 class Server:
-    def __init__(self, backend=None, hbm_budget: int = 8 << 30, max_in_flight: int = 16,
+    def __init__(self, backend=None, hbm_budget: int = 8 << 30, max_in_flight: int = 64,
                  batch_window: float = 0.001, max_batch: int = 256,
                  clock: Callable[[], float] = time.perf_counter):
         self.backend = backend if backend is not None else GpuBackend()
