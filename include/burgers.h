@@ -62,7 +62,7 @@ typedef enum { BURGERS_F32 = 0, BURGERS_F64 = 1 } burgers_dtype;
 
 /*
  * One problem instance (Sec. 2.2 and 2.5).
- *   n       stored grid nodes, 3 <= n <= 2^31-1.  Periodic: nodes x_i = i*dx, dx = length/n, node n is
+ *   n       stored grid nodes, 3 <= n <= 2^31 - 65536.  Periodic: nodes x_i = i*dx, dx = length/n, node n is
  *           node 0 again (eq. 18).  Dirichlet: dx = length/(n-1); nodes 0 and n-1 hold left and right
  *           (eqs. 16-17), and the n-2 interior nodes are the unknowns.
  *   length  domain length L > 0.

@@ -26,8 +26,12 @@ double grid_dx(const burgers_problem& p) {
                                      : p.length / static_cast<double>(p.n - 1);
 }
 
+// Largest instance: node indices of a window (first node + up to 8192) and of staged blocks stay within
+// 32-bit integers.
+constexpr int64_t kMaxNodes = (int64_t{1} << 31) - 65536;
+
 bool valid_problem(const burgers_problem& p) {
-  if (p.n < 3 || p.n > INT32_MAX) return false;
+  if (p.n < 3 || p.n > kMaxNodes) return false;
   if (!is_finite(p.length) || p.length <= 0) return false;
   if (!is_finite(p.nu) || p.nu < 0) return false;
   if (!is_finite(p.dt) || p.dt <= 0) return false;
@@ -69,8 +73,8 @@ std::vector<Tile> stream_tiles(const burgers_ctx* ctx, const std::vector<int32_t
   std::vector<Tile> tiles;
   for (int32_t i : members) {
     const int32_t n = static_cast<int32_t>(ctx->probs[i].n);
-    for (int32_t s = 0; s < n; s += tile)
-      tiles.push_back(Tile{ctx->offsets[i], n, ctx->probs[i].bc, i, s});
+    for (int64_t s = 0; s < n; s += tile)   // 64-bit counter: n may be close to INT32_MAX
+      tiles.push_back(Tile{ctx->offsets[i], n, ctx->probs[i].bc, i, static_cast<int32_t>(s)});
   }
   return tiles;
 }
@@ -138,17 +142,19 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
       const int32_t halo = T * (rk4 ? 4 : 1);
       const int32_t wout = cap - 2 * halo;
       if (wout < 1) return BURGERS_E_UNSUPPORTED;
-      for (int32_t lo = 0; lo < n; lo += wout) {
-        const int32_t hi = std::min(n, lo + wout);
-        BlockTile bt{i, 0, 0, 0, hi - lo, 0, rk4};
+      const int64_t nn = n;
+      for (int64_t lo = 0; lo < nn; lo += wout) {
+        const int64_t hi = std::min<int64_t>(nn, lo + wout);
+        BlockTile bt{i, 0, 0, 0, static_cast<int32_t>(hi - lo), 0, rk4};
         if (periodic) {
-          bt.first = ((lo - halo) % n + n) % n;
-          bt.width = (hi - lo) + 2 * halo;
+          bt.first = static_cast<int32_t>(((lo - halo) % nn + nn) % nn);
+          bt.width = static_cast<int32_t>((hi - lo) + 2 * halo);
           bt.lo = halo;
         } else {
-          bt.first = std::max(0, lo - halo);
-          bt.width = std::min(n, hi + halo) - bt.first;
-          bt.lo = lo - bt.first;
+          const int64_t first = std::max<int64_t>(0, lo - halo);
+          bt.first = static_cast<int32_t>(first);
+          bt.width = static_cast<int32_t>(std::min<int64_t>(nn, hi + halo) - first);
+          bt.lo = static_cast<int32_t>(lo - first);
         }
         win.push_back(bt);
       }
@@ -298,8 +304,8 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     auto& lv = plan->levels[l];
     std::vector<ChunkBlock> blocks;
     for (size_t si = 0; si < red_sys[l].size(); ++si)
-      for (int32_t c = 0; c < red_sys[l][si].chunks; c += burgers::kReduceBlock)
-        blocks.push_back(ChunkBlock{static_cast<int32_t>(si), c});
+      for (int64_t c = 0; c < red_sys[l][si].chunks; c += burgers::kReduceBlock)
+        blocks.push_back(ChunkBlock{static_cast<int32_t>(si), static_cast<int32_t>(c)});
     lv.sys = std::make_unique<DevBuf>();
     lv.blocks = std::make_unique<DevBuf>();
     lv.wg = std::make_unique<DevBuf>();
@@ -519,8 +525,8 @@ hipError_t build_array_solve(burgers_ctx* ctx, const std::vector<std::tuple<int3
     auto& lv = plan.levels[l];
     std::vector<ChunkBlock> blocks;
     for (size_t si = 0; si < red_sys[l].size(); ++si)
-      for (int32_t c = 0; c < red_sys[l][si].chunks; c += burgers::kReduceBlock)
-        blocks.push_back(ChunkBlock{static_cast<int32_t>(si), c});
+      for (int64_t c = 0; c < red_sys[l][si].chunks; c += burgers::kReduceBlock)
+        blocks.push_back(ChunkBlock{static_cast<int32_t>(si), static_cast<int32_t>(c)});
     lv.sys = std::make_unique<DevBuf>();
     lv.blocks = std::make_unique<DevBuf>();
     lv.wg = std::make_unique<DevBuf>();
@@ -545,7 +551,8 @@ burgers_status ensure_newton(burgers_ctx* ctx, const std::vector<int32_t>& membe
     const burgers_problem& p = ctx->probs[i];
     const int32_t n = static_cast<int32_t>(p.n);
     const int32_t R = p.bc == BURGERS_BC_PERIODIC ? n : n - 2;
-    for (int32_t s0 = 0; s0 < n; s0 += 256) tiles.push_back(burgers::AdjTile{ctx->offsets[i], rows, n, p.bc, i, s0, 0, 0});
+    for (int64_t s0 = 0; s0 < n; s0 += 256)
+      tiles.push_back(burgers::AdjTile{ctx->offsets[i], rows, n, p.bc, i, static_cast<int32_t>(s0), 0, 0});
     roots.emplace_back(i, rows, R);
     rows += R;
   }
@@ -585,8 +592,9 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
     const burgers_problem& p = ctx->probs[i];
     const int32_t n = static_cast<int32_t>(p.n);
     slot_begin[i] = slot;
-    for (int32_t s = 0; s < n; s += tile)
-      (p.scheme == BURGERS_BTCS ? bt : et).push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, s, slot++, 0});
+    for (int64_t s = 0; s < n; s += tile)
+      (p.scheme == BURGERS_BTCS ? bt : et)
+          .push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, static_cast<int32_t>(s), slot++, 0});
     if (p.scheme == BURGERS_BTCS)
       roots.emplace_back(i, sys_off[i], static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2));
   }

@@ -66,7 +66,7 @@ def test_create_rejects_invalid_problems_without_a_device(lib):
     import paper_2601_12204_amd as B
     good = W.Problem(n=16, length=1.0, nu=0.01, dt=1e-3)
     bad = [dict(n=2), dict(length=0.0), dict(nu=-1.0), dict(dt=0.0), dict(dt=float("nan")),
-           dict(bc=2), dict(scheme=5), dict(left=float("inf"))]
+           dict(bc=2), dict(scheme=5), dict(scheme=-1), dict(left=float("inf")), dict(n=(1 << 31) - 65535)]
     for change in bad:
         p = W.Problem(**{**good.__dict__, **change})
         arr = (B.CProblem * 1)(B.to_cproblem(p))
