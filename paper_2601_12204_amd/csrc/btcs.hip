@@ -424,6 +424,100 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
   }
 }
 
+// Rows of a Newton iteration (fully implicit central-convection step, eqs. 10-14) for the whole system of
+// one instance: the Jacobian row of eq. 11 at the iterate x (staged in LDS, unknown k at padded(k)) and
+// the right-hand side -F, with the old state u read from HBM.  The increment of a Dirichlet neighbour is
+// zero, so the end rows simply drop that coupling.
+template <typename S>
+struct NewtonRows {
+  const double* st;
+  const S* __restrict__ u;
+  double half_r, D, a, b;
+  bool periodic;
+  __device__ __forceinline__ void row(int, int k, int R, double& al, double& be, double& ga, double& de) const {
+    const double xm = k > 0 ? st[padded(k - 1)] : (periodic ? st[padded(R - 1)] : a);
+    const double xp = k < R - 1 ? st[padded(k + 1)] : (periodic ? st[padded(0)] : b);
+    const double xi = st[padded(k)];
+    const double F = (xi - static_cast<double>(u[k])) + (half_r * xi * (xp - xm) - D * ((xp + xm) - 2.0 * xi));
+    al = -(half_r * xi) - D;
+    be = (1.0 + 2.0 * D) + half_r * (xp - xm);
+    ga = half_r * xi - D;
+    de = -F;
+    if (!periodic) {
+      if (k == 0) al = 0.0;
+      if (k == R - 1) ga = 0.0;
+    }
+  }
+  __device__ __forceinline__ void boundary(int, int, int, double&, double&, double&, double&) const {}
+};
+
+// One Newton iteration for systems of up to NT x MC rows, one workgroup per system: stage the iterate,
+// eliminate the Jacobian's chunks, PCR, recover the increment into the staging buffer and add it to the
+// iterate in HBM (x is the output state buffer, updated in place).
+template <typename S, int NT, int MC>
+__global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void newton_wg_kernel(const InstDesc* __restrict__ inst,
+                                                                         const SysDesc* __restrict__ systems,
+                                                                         const S* __restrict__ u, S* __restrict__ x) {
+  using T = double;
+  constexpr int kPcrBytes = 3 * 2 * NT * static_cast<int>(sizeof(T));
+  constexpr int kStageBytes = padded_size(NT * MC) * static_cast<int>(sizeof(T));
+  constexpr int kBytes = kStageBytes > kPcrBytes ? kStageBytes : kPcrBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  T* sA = reinterpret_cast<T*>(smem);
+  T* sC = sA + 2 * NT;
+  T* sD = sC + 2 * NT;
+  T* stage = reinterpret_cast<T*>(smem);
+  const SysDesc sys = systems[blockIdx.x];
+  const InstDesc d = inst[sys.inst];
+  const bool dir = d.bc == kDirichlet;
+  const int R = sys.rows, P = sys.chunks;
+  const int tid = threadIdx.x;
+  const int64_t o = d.off + (dir ? 1 : 0);
+  S* __restrict__ xs = x + o;
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    const int i = tid + j * NT;
+    if (i < R) stage[padded(i)] = static_cast<T>(xs[i]);
+  }
+  __syncthreads();
+  const NewtonRows<S> rows{stage, u + o, d.r / 2.0, d.D, d.a, d.b, !dir};
+  if (R == 1) {   // a single Dirichlet unknown
+    if (tid == 0) {
+      T al, be, ga, de;
+      rows.row(0, 0, 1, al, be, ga, de);
+      xs[0] = static_cast<S>(stage[0] + de / be);
+    }
+    return;
+  }
+  T al[MC], ga[MC], de[MC];
+  T AF, CF, DF, AE, CE, DE;
+  int s = 0, m = 0;
+  if (tid < P) {
+    chunk_span(tid, R, P, s, m);
+    chunk_eliminate<T, MC>(rows, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+  }
+  __syncthreads();                             // the PCR arrays overlay the staged iterate
+  if (tid < P) {
+    sA[2 * tid] = AF; sC[2 * tid] = CF; sD[2 * tid] = DF;
+    sA[2 * tid + 1] = AE; sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
+  }
+  __syncthreads();
+  pcr_cyclic<T, NT>(sA, sC, sD, 2 * P);
+  T F = T(0), E = T(0);
+  if (tid < P) {
+    F = sD[2 * tid];
+    E = sD[2 * tid + 1];
+  }
+  __syncthreads();
+  if (tid < P) chunk_recover<T, MC>(PtrDst<T>{stage}, s, m, al, ga, de, F, E);   // increments, unpadded
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    const int i = tid + j * NT;
+    if (i < R) xs[i] = static_cast<S>(static_cast<T>(xs[i]) + stage[i]);
+  }
+}
+
 // Resident solver: one workgroup keeps one system (<= 8192 rows) in registers, MC rows per lane (NT
 // lanes x MC = 8192), for all steps of a launch.  Each step is the whole-system solver's step without the trips to HBM; the
 // state is rounded through S once per step as the per-step kernel's store would, so both solvers agree
@@ -849,7 +943,28 @@ hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, vo
   return hipGetLastError();
 }
 
-// Width class of a system of up to 8192 rows.  A system of exactly 8192 rows runs the exact kernels
+template <typename S>
+void newton_launch(const burgers_ctx* ctx, const WgGroup& g, const S* u, S* x) {
+  const InstDesc* inst = ctx->inst.as<InstDesc>();
+  const SysDesc* sys = g.sys->as<SysDesc>();
+  const unsigned n = static_cast<unsigned>(g.n);
+  hipStream_t st = ctx->stream;
+  switch (g.shape.lanes) {   // chunks of at most 8 rows in every class (8192 rows: 1024 lanes)
+    case 128: newton_wg_kernel<S, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, x); break;
+    case 256: newton_wg_kernel<S, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, x); break;
+    case 512: newton_wg_kernel<S, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, x); break;
+    default: newton_wg_kernel<S, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, x); break;
+  }
+}
+
+hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, const void* u, void* x) {
+  if (group.n <= 0) return hipSuccess;
+  if (ctx->dtype == BURGERS_F64) newton_launch<double>(ctx, group, static_cast<const double*>(u), static_cast<double*>(x));
+  else newton_launch<float>(ctx, group, static_cast<const float*>(u), static_cast<float*>(x));
+  return hipGetLastError();
+}
+
+// Width class of a system of up to 8192 rows.// Width class of a system of up to 8192 rows.  A system of exactly 8192 rows runs the exact kernels
 // (`threads` = 512 lanes of 16 rows, or 1024 of 8); any other size takes the narrowest workgroup whose
 // lanes hold at most 8 rows each, so ragged chunks never need more than 8 registers per row array.
 WidthClass btcs_width_class(int rows, int threads) {

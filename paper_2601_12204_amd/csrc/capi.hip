@@ -399,12 +399,16 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
       burgers::NewtonPlan& np = *ctx->newton;
       const burgers::AdjTile* nt = np.tiles->as<burgers::AdjTile>();
       if ((e = burgers::launch_newton_init(ctx, nt, np.n_tiles, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+      const burgers::AdjTile* lt = np.long_tiles->as<burgers::AdjTile>();
       for (int it = 0; it < burgers::kNewtonIters; ++it) {
-        if ((e = burgers::launch_newton_assemble(ctx, nt, np.n_tiles, bufs[cur], bufs[cur ^ 1], np.NA.as<double>(),
+        for (const burgers::WgGroup& g : np.whole)
+          if ((e = burgers::launch_newton_whole(ctx, g, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+        if (np.n_long_tiles == 0) continue;
+        if ((e = burgers::launch_newton_assemble(ctx, lt, np.n_long_tiles, bufs[cur], bufs[cur ^ 1], np.NA.as<double>(),
                                                  np.NC.as<double>(), np.ND.as<double>())) != hipSuccess ||
             (e = burgers::launch_array_solve(ctx, np.solve, np.NA.as<double>(), np.NC.as<double>(), np.ND.as<double>(),
                                              np.NX.as<double>())) != hipSuccess ||
-            (e = burgers::launch_newton_update(ctx, nt, np.n_tiles, bufs[cur ^ 1], np.NX.as<double>())) != hipSuccess)
+            (e = burgers::launch_newton_update(ctx, lt, np.n_long_tiles, bufs[cur ^ 1], np.NX.as<double>())) != hipSuccess)
           return e;
       }
     }
@@ -540,29 +544,53 @@ hipError_t build_array_solve(burgers_ctx* ctx, const std::vector<std::tuple<int3
   return hipSuccess;
 }
 
-// Newton plan over the given instances (built once per context).
+// Newton plan over the given instances (built once per context): systems of up to 8192 rows iterate in
+// one fused kernel per iteration (grouped by width class), longer ones through the array path.
 burgers_status ensure_newton(burgers_ctx* ctx, const std::vector<int32_t>& members) {
   if (ctx->newton) return BURGERS_OK;
   auto np = std::make_unique<burgers::NewtonPlan>();
-  std::vector<burgers::AdjTile> tiles;
+  const int cap = burgers::btcs_wg_capacity();
+  std::vector<burgers::AdjTile> tiles, long_tiles;
   std::vector<std::tuple<int32_t, int64_t, int32_t>> roots;
+  std::map<std::tuple<int, int, bool>, std::vector<SysDesc>> groups;
   int64_t rows = 0;
   for (int32_t i : members) {
     const burgers_problem& p = ctx->probs[i];
     const int32_t n = static_cast<int32_t>(p.n);
     const int32_t R = p.bc == BURGERS_BC_PERIODIC ? n : n - 2;
     for (int64_t s0 = 0; s0 < n; s0 += 256)
-      tiles.push_back(burgers::AdjTile{ctx->offsets[i], rows, n, p.bc, i, static_cast<int32_t>(s0), 0, 0});
+      tiles.push_back(burgers::AdjTile{ctx->offsets[i], 0, n, p.bc, i, static_cast<int32_t>(s0), 0, 0});
+    if (R <= cap) {
+      // 8192-row systems take 1024 lanes of 8 rows (the Newton rows need more registers than BTCS ones)
+      const burgers::WidthClass w = burgers::btcs_width_class(R, 1024);
+      groups[std::make_tuple(w.lanes, w.chunk, w.exact)].push_back(
+          SysDesc{0, -1, R, burgers::btcs_chunks(R, w.lanes), i, 0});
+      continue;
+    }
+    for (int64_t s0 = 0; s0 < n; s0 += 256)
+      long_tiles.push_back(burgers::AdjTile{ctx->offsets[i], rows, n, p.bc, i, static_cast<int32_t>(s0), 0, 0});
     roots.emplace_back(i, rows, R);
     rows += R;
   }
   int64_t rows_used = rows;
   hipError_t e;
   np->tiles = std::make_unique<DevBuf>();
-  if ((e = upload_on(ctx->stream, *np->tiles, tiles)) != hipSuccess) return from_hip(e);
+  np->long_tiles = std::make_unique<DevBuf>();
+  if ((e = upload_on(ctx->stream, *np->tiles, tiles)) != hipSuccess ||
+      (e = upload_on(ctx->stream, *np->long_tiles, long_tiles)) != hipSuccess)
+    return from_hip(e);
   np->n_tiles = static_cast<int64_t>(tiles.size());
+  np->n_long_tiles = static_cast<int64_t>(long_tiles.size());
+  for (auto& kv : groups) {
+    burgers::WgGroup g;
+    g.shape = burgers::WidthClass{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first)};
+    g.sys = std::make_unique<DevBuf>();
+    g.n = static_cast<int32_t>(kv.second.size());
+    if ((e = upload_on(ctx->stream, *g.sys, kv.second)) != hipSuccess) return from_hip(e);
+    np->whole.push_back(std::move(g));
+  }
   if ((e = build_array_solve(ctx, roots, np->solve, rows_used)) != hipSuccess) return from_hip(e);
-  const size_t lb = static_cast<size_t>(std::max<int64_t>(rows_used, 1)) * sizeof(double);
+  const size_t lb = static_cast<size_t>(rows_used) * sizeof(double);
   if ((e = np->NA.alloc(lb, ctx->stream)) != hipSuccess || (e = np->NC.alloc(lb, ctx->stream)) != hipSuccess ||
       (e = np->ND.alloc(lb, ctx->stream)) != hipSuccess || (e = np->NX.alloc(lb, ctx->stream)) != hipSuccess)
     return from_hip(e);

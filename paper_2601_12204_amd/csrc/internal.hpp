@@ -185,9 +185,12 @@ struct AdjointPlan {
 // binary64 arrays and solved by the partition solver's array path.
 constexpr int kNewtonIters = 4;
 struct NewtonPlan {
-  std::unique_ptr<DevBuf> tiles;                    // AdjTile[] (256 nodes each) of the Newton instances
+  std::unique_ptr<DevBuf> tiles;                    // AdjTile[] (256 nodes each) of all Newton instances
   int64_t n_tiles = 0;
-  BtcsPlan solve;                                   // partition hierarchy over their systems
+  std::vector<WgGroup> whole;                       // systems of up to 8192 rows: one fused kernel per iteration
+  std::unique_ptr<DevBuf> long_tiles;               // AdjTile[] of the longer ones (array path)
+  int64_t n_long_tiles = 0;
+  BtcsPlan solve;                                   // partition hierarchy over the longer systems
   DevBuf NA, NC, ND, NX;
 };
 
@@ -263,6 +266,7 @@ int btcs_reduce_chunk();                // target rows per chunk in the partitio
 constexpr int kReduceBlock = 256;       // chunks per workgroup in the partition kernels
 hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out);
 hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, void* u, int steps);
+hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, const void* u, void* x);
 WidthClass btcs_width_class(int rows, int threads);
 int btcs_chunks(int rows, int threads);
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,

@@ -531,3 +531,30 @@ def test_newton_mixed_and_unsupported():
         B.adjoint_into(s, u, u.clone(), 3, 2, g, gn)
     assert err.value.status == -2
     s.close()
+
+
+# ----------------------------------------------------------------------------- degenerate cases
+def test_degenerate_inputs():
+    """Inviscid instances (nu = 0: D = 0, the BTCS rows keep their unit row sums and dominance), a zero
+    state, and zero steps, for every scheme: results match the oracle (bitwise for explicit schemes) and
+    zero steps leave the state untouched."""
+    rng = np.random.default_rng(127)
+    problems, states = [], []
+    for k, n in enumerate([3, 5, 64, 700, 8192, 9000]):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            for scheme in (W.EXPLICIT, W.BTCS, W.RK4, W.CN, W.NEWTON):
+                x = W.node_coordinates(n, 2 * np.pi, bc)
+                zero = (k + scheme) % 3 == 0
+                u = np.zeros(n) if zero else 1.0 + 0.5 * np.sin(x + rng.uniform(0, 6))
+                left, right = (0.0, 0.0) if zero else (float(u[0]), float(u[-1]))
+                dx = 2 * np.pi / n if bc == W.BC_PERIODIC else 2 * np.pi / (n - 1)
+                dt = 0.4 * dx / 1.5 * (3.0 if scheme in (W.BTCS, W.CN) else 1.0)
+                problems.append(W.Problem(n=n, length=2 * np.pi, nu=0.0, dt=dt, bc=bc, scheme=scheme,
+                                          left=left, right=right))
+                states.append(u)
+    batch = W._pack(problems, states)
+    announce("degenerate: nu = 0, zero states, zero steps")
+    same = device_run(batch, 0, "f64", how="run")
+    assert np.array_equal(same, batch.u0)
+    got = device_run(batch, 7, "f64", how="run")
+    check_batch(batch, got, 7, "f64")
