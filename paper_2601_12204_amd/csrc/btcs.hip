@@ -49,8 +49,9 @@ __device__ __forceinline__ double recip(double x) {
   return __builtin_fma(r, e, r);
 }
 
-// Couplings below this fraction of a row's diagonal are below binary64 rounding of the solution.
-constexpr double kNegligible = 0x1p-60;
+// Couplings below this fraction of a row's (unit) diagonal are negligible: dropping them changes a
+// solution value by less than half an ulp of the largest value it couples to.
+constexpr double kNegligible = 0x1p-54;
 
 // Row sources of the chunk elimination.  row() returns row k as assembled; boundary() then folds the
 // Dirichlet values into the reduced rows of the chunk that holds the first or last row of the system
