@@ -237,53 +237,97 @@ __device__ __forceinline__ void chunk_span(int k, int R, int P, int& s, int& m) 
   m = q + (k < rho ? 1 : 0);
 }
 
-// Cyclic PCR on R2 (a power of two, <= 2 NT) rows with coefficients in LDS, every row kept normalised
-// to a unit diagonal:  A_i x_{i-s} + x_i + C_i x_{i+s} = D_i.  One step combines row i with rows i-s and
-// i+s and renormalises.  Indices wrap modulo R2; a non-cyclic system simply carries zero corner
-// couplings.  After log2(R2) steps every row couples only to itself and the solution is D / (1 + A + C).
-// The reduction stops earlier once every remaining coupling is negligible; the solution is then D.  The
-// result is left in sD.
+// One PCR step on a row normalised to a unit diagonal,  a x_{i-s} + x_i + c x_{i+s} = d,  with its two
+// partners  x_{i-s} + cm x_i + ... = dm  (coefficients am, cm, dm) and  ap x_i + x_{i+s} + ... = dp:
+// subtracting a times the first and c times the second leaves a row coupling x_{i-2s} and x_{i+2s},
+// renormalised.
+template <typename T>
+__device__ __forceinline__ void pcr_combine(T a0, T c0, T d0, T am, T cm, T dm, T ap, T cp, T dp, T& na, T& nc,
+                                            T& nd) {
+  const T inv = recip(__builtin_fma(-c0, ap, __builtin_fma(-a0, cm, T(1))));
+  const T a = a0 * inv, c = c0 * inv;
+  na = -(a * am);
+  nc = -(c * cp);
+  nd = __builtin_fma(-c, dp, __builtin_fma(-a, dm, d0 * inv));
+}
+
+// Workspace of pcr_pairs in LDS: two buffers of three arrays (sub, super, rhs) of 2 NT rows, and one flag
+// per wave for each buffer.
 template <typename T, int NT>
-__device__ __forceinline__ void pcr_cyclic(T* sA, T* sC, T* sD, int R2) {
-  const int tid = threadIdx.x;
-  bool done = false;
-  for (int s = 1; s < R2 && !done; s <<= 1) {
-    T nA[2], nC[2], nD[2];
-    int live = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = tid + h * NT;
-      if (i < R2) {
-        const int im = (i - s) & (R2 - 1);
-        const int ip = (i + s) & (R2 - 1);
-        const T inv = recip(__builtin_fma(-sC[i], sA[ip], __builtin_fma(-sA[i], sC[im], T(1))));
-        const T a = sA[i] * inv, c = sC[i] * inv;
-        nA[h] = -(a * sA[im]);
-        nC[h] = -(c * sC[ip]);
-        nD[h] = __builtin_fma(-c, sD[ip], __builtin_fma(-a, sD[im], sD[i] * inv));
-        live |= (__builtin_fabs(nA[h]) + __builtin_fabs(nC[h])) > kNegligible;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = tid + h * NT;
-      if (i < R2) {
-        sA[i] = nA[h];
-        sC[i] = nC[h];
-        sD[i] = nD[h];
-      }
-    }
-    done = !__syncthreads_or(live);
-  }
-  if (!done) {   // ran all log2(R2) steps: the remaining couplings point at the row itself
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = tid + h * NT;
-      if (i < R2) sD[i] = sD[i] / ((T(1) + sA[i]) + sC[i]);
-    }
+struct PcrSpace {
+  static constexpr int kRows = 2 * NT;
+  static constexpr int kWaves = (NT + 63) / 64;
+  T* rows;     // 2 buffers x 3 arrays x kRows
+  int* flags;  // 2 buffers x kWaves
+  static constexpr int kBytes = 2 * 3 * kRows * static_cast<int>(sizeof(T));
+};
+
+// Cyclic PCR on the 2P reduced rows of P chunks (P a power of two, P <= NT), every row normalised to a
+// unit diagonal:  A_i x_{i-s} + x_i + C_i x_{i+s} = D_i.  Lane t < P owns rows 2t (its chunk's F row) and
+// 2t+1 (its E row) and keeps them in registers; each step publishes them to LDS, F rows at [0, P) and E
+// rows at [P, 2P), so the partners of either row at any distance sit at consecutive positions across
+// the wave.  Indices wrap modulo 2P; a non-cyclic system simply carries zero corner couplings.  After
+// log2(2P) steps every row couples only to itself and the solution is D / (1 + A + C); the reduction
+// stops earlier once every coupling of every row is negligible, and the solution is then D.
+// The steps alternate between the two buffers, so one barrier per step orders both the reads after the
+// writes and the next step's writes after the reads.  Each wave's vote on stopping rides in the same
+// buffer as its rows.  On return F and E hold the solution of rows 2t and 2t+1.
+template <typename T, int NT>
+__device__ __forceinline__ void pcr_pairs(const PcrSpace<T, NT>& w, int P, T fa, T fc, T fd, T ea, T ec, T ed,
+                                          T& F, T& E) {
+  constexpr int kR = PcrSpace<T, NT>::kRows;
+  constexpr int kW = PcrSpace<T, NT>::kWaves;
+  const int t = threadIdx.x;
+  const bool own = t < P;
+  const int mask = P - 1;
+  if (own) {
+    T* A = w.rows;
+    A[t] = fa; A[kR + t] = fc; A[2 * kR + t] = fd;
+    A[P + t] = ea; A[kR + P + t] = ec; A[2 * kR + P + t] = ed;
   }
   __syncthreads();
+  int b = 0;
+  bool done = false;
+  for (int s = 1; s < 2 * P && !done; s <<= 1) {
+    const T* A = w.rows + b * 3 * kR;
+    const T* C = A + kR;
+    const T* D = C + kR;
+    bool live = false;
+    if (own) {
+      T nfa, nfc, nfd, nea, nec, ned;
+      if (s == 1) {   // F row: partners E_{t-1} and E_t; E row: partners F_t and F_{t+1}
+        const int m = P + ((t - 1) & mask), p = (t + 1) & mask;
+        pcr_combine(fa, fc, fd, A[m], C[m], D[m], ea, ec, ed, nfa, nfc, nfd);
+        pcr_combine(ea, ec, ed, fa, fc, fd, A[p], C[p], D[p], nea, nec, ned);
+      } else {        // rows 2t -+ s and 2t+1 -+ s: the same kind of row, s/2 lanes away
+        const int h = s >> 1;
+        const int m = (t - h) & mask, p = (t + h) & mask;
+        pcr_combine(fa, fc, fd, A[m], C[m], D[m], A[p], C[p], D[p], nfa, nfc, nfd);
+        pcr_combine(ea, ec, ed, A[P + m], C[P + m], D[P + m], A[P + p], C[P + p], D[P + p], nea, nec, ned);
+      }
+      fa = nfa; fc = nfc; fd = nfd;
+      ea = nea; ec = nec; ed = ned;
+      live = (__builtin_fabs(fa) + __builtin_fabs(fc)) > kNegligible ||
+             (__builtin_fabs(ea) + __builtin_fabs(ec)) > kNegligible;
+      T* nA = w.rows + (1 - b) * 3 * kR;
+      nA[t] = fa; nA[kR + t] = fc; nA[2 * kR + t] = fd;
+      nA[P + t] = ea; nA[kR + P + t] = ec; nA[2 * kR + P + t] = ed;
+    }
+    const bool wave_live = __ballot(live) != 0;
+    if ((t & 63) == 0) w.flags[(1 - b) * kW + (t >> 6)] = wave_live ? 1 : 0;
+    __syncthreads();
+    b = 1 - b;
+    int any = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) any |= w.flags[b * kW + k];
+    done = any == 0;
+  }
+  if (!done) {   // ran all log2(2P) steps: the remaining couplings point at the row itself
+    fd = fd / ((T(1) + fa) + fc);
+    ed = ed / ((T(1) + ea) + ec);
+  }
+  F = fd;
+  E = ed;
 }
 
 // Coalesced copies of a block's rows between HBM and LDS: all loads are issued before the first LDS
@@ -335,13 +379,12 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
     S* __restrict__ out, const double* __restrict__ LA, const double* __restrict__ LC,
     const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
-  constexpr int kPcrBytes = 3 * 2 * NT * static_cast<int>(sizeof(T));
+  using Pcr = PcrSpace<T, NT>;
   constexpr int kStageBytes = FromState ? padded_size(NT * MC) * static_cast<int>(sizeof(S)) : 0;
-  constexpr int kBytes = kStageBytes > kPcrBytes ? kStageBytes : kPcrBytes;
+  constexpr int kBytes = kStageBytes > Pcr::kBytes ? kStageBytes : Pcr::kBytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
-  T* sA = reinterpret_cast<T*>(smem);
-  T* sC = sA + 2 * NT;
-  T* sD = sC + 2 * NT;
+  __shared__ int pcr_flags[2 * Pcr::kWaves];
+  const Pcr pcr{reinterpret_cast<T*>(smem), pcr_flags};
   S* stage = reinterpret_cast<S*>(smem);
 
   const SysDesc sys = systems[blockIdx.x];
@@ -387,7 +430,7 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
   }
 
   T al[MC], ga[MC], de[MC];
-  T AF, CF, DF, AE, CE, DE;
+  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
   int s = 0, m = 0;
   if (tid < P) {
     chunk_span(tid, R, P, s, m);
@@ -401,20 +444,11 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
       chunk_eliminate<T, MC>(asrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
     }
   }
-  if constexpr (FromState) __syncthreads();   // the PCR arrays overlay the staged rows
-  if (tid < P) {
-    sA[2 * tid] = AF; sC[2 * tid] = CF; sD[2 * tid] = DF;
-    sA[2 * tid + 1] = AE; sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
-  }
-  __syncthreads();
-  pcr_cyclic<T, NT>(sA, sC, sD, 2 * P);
+  if constexpr (FromState) __syncthreads();   // the PCR rows overlay the staged rows
   T F = T(0), E = T(0);
-  if (tid < P) {
-    F = sD[2 * tid];
-    E = sD[2 * tid + 1];
-  }
+  // (PCR's last barrier follows its last read of the rows, so the staging buffer is free on return)
+  pcr_pairs<T, NT>(pcr, P, AF, CF, DF, AE, CE, DE, F, E);
   if constexpr (FromState) {
-    __syncthreads();                           // all ends read before the staging buffer is reused
     if (tid < P) chunk_recover<T, MC>(sdst, s, m, al, ga, de, F, E);
     __syncthreads();
     const int64_t o = d.off + (d.bc == kDirichlet ? 1 : 0);
@@ -460,13 +494,12 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void newton_wg_kernel(const I
                                                                          const SysDesc* __restrict__ systems,
                                                                          const S* __restrict__ u, S* __restrict__ x) {
   using T = double;
-  constexpr int kPcrBytes = 3 * 2 * NT * static_cast<int>(sizeof(T));
+  using Pcr = PcrSpace<T, NT>;
   constexpr int kStageBytes = padded_size(NT * MC) * static_cast<int>(sizeof(T));
-  constexpr int kBytes = kStageBytes > kPcrBytes ? kStageBytes : kPcrBytes;
+  constexpr int kBytes = kStageBytes > Pcr::kBytes ? kStageBytes : Pcr::kBytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
-  T* sA = reinterpret_cast<T*>(smem);
-  T* sC = sA + 2 * NT;
-  T* sD = sC + 2 * NT;
+  __shared__ int pcr_flags[2 * Pcr::kWaves];
+  const Pcr pcr{reinterpret_cast<T*>(smem), pcr_flags};
   T* stage = reinterpret_cast<T*>(smem);
   const SysDesc sys = systems[blockIdx.x];
   const InstDesc d = inst[sys.inst];
@@ -491,25 +524,15 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void newton_wg_kernel(const I
     return;
   }
   T al[MC], ga[MC], de[MC];
-  T AF, CF, DF, AE, CE, DE;
+  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
   int s = 0, m = 0;
   if (tid < P) {
     chunk_span(tid, R, P, s, m);
     chunk_eliminate<T, MC>(rows, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
-  __syncthreads();                             // the PCR arrays overlay the staged iterate
-  if (tid < P) {
-    sA[2 * tid] = AF; sC[2 * tid] = CF; sD[2 * tid] = DF;
-    sA[2 * tid + 1] = AE; sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
-  }
-  __syncthreads();
-  pcr_cyclic<T, NT>(sA, sC, sD, 2 * P);
+  __syncthreads();                             // the PCR rows overlay the staged iterate
   T F = T(0), E = T(0);
-  if (tid < P) {
-    F = sD[2 * tid];
-    E = sD[2 * tid + 1];
-  }
-  __syncthreads();
+  pcr_pairs<T, NT>(pcr, P, AF, CF, DF, AE, CE, DE, F, E);   // ends its use of the rows with a barrier
   if (tid < P) chunk_recover<T, MC>(PtrDst<T>{stage}, s, m, al, ga, de, F, E);   // increments, unpadded
   __syncthreads();
 #pragma unroll
@@ -528,10 +551,10 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, S* __restrict__ u,
     int steps) {
   using T = double;
-  __shared__ T pcr[3 * 2 * NT];
-  T* sA = pcr;
-  T* sC = sA + 2 * NT;
-  T* sD = sC + 2 * NT;
+  using Pcr = PcrSpace<T, NT>;
+  __shared__ T pcr_rows[Pcr::kBytes / sizeof(T)];
+  __shared__ int pcr_flags[2 * Pcr::kWaves];
+  const Pcr pcr{pcr_rows, pcr_flags};
   const SysDesc sys = systems[blockIdx.x];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
@@ -569,20 +592,10 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
   }
   const ValueRows src{d.r, d.D, DirichletEnds{d.a, d.b, dir}};
   for (int step = 0; step < steps; ++step) {
-    T AF, CF, DF, AE, CE, DE;
-    if (tid < P) {
-      chunk_eliminate<T, MC, true>(src, s, EXACT ? MC : m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
-      sA[2 * tid] = AF; sC[2 * tid] = CF; sD[2 * tid] = DF;
-      sA[2 * tid + 1] = AE; sC[2 * tid + 1] = CE; sD[2 * tid + 1] = DE;
-    }
-    __syncthreads();
-    pcr_cyclic<T, NT>(sA, sC, sD, 2 * P);
+    T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
+    if (tid < P) chunk_eliminate<T, MC, true>(src, s, EXACT ? MC : m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
     T F = T(0), E = T(0);
-    if (tid < P) {
-      F = sD[2 * tid];
-      E = sD[2 * tid + 1];
-    }
-    __syncthreads();                           // ends read before the next step rewrites the arrays
+    pcr_pairs<T, NT>(pcr, P, AF, CF, DF, AE, CE, DE, F, E);
     if (tid < P) chunk_recover_in_place<S>(EXACT ? MC : m, al, ga, de, F, E);
   }
   if (tid < P) {

@@ -160,10 +160,10 @@ __device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBl
         acc[j] = K;
         out[j] = v[j] + T(0.5) * K;
       } else if constexpr (STAGE == 2) {
-        acc[j] = acc[j] + T(2) * K;
+        acc[j] = fma_exact(T(2), K, acc[j]);
         out[j] = v[j] + T(0.5) * K;
       } else if constexpr (STAGE == 3) {
-        acc[j] = acc[j] + T(2) * K;
+        acc[j] = fma_exact(T(2), K, acc[j]);
         out[j] = v[j] + K;
       } else {
         v[j] = v[j] + (acc[j] + K) / T(6);

@@ -8,6 +8,18 @@
 
 namespace burgers {
 
+// a * b + c rounded once.  Used only where a * b is exact (a = +-2), so it rounds exactly like the
+// unfused a * b + c while taking one instruction instead of two (for |b| below half the largest
+// finite value, where 2b cannot overflow).
+template <typename T>
+__device__ __forceinline__ T fma_exact(T a, T b, T c) {
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_fma(a, b, c);
+  } else {
+    return __builtin_fmaf(a, b, c);
+  }
+}
+
 // Explicit forward-Euler update of one node (Sec. 2.3, eq. 21): first-order upwind convection whose
 // side follows the sign of c = r u_i (eq. 3 and the text after it), central diffusion (eq. 4):
 //   u' = ((u - max(c,0) (u - u_m)) - min(c,0) (u_p - u)) + D ((u_p + u_m) - 2u).
@@ -18,7 +30,7 @@ template <typename T>
 __device__ __forceinline__ T upwind_central(T ui, T um, T up, T r, T D) {
   const T c = r * ui;
   const T diff = c > T(0) ? ui - um : up - ui;
-  const T lap = (up + um) - T(2) * ui;
+  const T lap = fma_exact(T(-2), ui, up + um);  // (u_p + u_m) - 2u
   return (ui - c * diff) + D * lap;
 }
 
@@ -29,7 +41,7 @@ template <typename T>
 __device__ __forceinline__ T rk4_increment(T vi, T vm, T vp, T r, T D) {
   const T c = r * vi;
   const T diff = c > T(0) ? vi - vm : vp - vi;
-  const T lap = (vp + vm) - T(2) * vi;
+  const T lap = fma_exact(T(-2), vi, vp + vm);  // (v_p + v_m) - 2v
   return D * lap - c * diff;
 }
 
