@@ -612,7 +612,8 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
 // zero, removes every in-segment coupling, leaving
 //     x_i + P_i L + Q_i Rt = D_i        (the segment's solution as a function of its two neighbours).
 // Each sweep combines row i with rows i - s and i + s and renormalises; the loop stops early once all
-// remaining in-segment couplings are negligible.  Arrays are indexed by row, five of them in LDS.
+// remaining in-segment couplings are negligible.  Five arrays in LDS; the block's first row (chunk 0's F
+// row) sits at index 0 and its last row (the last chunk's E row) at index Rb - 1.
 struct SpikeRows {
   double* A;
   double* C;
@@ -621,64 +622,91 @@ struct SpikeRows {
   double* Q;
 };
 constexpr int kSpikeRows = 2 * kReduceBlock;
+constexpr int kSpikeWaves = kReduceBlock / 64;
 
-__device__ __forceinline__ void spike_pcr(const SpikeRows& S, int Rb) {
-  using T = double;
-  const int tid = threadIdx.x;
+// One row of a block's spike system: unit diagonal, couplings a (row i - s) and c (row i + s), right-hand
+// side d, and the spike columns p (previous block's last unknown L) and q (next block's first unknown Rt).
+struct SpikeRow {
+  double a, c, d, p, q;
+};
+
+__device__ __forceinline__ SpikeRow spike_load(const SpikeRows& S, int i) {
+  return SpikeRow{S.A[i], S.C[i], S.D[i], S.P[i], S.Q[i]};
+}
+
+__device__ __forceinline__ void spike_store(const SpikeRows& S, int i, const SpikeRow& r) {
+  S.A[i] = r.a; S.C[i] = r.c; S.D[i] = r.d; S.P[i] = r.p; S.Q[i] = r.q;
+}
+
+// One PCR step of row r with its partners m (distance -s) and p (distance +s), as pcr_combine, also
+// carried through the two spike columns.
+__device__ __forceinline__ SpikeRow spike_combine(const SpikeRow& r, const SpikeRow& m, const SpikeRow& p) {
+  const double inv = recip(__builtin_fma(-r.c, p.a, __builtin_fma(-r.a, m.c, 1.0)));
+  const double a = r.a * inv, c = r.c * inv;
+  SpikeRow n;
+  n.a = -(a * m.a);
+  n.c = -(c * p.c);
+  n.d = __builtin_fma(-c, p.d, __builtin_fma(-a, m.d, r.d * inv));
+  n.p = __builtin_fma(-c, p.p, __builtin_fma(-a, m.p, r.p * inv));
+  n.q = __builtin_fma(-c, p.q, __builtin_fma(-a, m.q, r.q * inv));
+  return n;
+}
+
+// PCR over a block's Rb = 2 Pb spike rows; rows outside [0, Rb) are zero.  Lane t < Pb owns chunk t's F
+// row (row 2t) and E row (row 2t+1) and keeps them in registers (f, e); each step publishes them to LDS,
+// F rows at [0, Pb) and E rows at [Pb, Rb), so the partners of either row at any distance sit at
+// consecutive positions across the wave.  Stops once every coupling is negligible (or all couplings
+// have left the segment).  On return the rows are in registers and in S, after a barrier.  Each wave's
+// vote on stopping travels through `flags`.
+__device__ __forceinline__ void spike_pcr(const SpikeRows& S, int* flags, int Pb, SpikeRow& f, SpikeRow& e) {
+  const int t = threadIdx.x;
+  const bool own = t < Pb;
+  const int Rb = 2 * Pb;
+  const SpikeRow zero{0.0, 0.0, 0.0, 0.0, 0.0};
+  if (own) {
+    spike_store(S, t, f);
+    spike_store(S, Pb + t, e);
+  }
+  __syncthreads();
   bool done = false;
   for (int s = 1; s < Rb && !done; s <<= 1) {
-    T nA[2], nC[2], nD[2], nP[2], nQ[2];
-    int live = 0;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = tid + h * kReduceBlock;
-      if (i < Rb) {
-        const int im = i - s, ip = i + s;
-        const T Am = im >= 0 ? S.A[im] : T(0), Cm = im >= 0 ? S.C[im] : T(0);
-        const T Dm = im >= 0 ? S.D[im] : T(0), Pm = im >= 0 ? S.P[im] : T(0), Qm = im >= 0 ? S.Q[im] : T(0);
-        const T Ap = ip < Rb ? S.A[ip] : T(0), Cp = ip < Rb ? S.C[ip] : T(0);
-        const T Dp = ip < Rb ? S.D[ip] : T(0), Pp = ip < Rb ? S.P[ip] : T(0), Qp = ip < Rb ? S.Q[ip] : T(0);
-        const T inv = recip(__builtin_fma(-S.C[i], Ap, __builtin_fma(-S.A[i], Cm, T(1))));
-        const T a = S.A[i] * inv, c = S.C[i] * inv;
-        nA[h] = -(a * Am);
-        nC[h] = -(c * Cp);
-        nD[h] = __builtin_fma(-c, Dp, __builtin_fma(-a, Dm, S.D[i] * inv));
-        nP[h] = __builtin_fma(-c, Pp, __builtin_fma(-a, Pm, S.P[i] * inv));
-        nQ[h] = __builtin_fma(-c, Qp, __builtin_fma(-a, Qm, S.Q[i] * inv));
-        live |= (__builtin_fabs(nA[h]) + __builtin_fabs(nC[h])) > kNegligible;
+    bool live = false;
+    SpikeRow nf = zero, ne = zero;
+    if (own) {
+      if (s == 1) {   // F row: partners E_{t-1} and E_t; E row: partners F_t and F_{t+1}
+        nf = spike_combine(f, t > 0 ? spike_load(S, Pb + t - 1) : zero, e);
+        ne = spike_combine(e, f, t + 1 < Pb ? spike_load(S, t + 1) : zero);
+      } else {        // the same kind of row, s/2 lanes away
+        const int h = s >> 1;
+        const bool hm = t >= h, hp = t + h < Pb;
+        nf = spike_combine(f, hm ? spike_load(S, t - h) : zero, hp ? spike_load(S, t + h) : zero);
+        ne = spike_combine(e, hm ? spike_load(S, Pb + t - h) : zero, hp ? spike_load(S, Pb + t + h) : zero);
       }
+      live = (__builtin_fabs(nf.a) + __builtin_fabs(nf.c)) > kNegligible ||
+             (__builtin_fabs(ne.a) + __builtin_fabs(ne.c)) > kNegligible;
     }
+    const bool wave_live = __ballot(live) != 0;
+    __syncthreads();                           // every partner read before the rows are overwritten
+    if (own) {
+      f = nf;
+      e = ne;
+      spike_store(S, t, f);
+      spike_store(S, Pb + t, e);
+    }
+    if ((t & 63) == 0) flags[t >> 6] = wave_live ? 1 : 0;
     __syncthreads();
+    int any = 0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = tid + h * kReduceBlock;
-      if (i < Rb) {
-        S.A[i] = nA[h];
-        S.C[i] = nC[h];
-        S.D[i] = nD[h];
-        S.P[i] = nP[h];
-        S.Q[i] = nQ[h];
-      }
-    }
-    done = !__syncthreads_or(live);
+    for (int k = 0; k < kSpikeWaves; ++k) any |= flags[k];
+    done = any == 0;
   }
 }
 
-// Chunk pair t of the block into the spike rows (row 2t: F row, row 2t + 1: E row); the segment's outer
-// couplings go to the P and Q columns.
-__device__ __forceinline__ void spike_put(const SpikeRows& S, int t, int Rb, double AF, double CF, double DF,
-                                          double AE, double CE, double DE) {
-  const int f = 2 * t, e = 2 * t + 1;
-  S.A[f] = f == 0 ? 0.0 : AF;
-  S.P[f] = f == 0 ? AF : 0.0;
-  S.C[f] = CF;
-  S.Q[f] = 0.0;
-  S.D[f] = DF;
-  S.A[e] = AE;
-  S.P[e] = 0.0;
-  S.C[e] = e == Rb - 1 ? 0.0 : CE;
-  S.Q[e] = e == Rb - 1 ? CE : 0.0;
-  S.D[e] = DE;
+// Chunk t's two reduced rows in spike form; the segment's outer couplings go to the P and Q columns.
+__device__ __forceinline__ void spike_init(int t, int Pb, double AF, double CF, double DF, double AE, double CE,
+                                           double DE, SpikeRow& f, SpikeRow& e) {
+  f = SpikeRow{t == 0 ? 0.0 : AF, CF, DF, t == 0 ? AF : 0.0, 0.0};
+  e = SpikeRow{AE, t == Pb - 1 ? 0.0 : CE, DE, 0.0, t == Pb - 1 ? CE : 0.0};
 }
 
 // The block's two rows in the partition form (tridiagonal over first/last unknowns of all blocks),
@@ -770,6 +798,7 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
   S* stage = reinterpret_cast<S*>(smem);
   T* sp = reinterpret_cast<T*>(smem);
   const SpikeRows SR{sp, sp + kSpikeRows, sp + 2 * kSpikeRows, sp + 3 * kSpikeRows, sp + 4 * kSpikeRows};
+  __shared__ int spike_flags[kSpikeWaves];
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const InstDesc d = inst[sys.inst];
@@ -790,9 +819,9 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
                                   sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
   __syncthreads();                             // every chunk read before the spike rows overlay the stage
-  if (tid < Pb) spike_put(SR, tid, Rb, AF, CF, DF, AE, CE, DE);
-  __syncthreads();
-  spike_pcr(SR, Rb);
+  SpikeRow f, e;
+  spike_init(tid, Pb, AF, CF, DF, AE, CE, DE, f, e);
+  spike_pcr(SR, spike_flags, Pb, f, e);
   if (tid == 0) {
     spike_ends(SR, Rb, AF, CF, DF, AE, CE, DE);
     const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock);
@@ -817,13 +846,13 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   S* stage = reinterpret_cast<S*>(smem);
   T* sp = reinterpret_cast<T*>(smem);
   const SpikeRows SR{sp, sp + kSpikeRows, sp + 2 * kSpikeRows, sp + 3 * kSpikeRows, sp + 4 * kSpikeRows};
+  __shared__ int spike_flags[kSpikeWaves];
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
   const int tid = threadIdx.x;
   const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
-  const int Rb = 2 * Pb;
   const int blk = cb.chunk0 / kReduceBlock;
   const int nblk = (sys.chunks + kReduceBlock - 1) / kReduceBlock;
   int rs, re;
@@ -838,10 +867,10 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
     chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
                                   sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
-  __syncthreads();
-  if (tid < Pb) spike_put(SR, tid, Rb, AF, CF, DF, AE, CE, DE);
-  __syncthreads();
-  spike_pcr(SR, Rb);
+  __syncthreads();                             // every chunk read before the spike rows overlay the stage
+  SpikeRow f, e;
+  spike_init(tid, Pb, AF, CF, DF, AE, CE, DE, f, e);
+  spike_pcr(SR, spike_flags, Pb, f, e);        // ends with a barrier after its last read of SR
   // neighbours' end unknowns; a Dirichlet system's outer blocks have P = 0 or Q = 0 and ignore them
   const T* X = LX + sys.red_off;
   const bool periodic = !dir;
@@ -849,11 +878,9 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   const T Rt = blk + 1 < nblk ? X[2 * blk + 2] : (periodic ? X[0] : T(0));
   T F = T(0), E = T(0);
   if (tid < Pb) {
-    const int f = 2 * tid, e = 2 * tid + 1;
-    F = __builtin_fma(-SR.Q[f], Rt, __builtin_fma(-SR.P[f], L, SR.D[f]));
-    E = __builtin_fma(-SR.Q[e], Rt, __builtin_fma(-SR.P[e], L, SR.D[e]));
+    F = __builtin_fma(-f.q, Rt, __builtin_fma(-f.p, L, f.d));
+    E = __builtin_fma(-e.q, Rt, __builtin_fma(-e.p, L, e.d));
   }
-  __syncthreads();                             // spike rows read before the stage is rewritten
   if (tid < Pb) chunk_recover<T, kRedChunk>(LdsDst<S>{stage, rs}, s, m, al, ga, de, F, E);
   __syncthreads();
   const int64_t o = d.off + (dir ? 1 : 0) + rs;
