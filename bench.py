@@ -118,6 +118,21 @@ def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000, explici
     return res
 
 
+def bench_c2_plain(B, torch, n_exp=200, n_btcs=50):
+    """The plain steppers on the C2 batch, one HBM pass per step: the streaming explicit kernel
+    (plan path 1) and the per-step whole-system BTCS kernel (plan path 1), each moving the state in and
+    out once per step (2 words per node).  Reports their HBM rate against the 8 TB/s peak."""
+    out = {}
+    nodes = 4096 * 8192
+    for name, dtype, word in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
+        r = bench_c2(B, torch, dtype, 1, 1, n_exp=n_exp, n_btcs=n_btcs, explicit_path=1, btcs_path=1)
+        for leg, ms in (("explicit_stream", r["explicit_launch_ms"]), ("btcs_per_step", r["btcs_step_ms"])):
+            gbs = 2 * word * nodes / (ms * 1e-3) / 1e9
+            out[f"{leg}_{name}"] = {"ms_per_step": ms, "glups": nodes / (ms * 1e-3) / 1e9,
+                                    "algorithmic_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def bench_c2_rk4(B, torch, nsteps=2500, reps=2):
     """The C2 batch (4096 x 8192 periodic, FP64) advanced by classical RK4 (eq. 22) at the CFL dt:
     four explicit stages per step, all steps of an instance in one on-chip launch."""
@@ -459,7 +474,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
-    ap.add_argument("--legs", default="c2,c2f32,c2rk4,c2cn,c2newton,c1,c3,c4,c5,serve",
+    ap.add_argument("--legs", default="c2,c2f32,c2plain,c2rk4,c2cn,c2newton,c1,c3,c4,c5,serve",
                     help="comma-separated side measurements to run (profiling runs select one)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--exp-steps", type=int, default=10_000, help="explicit steps per step (profiling runs)")
@@ -489,6 +504,9 @@ def main():
     if "c2f32" in legs:
         log("C2 FP32")
         extra["c2_f32"] = bench_c2(B, torch, torch.float32, 1, 1)
+    if "c2plain" in legs:
+        log("C2 plain steppers")
+        extra["c2_plain_hbm"] = bench_c2_plain(B, torch)
     if "c2rk4" in legs:
         log("C2 RK4")
         extra["c2_rk4_f64"] = bench_c2_rk4(B, torch)

@@ -74,7 +74,7 @@ std::vector<Tile> stream_tiles(const burgers_ctx* ctx, const std::vector<int32_t
   for (int32_t i : members) {
     const int32_t n = static_cast<int32_t>(ctx->probs[i].n);
     for (int64_t s = 0; s < n; s += tile)   // 64-bit counter: n may be close to INT32_MAX
-      tiles.push_back(Tile{ctx->offsets[i], n, ctx->probs[i].bc, i, static_cast<int32_t>(s)});
+      tiles.push_back(Tile{ctx->offsets[i], n, static_cast<int32_t>(s), ctx->probs[i].bc, i});
   }
   return tiles;
 }

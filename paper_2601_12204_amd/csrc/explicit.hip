@@ -34,8 +34,16 @@ constexpr int kBlockThreads = 512;
 constexpr int kBlockChunk = 16;
 
 template <typename T> struct Vec;
-template <> struct Vec<double> { using type = double2; static constexpr int n = 2; };
-template <> struct Vec<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec<double> {
+  using type = double2;
+  typedef double ext __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+template <> struct Vec<float> {
+  using type = float4;
+  typedef float ext __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
 
 template <typename T>
 __global__ __launch_bounds__(kStreamThreads) void explicit_stream_kernel(
@@ -45,23 +53,29 @@ __global__ __launch_bounds__(kStreamThreads) void explicit_stream_kernel(
   using VT = typename Vec<T>::type;
   const Tile t = tiles[blockIdx.x];
   const int n = t.n;
-  const int i0 = t.start + static_cast<int>(threadIdx.x) * V;
-  if (i0 >= n) return;
+  // A lane past the instance's end repeats the last vector's work and stores the same values to the
+  // same nodes as the lane that owns it, so no lane branches before its loads.
+  const int i0 = min(t.start + static_cast<int>(threadIdx.x) * V, (n - 1) / V * V);
   const T* __restrict__ src = u + t.off;
   T* __restrict__ dst = out + t.off;
   const bool periodic = t.bc == kPeriodic;
 
   // Instance starts are aligned to 64 elements and i0 is a multiple of V, so this vector lies inside
-  // the instance's padded extent even when it runs past node n-1.
+  // the instance's padded extent even when it runs past node n-1.  The two neighbour loads take
+  // selected addresses (wrapping periodically) rather than branches, and no branch precedes them, so
+  // every lane issues its three loads right after the tile's scalar loads; a Dirichlet end then
+  // replaces the wrapped value by its boundary value.
   const VT vv = *reinterpret_cast<const VT*>(src + i0);
+  const T lraw = src[i0 > 0 ? i0 - 1 : n - 1];
+  const T rraw = src[i0 + V < n ? i0 + V : 0];
   const InstDesc d = inst[t.inst];
   const T r = static_cast<T>(d.r), D = static_cast<T>(d.D);
   const T a = static_cast<T>(d.a), b = static_cast<T>(d.b);
   T v[V];
   __builtin_memcpy(v, &vv, sizeof(VT));
-  const T left = i0 > 0 ? src[i0 - 1] : (periodic ? src[n - 1] : a);
-  const T right = i0 + V < n ? src[i0 + V] : (periodic ? src[0] : b);
-  const T wrap_right = periodic ? src[0] : b;   // neighbour of node n-1
+  const T left = periodic || i0 > 0 ? lraw : a;
+  // the value beyond node n-1 (node 0, or b); only the lane whose vector reaches node n-1 uses it
+  const T right = periodic || i0 + V < n ? rraw : b;
 
   T o[V];
 #pragma unroll
@@ -69,7 +83,7 @@ __global__ __launch_bounds__(kStreamThreads) void explicit_stream_kernel(
     const int j = i0 + k;
     T um = k == 0 ? left : v[k - 1];
     T up = k == V - 1 ? right : v[k + 1];
-    if (j == n - 1) up = wrap_right;
+    if (j == n - 1) up = right;
     if (!periodic) {
       if (j == 1) um = a;
       if (j == n - 2) up = b;
@@ -82,9 +96,10 @@ __global__ __launch_bounds__(kStreamThreads) void explicit_stream_kernel(
     o[k] = res;
   }
   if (i0 + V <= n) {
-    VT ov;
-    __builtin_memcpy(&ov, o, sizeof(VT));
-    *reinterpret_cast<VT*>(dst + i0) = ov;
+    // The new state is not read again by this launch: stream it past the caches.
+    typename Vec<T>::ext ov;
+    __builtin_memcpy(&ov, o, sizeof(ov));
+    __builtin_nontemporal_store(ov, reinterpret_cast<typename Vec<T>::ext*>(dst + i0));
   } else {
 #pragma unroll
     for (int k = 0; k < V; ++k)

@@ -35,9 +35,9 @@ struct InstDesc {
 struct Tile {
   int64_t off;
   int32_t n;
+  int32_t start;   // off, n and start share the first 16 bytes: one scalar load addresses the tile
   int32_t bc;
   int32_t inst;
-  int32_t start;
 };
 
 // A window of one instance advanced several steps per launch by the temporal-blocking kernel.  Window

@@ -173,6 +173,29 @@ def test_btcs_block_partition_beyond_one_level(n):
     assert rel_err(got, ref) <= TOL_F64
 
 
+@pytest.mark.parametrize("factor", [1000.0, 10000.0])
+@pytest.mark.parametrize("path", [0, 1])
+def test_btcs_stiff_steps(factor, path):
+    """BTCS steps far beyond the CFL step (diffusion number D up to ~2500): the reduced systems stay
+    strongly coupled over many chunks, so the PCR runs many more steps than at 10x dt (up to all of
+    them in the narrow width classes), in every width class and in the block partition, against the
+    oracle (whose own distance from a dense solve of these systems is ~1e-14)."""
+    sizes = [8192, 6000, 2000, 700, 70, 9, 20000, 3 * 4096 * 16 + 40]
+    problems, states = [], []
+    for k, n in enumerate(sizes):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            b = W.random_batch(1300 + 2 * k + bc, 1, n, n, bc=bc, scheme=W.BTCS, amplitude=2.0)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    batch = W._pack(problems, states)
+    set_cfl_steps(batch, scheme=W.BTCS, btcs_factor=factor)
+    announce(f"btcs stiff x{factor} path={path} sizes={sizes}")
+    got = device_run(batch, 4, "f64", how="step_btcs", plan={"btcs_path": path})
+    ref = oracle_run(batch, 4, "f64", scheme=W.BTCS)
+    errs = per_instance_rel(batch, got, ref)
+    assert errs.max() <= TOL_F64, errs
+
+
 def test_repeatable_and_resumable():
     """Identical runs are bitwise identical (no races); run(n1) then run(n2) equals run(n1 + n2)."""
     batch = set_cfl_steps(W.random_batch(25, 20, 3, 20000, amplitude=2.0))
