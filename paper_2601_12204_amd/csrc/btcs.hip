@@ -72,6 +72,31 @@ struct ArrayRows {
   __device__ __forceinline__ void boundary(int, int, int, T&, T&, T&, T&) const {}
 };
 
+// Rows of a reduced system preloaded into registers: a lane issues all its loads before the elimination
+// starts instead of waiting for one row's loads at every step of the pivot chain.
+template <typename T, int M>
+struct RegRows {
+  T a[M], c[M], d[M];
+  __device__ __forceinline__ void load(const T* __restrict__ A, const T* __restrict__ C,
+                                       const T* __restrict__ D, int s, int m) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      if (j < m) {
+        a[j] = A[s + j];
+        c[j] = C[s + j];
+        d[j] = D[s + j];
+      }
+    }
+  }
+  __device__ __forceinline__ void row(int j, int, int, T& al, T& be, T& ga, T& de) const {
+    al = a[j];
+    be = T(1);
+    ga = c[j];
+    de = d[j];
+  }
+  __device__ __forceinline__ void boundary(int, int, int, T&, T&, T&, T&) const {}
+};
+
 // Dirichlet values of a level-0 system: row 0 reads x_{-1} = a, row R-1 reads x_R = b.  In the reduced
 // rows, x_{-1} enters only the chunk's F row (coefficient AF) and x_R only its E row (coefficient CE),
 // so moving the known values to the right-hand side is DF -= AF a, AF = 0 and DE -= CE b, CE = 0.
@@ -117,6 +142,39 @@ struct LdsDst {
   int base;
   __device__ __forceinline__ void write(int, int k, double v) const { st[padded(k - base)] = static_cast<S>(v); }
 };
+
+// Old state values of rows s..s+m-1 staged in LDS (row k at padded(k - base)) into de[], the input of
+// the in-place elimination over ValueRows: every LDS read is issued before the pivot chain starts.
+// The rows then round exactly as LdsRows would assemble them.
+template <typename S, typename T, int M>
+__device__ __forceinline__ void load_staged(const S* st, int base, int s, int m, T (&de)[M]) {
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+    if (j < m) de[j] = static_cast<T>(st[padded(s + j - base)]);
+}
+
+// Reduced systems of at least this many rows are read and written by the workgroup solver through LDS
+// (coalesced); smaller ones lane by lane, which saves the transposes' barriers.
+constexpr int kCoalesceRows = 2048;
+
+// Rows held coalesced (lane t: rows t + j NT) to the lanes' chunks (lane t < P: rows s..s+m-1) through
+// the LDS buffer `st`; ends with a barrier, so the next call may reuse the buffer.
+template <typename T, int NT, int MC>
+__device__ __forceinline__ void stage_transpose(T* st, const T (&v)[MC], int R, int P, int s, int m, T (&out)[MC]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    const int i = tid + j * NT;
+    if (i < R) st[padded(i)] = v[j];
+  }
+  __syncthreads();
+  if (tid < P) {
+#pragma unroll
+    for (int j = 0; j < MC; ++j)
+      if (j < m) out[j] = st[padded(s + j)];
+  }
+  __syncthreads();
+}
 
 // Row k of a level-0 system from its old value ui (resident solver, where the values live in registers).
 struct ValueRows {
@@ -373,19 +431,22 @@ __device__ __forceinline__ void stage_out_cn(const S* stage, const S* __restrict
 // (coalesced loads), eliminate chunks from LDS, solve the reduced system by PCR in the same LDS, write
 // the new values back into the staging buffer and store them coalesced, with the Dirichlet boundary
 // nodes.  Reduced systems of the partition levels read (A, C, D) and write X in HBM directly.
+// (Reduced systems are few and large, one workgroup each: their rows preloaded in registers matter more
+// than a second workgroup per CU.)
 template <typename S, bool FromState, int NT, int MC, bool EXACT = false>
-__global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
+__global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_wg_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, const S* __restrict__ u,
     S* __restrict__ out, const double* __restrict__ LA, const double* __restrict__ LC,
     const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
   using Pcr = PcrSpace<T, NT>;
-  constexpr int kStageBytes = FromState ? padded_size(NT * MC) * static_cast<int>(sizeof(S)) : 0;
+  constexpr int kStageBytes = padded_size(NT * MC) * static_cast<int>(FromState ? sizeof(S) : sizeof(T));
   constexpr int kBytes = kStageBytes > Pcr::kBytes ? kStageBytes : Pcr::kBytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
   __shared__ int pcr_flags[2 * Pcr::kWaves];
   const Pcr pcr{reinterpret_cast<T*>(smem), pcr_flags};
   S* stage = reinterpret_cast<S*>(smem);
+  T* tstage = reinterpret_cast<T*>(smem);   // reduced systems: one coefficient array at a time
 
   const SysDesc sys = systems[blockIdx.x];
   const int R = sys.rows, P = sys.chunks;
@@ -438,11 +499,35 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
       s = tid * MC;
       m = MC;
     }
-    if constexpr (FromState) {
-      chunk_eliminate<T, MC>(ssrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
-    } else {
-      chunk_eliminate<T, MC>(asrc, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+  }
+  if constexpr (FromState) {
+    if (tid < P) {
+      load_staged<S>(stage, 0, s, m, de);
+      chunk_eliminate<T, MC, true>(ValueRows{d.r, d.D, ssrc.ends}, s, m, R, al, ga, de, AF, CF, DF, AE, CE,
+                                   DE);
     }
+  } else if (R >= kCoalesceRows) {
+    // One workgroup reads the whole reduced system: coalesced loads of the three arrays (every load in
+    // flight at once), then each array transposed through LDS into the lanes' chunks.
+    T va[MC], vc[MC], vd[MC];
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      const int i = tid + j * NT;
+      if (i < R) {
+        va[j] = asrc.A[i];
+        vc[j] = asrc.C[i];
+        vd[j] = asrc.Dv[i];
+      }
+    }
+    RegRows<T, MC> rr;
+    stage_transpose<T, NT, MC>(tstage, va, R, P, s, m, rr.a);
+    stage_transpose<T, NT, MC>(tstage, vc, R, P, s, m, rr.c);
+    stage_transpose<T, NT, MC>(tstage, vd, R, P, s, m, rr.d);
+    if (tid < P) chunk_eliminate<T, MC>(rr, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+  } else if (tid < P) {   // small systems: the lanes' own rows straight from HBM, all loads up front
+    RegRows<T, MC> rr;
+    rr.load(asrc.A, asrc.C, asrc.Dv, s, m);
+    chunk_eliminate<T, MC>(rr, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
   if constexpr (FromState) __syncthreads();   // the PCR rows overlay the staged rows
   T F = T(0), E = T(0);
@@ -454,6 +539,14 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_wg_kernel(
     const int64_t o = d.off + (d.bc == kDirichlet ? 1 : 0);
     if (sys.cn) stage_out_cn<S, NT, MC>(stage, u + o, out + o, R);
     else stage_out<S, NT, MC>(stage, out + o, R);
+  } else if (R >= kCoalesceRows) {   // through LDS again, for a coalesced store
+    if (tid < P) chunk_recover<T, MC>(LdsDst<T>{tstage, 0}, s, m, al, ga, de, F, E);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      const int i = tid + j * NT;
+      if (i < R) adst.x[i] = tstage[padded(i)];
+    }
   } else {
     if (tid < P) chunk_recover<T, MC>(adst, s, m, al, ga, de, F, E);
   }
@@ -743,7 +836,7 @@ __device__ __forceinline__ void block_rows(const SysDesc& sys, int c0, int& rs, 
 
 // Partition level of a reduced system held in (A, C, D) arrays, forward half: every thread eliminates
 // one chunk and stores its two reduced rows.
-__global__ __launch_bounds__(kReduceBlock) void btcs_array_reduce_kernel(
+__global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_reduce_kernel(
     const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, double* __restrict__ LA,
     double* __restrict__ LC, double* __restrict__ LD) {
   using T = double;
@@ -755,7 +848,8 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_array_reduce_kernel(
   T AF, CF, DF, AE, CE, DE;
   int s, m;
   chunk_span(k, sys.rows, sys.chunks, s, m);
-  const ArrayRows<T> rows{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
+  RegRows<T, kRedChunk> rows;
+  rows.load(LA + sys.in_off, LC + sys.in_off, LD + sys.in_off, s, m);
   chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
   LA[o] = AF; LC[o] = CF; LD[o] = DF;
@@ -763,7 +857,7 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_array_reduce_kernel(
 }
 
 // Backward half: re-eliminate the chunk and recover its rows from the solved reduced unknowns.
-__global__ __launch_bounds__(kReduceBlock) void btcs_array_backsub_kernel(
+__global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_backsub_kernel(
     const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, const double* __restrict__ LA,
     const double* __restrict__ LC, const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
@@ -778,7 +872,8 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_array_backsub_kernel(
   const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
   const T F = LX[o];
   const T E = LX[o + 1];
-  const ArrayRows<T> rows{LA + sys.in_off, LC + sys.in_off, LD + sys.in_off};
+  RegRows<T, kRedChunk> rows;
+  rows.load(LA + sys.in_off, LC + sys.in_off, LD + sys.in_off, s, m);
   chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   chunk_recover<T, kRedChunk>(PtrDst<T>{LX + sys.in_off}, s, m, al, ga, de, F, E);
 }
@@ -815,8 +910,9 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
     int s, m;
     chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
     T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
-                                  sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
+    load_staged<S>(stage, rs, s, m, de);
+    chunk_eliminate<T, kRedChunk, true>(ValueRows{d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m, sys.rows, al,
+                                        ga, de, AF, CF, DF, AE, CE, DE);
   }
   __syncthreads();                             // every chunk read before the spike rows overlay the stage
   SpikeRow f, e;
@@ -864,8 +960,9 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
   if (tid < Pb) {
     chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
-    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
-                                  sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
+    load_staged<S>(stage, rs, s, m, de);
+    chunk_eliminate<T, kRedChunk, true>(ValueRows{d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m, sys.rows, al,
+                                        ga, de, AF, CF, DF, AE, CE, DE);
   }
   __syncthreads();                             // every chunk read before the spike rows overlay the stage
   SpikeRow f, e;

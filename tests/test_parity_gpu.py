@@ -159,11 +159,12 @@ def test_c3_btcs_full_size():
     assert np.max(np.abs(inc - inc_ref)) <= 4 * 64 * np.finfo(np.float64).eps
 
 
-@pytest.mark.parametrize("n", [4096 * 4096 + 4096, 3 * 4096 * 16 + 40])
+@pytest.mark.parametrize("n", [4096 * 4096 + 4096, 3 * 4096 * 16 + 40, 1537 * 4096 + 77])
 def test_btcs_block_partition_beyond_one_level(n):
     """Periodic systems whose block-partition level leaves more than one workgroup's worth of rows
-    (n = 2^24 + 4096: 8194 reduced rows, so one array level follows) and a multi-block system with a
-    ragged last block, 3 BTCS steps at 10x dt against the oracle."""
+    (n = 2^24 + 4096: 8194 reduced rows, so one array level follows), a multi-block system with a
+    ragged last block, and one whose 3076-row reduced system takes the workgroup solver's coalesced
+    (LDS-transposed) path with ragged chunks; 3 BTCS steps at 10x dt against the oracle."""
     b = W.random_batch(91, 1, n, n, bc=W.BC_PERIODIC, scheme=W.BTCS, amplitude=2.0)
     p = b.problems[0]
     p.dt = 10 * oracle.cfl_dt(p.n, p.length, p.nu, p.bc, b.umax[0], 0.5)
