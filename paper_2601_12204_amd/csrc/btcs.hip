@@ -910,9 +910,8 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
     int s, m;
     chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
     T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-    load_staged<S>(stage, rs, s, m, de);
-    chunk_eliminate<T, kRedChunk, true>(ValueRows{d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m, sys.rows, al,
-                                        ga, de, AF, CF, DF, AE, CE, DE);
+    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
+                                  sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
   __syncthreads();                             // every chunk read before the spike rows overlay the stage
   SpikeRow f, e;
@@ -960,9 +959,8 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
   if (tid < Pb) {
     chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
-    load_staged<S>(stage, rs, s, m, de);
-    chunk_eliminate<T, kRedChunk, true>(ValueRows{d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m, sys.rows, al,
-                                        ga, de, AF, CF, DF, AE, CE, DE);
+    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
+                                  sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   }
   __syncthreads();                             // every chunk read before the spike rows overlay the stage
   SpikeRow f, e;
