@@ -388,6 +388,183 @@ __device__ __forceinline__ void pcr_pairs(const PcrSpace<T, NT>& w, int P, T fa,
   E = ed;
 }
 
+// ---- Interface partition of a whole system (the resident and the per-step workgroup solvers) ----------
+//
+// Lane t < P owns rows s..s+m-1 (m >= 2) of a system of R rows, and its last row is the chunk's interface
+// unknown y_t = x_{s+m-1}.  The interior rows j = 0..m-2 lie between y_{t-1} (row s-1, the previous
+// chunk's interface; cyclically for a periodic system) and y_t, so eliminating them expresses each as
+//     x_j = de[j] - al[j] y_{t-1} - ga[j] y_t.
+// Substituting into y_t's own row its two neighbours, x_{m-2} of this chunk and the first interior row
+// of the next chunk (received from lane t+1), leaves one row per chunk,
+//     A_t y_{t-1} + y_t + C_t y_{t+1} = D_t,
+// a cyclic system of P rows solved by PCR with one row per lane.  A Dirichlet system moves its two
+// boundary values into the right-hand sides of its first and last rows, which removes the couplings
+// across its ends, so its interface system is not cyclic.  Compared with reducing every chunk to two
+// rows (F, E), this halves the reduced system and replaces its first PCR step by one exchange between
+// neighbouring lanes.
+
+// Eliminates the interior rows (in place: de[j] holds row j's old state value on entry) and returns the
+// interface row's coefficients (ia y_{t-1}-side neighbour x_{m-2}, ib, ic towards the next chunk, id).
+template <typename T, int M>
+__device__ __forceinline__ void interface_eliminate(const ValueRows& src, int s, int m, int R, T (&al)[M],
+                                                    T (&ga)[M], T (&de)[M], T& ia, T& ib, T& ic, T& id) {
+  const DirichletEnds& ends = src.ends;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (j < m) {
+      T aj, bj, cj, dj;
+      src.row_value(de[j], s + j, R, aj, bj, cj, dj);
+      if (j == 0 && ends.dirichlet && s == 0) {   // x_{-1} = a
+        dj = __builtin_fma(-aj, static_cast<T>(ends.a), dj);
+        aj = T(0);
+      }
+      if (j == m - 1) {
+        if (ends.dirichlet && s + m == R) {        // x_R = b
+          dj = __builtin_fma(-cj, static_cast<T>(ends.b), dj);
+          cj = T(0);
+        }
+        ia = aj;
+        ib = bj;
+        ic = cj;
+        id = dj;
+      } else if (j == 0) {
+        const T inv = recip(bj);
+        al[0] = aj * inv;
+        ga[0] = cj * inv;
+        de[0] = dj * inv;
+      } else {
+        const T inv = recip(__builtin_fma(-aj, ga[j - 1], bj));
+        const T ai = aj * inv;
+        al[j] = -(ai * al[j - 1]);
+        ga[j] = cj * inv;
+        de[j] = __builtin_fma(-ai, de[j - 1], dj * inv);
+      }
+    }
+  }
+  // backward: the coupling to x_{j+1} becomes a coupling to y_t (row m-2 already has this form)
+#pragma unroll
+  for (int j = M - 3; j >= 0; --j) {
+    if (j <= m - 3) {
+      const T g = ga[j];
+      de[j] = __builtin_fma(-g, de[j + 1], de[j]);
+      al[j] = __builtin_fma(-g, al[j + 1], al[j]);
+      ga[j] = -(g * ga[j + 1]);
+    }
+  }
+}
+
+// LDS of the interface solve: the first interior rows exchanged between neighbouring lanes, and two
+// buffers of the interface rows for PCR (three arrays of NT each), plus one stop flag per wave and buffer.
+template <typename T, int NT>
+struct InterfaceSpace {
+  static constexpr int kWaves = (NT + 63) / 64;
+  static constexpr int kBytes = 3 * 3 * NT * static_cast<int>(sizeof(T));
+  T* xchg;     // 3 x NT
+  T* rows;     // 2 buffers x 3 arrays x NT
+  int* flags;  // 2 x kWaves
+};
+
+// Solves the interface system.  Lane t < P passes its chunk's first interior row (al0, ga0, de0), its
+// last interior row (alL, gaL, deL) and its interface row (ia, ib, ic, id); on return y = y_t and
+// yp = y_{t-1}.  Ends with a barrier after its last write to LDS; its last reads (yp) follow that
+// barrier, so a caller that reuses the LDS for anything else must synchronise first.
+template <typename T, int NT>
+__device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, int P, T al0, T ga0, T de0,
+                                                T alL, T gaL, T deL, T ia, T ib, T ic, T id, T& y, T& yp) {
+  constexpr int kR = NT;
+  constexpr int kW = InterfaceSpace<T, NT>::kWaves;
+  const int t = threadIdx.x;
+  const bool own = t < P;
+  const int mask = P - 1;
+  if (own) {
+    w.xchg[t] = al0;
+    w.xchg[NT + t] = ga0;
+    w.xchg[2 * NT + t] = de0;
+  }
+  __syncthreads();
+  T a = T(0), c = T(0), d = T(0);
+  if (own) {
+    const int n = (t + 1) & mask;
+    const T nal = w.xchg[n], nga = w.xchg[NT + n], nde = w.xchg[2 * NT + n];
+    const T inv = recip(__builtin_fma(-ic, nal, __builtin_fma(-ia, gaL, ib)));
+    a = -(ia * alL) * inv;
+    c = -(ic * nga) * inv;
+    d = __builtin_fma(-ic, nde, __builtin_fma(-ia, deL, id)) * inv;
+    T* A = w.rows;
+    A[t] = a; A[kR + t] = c; A[2 * kR + t] = d;
+  }
+  __syncthreads();
+  int b = 0;
+  bool done = false;
+  for (int s = 1; s < P && !done; s <<= 1) {
+    const T* A = w.rows + b * 3 * kR;
+    const T* C = A + kR;
+    const T* D = C + kR;
+    bool live = false;
+    if (own) {
+      const int mi = (t - s) & mask, pi = (t + s) & mask;
+      pcr_combine(a, c, d, A[mi], C[mi], D[mi], A[pi], C[pi], D[pi], a, c, d);
+      live = (__builtin_fabs(a) + __builtin_fabs(c)) > kNegligible;
+      T* nA = w.rows + (1 - b) * 3 * kR;
+      nA[t] = a; nA[kR + t] = c; nA[2 * kR + t] = d;
+    }
+    const bool wave_live = __ballot(live) != 0;
+    if ((t & 63) == 0) w.flags[(1 - b) * kW + (t >> 6)] = wave_live ? 1 : 0;
+    __syncthreads();
+    b = 1 - b;
+    int any = 0;
+#pragma unroll
+    for (int k = 0; k < kW; ++k) any |= w.flags[b * kW + k];
+    done = any == 0;
+  }
+  y = T(0);
+  yp = T(0);
+  if (own) {
+    // every row's final coefficients are in buffer b; a row still coupled after all log2(P) steps
+    // couples only to itself
+    const int mi = (t - 1) & mask;
+    const T* A = w.rows + b * 3 * kR;
+    const T am = A[mi], cm = A[kR + mi], dm = A[2 * kR + mi];
+    y = done ? d : d / ((T(1) + a) + c);
+    yp = done ? dm : dm / ((T(1) + am) + cm);
+  }
+}
+
+// One interface-partition solve of a whole system: eliminate (lanes with rows), exchange, PCR.  On
+// return y = y_t and yp = y_{t-1} (see interface_solve for the LDS contract).
+template <typename T, int NT, int M>
+__device__ __forceinline__ void interface_step(const InterfaceSpace<T, NT>& w, const ValueRows& src, bool own, int s,
+                                               int m, int R, int P, T (&al)[M], T (&ga)[M], T (&de)[M], T& y,
+                                               T& yp) {
+  T ia = T(0), ib = T(1), ic = T(0), id = T(0);
+  T alL = T(0), gaL = T(0), deL = T(0);
+  if (own) {
+    interface_eliminate<T, M>(src, s, m, R, al, ga, de, ia, ib, ic, id);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      if (j == m - 2) {
+        alL = al[j];
+        gaL = ga[j];
+        deL = de[j];
+      }
+    }
+  }
+  interface_solve<T, NT>(w, P, own ? al[0] : T(0), own ? ga[0] : T(0), own ? de[0] : T(0), alL, gaL, deL, ia, ib,
+                         ic, id, y, yp);
+}
+
+// Interior rows from the interface unknowns (in place, rounded through the state type S as a store to
+// and reload from the state buffer would round them); row m-1 is y_t itself.
+template <typename S, typename T, int M>
+__device__ __forceinline__ void interface_recover_in_place(int m, const T (&al)[M], const T (&ga)[M], T (&de)[M],
+                                                           T yp, T y) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (j < m - 1) de[j] = static_cast<T>(static_cast<S>(__builtin_fma(-ga[j], y, __builtin_fma(-al[j], yp, de[j]))));
+    if (j == m - 1) de[j] = static_cast<T>(static_cast<S>(y));
+  }
+}
+
 // Coalesced copies of a block's rows between HBM and LDS: all loads are issued before the first LDS
 // store, so a wave has its whole share of the block in flight at once.
 template <typename S, int NT = kReduceBlock, int J = kRedChunk>
@@ -440,11 +617,14 @@ __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_w
     const double* __restrict__ LD, double* __restrict__ LX) {
   using T = double;
   using Pcr = PcrSpace<T, NT>;
+  using IS = InterfaceSpace<T, NT>;
   constexpr int kStageBytes = padded_size(NT * MC) * static_cast<int>(FromState ? sizeof(S) : sizeof(T));
-  constexpr int kBytes = kStageBytes > Pcr::kBytes ? kStageBytes : Pcr::kBytes;
+  constexpr int kSolveBytes = FromState ? IS::kBytes : Pcr::kBytes;
+  constexpr int kBytes = kStageBytes > kSolveBytes ? kStageBytes : kSolveBytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
-  __shared__ int pcr_flags[2 * Pcr::kWaves];
+  __shared__ int pcr_flags[2 * (FromState ? IS::kWaves : Pcr::kWaves)];
   const Pcr pcr{reinterpret_cast<T*>(smem), pcr_flags};
+  const IS iws{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + 3 * NT, pcr_flags};
   S* stage = reinterpret_cast<S*>(smem);
   T* tstage = reinterpret_cast<T*>(smem);   // reduced systems: one coefficient array at a time
 
@@ -491,7 +671,6 @@ __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_w
   }
 
   T al[MC], ga[MC], de[MC];
-  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
   int s = 0, m = 0;
   if (tid < P) {
     chunk_span(tid, R, P, s, m);
@@ -501,54 +680,63 @@ __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_w
     }
   }
   if constexpr (FromState) {
+    // whole systems: the interface partition, as in the resident solver (the two agree bitwise)
+    if (tid < P) load_staged<S>(stage, 0, s, m, de);
+    __syncthreads();                           // every lane's rows read: the interface LDS overlays them
+    T y, yp;
+    interface_step<T, NT, MC>(iws, ValueRows{d.r, d.D, ssrc.ends}, tid < P, s, m, R, P, al, ga, de, y, yp);
+    __syncthreads();                           // the interface unknowns read before the rows are rewritten
     if (tid < P) {
-      load_staged<S>(stage, 0, s, m, de);
-      chunk_eliminate<T, MC, true>(ValueRows{d.r, d.D, ssrc.ends}, s, m, R, al, ga, de, AF, CF, DF, AE, CE,
-                                   DE);
-    }
-  } else if (R >= kCoalesceRows) {
-    // One workgroup reads the whole reduced system: coalesced loads of the three arrays (every load in
-    // flight at once), then each array transposed through LDS into the lanes' chunks.
-    T va[MC], vc[MC], vd[MC];
 #pragma unroll
-    for (int j = 0; j < MC; ++j) {
-      const int i = tid + j * NT;
-      if (i < R) {
-        va[j] = asrc.A[i];
-        vc[j] = asrc.C[i];
-        vd[j] = asrc.Dv[i];
+      for (int j = 0; j < MC; ++j) {
+        if (j < m - 1) sdst.write(j, s + j, __builtin_fma(-ga[j], y, __builtin_fma(-al[j], yp, de[j])));
+        if (j == m - 1) sdst.write(j, s + j, y);
       }
     }
-    RegRows<T, MC> rr;
-    stage_transpose<T, NT, MC>(tstage, va, R, P, s, m, rr.a);
-    stage_transpose<T, NT, MC>(tstage, vc, R, P, s, m, rr.c);
-    stage_transpose<T, NT, MC>(tstage, vd, R, P, s, m, rr.d);
-    if (tid < P) chunk_eliminate<T, MC>(rr, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
-  } else if (tid < P) {   // small systems: the lanes' own rows straight from HBM, all loads up front
-    RegRows<T, MC> rr;
-    rr.load(asrc.A, asrc.C, asrc.Dv, s, m);
-    chunk_eliminate<T, MC>(rr, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
-  }
-  if constexpr (FromState) __syncthreads();   // the PCR rows overlay the staged rows
-  T F = T(0), E = T(0);
-  // (PCR's last barrier follows its last read of the rows, so the staging buffer is free on return)
-  pcr_pairs<T, NT>(pcr, P, AF, CF, DF, AE, CE, DE, F, E);
-  if constexpr (FromState) {
-    if (tid < P) chunk_recover<T, MC>(sdst, s, m, al, ga, de, F, E);
     __syncthreads();
     const int64_t o = d.off + (d.bc == kDirichlet ? 1 : 0);
     if (sys.cn) stage_out_cn<S, NT, MC>(stage, u + o, out + o, R);
     else stage_out<S, NT, MC>(stage, out + o, R);
-  } else if (R >= kCoalesceRows) {   // through LDS again, for a coalesced store
-    if (tid < P) chunk_recover<T, MC>(LdsDst<T>{tstage, 0}, s, m, al, ga, de, F, E);
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < MC; ++j) {
-      const int i = tid + j * NT;
-      if (i < R) adst.x[i] = tstage[padded(i)];
-    }
+    return;
   } else {
-    if (tid < P) chunk_recover<T, MC>(adst, s, m, al, ga, de, F, E);
+    T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
+    if (R >= kCoalesceRows) {
+      // One workgroup reads the whole reduced system: coalesced loads of the three arrays (every load in
+      // flight at once), then each array transposed through LDS into the lanes' chunks.
+      T va[MC], vc[MC], vd[MC];
+#pragma unroll
+      for (int j = 0; j < MC; ++j) {
+        const int i = tid + j * NT;
+        if (i < R) {
+          va[j] = asrc.A[i];
+          vc[j] = asrc.C[i];
+          vd[j] = asrc.Dv[i];
+        }
+      }
+      RegRows<T, MC> rr;
+      stage_transpose<T, NT, MC>(tstage, va, R, P, s, m, rr.a);
+      stage_transpose<T, NT, MC>(tstage, vc, R, P, s, m, rr.c);
+      stage_transpose<T, NT, MC>(tstage, vd, R, P, s, m, rr.d);
+      if (tid < P) chunk_eliminate<T, MC>(rr, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+    } else if (tid < P) {   // small systems: the lanes' own rows straight from HBM, all loads up front
+      RegRows<T, MC> rr;
+      rr.load(asrc.A, asrc.C, asrc.Dv, s, m);
+      chunk_eliminate<T, MC>(rr, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+    }
+    T F = T(0), E = T(0);
+    // (PCR's last barrier follows its last read of the rows, so the staging buffer is free on return)
+    pcr_pairs<T, NT>(pcr, P, AF, CF, DF, AE, CE, DE, F, E);
+    if (R >= kCoalesceRows) {   // through LDS again, for a coalesced store
+      if (tid < P) chunk_recover<T, MC>(LdsDst<T>{tstage, 0}, s, m, al, ga, de, F, E);
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < MC; ++j) {
+        const int i = tid + j * NT;
+        if (i < R) adst.x[i] = tstage[padded(i)];
+      }
+    } else {
+      if (tid < P) chunk_recover<T, MC>(adst, s, m, al, ga, de, F, E);
+    }
   }
 }
 
@@ -644,10 +832,10 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, S* __restrict__ u,
     int steps) {
   using T = double;
-  using Pcr = PcrSpace<T, NT>;
-  __shared__ T pcr_rows[Pcr::kBytes / sizeof(T)];
-  __shared__ int pcr_flags[2 * Pcr::kWaves];
-  const Pcr pcr{pcr_rows, pcr_flags};
+  using IS = InterfaceSpace<T, NT>;
+  __shared__ T iface_lds[IS::kBytes / sizeof(T)];
+  __shared__ int iface_flags[2 * IS::kWaves];
+  const IS ws{iface_lds, iface_lds + 3 * NT, iface_flags};
   const SysDesc sys = systems[blockIdx.x];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
@@ -684,12 +872,11 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
       if (j < m) de[j] = static_cast<T>(x[s + j]);
   }
   const ValueRows src{d.r, d.D, DirichletEnds{d.a, d.b, dir}};
+  const int mm = EXACT ? MC : m;
   for (int step = 0; step < steps; ++step) {
-    T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
-    if (tid < P) chunk_eliminate<T, MC, true>(src, s, EXACT ? MC : m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
-    T F = T(0), E = T(0);
-    pcr_pairs<T, NT>(pcr, P, AF, CF, DF, AE, CE, DE, F, E);
-    if (tid < P) chunk_recover_in_place<S>(EXACT ? MC : m, al, ga, de, F, E);
+    T y, yp;
+    interface_step<T, NT, MC>(ws, src, tid < P, s, mm, R, P, al, ga, de, y, yp);
+    if (tid < P) interface_recover_in_place<S>(mm, al, ga, de, yp, y);
   }
   if (tid < P) {
 #pragma unroll
