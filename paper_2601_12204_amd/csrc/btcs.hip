@@ -403,17 +403,19 @@ __device__ __forceinline__ void pcr_pairs(const PcrSpace<T, NT>& w, int P, T fa,
 // rows (F, E), this halves the reduced system and replaces its first PCR step by one exchange between
 // neighbouring lanes.
 
-// Eliminates the interior rows (in place: de[j] holds row j's old state value on entry) and returns the
-// interface row's coefficients (ia y_{t-1}-side neighbour x_{m-2}, ib, ic towards the next chunk, id).
-template <typename T, int M>
-__device__ __forceinline__ void interface_eliminate(const ValueRows& src, int s, int m, int R, T (&al)[M],
-                                                    T (&ga)[M], T (&de)[M], T& ia, T& ib, T& ic, T& id) {
+// Eliminates the interior rows and returns the interface row's coefficients (ia on the neighbour
+// x_{m-2}, ib, ic on the row after the chunk, id).  IN_PLACE: de[j] holds row j's old state value on
+// entry (ValueRows); otherwise the source assembles row j itself (LdsRows).
+template <typename T, int M, bool IN_PLACE = true, typename Src>
+__device__ __forceinline__ void interface_eliminate(const Src& src, int s, int m, int R, T (&al)[M], T (&ga)[M],
+                                                    T (&de)[M], T& ia, T& ib, T& ic, T& id) {
   const DirichletEnds& ends = src.ends;
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     if (j < m) {
       T aj, bj, cj, dj;
-      src.row_value(de[j], s + j, R, aj, bj, cj, dj);
+      if constexpr (IN_PLACE) src.row_value(de[j], s + j, R, aj, bj, cj, dj);
+      else src.row(j, s + j, R, aj, bj, cj, dj);
       if (j == 0 && ends.dirichlet && s == 0) {   // x_{-1} = a
         dj = __builtin_fma(-aj, static_cast<T>(ends.a), dj);
         aj = T(0);
@@ -885,38 +887,14 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
   }
 }
 
-// In-block reduction of the block partition kernels.  A workgroup's chunk pairs form a segment of
-// Rb <= 512 reduced rows (unit diagonal) whose first row couples to the previous block's last unknown L
-// and whose last row couples to the next block's first unknown Rt.  Those two couplings are moved into
-// two extra columns (P for L, Q for Rt), and PCR over the segment, with out-of-segment rows taken as
-// zero, removes every in-segment coupling, leaving
-//     x_i + P_i L + Q_i Rt = D_i        (the segment's solution as a function of its two neighbours).
-// Each sweep combines row i with rows i - s and i + s and renormalises; the loop stops early once all
-// remaining in-segment couplings are negligible.  Five arrays in LDS; the block's first row (chunk 0's F
-// row) sits at index 0 and its last row (the last chunk's E row) at index Rb - 1.
-struct SpikeRows {
-  double* A;
-  double* C;
-  double* D;
-  double* P;
-  double* Q;
-};
-constexpr int kSpikeRows = 2 * kReduceBlock;
 constexpr int kSpikeWaves = kReduceBlock / 64;
 
-// One row of a block's spike system: unit diagonal, couplings a (row i - s) and c (row i + s), right-hand
-// side d, and the spike columns p (previous block's last unknown L) and q (next block's first unknown Rt).
+// One row of a block's interface system in spike form: unit diagonal, couplings a (row i - s) and c
+// (row i + s), right-hand side d, and the spike columns p (on the previous block's last unknown L) and q
+// (on the next block's first unknown Rt).
 struct SpikeRow {
   double a, c, d, p, q;
 };
-
-__device__ __forceinline__ SpikeRow spike_load(const SpikeRows& S, int i) {
-  return SpikeRow{S.A[i], S.C[i], S.D[i], S.P[i], S.Q[i]};
-}
-
-__device__ __forceinline__ void spike_store(const SpikeRows& S, int i, const SpikeRow& r) {
-  S.A[i] = r.a; S.C[i] = r.c; S.D[i] = r.d; S.P[i] = r.p; S.Q[i] = r.q;
-}
 
 // One PCR step of row r with its partners m (distance -s) and p (distance +s), as pcr_combine, also
 // carried through the two spike columns.
@@ -932,73 +910,15 @@ __device__ __forceinline__ SpikeRow spike_combine(const SpikeRow& r, const Spike
   return n;
 }
 
-// PCR over a block's Rb = 2 Pb spike rows; rows outside [0, Rb) are zero.  Lane t < Pb owns chunk t's F
-// row (row 2t) and E row (row 2t+1) and keeps them in registers (f, e); each step publishes them to LDS,
-// F rows at [0, Pb) and E rows at [Pb, Rb), so the partners of either row at any distance sit at
-// consecutive positions across the wave.  Stops once every coupling is negligible (or all couplings
-// have left the segment).  On return the rows are in registers and in S, after a barrier.  Each wave's
-// vote on stopping travels through `flags`.
-__device__ __forceinline__ void spike_pcr(const SpikeRows& S, int* flags, int Pb, SpikeRow& f, SpikeRow& e) {
-  const int t = threadIdx.x;
-  const bool own = t < Pb;
-  const int Rb = 2 * Pb;
-  const SpikeRow zero{0.0, 0.0, 0.0, 0.0, 0.0};
-  if (own) {
-    spike_store(S, t, f);
-    spike_store(S, Pb + t, e);
-  }
-  __syncthreads();
-  bool done = false;
-  for (int s = 1; s < Rb && !done; s <<= 1) {
-    bool live = false;
-    SpikeRow nf = zero, ne = zero;
-    if (own) {
-      if (s == 1) {   // F row: partners E_{t-1} and E_t; E row: partners F_t and F_{t+1}
-        nf = spike_combine(f, t > 0 ? spike_load(S, Pb + t - 1) : zero, e);
-        ne = spike_combine(e, f, t + 1 < Pb ? spike_load(S, t + 1) : zero);
-      } else {        // the same kind of row, s/2 lanes away
-        const int h = s >> 1;
-        const bool hm = t >= h, hp = t + h < Pb;
-        nf = spike_combine(f, hm ? spike_load(S, t - h) : zero, hp ? spike_load(S, t + h) : zero);
-        ne = spike_combine(e, hm ? spike_load(S, Pb + t - h) : zero, hp ? spike_load(S, Pb + t + h) : zero);
-      }
-      live = (__builtin_fabs(nf.a) + __builtin_fabs(nf.c)) > kNegligible ||
-             (__builtin_fabs(ne.a) + __builtin_fabs(ne.c)) > kNegligible;
-    }
-    const bool wave_live = __ballot(live) != 0;
-    __syncthreads();                           // every partner read before the rows are overwritten
-    if (own) {
-      f = nf;
-      e = ne;
-      spike_store(S, t, f);
-      spike_store(S, Pb + t, e);
-    }
-    if ((t & 63) == 0) flags[t >> 6] = wave_live ? 1 : 0;
-    __syncthreads();
-    int any = 0;
-#pragma unroll
-    for (int k = 0; k < kSpikeWaves; ++k) any |= flags[k];
-    done = any == 0;
-  }
-}
-
-// Chunk t's two reduced rows in spike form; the segment's outer couplings go to the P and Q columns.
-__device__ __forceinline__ void spike_init(int t, int Pb, double AF, double CF, double DF, double AE, double CE,
-                                           double DE, SpikeRow& f, SpikeRow& e) {
-  f = SpikeRow{t == 0 ? 0.0 : AF, CF, DF, t == 0 ? AF : 0.0, 0.0};
-  e = SpikeRow{AE, t == Pb - 1 ? 0.0 : CE, DE, 0.0, t == Pb - 1 ? CE : 0.0};
-}
-
-// The block's two rows in the partition form (tridiagonal over first/last unknowns of all blocks),
-// from the end rows of the spike form:  x_0 + P_0 L + Q_0 Rt = D_0,  x_e + P_e L + Q_e Rt = D_e.
+// The block's two rows in the partition form (tridiagonal over the first and last unknowns of all
+// blocks), from the spike form of its first and last unknowns,
+//   x_0 + P_0 L + Q_0 Rt = D_0,   x_e + P_e L + Q_e Rt = D_e:
 //   F row:  (P_0 - k P_e) L + x_0 - k x_e = D_0 - k D_e,        k = Q_0 / Q_e
 //   E row:  -h x_0 + x_e + (Q_e - h Q_0) Rt = D_e - h D_0,     h = P_e / P_0
 // A block with no left (right) neighbour coupling has P = 0 (Q = 0) throughout; then h = 0 (k = 0).
-__device__ __forceinline__ void spike_ends(const SpikeRows& S, int Rb, double& AF, double& CF, double& DF,
-                                           double& AE, double& CE, double& DE) {
-  const int e = Rb - 1;
-  const double P0 = S.P[0], Q0 = S.Q[0], D0 = S.D[0];
-  const double Pe = S.P[e], Qe = S.Q[e], De = S.D[e];
+__device__ __forceinline__ void partition_rows(double P0, double Q0, double D0, double Pe, double Qe, double De,
+                                               double& AF, double& CF, double& DF, double& AE, double& CE,
+                                               double& DE) {
   const double k = Qe != 0.0 ? Q0 / Qe : 0.0;
   const double h = P0 != 0.0 ? Pe / P0 : 0.0;
   AF = __builtin_fma(-k, Pe, P0);
@@ -1007,6 +927,117 @@ __device__ __forceinline__ void spike_ends(const SpikeRows& S, int Rb, double& A
   AE = -h;
   CE = __builtin_fma(-h, Q0, Qe);
   DE = __builtin_fma(-h, D0, De);
+}
+
+// ---- Interface partition inside a block of a long system ------------------------------------------
+// Within a block, chunk t's interior rows lie between the interface unknowns y_{t-1} and y_t as in the
+// whole-system solver.  The block's first chunk has L (the previous block's last unknown, row rs - 1)
+// on its left, and its last chunk's interface row couples to Rt (the next block's first unknown, row
+// re).  Both stay symbolic as spike columns, so PCR over the block's Pb interface rows (one per lane,
+// rows outside the block taken as zero) leaves  y_t + P_t L + Q_t Rt = D_t.  The block's first unknown
+// is its first chunk's first interior row, x = de_0 - al_0 L - ga_0 y_0, and its last is y_{Pb-1}.
+
+// LDS of a block's interface solve (it overlays the staged rows once every chunk has been read): the
+// exchanged first interior rows, two buffers of the interface rows' five columns, and the waves' votes.
+struct BlockIfaceSpace {
+  static constexpr int kN = kReduceBlock;
+  static constexpr int kBytes = (3 + 2 * 5) * kN * 8;
+  double* xchg;   // 3 x kN
+  double* rows;   // 2 buffers x 5 columns x kN
+  int* flags;     // 2 x kSpikeWaves
+  __device__ __forceinline__ SpikeRow load(int b, int i) const {
+    const double* r = rows + b * 5 * kN;
+    return SpikeRow{r[i], r[kN + i], r[2 * kN + i], r[3 * kN + i], r[4 * kN + i]};
+  }
+  __device__ __forceinline__ void store(int b, int i, const SpikeRow& v) const {
+    double* r = rows + b * 5 * kN;
+    r[i] = v.a; r[kN + i] = v.c; r[2 * kN + i] = v.d; r[3 * kN + i] = v.p; r[4 * kN + i] = v.q;
+  }
+};
+
+// Lane t < Pb passes its chunk's first interior row (al0, ga0, de0), its last interior row (alL, gaL,
+// deL) and its interface row (ia, ib, ic, id).  On return r is the lane's final spike row and the
+// result is the buffer that holds every lane's final row.  Starts by writing the LDS (the caller
+// synchronises after its last read of what the space overlays) and ends with a barrier.
+__device__ __forceinline__ int block_iface_solve(const BlockIfaceSpace& w, int Pb, double al0, double ga0,
+                                                 double de0, double alL, double gaL, double deL, double ia,
+                                                 double ib, double ic, double id, SpikeRow& r) {
+  constexpr int kN = BlockIfaceSpace::kN;
+  const int t = threadIdx.x;
+  const bool own = t < Pb;
+  const SpikeRow zero{0.0, 0.0, 0.0, 0.0, 0.0};
+  if (own) {
+    w.xchg[t] = al0;
+    w.xchg[kN + t] = ga0;
+    w.xchg[2 * kN + t] = de0;
+  }
+  __syncthreads();
+  r = zero;
+  if (own) {
+    const bool next = t + 1 < Pb;
+    const double nal = next ? w.xchg[t + 1] : 0.0;
+    const double nga = next ? w.xchg[kN + t + 1] : 0.0;
+    const double nde = next ? w.xchg[2 * kN + t + 1] : 0.0;
+    const double inv = recip(__builtin_fma(-ic, nal, __builtin_fma(-ia, gaL, ib)));
+    const double lower = -(ia * alL) * inv;   // on y_{t-1}, which is L for the block's first chunk
+    r.a = t > 0 ? lower : 0.0;
+    r.p = t > 0 ? 0.0 : lower;
+    r.c = next ? -(ic * nga) * inv : 0.0;     // on y_{t+1}, or directly on Rt for the last chunk
+    r.q = next ? 0.0 : ic * inv;
+    r.d = __builtin_fma(-ic, nde, __builtin_fma(-ia, deL, id)) * inv;
+    w.store(0, t, r);
+  }
+  __syncthreads();
+  int b = 0;
+  bool done = false;
+  for (int s = 1; s < Pb && !done; s <<= 1) {
+    bool live = false;
+    if (own) {
+      r = spike_combine(r, t >= s ? w.load(b, t - s) : zero, t + s < Pb ? w.load(b, t + s) : zero);
+      live = (__builtin_fabs(r.a) + __builtin_fabs(r.c)) > kNegligible;
+      w.store(1 - b, t, r);
+    }
+    const bool wave_live = __ballot(live) != 0;
+    if ((t & 63) == 0) w.flags[(1 - b) * kSpikeWaves + (t >> 6)] = wave_live ? 1 : 0;
+    __syncthreads();
+    b = 1 - b;
+    int any = 0;
+#pragma unroll
+    for (int k = 0; k < kSpikeWaves; ++k) any |= w.flags[b * kSpikeWaves + k];
+    done = any == 0;
+  }
+  return b;
+}
+
+// A block's chunks eliminated (rows staged in LDS) and its interface system solved; returns the buffer
+// of the final rows.  al/ga/de keep the chunk's interior rows for the recovery.
+template <typename S>
+__device__ __forceinline__ int block_iface_step(const BlockIfaceSpace& w, const S* stage, const InstDesc& d,
+                                                const SysDesc& sys, const ChunkBlock& cb, int rs, int Pb, int& s,
+                                                int& m, double (&al)[kRedChunk], double (&ga)[kRedChunk],
+                                                double (&de)[kRedChunk], SpikeRow& r) {
+  using T = double;
+  const bool dir = d.bc == kDirichlet;
+  const int tid = threadIdx.x;
+  T ia = T(0), ib = T(1), ic = T(0), id = T(0), alL = T(0), gaL = T(0), deL = T(0);
+  s = 0;
+  m = 0;
+  if (tid < Pb) {
+    chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
+    interface_eliminate<T, kRedChunk, false>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
+                                             sys.rows, al, ga, de, ia, ib, ic, id);
+#pragma unroll
+    for (int j = 0; j < kRedChunk; ++j) {
+      if (j == m - 2) {
+        alL = al[j];
+        gaL = ga[j];
+        deL = de[j];
+      }
+    }
+  }
+  __syncthreads();                             // every chunk read before the interface LDS overlays the stage
+  return block_iface_solve(w, Pb, tid < Pb ? al[0] : T(0), tid < Pb ? ga[0] : T(0), tid < Pb ? de[0] : T(0), alL,
+                           gaL, deL, ia, ib, ic, id, r);
 }
 
 // Rows [rs, re) of the chunks a partition workgroup owns: chunk k spans chunk_span(k).
@@ -1066,46 +1097,41 @@ __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_backsub_kernel(
 }
 
 // Block partition, forward half (level 0 of a long system): a workgroup stages its 256 chunks' rows
-// (<= 4096) through LDS, eliminates every chunk, reduces the block's chunk pairs to the spike form by
-// PCR and stores the block's two partition rows at red_off + 2 * (block index within the system).
+// (<= 4096) through LDS, eliminates every chunk, solves the block's interface system in spike form and
+// stores the block's two partition rows at red_off + 2 * (block index within the system).
 template <typename S>
-__global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
+__global__ __launch_bounds__(kReduceBlock, 4) void btcs_block_reduce_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
     const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, double* __restrict__ LA,
     double* __restrict__ LC, double* __restrict__ LD) {
   using T = double;
   constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
-  constexpr int kSpikeBytes = 5 * kSpikeRows * static_cast<int>(sizeof(T));
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kStageBytes > kSpikeBytes ? kStageBytes : kSpikeBytes];
+  constexpr int kBytes = kStageBytes > BlockIfaceSpace::kBytes ? kStageBytes : BlockIfaceSpace::kBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  __shared__ int iface_flags[2 * kSpikeWaves];
   S* stage = reinterpret_cast<S*>(smem);
-  T* sp = reinterpret_cast<T*>(smem);
-  const SpikeRows SR{sp, sp + kSpikeRows, sp + 2 * kSpikeRows, sp + 3 * kSpikeRows, sp + 4 * kSpikeRows};
-  __shared__ int spike_flags[kSpikeWaves];
+  T* lds = reinterpret_cast<T*>(smem);
+  const BlockIfaceSpace w{lds, lds + 3 * BlockIfaceSpace::kN, iface_flags};
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
   const int tid = threadIdx.x;
   const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
-  const int Rb = 2 * Pb;
   int rs, re;
   block_rows(sys, cb.chunk0, rs, re);
   stage_in(stage, u + d.off + (dir ? 1 : 0) + rs, re - rs);
   __syncthreads();
-  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
-  if (tid < Pb) {
-    int s, m;
-    chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
-    T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
-                                  sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-  }
-  __syncthreads();                             // every chunk read before the spike rows overlay the stage
-  SpikeRow f, e;
-  spike_init(tid, Pb, AF, CF, DF, AE, CE, DE, f, e);
-  spike_pcr(SR, spike_flags, Pb, f, e);
+  int s, m;
+  T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
+  SpikeRow r;
+  const int b = block_iface_step(w, stage, d, sys, cb, rs, Pb, s, m, al, ga, de, r);
   if (tid == 0) {
-    spike_ends(SR, Rb, AF, CF, DF, AE, CE, DE);
+    // first unknown: x = de_0 - al_0 L - ga_0 y_0 with y_0 = D_0 - P_0 L - Q_0 Rt; last: y_{Pb-1}
+    const SpikeRow e = w.load(b, Pb - 1);
+    T AF, CF, DF, AE, CE, DE;
+    partition_rows(__builtin_fma(-ga[0], r.p, al[0]), -(ga[0] * r.q), __builtin_fma(-ga[0], r.d, de[0]), e.p, e.q,
+                   e.d, AF, CF, DF, AE, CE, DE);
     const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock);
     LA[o] = AF; LC[o] = CF; LD[o] = DF;
     LA[o + 1] = AE; LC[o + 1] = CE; LD[o + 1] = DE;
@@ -1113,9 +1139,10 @@ __global__ __launch_bounds__(kReduceBlock) void btcs_block_reduce_kernel(
 }
 
 // Block partition, backward half: the block repeats the forward reduction (keeping its chunks'
-// elimination in registers), takes its neighbours' solved end unknowns L = E of the previous block and
-// Rt = F of the next block (cyclically for periodic systems), evaluates x_i = D_i - P_i L - Q_i Rt for
-// its chunk ends, recovers every chunk and stores the new state coalesced (with the Dirichlet nodes).
+// elimination in registers), takes its neighbours' solved end unknowns L (the previous block's last)
+// and Rt (the next block's first; both cyclically for periodic systems), evaluates every interface
+// unknown y_t = D_t - P_t L - Q_t Rt, recovers every chunk and stores the new state coalesced (with
+// the Dirichlet nodes).
 template <typename S>
 __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
@@ -1123,12 +1150,12 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
     const double* __restrict__ LX) {
   using T = double;
   constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
-  constexpr int kSpikeBytes = 5 * kSpikeRows * static_cast<int>(sizeof(T));
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kStageBytes > kSpikeBytes ? kStageBytes : kSpikeBytes];
+  constexpr int kBytes = kStageBytes > BlockIfaceSpace::kBytes ? kStageBytes : BlockIfaceSpace::kBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  __shared__ int iface_flags[2 * kSpikeWaves];
   S* stage = reinterpret_cast<S*>(smem);
-  T* sp = reinterpret_cast<T*>(smem);
-  const SpikeRows SR{sp, sp + kSpikeRows, sp + 2 * kSpikeRows, sp + 3 * kSpikeRows, sp + 4 * kSpikeRows};
-  __shared__ int spike_flags[kSpikeWaves];
+  T* lds = reinterpret_cast<T*>(smem);
+  const BlockIfaceSpace w{lds, lds + 3 * BlockIfaceSpace::kN, iface_flags};
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   const InstDesc d = inst[sys.inst];
@@ -1141,29 +1168,34 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   block_rows(sys, cb.chunk0, rs, re);
   stage_in(stage, u + d.off + (dir ? 1 : 0) + rs, re - rs);
   __syncthreads();
-  int s = 0, m = 0;
+  int s, m;
   T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
-  if (tid < Pb) {
-    chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
-    chunk_eliminate<T, kRedChunk>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
-                                  sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
-  }
-  __syncthreads();                             // every chunk read before the spike rows overlay the stage
-  SpikeRow f, e;
-  spike_init(tid, Pb, AF, CF, DF, AE, CE, DE, f, e);
-  spike_pcr(SR, spike_flags, Pb, f, e);        // ends with a barrier after its last read of SR
+  SpikeRow r;
+  const int b = block_iface_step(w, stage, d, sys, cb, rs, Pb, s, m, al, ga, de, r);
   // neighbours' end unknowns; a Dirichlet system's outer blocks have P = 0 or Q = 0 and ignore them
   const T* X = LX + sys.red_off;
   const bool periodic = !dir;
   const T L = blk > 0 ? X[2 * blk - 1] : (periodic ? X[2 * nblk - 1] : T(0));
   const T Rt = blk + 1 < nblk ? X[2 * blk + 2] : (periodic ? X[0] : T(0));
-  T F = T(0), E = T(0);
+  T y = T(0), yp = T(0);
   if (tid < Pb) {
-    F = __builtin_fma(-f.q, Rt, __builtin_fma(-f.p, L, f.d));
-    E = __builtin_fma(-e.q, Rt, __builtin_fma(-e.p, L, e.d));
+    y = __builtin_fma(-r.q, Rt, __builtin_fma(-r.p, L, r.d));
+    if (tid > 0) {
+      const SpikeRow q = w.load(b, tid - 1);
+      yp = __builtin_fma(-q.q, Rt, __builtin_fma(-q.p, L, q.d));
+    } else {
+      yp = L;
+    }
   }
-  if (tid < Pb) chunk_recover<T, kRedChunk>(LdsDst<S>{stage, rs}, s, m, al, ga, de, F, E);
+  __syncthreads();                             // the interface rows read before the stage is rewritten
+  if (tid < Pb) {
+    const LdsDst<S> dst{stage, rs};
+#pragma unroll
+    for (int j = 0; j < kRedChunk; ++j) {
+      if (j < m - 1) dst.write(j, s + j, __builtin_fma(-ga[j], y, __builtin_fma(-al[j], yp, de[j])));
+      if (j == m - 1) dst.write(j, s + j, y);
+    }
+  }
   __syncthreads();
   const int64_t o = d.off + (dir ? 1 : 0) + rs;
   if (sys.cn) stage_out_cn(stage, u + o, out + o, re - rs);
