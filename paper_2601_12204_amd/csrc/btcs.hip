@@ -460,10 +460,14 @@ __device__ __forceinline__ void interface_eliminate(const Src& src, int s, int m
 template <typename T, int NT>
 struct InterfaceSpace {
   static constexpr int kWaves = (NT + 63) / 64;
+  static constexpr int kVoteWords = (kWaves + 7) / 8;   // one byte per wave, read back as 64-bit words
   static constexpr int kBytes = 3 * 3 * NT * static_cast<int>(sizeof(T));
-  T* xchg;     // 3 x NT
-  T* rows;     // 2 buffers x 3 arrays x NT
-  int* flags;  // 2 x kWaves
+  T* xchg;          // 3 x NT
+  T* rows;          // 2 buffers x 3 arrays x NT
+  uint64_t* votes;  // 2 x kVoteWords; zeroed once (clear_votes) before the kernel's first barrier
+  __device__ __forceinline__ void clear_votes() const {
+    if (threadIdx.x < 2 * kVoteWords) votes[threadIdx.x] = 0;
+  }
 };
 
 // Solves the interface system.  Lane t < P passes its chunk's first interior row (al0, ga0, de0), its
@@ -474,7 +478,6 @@ template <typename T, int NT>
 __device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, int P, T al0, T ga0, T de0,
                                                 T alL, T gaL, T deL, T ia, T ib, T ic, T id, T& y, T& yp) {
   constexpr int kR = NT;
-  constexpr int kW = InterfaceSpace<T, NT>::kWaves;
   const int t = threadIdx.x;
   const bool own = t < P;
   const int mask = P - 1;
@@ -511,12 +514,13 @@ __device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, 
       nA[t] = a; nA[kR + t] = c; nA[2 * kR + t] = d;
     }
     const bool wave_live = __ballot(live) != 0;
-    if ((t & 63) == 0) w.flags[(1 - b) * kW + (t >> 6)] = wave_live ? 1 : 0;
+    constexpr int kV = InterfaceSpace<T, NT>::kVoteWords;
+    if ((t & 63) == 0) reinterpret_cast<unsigned char*>(w.votes + (1 - b) * kV)[t >> 6] = wave_live ? 1 : 0;
     __syncthreads();
     b = 1 - b;
-    int any = 0;
+    uint64_t any = 0;
 #pragma unroll
-    for (int k = 0; k < kW; ++k) any |= w.flags[b * kW + k];
+    for (int k = 0; k < kV; ++k) any |= w.votes[b * kV + k];
     done = any == 0;
   }
   y = T(0);
@@ -526,9 +530,12 @@ __device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, 
     // couples only to itself
     const int mi = (t - 1) & mask;
     const T* A = w.rows + b * 3 * kR;
-    const T am = A[mi], cm = A[kR + mi], dm = A[2 * kR + mi];
-    y = done ? d : d / ((T(1) + a) + c);
-    yp = done ? dm : dm / ((T(1) + am) + cm);
+    y = d;
+    yp = A[2 * kR + mi];
+    if (!done) {   // (uniform across the workgroup)
+      y = d / ((T(1) + a) + c);
+      yp = yp / ((T(1) + A[mi]) + A[kR + mi]);
+    }
   }
 }
 
@@ -624,9 +631,11 @@ __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_w
   constexpr int kSolveBytes = FromState ? IS::kBytes : Pcr::kBytes;
   constexpr int kBytes = kStageBytes > kSolveBytes ? kStageBytes : kSolveBytes;
   __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
-  __shared__ int pcr_flags[2 * (FromState ? IS::kWaves : Pcr::kWaves)];
+  __shared__ int pcr_flags[2 * Pcr::kWaves];
+  __shared__ uint64_t iface_votes[2 * IS::kVoteWords];
   const Pcr pcr{reinterpret_cast<T*>(smem), pcr_flags};
-  const IS iws{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + 3 * NT, pcr_flags};
+  const IS iws{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + 3 * NT, iface_votes};
+  iws.clear_votes();
   S* stage = reinterpret_cast<S*>(smem);
   T* tstage = reinterpret_cast<T*>(smem);   // reduced systems: one coefficient array at a time
 
@@ -836,8 +845,9 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
   using T = double;
   using IS = InterfaceSpace<T, NT>;
   __shared__ T iface_lds[IS::kBytes / sizeof(T)];
-  __shared__ int iface_flags[2 * IS::kWaves];
-  const IS ws{iface_lds, iface_lds + 3 * NT, iface_flags};
+  __shared__ uint64_t iface_votes[2 * IS::kVoteWords];
+  const IS ws{iface_lds, iface_lds + 3 * NT, iface_votes};
+  ws.clear_votes();
   const SysDesc sys = systems[blockIdx.x];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
