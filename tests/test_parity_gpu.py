@@ -116,6 +116,42 @@ def test_c2_full_size_sampled(dtype):
         check_batch(sub, got_sub, steps, dtype, scheme=scheme, threads=len(sample))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c4_full_size_sampled(dtype):
+    """The ragged batch of 10^4 instances (N log-uniform in [64, 65536], mixed BCs and schemes) in the
+    benchmark's launch configuration: one graph-replayed run_mixed call, explicit instances 10^3 steps
+    at the CFL step and BTCS instances 10^2 steps at 10x; sampled instances of every size range (whole
+    and windowed explicit, resident and block-partition BTCS) recomputed by the oracle."""
+    import paper_2601_12204_amd as B
+    import torch
+    batch = set_cfl_steps(W.ragged_batch(10_000), explicit_factor=1.0, btcs_factor=10.0)
+    ns = np.array([p.n for p in batch.problems])
+    schemes = np.array([p.scheme for p in batch.problems])
+    sample = []
+    for sch in (W.EXPLICIT, W.BTCS):
+        idx = np.flatnonzero(schemes == sch)
+        by_n = idx[np.argsort(ns[idx], kind="stable")]
+        picks = [by_n[0], by_n[len(by_n) // 4], by_n[len(by_n) // 2], by_n[(3 * len(by_n)) // 4], by_n[-1]]
+        picks += [i for i in idx if 8192 < ns[i] <= 8192 + 4096][:2] + [i for i in idx if ns[i] == 8192][:1]
+        sample += sorted(set(int(i) for i in picks))
+    announce(f"C4 full size {dtype} run_mixed 1000/100 graph, sample {sample}")
+    td = torch.float64 if dtype == "f64" else torch.float32
+    solver = B.Solver(batch.problems, dtype=td)
+    try:
+        solver.set_plan(use_graph=1)
+        u = solver.pack_flat(batch.u0, batch.offsets)
+        solver.run_mixed(u, 1000, 100)
+        solver.sync()
+        got = solver.unpack_flat(u)
+    finally:
+        solver.close()
+    for sch, steps in ((W.EXPLICIT, 1000), (W.BTCS, 100)):
+        part = [b for b in sample if schemes[b] == sch]
+        sub = W.subset(batch, part)
+        got_sub = np.concatenate([got[batch.offsets[b]:batch.offsets[b + 1]] for b in part])
+        check_batch(sub, got_sub, steps, dtype, scheme=sch, threads=len(part))
+
+
 def test_c3_explicit_full_size_sampled_nodes():
     """N = 2^24 Dirichlet grid, 1024 explicit steps; sampled nodes recomputed from their dependency cone."""
     b = W.c3_problem()
