@@ -107,13 +107,6 @@ __global__ __launch_bounds__(kStreamThreads) void explicit_stream_kernel(
   }
 }
 
-// Chunk of the window held by lane t: nodes [s, s + m) of a window of W nodes split over P lanes.
-__device__ __forceinline__ void lane_span(int t, int W, int P, int& s, int& m) {
-  const int q = W / P, rho = W - q * P;
-  s = t * q + (t < rho ? t : rho);
-  m = q + (t < rho ? 1 : 0);
-}
-
 // LDS staging of window I/O: half the lanes' chunks at a time (at most 4096 nodes), padded by one element
 // every 16 nodes so that lanes reading their 16-node chunks (a stride of 17 elements) hit distinct banks.
 constexpr int kStageNodes = kBlockThreads * kBlockChunk / 2;
@@ -121,26 +114,32 @@ __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
 
 // One step of a lane's chunk: out[j] from in[j-1], in[j], in[j+1], with the neighbours' end values
 // `left` and `right`; fixed nodes keep their value.
+//
+// Every lane holds a full chunk of M nodes except the window's last lane, which holds mlast (the same
+// for the whole workgroup).  That lane's slot mlast holds its right neighbour's value (pad_last), so
+// all lanes run the same unguarded code; the results in the last lane's slots past mlast - 1 are never
+// used.  The fixed last node (fix_last, last lane only) is node mlast - 1.
 template <typename T, bool EXACT>
 __device__ __forceinline__ void chunk_step(const T (&in)[kBlockChunk], T (&out)[kBlockChunk], T left, T right,
-                                           int m, bool fix_first, bool fix_last, T r, T D) {
+                                           int mlast, bool fix_first, bool fix_last, T r, T D) {
   constexpr int M = kBlockChunk;
   T prev = left;
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    if (EXACT || j < m) {
-      T up;
-      if (EXACT) {
-        up = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
-      } else {
-        up = right;
-        if (j + 1 < M && j + 1 < m) up = in[j + 1 < M ? j + 1 : j];
-      }
-      const bool fixed = (j == 0 && fix_first) || (EXACT ? (j == M - 1 && fix_last) : (j == m - 1 && fix_last));
-      out[j] = fixed ? in[j] : upwind_central(in[j], prev, up, r, D);
-      prev = in[j];
-    }
+    const T up = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
+    const bool fixed = (j == 0 && fix_first) || (j == (EXACT ? M : mlast) - 1 && fix_last);
+    out[j] = fixed ? in[j] : upwind_central(in[j], prev, up, r, D);
+    prev = in[j];
   }
+}
+
+// The window's last lane (is_last) takes its right neighbour's value into slot mlast when its chunk is
+// short (see chunk_step); every branch here is uniform.
+template <typename T>
+__device__ __forceinline__ void pad_last(T (&x)[kBlockChunk], int mlast, bool is_last, T right) {
+#pragma unroll
+  for (int j = 0; j < kBlockChunk; ++j)
+    if (j == mlast) x[j] = is_last ? right : x[j];
 }
 
 // One RK4 stage of a lane's chunk (Sec. 2.7.1, eq. 22): K = increment of the stage input `in` (with
@@ -189,17 +188,19 @@ __device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBl
 
 // Publish a lane's chunk end values in exchange buffer `buf`, wait, and read the neighbours' ends.
 template <typename T, bool EXACT>
-__device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf, int t, int P, int m, bool active,
-                                              T (*s_first)[kBlockThreads], T (*s_last)[kBlockThreads], T& left,
-                                              T& right) {
+__device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf, int t, int P, int mlast,
+                                              bool active, T (*s_first)[kBlockThreads], T (*s_last)[kBlockThreads],
+                                              T& left, T& right) {
   constexpr int M = kBlockChunk;
   if (active) {
     s_first[buf][t] = x[0];
     T last = x[M - 1];
-    if (!EXACT) {
+    if (!EXACT) {   // the window's last lane holds mlast nodes (uniform index, one select)
+      T tail = x[M - 1];
 #pragma unroll
       for (int j = 0; j < M; ++j)
-        if (j == m - 1) last = x[j];
+        if (j == mlast - 1) tail = x[j];
+      if (t == P - 1) last = tail;
     }
     s_last[buf][t] = last;
   }
@@ -221,19 +222,21 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   const int n = d.n;
   const bool periodic = d.bc == kPeriodic;
   const int W = bt.width;                       // window nodes
-  const int P = EXACT ? kBlockThreads : (W < kBlockThreads ? W : kBlockThreads);
+  // lane t holds nodes [M t, M t + m): full chunks, except that the last of the P lanes holds mlast
+  const int P = EXACT ? kBlockThreads : (W + M - 1) / M;
+  const int mlast = EXACT ? M : W - M * (P - 1);
   const int t = threadIdx.x;
   const bool active = t < P;
-  int s = 0, m = 0;
-  if (active) lane_span(t, W, P, s, m);
-  if (EXACT) m = M;
+  const int s = M * t;
+  const int m = !active ? 0 : (t == P - 1 ? mlast : M);
   const int half = P / 2;                       // lanes [0, half) and [half, P) are staged in turn
   T v[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = T(0);
   // window node w is instance node (bt.first + w) mod n; the window wraps only for periodic instances
   for (int h = 0; h < 2; ++h) {
-    int r0, r1, mm;
-    lane_span(h == 0 ? 0 : half, W, P, r0, mm);
-    if (h == 0) lane_span(half, W, P, r1, mm); else r1 = W;
+    const int r0 = h == 0 ? 0 : M * half;
+    const int r1 = h == 0 ? M * half : W;
     for (int w = r0 + t; w < r1; w += kBlockThreads) {
       int g = bt.first + w;
       if (g >= n) g -= n;
@@ -266,28 +269,37 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
     // four stages per step, each after an exchange of the stage's end values (buffers alternate)
     T acc[M];
     for (int step = 0; step < steps; ++step) {
-      exchange_ends<T, EXACT>(v, 0, t, P, m, active, s_first, s_last, left, right);
+      exchange_ends<T, EXACT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
       if (active) rk4_stage<T, EXACT, 1>(v, v, w, acc, left, right, m, fix_first, fix_last, r, D);
-      exchange_ends<T, EXACT>(w, 1, t, P, m, active, s_first, s_last, left, right);
+      exchange_ends<T, EXACT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
       if (active) rk4_stage<T, EXACT, 2>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
-      exchange_ends<T, EXACT>(w, 0, t, P, m, active, s_first, s_last, left, right);
+      exchange_ends<T, EXACT>(w, 0, t, P, mlast, active, s_first, s_last, left, right);
       if (active) rk4_stage<T, EXACT, 3>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
-      exchange_ends<T, EXACT>(w, 1, t, P, m, active, s_first, s_last, left, right);
+      exchange_ends<T, EXACT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
       if (active) rk4_stage<T, EXACT, 4>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
     }
   } else {
   // two steps per iteration: v -> w, then w -> v (exchange buffers 0 and 1 alternate)
   int step = 0;
+  // (a wave with no active lane skips the arithmetic; inside a step nothing branches on the lane)
+  const bool is_last = t == P - 1;
   for (; step + 2 <= steps; step += 2) {
-    exchange_ends<T, EXACT>(v, 0, t, P, m, active, s_first, s_last, left, right);
-    if (active) chunk_step<T, EXACT>(v, w, left, right, m, fix_first, fix_last, r, D);
-    exchange_ends<T, EXACT>(w, 1, t, P, m, active, s_first, s_last, left, right);
-    if (active) chunk_step<T, EXACT>(w, v, left, right, m, fix_first, fix_last, r, D);
+    exchange_ends<T, EXACT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+    if (active) {
+      if (!EXACT) pad_last(v, mlast, is_last, right);
+      chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D);
+    }
+    exchange_ends<T, EXACT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
+    if (active) {
+      if (!EXACT) pad_last(w, mlast, is_last, right);
+      chunk_step<T, EXACT>(w, v, left, right, mlast, fix_first, fix_last, r, D);
+    }
   }
   if (step < steps) {
-    exchange_ends<T, EXACT>(v, 0, t, P, m, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
-      chunk_step<T, EXACT>(v, w, left, right, m, fix_first, fix_last, r, D);
+      if (!EXACT) pad_last(v, mlast, is_last, right);
+      chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D);
 #pragma unroll
       for (int j = 0; j < M; ++j) v[j] = w[j];
     }
@@ -296,9 +308,8 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
 
   // store the window's output nodes [bt.lo, bt.lo + bt.count), staged like the load
   for (int h = 0; h < 2; ++h) {
-    int r0, r1, mm;
-    lane_span(h == 0 ? 0 : half, W, P, r0, mm);
-    if (h == 0) lane_span(half, W, P, r1, mm); else r1 = W;
+    const int r0 = h == 0 ? 0 : M * half;
+    const int r1 = h == 0 ? M * half : W;
     if (active && (h == 0) == (t < half)) {
 #pragma unroll
       for (int j = 0; j < M; ++j)
