@@ -160,7 +160,21 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
       }
     }
     auto fe_first = [](const BlockTile& x, const BlockTile& y) { return x.rk4 < y.rk4; };
-    std::stable_sort(whole.begin(), whole.end(), fe_first);
+    // whole instances: by workgroup width (widest first), then forward Euler before RK4
+    auto lanes_of = [](const BlockTile& x) { return burgers::explicit_block_lanes(x.width); };
+    std::stable_sort(whole.begin(), whole.end(), [&](const BlockTile& x, const BlockTile& y) {
+      const int lx = lanes_of(x), ly = lanes_of(y);
+      return lx != ly ? lx > ly : x.rk4 < y.rk4;
+    });
+    plan->whole_classes.clear();
+    for (size_t k = 0; k < whole.size();) {
+      const int lanes = lanes_of(whole[k]);
+      size_t e = k;
+      int64_t rk4 = 0;
+      while (e < whole.size() && lanes_of(whole[e]) == lanes) rk4 += whole[e++].rk4 ? 1 : 0;
+      plan->whole_classes.push_back({lanes, static_cast<int64_t>(k), static_cast<int64_t>(e - k) - rk4, rk4});
+      k = e;
+    }
     std::stable_sort(win.begin(), win.end(), fe_first);
     plan->whole = std::make_unique<DevBuf>();
     plan->win = std::make_unique<DevBuf>();
@@ -358,9 +372,10 @@ hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) 
   const int64_t whole_chunk = pl.path == 3 ? pl.depth : (int64_t{1} << 30);
   for (int64_t done = 0; done < nsteps;) {
     const int k = static_cast<int>(std::min(whole_chunk, nsteps - done));
-    if ((e = burgers::launch_explicit_block(ctx, pl.whole->as<BlockTile>(), pl.n_whole - pl.n_whole_rk4,
-                                            pl.n_whole_rk4, u, u, k)) != hipSuccess)
-      return e;
+    for (const auto& c : pl.whole_classes)
+      if ((e = burgers::launch_explicit_block(ctx, pl.whole->as<BlockTile>() + c.offset, c.n_fe, c.n_rk4, u, u, k,
+                                              c.lanes)) != hipSuccess)
+        return e;
     done += k;
   }
   // windows of long instances: `depth` steps per launch, ping-pong

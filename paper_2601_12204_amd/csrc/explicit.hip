@@ -109,7 +109,8 @@ __global__ __launch_bounds__(kStreamThreads) void explicit_stream_kernel(
 
 // LDS staging of window I/O: half the lanes' chunks at a time (at most 4096 nodes), padded by one element
 // every 16 nodes so that lanes reading their 16-node chunks (a stride of 17 elements) hit distinct banks.
-constexpr int kStageNodes = kBlockThreads * kBlockChunk / 2;
+template <int NT>
+constexpr int stage_nodes() { return NT * kBlockChunk / 2; }
 __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
 
 // One step of a lane's chunk: out[j] from in[j-1], in[j], in[j+1], with the neighbours' end values
@@ -187,9 +188,9 @@ __device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBl
 }
 
 // Publish a lane's chunk end values in exchange buffer `buf`, wait, and read the neighbours' ends.
-template <typename T, bool EXACT>
+template <typename T, bool EXACT, int NT>
 __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf, int t, int P, int mlast,
-                                              bool active, T (*s_first)[kBlockThreads], T (*s_last)[kBlockThreads],
+                                              bool active, T (*s_first)[NT], T (*s_last)[NT],
                                               T& left, T& right) {
   constexpr int M = kBlockChunk;
   if (active) {
@@ -211,19 +212,19 @@ __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf
   }
 }
 
-// Temporal-blocking body.  EXACT: the window has exactly kBlockThreads * kBlockChunk nodes, so every lane
+// Temporal-blocking body over NT lanes.  EXACT: the window has exactly NT * kBlockChunk nodes, so every lane
 // holds a full chunk and the guards below fold away.
-template <typename T, bool EXACT, bool RK4>
+template <typename T, bool EXACT, bool RK4, int NT>
 __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& d, const T* __restrict__ src,
                                            T* __restrict__ dst, int steps, T* stage,
-                                           T (*s_first)[kBlockThreads], T (*s_last)[kBlockThreads]) {
+                                           T (*s_first)[NT], T (*s_last)[NT]) {
   constexpr int M = kBlockChunk;
   const T r = static_cast<T>(d.r), D = static_cast<T>(d.D);
   const int n = d.n;
   const bool periodic = d.bc == kPeriodic;
   const int W = bt.width;                       // window nodes
   // lane t holds nodes [M t, M t + m): full chunks, except that the last of the P lanes holds mlast
-  const int P = EXACT ? kBlockThreads : (W + M - 1) / M;
+  const int P = EXACT ? NT : (W + M - 1) / M;
   const int mlast = EXACT ? M : W - M * (P - 1);
   const int t = threadIdx.x;
   const bool active = t < P;
@@ -237,7 +238,7 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   for (int h = 0; h < 2; ++h) {
     const int r0 = h == 0 ? 0 : M * half;
     const int r1 = h == 0 ? M * half : W;
-    for (int w = r0 + t; w < r1; w += kBlockThreads) {
+    for (int w = r0 + t; w < r1; w += NT) {
       int g = bt.first + w;
       if (g >= n) g -= n;
       stage[spad(w - r0)] = src[g];
@@ -269,13 +270,13 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
     // four stages per step, each after an exchange of the stage's end values (buffers alternate)
     T acc[M];
     for (int step = 0; step < steps; ++step) {
-      exchange_ends<T, EXACT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+      exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
       if (active) rk4_stage<T, EXACT, 1>(v, v, w, acc, left, right, m, fix_first, fix_last, r, D);
-      exchange_ends<T, EXACT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
+      exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
       if (active) rk4_stage<T, EXACT, 2>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
-      exchange_ends<T, EXACT>(w, 0, t, P, mlast, active, s_first, s_last, left, right);
+      exchange_ends<T, EXACT, NT>(w, 0, t, P, mlast, active, s_first, s_last, left, right);
       if (active) rk4_stage<T, EXACT, 3>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
-      exchange_ends<T, EXACT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
+      exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
       if (active) rk4_stage<T, EXACT, 4>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
     }
   } else {
@@ -284,19 +285,19 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   // (a wave with no active lane skips the arithmetic; inside a step nothing branches on the lane)
   const bool is_last = t == P - 1;
   for (; step + 2 <= steps; step += 2) {
-    exchange_ends<T, EXACT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       if (!EXACT) pad_last(v, mlast, is_last, right);
       chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D);
     }
-    exchange_ends<T, EXACT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       if (!EXACT) pad_last(w, mlast, is_last, right);
       chunk_step<T, EXACT>(w, v, left, right, mlast, fix_first, fix_last, r, D);
     }
   }
   if (step < steps) {
-    exchange_ends<T, EXACT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       if (!EXACT) pad_last(v, mlast, is_last, right);
       chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D);
@@ -318,7 +319,7 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
     __syncthreads();
     const int o0 = r0 > bt.lo ? r0 : bt.lo;
     const int o1 = r1 < bt.lo + bt.count ? r1 : bt.lo + bt.count;
-    for (int w = o0 + t; w < o1; w += kBlockThreads) {
+    for (int w = o0 + t; w < o1; w += NT) {
       int g = bt.first + w;
       if (g >= n) g -= n;
       dst[g] = stage[spad(w - r0)];
@@ -327,24 +328,29 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   }
 }
 
-// One workgroup per window; full-size windows take the specialised body.  RK4 windows run in a kernel
-// of their own, so that the forward-Euler kernel keeps its smaller register footprint.
-template <typename T, bool RK4>
-__global__ __launch_bounds__(kBlockThreads) void explicit_block_kernel(
+// One workgroup of NT lanes per window or whole instance; full-size windows of the widest class take the
+// specialised body.  RK4 windows run in a kernel of their own, so that the forward-Euler kernel keeps its
+// smaller register footprint.  Narrower classes serve smaller whole instances: fewer idle waves at each
+// step's barrier, and more workgroups per CU.
+template <typename T, bool RK4, int NT = kBlockThreads>
+__global__ __launch_bounds__(NT) void explicit_block_kernel(
     const InstDesc* __restrict__ inst, const BlockTile* __restrict__ tiles, const T* __restrict__ u,
     T* __restrict__ out, int steps) {
-  __shared__ T s_first[2][kBlockThreads];
-  __shared__ T s_last[2][kBlockThreads];
-  __shared__ T stage[kStageNodes + kStageNodes / 16 + 1];
+  constexpr int kStage = stage_nodes<NT>();
+  __shared__ T s_first[2][NT];
+  __shared__ T s_last[2][NT];
+  __shared__ T stage[kStage + kStage / 16 + 1];
   const BlockTile bt = tiles[blockIdx.x];
   const InstDesc d = inst[bt.inst];
   const T* src = u + d.off;
   T* dst = out + d.off;
-  if (bt.width == kBlockThreads * kBlockChunk) {
-    block_body<T, true, RK4>(bt, d, src, dst, steps, stage, s_first, s_last);
-  } else {
-    block_body<T, false, RK4>(bt, d, src, dst, steps, stage, s_first, s_last);
+  if constexpr (NT == kBlockThreads) {
+    if (bt.width == NT * kBlockChunk) {
+      block_body<T, true, RK4, NT>(bt, d, src, dst, steps, stage, s_first, s_last);
+      return;
+    }
   }
+  block_body<T, false, RK4, NT>(bt, d, src, dst, steps, stage, s_first, s_last);
 }
 
 // Copy the nodes of a set of tiles (the instances of one subset) from src to dst.
@@ -405,26 +411,43 @@ hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int NT>
 void block_launch(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4, const void* u,
                   void* out, int steps) {
   const InstDesc* inst = ctx->inst.as<InstDesc>();
   const T* src = static_cast<const T*>(u);
   T* dst = static_cast<T*>(out);
   if (n_fe > 0)
-    explicit_block_kernel<T, false><<<static_cast<unsigned>(n_fe), kBlockThreads, 0, ctx->stream>>>(
-        inst, tiles, src, dst, steps);
+    explicit_block_kernel<T, false, NT><<<static_cast<unsigned>(n_fe), NT, 0, ctx->stream>>>(inst, tiles, src, dst,
+                                                                                            steps);
   if (n_rk4 > 0)
-    explicit_block_kernel<T, true><<<static_cast<unsigned>(n_rk4), kBlockThreads, 0, ctx->stream>>>(
-        inst, tiles + n_fe, src, dst, steps);
+    explicit_block_kernel<T, true, NT><<<static_cast<unsigned>(n_rk4), NT, 0, ctx->stream>>>(inst, tiles + n_fe, src,
+                                                                                            dst, steps);
+}
+
+template <typename T>
+void block_launch_lanes(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4, const void* u,
+                        void* out, int steps, int lanes) {
+  switch (lanes) {
+    case 64: block_launch<T, 64>(ctx, tiles, n_fe, n_rk4, u, out, steps); break;
+    case 128: block_launch<T, 128>(ctx, tiles, n_fe, n_rk4, u, out, steps); break;
+    case 256: block_launch<T, 256>(ctx, tiles, n_fe, n_rk4, u, out, steps); break;
+    default: block_launch<T, kBlockThreads>(ctx, tiles, n_fe, n_rk4, u, out, steps); break;
+  }
 }
 
 hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4,
-                                 const void* u, void* out, int steps) {
+                                 const void* u, void* out, int steps, int lanes) {
   if (n_fe + n_rk4 <= 0 || steps <= 0) return hipSuccess;
-  if (ctx->dtype == BURGERS_F64) block_launch<double>(ctx, tiles, n_fe, n_rk4, u, out, steps);
-  else block_launch<float>(ctx, tiles, n_fe, n_rk4, u, out, steps);
+  if (ctx->dtype == BURGERS_F64) block_launch_lanes<double>(ctx, tiles, n_fe, n_rk4, u, out, steps, lanes);
+  else block_launch_lanes<float>(ctx, tiles, n_fe, n_rk4, u, out, steps, lanes);
   return hipGetLastError();
+}
+
+int explicit_block_lanes(int n) {
+  int lanes = 64;
+  while (lanes < kBlockThreads && lanes * kBlockChunk < n) lanes *= 2;
+  return lanes;
 }
 
 }  // namespace burgers

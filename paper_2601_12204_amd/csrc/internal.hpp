@@ -163,6 +163,13 @@ struct ExplicitPlan {
   std::unique_ptr<DevBuf> whole, win;        // BlockTile[]
   int64_t n_whole = 0, n_win = 0;            // of which the last n_*_rk4 take RK4 steps
   int64_t n_whole_rk4 = 0, n_win_rk4 = 0;
+  // whole instances by workgroup width: `whole` holds each class's tiles contiguously (forward Euler
+  // first, then RK4)
+  struct WholeClass {
+    int lanes;
+    int64_t offset, n_fe, n_rk4;
+  };
+  std::vector<WholeClass> whole_classes;
   std::unique_ptr<DevBuf> win_copy;          // Tile[] of the windowed instances (copy-back)
   int64_t n_win_copy = 0;
   int path = 1;                              // 1 stream, 2 resident, 3 tiled
@@ -231,8 +238,10 @@ namespace burgers {
 hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles,
                                   const void* u, void* out);
 // Windows tiles[0, n_fe) advance by forward Euler and tiles[n_fe, n_fe + n_rk4) by RK4.
+// Temporal-blocking launch over `lanes`-wide workgroups (64, 128, 256 or 512; windows always take 512).
 hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4,
-                                 const void* u, void* out, int steps);
+                                 const void* u, void* out, int steps, int lanes = 512);
+int explicit_block_lanes(int n);   // narrowest workgroup that holds a whole instance of n nodes
 hipError_t launch_copy_tiles(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* src,
                              void* dst);
 int explicit_tile_nodes(burgers_dtype dt);
