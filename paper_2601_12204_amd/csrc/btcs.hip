@@ -1216,6 +1216,23 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   }
 }
 
+// The reduced systems of a partition level, one workgroup each, in the narrowest width that holds the
+// level's widest system (small reduced systems leave most of a 512-lane workgroup idle).
+template <typename S>
+void reduced_wg_launch(const BtcsPlan::Level& lv, const InstDesc* inst, const S* u, S* out, double* LA,
+                       double* LC, double* LD, double* LX, hipStream_t st) {
+  const SysDesc* sys = lv.wg->as<SysDesc>();
+  const unsigned n = static_cast<unsigned>(lv.n_wg);
+  switch (lv.wg_lanes) {
+    case 64: btcs_wg_kernel<S, false, 64, kWgChunk><<<n, 64, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
+    case 128: btcs_wg_kernel<S, false, 128, kWgChunk><<<n, 128, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
+    case 256: btcs_wg_kernel<S, false, 256, kWgChunk><<<n, 256, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
+    default:
+      btcs_wg_kernel<S, false, kWgThreads, kWgChunk><<<n, kWgThreads, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX);
+      break;
+  }
+}
+
 template <typename S>
 hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* uv, void* outv) {
   const S* u = static_cast<const S*>(uv);
@@ -1243,10 +1260,7 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   // backward: whole-system solves of each level, then back-substitution of the reduced systems
   for (int l = L - 1; l >= 1; --l) {
     const auto& lv = plan.levels[l];
-    if (lv.n_wg) {
-      btcs_wg_kernel<S, false, kWgThreads, kWgChunk><<<lv.n_wg, kWgThreads, 0, st>>>(
-          inst, lv.wg->as<SysDesc>(), u, out, LA, LC, LD, LX);
-    }
+    if (lv.n_wg) reduced_wg_launch<S>(lv, inst, u, out, LA, LC, LD, LX, st);
     if (lv.n_blocks) {
       btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
                                                                       lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);
@@ -1358,6 +1372,13 @@ int btcs_wg_chunks(int rows) {
 
 int btcs_reduce_chunk() { return kRedChunk; }
 
+int btcs_wg_lanes(const std::vector<SysDesc>& systems) {
+  int lanes = 64;
+  for (const SysDesc& sd : systems)
+    while (lanes < sd.chunks) lanes *= 2;
+  return lanes < kWgThreads ? lanes : kWgThreads;
+}
+
 // Solve systems stored in (A, C, D) arrays with unit diagonal (all levels array-sourced); the solution
 // lands in X at each root system's offset.  levels[0] holds the roots that need partitioning.
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
@@ -1375,9 +1396,7 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
   }
   for (int l = L - 1; l >= 0; --l) {
     const auto& lv = plan.levels[l];
-    if (lv.n_wg)
-      btcs_wg_kernel<double, false, kWgThreads, kWgChunk><<<lv.n_wg, kWgThreads, 0, st>>>(
-          inst, lv.wg->as<SysDesc>(), none, none_out, LA, LC, LD, LX);
+    if (lv.n_wg) reduced_wg_launch<double>(lv, inst, none, none_out, LA, LC, LD, LX, st);
     if (lv.n_blocks)
       btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
                                                                       lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);

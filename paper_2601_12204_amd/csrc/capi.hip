@@ -328,6 +328,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
       return from_hip(e);
     lv.n_blocks = static_cast<int32_t>(blocks.size());
     lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
+    lv.wg_lanes = burgers::btcs_wg_lanes(wg_sys[l]);
   }
   ctx->btcs[set] = std::move(plan);
   return BURGERS_OK;
@@ -555,6 +556,7 @@ hipError_t build_array_solve(burgers_ctx* ctx, const std::vector<std::tuple<int3
       return e;
     lv.n_blocks = static_cast<int32_t>(blocks.size());
     lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
+    lv.wg_lanes = burgers::btcs_wg_lanes(wg_sys[l]);
   }
   return hipSuccess;
 }
