@@ -307,10 +307,10 @@ def dominant_roofline(c2):
         flops = EXPLICIT_FLOPS_PER_UPDATE * nodes * c2["n_exp"]
         achieved = flops / (exp_ms * 1e-3) / 1e12
         peak = EXPLICIT_ALU_PEAK / 1e12
-        traffic = profiled_traffic("explicit_block_kernel<double, false>", "c2_f64")
+        traffic = profiled_traffic("explicit_block_kernel<double, false, 512>", "c2_f64")
         return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic,
-                "kernel": "explicit_block_kernel<double, false>", "launches": c2["explicit_launches"],
+                "kernel": "explicit_block_kernel<double, false, 512>", "launches": c2["explicit_launches"],
                 "algorithmic_flops_per_launch": flops / c2["explicit_launches"],
                 "algorithmic_bytes_per_launch": 2 * word * nodes,
                 "peak_basis": "binary64 issue 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 inst/s, "
