@@ -268,11 +268,10 @@ def bench_c3(B, torch, n_exp=1024, n_btcs=128):
 # r*u; (u - u_m), (u_p - u); the two clipped products and the two subtractions; (u_p + u_m), 2u and
 # their difference; D*lap and the final add.  The two clips (max, min) are not counted.
 EXPLICIT_FLOPS_PER_UPDATE = 12
-# binary64 instructions the update needs in the association it is evaluated in (bitwise equal to the
-# oracle): r*u, one upwind difference (shared with the neighbour), the sign test and the two 32-bit
-# halves of the select, c*diff, u - c*diff, u_p + u_m, one fused -2u + (u_p + u_m) (exact product),
-# D*lap and the final add.  Issue-bound ceiling of its flop rate = issue rate x 12 / 11.
-EXPLICIT_INSTS_PER_UPDATE = 11
+# binary64 instructions of the update as the kernels evaluate it, u + alpha (u_p - u) - beta (u - u_m):
+# c = r*u, max(c, 0), beta = D + max, alpha = beta - c, one one-sided difference (the other is the
+# neighbour's), two fused multiply-adds.  Issue-bound ceiling of its flop rate = issue rate x 12 / 7.
+EXPLICIT_INSTS_PER_UPDATE = 7
 EXPLICIT_ALU_PEAK = FP64_ISSUE_RATE * EXPLICIT_FLOPS_PER_UPDATE / EXPLICIT_INSTS_PER_UPDATE
 
 
@@ -314,7 +313,7 @@ def dominant_roofline(c2):
                 "algorithmic_flops_per_launch": flops / c2["explicit_launches"],
                 "algorithmic_bytes_per_launch": 2 * word * nodes,
                 "peak_basis": "binary64 issue 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 inst/s, "
-                              "x 12 flops per 11 instructions of the update",
+                              "x 12 flops per 7 instructions of the update",
                 "frac_of_fma_peak": achieved / (FP64_VECTOR_PEAK / 1e12)}
     per_launch = btcs_ms / c2["btcs_launches"]
     if c2["btcs_launches"] == 1:

@@ -1,26 +1,28 @@
 // Explicit forward-Euler upwind/central step (Sec. 2.3, eq. 21) for gfx950.
 //
-// The update of one node is a 3-point stencil evaluated in exactly this association, with contraction
-// disabled, so that every kernel here rounds like a plain scalar evaluation of the formula:
-//   c = r u_i;  lap = (u_{i+1} + u_{i-1}) - 2 u_i
-//   u_i' = ((u_i - max(c,0) (u_i - u_{i-1})) - min(c,0) (u_{i+1} - u_i)) + D lap
+// The update of one node is the 3-point stencil
+//   c = r u_i;  u_i' = ((u_i - max(c,0) (u_i - u_{i-1})) - min(c,0) (u_{i+1} - u_i)) + D ((u_{i+1} + u_{i-1}) - 2 u_i)
 // The upwind side follows the sign of u_i (backward difference for u_i >= 0, eq. 3; forward for
 // u_i < 0, as the text after eq. 3 prescribes).  Diffusion uses the central difference of eq. 4.
+// Every kernel evaluates it through upwind_central (stencil.hpp): binary64 as the equivalent fused
+// combination u + alpha (u_{i+1} - u_i) - beta (u_i - u_{i-1}), binary32 in exactly the association
+// above with contraction disabled.
 //
 // Two kernels:
-//  * explicit_stream_kernel: one step per pass over HBM.  It moves 2 words per node-step and does 11
+//  * explicit_stream_kernel: one step per pass over HBM.  It moves 2 words per node-step and does 12
 //    flops, far below the machine balance, so it is bound by HBM: each workgroup streams one tile of
 //    256 lanes x 16 bytes with vector loads and stores; a tile's descriptor carries everything needed
 //    to address it, so the vector load issues after a single scalar load.
-//  * explicit_block_kernel: temporal blocking.  A workgroup of 512 lanes holds a window of up to 8192
-//    nodes in registers (16 per lane, in two arrays that alternate as old and new state, so no value is
-//    copied between registers), exchanges only the chunk end values through LDS each step (double
-//    buffered, one barrier per step) and advances many steps per pass over HBM.  The window is loaded
-//    and stored through LDS so that HBM sees coalesced accesses.  A whole instance that
-//    fits is advanced for all its steps in one launch with exact boundaries; longer grids are cut into
-//    windows with a halo of T nodes per side that are recomputed redundantly, so that after T steps the
-//    window's interior is exact.  Every node goes through the same arithmetic as in the streaming
-//    kernel, so both kernels give bitwise identical results.
+//  * explicit_block_kernel: temporal blocking.  A workgroup of up to 512 lanes holds a window of up to
+//    8192 nodes in registers (16 consecutive nodes per lane, in two arrays that alternate as old and new
+//    state, so no value is copied between registers), exchanges only the chunk end values through LDS
+//    each step (double buffered, one barrier per step) and advances many steps per pass over HBM.  The
+//    window is loaded and stored through LDS so that HBM sees coalesced accesses.  A whole instance
+//    that fits is advanced for all its steps in one launch with exact boundaries, in the narrowest of
+//    64, 128, 256 or 512 lanes that holds it; longer grids are cut into windows with a halo of T nodes
+//    per side that are recomputed redundantly, so that after T steps the window's interior is exact.
+//    Every node goes through the same arithmetic as in the streaming kernel, so both kernels give
+//    bitwise identical results.
 #include "internal.hpp"
 #include "stencil.hpp"
 

@@ -1,8 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle on identical seeded inputs.
 
-Bars (gpu_util.check_batch): FP64 relative max-abs <= 1e-12 against the FP64 oracle.  The explicit
-kernels evaluate the update in the oracle's association with contraction off, so in both precisions they
-must also equal the oracle of their precision bitwise.  FP32 BTCS runs in binary64 arithmetic on a
+Bars (gpu_util.check_batch): FP64 relative max-abs <= 1e-12 against the FP64 oracle, per instance.  The
+binary64 explicit update is the fused convex-combination form, so it is held to that bar, and every
+device path of it (streaming, whole instances, windows at any depth) must agree with the others bitwise.
+The binary32 explicit update keeps the oracle's association with contraction off and must equal the FP32
+oracle bitwise.  FP32 BTCS runs in binary64 arithmetic on a
 binary32 state and must lie within 1e-5 of the exact discrete solution (the FP64 oracle from the same
 binary32 initial state); its distance from the FP32 oracle is bounded by that oracle's own error plus
 1e-5.  Small ragged cases span several tiles and ragged tails; full-size cases
@@ -14,8 +16,8 @@ import pytest
 
 import oracle
 import workloads as W
-from gpu_util import (TOL_F32, TOL_F64, announce, check_batch, device_run, oracle_run, per_instance_rel,
-                      rel_err, set_cfl_steps)
+from gpu_util import (TOL_F32, TOL_F64, announce, assert_explicit_parity, check_batch, device_run,
+                      oracle_run, per_instance_rel, rel_err, set_cfl_steps)
 
 pytestmark = pytest.mark.gpu
 TOL = {"f64": TOL_F64, "f32": TOL_F32}
@@ -28,7 +30,7 @@ def test_explicit_parity_ragged(dtype):
     got = device_run(batch, 50, dtype, how="step_explicit")
     ref = oracle_run(batch, 50, dtype, scheme=W.EXPLICIT)
     assert rel_err(got, ref) <= TOL[dtype]
-    assert np.array_equal(got, ref), "explicit step should round exactly like the oracle"
+    assert_explicit_parity(batch, got, ref, dtype)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -69,7 +71,9 @@ def test_explicit_edge_sizes(bc):
     announce(f"explicit edge sizes bc={bc}")
     got = device_run(batch, 9, "f64", how="step_explicit")
     ref = oracle_run(batch, 9, "f64", scheme=W.EXPLICIT)
-    assert np.array_equal(got, ref)
+    assert_explicit_parity(batch, got, ref, "f64")
+    stream = device_run(batch, 9, "f64", how="step_explicit", plan=dict(explicit_path=1))
+    assert np.array_equal(got, stream)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -167,16 +171,14 @@ def test_c3_explicit_full_size_sampled_nodes():
     front = int(0.3 * (p.n - 1))
     nodes += [front - 5, front, front + 7]
     u0 = b.u0
+    scale = float(np.max(np.abs(u0)))
     for i in nodes:
         lo, hi = max(0, i - steps - 1), min(p.n, i + steps + 2)
         win = u0[lo:hi].copy()
         a_w = p.left if lo == 0 else win[0]
         b_w = p.right if hi == p.n else win[-1]
         out = oracle.run_ratios(win, W.BC_DIRICHLET, a_w, b_w, r, D, steps)
-        assert got[i] == out[i - lo], i
-        inc_ref = out[i - lo] - u0[i]
-        inc = got[i] - u0[i]
-        assert abs(inc - inc_ref) <= 1e-9 * max(abs(inc_ref), 1e-300) or inc == inc_ref
+        assert abs(got[i] - out[i - lo]) <= TOL_F64 * scale, (i, got[i], out[i - lo])
 
 
 def test_c3_btcs_full_size():
@@ -263,27 +265,46 @@ def _ragged_long_batch(seed):
     return set_cfl_steps(W._pack(problems, states), scheme=W.EXPLICIT)
 
 
+EXPLICIT_PATHS = [(1, 0), (3, 1), (3, 5), (3, 16), (3, 32), (3, 200), (0, 0), (0, 7), (0, 300)]
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("path,depth", [(1, 0), (3, 1), (3, 5), (3, 16), (3, 32), (3, 200), (0, 0), (0, 7), (0, 300)])
-def test_explicit_paths_bitwise(dtype, path, depth):
+@pytest.mark.parametrize("path,depth", EXPLICIT_PATHS)
+def test_explicit_paths(dtype, path, depth):
     """Streaming, whole-instance and windowed temporal blocking at several depths, including step counts
-    that are not multiples of the depth, are all bitwise equal to the oracle."""
+    that are not multiples of the depth: FP64 within the tolerance of the oracle, FP32 bitwise equal."""
     batch = _ragged_long_batch(31)
     announce(f"explicit path={path} depth={depth} {dtype} 37 steps")
     got = device_run(batch, 37, dtype, how="step_explicit", plan=dict(explicit_path=path, tblock_depth=depth))
     ref = oracle_run(batch, 37, dtype, scheme=W.EXPLICIT)
-    assert np.array_equal(got, ref)
+    assert_explicit_parity(batch, got, ref, dtype)
+
+
+def test_explicit_paths_agree_bitwise_f64():
+    """Every binary64 explicit path rounds identically: one HBM pass per step, whole instances on chip,
+    and windows at any depth (halos recomputed redundantly) give bitwise equal states."""
+    batch = _ragged_long_batch(31)
+    results = []
+    for path, depth in EXPLICIT_PATHS:
+        announce(f"explicit f64 path={path} depth={depth} 37 steps (cross-path)")
+        results.append(device_run(batch, 37, "f64", how="step_explicit",
+                                  plan=dict(explicit_path=path, tblock_depth=depth)))
+    for (path, depth), got in zip(EXPLICIT_PATHS[1:], results[1:]):
+        assert np.array_equal(got, results[0]), (path, depth)
 
 
 @pytest.mark.parametrize("depth", [200, 0])
-def test_explicit_deep_windows_bitwise(depth):
+def test_explicit_deep_windows(depth):
     """Deep temporal blocking (200 steps per launch, and the default) over 450 steps: several launches
-    with a partial last one, windows whose halos span hundreds of nodes, bitwise equal to the oracle."""
+    with a partial last one, windows whose halos span hundreds of nodes: within the tolerance of the
+    oracle and bitwise equal to the streaming kernel (one HBM pass per step)."""
     batch = _ragged_long_batch(47)
     announce(f"explicit deep windows depth={depth} 450 steps")
     got = device_run(batch, 450, "f64", how="step_explicit", plan=dict(explicit_path=0, tblock_depth=depth))
     ref = oracle_run(batch, 450, "f64", scheme=W.EXPLICIT)
-    assert np.array_equal(got, ref)
+    assert_explicit_parity(batch, got, ref, "f64")
+    stream = device_run(batch, 450, "f64", how="step_explicit", plan=dict(explicit_path=1))
+    assert np.array_equal(got, stream)
 
 
 def test_explicit_resident_path_rejects_long_instances():
@@ -393,10 +414,8 @@ def test_run_mixed_step_counts(graph):
     imp = oracle_run(batch, 5, "f64", scheme=W.BTCS)
     for b, p in enumerate(batch.problems):
         lo, hi = batch.offsets[b], batch.offsets[b + 1]
-        if p.scheme == W.EXPLICIT:
-            assert np.array_equal(got[lo:hi], exp[lo:hi]), b
-        else:
-            assert rel_err(got[lo:hi], imp[lo:hi]) <= TOL_F64, b
+        ref = exp if p.scheme == W.EXPLICIT else imp
+        assert rel_err(got[lo:hi], ref[lo:hi]) <= TOL_F64, b
 
 
 def test_autotune_keeps_state_and_results(tmp_path):
@@ -421,10 +440,8 @@ def test_autotune_keeps_state_and_results(tmp_path):
     imp = oracle_run(batch, 5, "f64", scheme=W.BTCS)
     for b, p in enumerate(batch.problems):
         lo, hi = batch.offsets[b], batch.offsets[b + 1]
-        if p.scheme == W.EXPLICIT:
-            assert np.array_equal(got[lo:hi], exp[lo:hi]), (b, plan)
-        else:
-            assert rel_err(got[lo:hi], imp[lo:hi]) <= TOL_F64, (b, plan)
+        ref = exp if p.scheme == W.EXPLICIT else imp
+        assert rel_err(got[lo:hi], ref[lo:hi]) <= TOL_F64, (b, plan)
     s2 = B.Solver(batch.problems, dtype=torch.float64)
     plan2, ms2, cached2 = s2.autotune(s2.pack_flat(batch.u0, batch.offsets), 20, 5, cache=cache)
     assert cached2 and plan2 == plan and s2.get_plan() == plan
@@ -441,14 +458,15 @@ def _rk4_batch(seed):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("depth", [0, 5, 16])
-def test_rk4_bitwise(dtype, depth):
-    """RK4 instances (whole on chip and windows with 4 halo nodes per step) bitwise equal to the oracle's
-    RK4, over 37 steps (several launches with a partial last one at depths 5 and 16)."""
+def test_rk4_parity(dtype, depth):
+    """RK4 instances (whole on chip and windows with 4 halo nodes per step) against the oracle's RK4 over
+    37 steps (several launches with a partial last one at depths 5 and 16): FP64 within the tolerance,
+    FP32 bitwise equal."""
     batch = _rk4_batch(61)
     announce(f"rk4 {dtype} depth={depth} 37 steps")
     got = device_run(batch, 37, dtype, how="run", plan=dict(tblock_depth=depth))
     ref = oracle_run(batch, 37, dtype)
-    assert np.array_equal(got, ref)
+    assert_explicit_parity(batch, got, ref, dtype)
 
 
 def test_rk4_mixed_with_euler_and_btcs():
@@ -470,10 +488,8 @@ def test_rk4_mixed_with_euler_and_btcs():
     imp = oracle_run(batch, 4, "f64")
     for b, p in enumerate(batch.problems):
         lo, hi = batch.offsets[b], batch.offsets[b + 1]
-        if p.scheme == W.BTCS:
-            assert rel_err(got[lo:hi], imp[lo:hi]) <= TOL_F64, b
-        else:
-            assert np.array_equal(got[lo:hi], exp[lo:hi]), b
+        ref = imp if p.scheme == W.BTCS else exp
+        assert rel_err(got[lo:hi], ref[lo:hi]) <= TOL_F64, b
 
 
 def test_rk4_unsupported_paths():
@@ -495,7 +511,7 @@ def test_rk4_unsupported_paths():
     assert err.value.status == -2
     s.close()
     got = device_run(batch, 9, "f64", how="step_explicit")
-    assert np.array_equal(got, oracle_run(batch, 9, "f64", scheme=W.EXPLICIT))
+    assert_explicit_parity(batch, got, oracle_run(batch, 9, "f64", scheme=W.EXPLICIT), "f64")
 
 
 # ----------------------------------------------------------------------------- Crank-Nicolson
@@ -596,7 +612,7 @@ def test_newton_mixed_and_unsupported():
 # ----------------------------------------------------------------------------- degenerate cases
 def test_degenerate_inputs():
     """Inviscid instances (nu = 0: D = 0, the BTCS rows keep their unit row sums and dominance), a zero
-    state, and zero steps, for every scheme: results match the oracle (bitwise for explicit schemes) and
+    state, and zero steps, for every scheme: results match the oracle (FP64 bar) and
     zero steps leave the state untouched."""
     rng = np.random.default_rng(127)
     problems, states = [], []
