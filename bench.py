@@ -269,9 +269,10 @@ def bench_c3(B, torch, n_exp=1024, n_btcs=128):
 # their difference; D*lap and the final add.  The two clips (max, min) are not counted.
 EXPLICIT_FLOPS_PER_UPDATE = 12
 # binary64 instructions of the update as the kernels evaluate it, u + alpha (u_p - u) - beta (u - u_m):
-# c = r*u, max(c, 0), beta = D + max, alpha = beta - c, one one-sided difference (the other is the
-# neighbour's), two fused multiply-adds.  Issue-bound ceiling of its flop rate = issue rate x 12 / 7.
-EXPLICIT_INSTS_PER_UPDATE = 7
+# beta = max(r*u + D, D) (a fused multiply-add and a max), alpha = beta - r*u (one fused multiply-add),
+# one one-sided difference (the other is the neighbour's), two fused multiply-adds.  Issue-bound ceiling
+# of its flop rate = issue rate x 12 / 6, which equals the published FMA-counted binary64 vector peak.
+EXPLICIT_INSTS_PER_UPDATE = 6
 EXPLICIT_ALU_PEAK = FP64_ISSUE_RATE * EXPLICIT_FLOPS_PER_UPDATE / EXPLICIT_INSTS_PER_UPDATE
 
 
@@ -313,7 +314,7 @@ def dominant_roofline(c2):
                 "algorithmic_flops_per_launch": flops / c2["explicit_launches"],
                 "algorithmic_bytes_per_launch": 2 * word * nodes,
                 "peak_basis": "binary64 issue 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 inst/s, "
-                              "x 12 flops per 7 instructions of the update",
+                              "x 12 flops per 6 instructions of the update",
                 "frac_of_fma_peak": achieved / (FP64_VECTOR_PEAK / 1e12)}
     per_launch = btcs_ms / c2["btcs_launches"]
     if c2["btcs_launches"] == 1:
