@@ -122,17 +122,30 @@ __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
 // for the whole workgroup).  That lane's slot mlast holds its right neighbour's value (pad_last), so
 // all lanes run the same unguarded code; the results in the last lane's slots past mlast - 1 are never
 // used.  The fixed last node (fix_last, last lane only) is node mlast - 1.
+//
+// EXACT (every chunk full): the chunk's two end nodes take their own coefficients (r0, D0) and
+// (r1, D1), which are zero at a fixed node, where the update then returns the node's value unchanged;
+// nothing branches, and the interior nodes, which need no neighbour value, come first, so that they
+// run while `left` and `right` are still in flight from LDS.
 template <typename T, bool EXACT>
 __device__ __forceinline__ void chunk_step(const T (&in)[kBlockChunk], T (&out)[kBlockChunk], T left, T right,
-                                           int mlast, bool fix_first, bool fix_last, T r, T D) {
+                                           int mlast, bool fix_first, bool fix_last, T r, T D, T r0, T D0,
+                                           T r1, T D1) {
   constexpr int M = kBlockChunk;
-  T prev = left;
+  if constexpr (EXACT) {
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
-    const T up = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
-    const bool fixed = (j == 0 && fix_first) || (j == (EXACT ? M : mlast) - 1 && fix_last);
-    out[j] = fixed ? in[j] : upwind_central(in[j], prev, up, r, D);
-    prev = in[j];
+    for (int j = 1; j < M - 1; ++j) out[j] = upwind_central(in[j], in[j - 1], in[j + 1], r, D);
+    out[0] = upwind_central(in[0], left, in[1], r0, D0);
+    out[M - 1] = upwind_central(in[M - 1], in[M - 2], right, r1, D1);
+  } else {
+    T prev = left;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const T up = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
+      const bool fixed = (j == 0 && fix_first) || (j == mlast - 1 && fix_last);
+      out[j] = fixed ? in[j] : upwind_central(in[j], prev, up, r, D);
+      prev = in[j];
+    }
   }
 }
 
@@ -284,25 +297,27 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   } else {
   // two steps per iteration: v -> w, then w -> v (exchange buffers 0 and 1 alternate)
   int step = 0;
+  const T r0 = fix_first ? T(0) : r, D0 = fix_first ? T(0) : D;
+  const T r1 = fix_last ? T(0) : r, D1 = fix_last ? T(0) : D;
   // (a wave with no active lane skips the arithmetic; inside a step nothing branches on the lane)
   const bool is_last = t == P - 1;
   for (; step + 2 <= steps; step += 2) {
     exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       if (!EXACT) pad_last(v, mlast, is_last, right);
-      chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D);
+      chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1);
     }
     exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       if (!EXACT) pad_last(w, mlast, is_last, right);
-      chunk_step<T, EXACT>(w, v, left, right, mlast, fix_first, fix_last, r, D);
+      chunk_step<T, EXACT>(w, v, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1);
     }
   }
   if (step < steps) {
     exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       if (!EXACT) pad_last(v, mlast, is_last, right);
-      chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D);
+      chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1);
 #pragma unroll
       for (int j = 0; j < M; ++j) v[j] = w[j];
     }
