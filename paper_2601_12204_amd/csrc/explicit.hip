@@ -166,37 +166,55 @@ __device__ __forceinline__ void pad_last(T (&x)[kBlockChunk], int mlast, bool is
 //   4: v = v + (acc + K)/6  (out unused)
 // `in` and `out` may be the same array: node j reads in[j-1] from a register kept before it is
 // overwritten.
+template <typename T, int STAGE>
+__device__ __forceinline__ void rk4_apply(T (&v)[kBlockChunk], T (&out)[kBlockChunk], T (&acc)[kBlockChunk], int j,
+                                          T K) {
+  if constexpr (STAGE == 1) {
+    acc[j] = K;
+    out[j] = v[j] + T(0.5) * K;
+  } else if constexpr (STAGE == 2) {
+    acc[j] = fma_exact(T(2), K, acc[j]);
+    out[j] = v[j] + T(0.5) * K;
+  } else if constexpr (STAGE == 3) {
+    acc[j] = fma_exact(T(2), K, acc[j]);
+    out[j] = v[j] + K;
+  } else {
+    v[j] = v[j] + (acc[j] + K) / T(6);
+  }
+}
+
+// EXACT (every chunk full): as in chunk_step, the two end nodes take their own coefficients (zero at a
+// fixed node, where K is then a zero) and come after the interior nodes; the four inputs the end nodes
+// read are kept first, since `out` may overwrite `in`.
 template <typename T, bool EXACT, int STAGE>
 __device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBlockChunk], T (&out)[kBlockChunk],
                                           T (&acc)[kBlockChunk], T left, T right, int m, bool fix_first,
-                                          bool fix_last, T r, T D) {
+                                          bool fix_last, T r, T D, T r0, T D0, T r1, T D1) {
   constexpr int M = kBlockChunk;
-  T prev = left;
+  if constexpr (EXACT) {
+    const T i0 = in[0], i1 = in[1], i2 = in[M - 2], i3 = in[M - 1];
+    T prev = i0;
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
-    if (EXACT || j < m) {
-      T up;
-      if (EXACT) {
-        up = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
-      } else {
-        up = right;
-        if (j + 1 < M && j + 1 < m) up = in[j + 1 < M ? j + 1 : j];
-      }
-      const bool fixed = (j == 0 && fix_first) || (EXACT ? (j == M - 1 && fix_last) : (j == m - 1 && fix_last));
+    for (int j = 1; j < M - 1; ++j) {
       const T cur = in[j];
-      const T K = fixed ? T(0) : rk4_increment(cur, prev, up, r, D);
+      const T K = rk4_increment(cur, prev, in[j + 1], r, D);
       prev = cur;
-      if constexpr (STAGE == 1) {
-        acc[j] = K;
-        out[j] = v[j] + T(0.5) * K;
-      } else if constexpr (STAGE == 2) {
-        acc[j] = fma_exact(T(2), K, acc[j]);
-        out[j] = v[j] + T(0.5) * K;
-      } else if constexpr (STAGE == 3) {
-        acc[j] = fma_exact(T(2), K, acc[j]);
-        out[j] = v[j] + K;
-      } else {
-        v[j] = v[j] + (acc[j] + K) / T(6);
+      rk4_apply<T, STAGE>(v, out, acc, j, K);
+    }
+    rk4_apply<T, STAGE>(v, out, acc, 0, rk4_increment(i0, left, i1, r0, D0));
+    rk4_apply<T, STAGE>(v, out, acc, M - 1, rk4_increment(i3, i2, right, r1, D1));
+  } else {
+    T prev = left;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      if (j < m) {
+        T up = right;
+        if (j + 1 < M && j + 1 < m) up = in[j + 1 < M ? j + 1 : j];
+        const bool fixed = (j == 0 && fix_first) || (j == m - 1 && fix_last);
+        const T cur = in[j];
+        const T K = fixed ? T(0) : rk4_increment(cur, prev, up, r, D);
+        prev = cur;
+        rk4_apply<T, STAGE>(v, out, acc, j, K);
       }
     }
   }
@@ -281,24 +299,25 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
 
   T w[M];
   T left = T(0), right = T(0);
+  // a full chunk's end nodes: zero coefficients where the node is held fixed (see chunk_step)
+  const T r0 = fix_first ? T(0) : r, D0 = fix_first ? T(0) : D;
+  const T r1 = fix_last ? T(0) : r, D1 = fix_last ? T(0) : D;
   if constexpr (RK4) {
     // four stages per step, each after an exchange of the stage's end values (buffers alternate)
     T acc[M];
     for (int step = 0; step < steps; ++step) {
       exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
-      if (active) rk4_stage<T, EXACT, 1>(v, v, w, acc, left, right, m, fix_first, fix_last, r, D);
+      if (active) rk4_stage<T, EXACT, 1>(v, v, w, acc, left, right, m, fix_first, fix_last, r, D, r0, D0, r1, D1);
       exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
-      if (active) rk4_stage<T, EXACT, 2>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
+      if (active) rk4_stage<T, EXACT, 2>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D, r0, D0, r1, D1);
       exchange_ends<T, EXACT, NT>(w, 0, t, P, mlast, active, s_first, s_last, left, right);
-      if (active) rk4_stage<T, EXACT, 3>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
+      if (active) rk4_stage<T, EXACT, 3>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D, r0, D0, r1, D1);
       exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
-      if (active) rk4_stage<T, EXACT, 4>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D);
+      if (active) rk4_stage<T, EXACT, 4>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D, r0, D0, r1, D1);
     }
   } else {
   // two steps per iteration: v -> w, then w -> v (exchange buffers 0 and 1 alternate)
   int step = 0;
-  const T r0 = fix_first ? T(0) : r, D0 = fix_first ? T(0) : D;
-  const T r1 = fix_last ? T(0) : r, D1 = fix_last ? T(0) : D;
   // (a wave with no active lane skips the arithmetic; inside a step nothing branches on the lane)
   const bool is_last = t == P - 1;
   for (; step + 2 <= steps; step += 2) {
