@@ -484,8 +484,9 @@ def main():
     ap.add_argument("--btcs-block", type=int, default=0, help="lanes per system of the BTCS solver (0 auto)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (instances shard "
-              "across GPUs without communication, see the design notes)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the instances are "
+              "independent, so a batch would shard across GPUs by instance without communication)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2601_12204_amd as B
