@@ -127,16 +127,34 @@ __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
 // (r1, D1), which are zero at a fixed node, where the update then returns the node's value unchanged;
 // nothing branches, and the interior nodes, which need no neighbour value, come first, so that they
 // run while `left` and `right` are still in flight from LDS.
-template <typename T, bool EXACT>
+//
+// ML > 0 (the last lane's count known at compile time, 1 <= ML <= M): every lane runs the same code.
+// Node ML - 1 is the last lane's last real node: its right neighbour is `right` there and in[ML] in
+// the other lanes (one select), and it takes (r1, D1), zero only where it is a fixed node; the last
+// lane's slots past ML - 1 are computed from finite values and never used.  With ML = 1, node 0 is
+// both a first and a last node and takes (rE, DE), zero where either end is fixed.
+template <typename T, bool EXACT, int ML = 0>
 __device__ __forceinline__ void chunk_step(const T (&in)[kBlockChunk], T (&out)[kBlockChunk], T left, T right,
                                            int mlast, bool fix_first, bool fix_last, T r, T D, T r0, T D0,
-                                           T r1, T D1) {
+                                           T r1, T D1, bool is_last = false, T rE = T(0), T DE = T(0)) {
   constexpr int M = kBlockChunk;
   if constexpr (EXACT) {
 #pragma unroll
     for (int j = 1; j < M - 1; ++j) out[j] = upwind_central(in[j], in[j - 1], in[j + 1], r, D);
     out[0] = upwind_central(in[0], left, in[1], r0, D0);
     out[M - 1] = upwind_central(in[M - 1], in[M - 2], right, r1, D1);
+  } else if constexpr (ML > 0) {
+#pragma unroll
+    for (int j = 1; j < M; ++j)
+      if (j != ML - 1) out[j] = upwind_central(in[j], in[j - 1], j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right, r, D);
+    constexpr int kNext = ML < M ? ML : M - 1;   // in[ML] exists only for ML < M
+    const T up = ML < M ? (is_last ? right : in[kNext]) : right;
+    if constexpr (ML == 1) {
+      out[0] = upwind_central(in[0], left, up, rE, DE);
+    } else {
+      out[0] = upwind_central(in[0], left, in[1], r0, D0);
+      out[ML - 1] = upwind_central(in[ML - 1], in[ML - 2], up, r1, D1);
+    }
   } else {
     T prev = left;
 #pragma unroll
@@ -221,7 +239,7 @@ __device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBl
 }
 
 // Publish a lane's chunk end values in exchange buffer `buf`, wait, and read the neighbours' ends.
-template <typename T, bool EXACT, int NT>
+template <typename T, bool EXACT, int NT, int ML = 0>
 __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf, int t, int P, int mlast,
                                               bool active, T (*s_first)[NT], T (*s_last)[NT],
                                               T& left, T& right) {
@@ -229,7 +247,9 @@ __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf
   if (active) {
     s_first[buf][t] = x[0];
     T last = x[M - 1];
-    if (!EXACT) {   // the window's last lane holds mlast nodes (uniform index, one select)
+    if constexpr (!EXACT && ML > 0) {
+      if (t == P - 1) last = x[ML - 1];
+    } else if (!EXACT) {   // the window's last lane holds mlast nodes (uniform index, one select)
       T tail = x[M - 1];
 #pragma unroll
       for (int j = 0; j < M; ++j)
@@ -247,7 +267,7 @@ __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf
 
 // Temporal-blocking body over NT lanes.  EXACT: the window has exactly NT * kBlockChunk nodes, so every lane
 // holds a full chunk and the guards below fold away.
-template <typename T, bool EXACT, bool RK4, int NT>
+template <typename T, bool EXACT, bool RK4, int NT, int ML = 0>
 __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& d, const T* __restrict__ src,
                                            T* __restrict__ dst, int steps, T* stage,
                                            T (*s_first)[NT], T (*s_last)[NT]) {
@@ -302,6 +322,8 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   // a full chunk's end nodes: zero coefficients where the node is held fixed (see chunk_step)
   const T r0 = fix_first ? T(0) : r, D0 = fix_first ? T(0) : D;
   const T r1 = fix_last ? T(0) : r, D1 = fix_last ? T(0) : D;
+  const bool fix_either = fix_first || fix_last;
+  const T rE = fix_either ? T(0) : r, DE = fix_either ? T(0) : D;
   if constexpr (RK4) {
     // four stages per step, each after an exchange of the stage's end values (buffers alternate)
     T acc[M];
@@ -321,22 +343,22 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   // (a wave with no active lane skips the arithmetic; inside a step nothing branches on the lane)
   const bool is_last = t == P - 1;
   for (; step + 2 <= steps; step += 2) {
-    exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT, NT, ML>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
-      if (!EXACT) pad_last(v, mlast, is_last, right);
-      chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1);
+      if (!EXACT && ML == 0) pad_last(v, mlast, is_last, right);
+      chunk_step<T, EXACT, ML>(v, w, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1, is_last, rE, DE);
     }
-    exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT, NT, ML>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
-      if (!EXACT) pad_last(w, mlast, is_last, right);
-      chunk_step<T, EXACT>(w, v, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1);
+      if (!EXACT && ML == 0) pad_last(w, mlast, is_last, right);
+      chunk_step<T, EXACT, ML>(w, v, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1, is_last, rE, DE);
     }
   }
   if (step < steps) {
-    exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT, NT, ML>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
-      if (!EXACT) pad_last(v, mlast, is_last, right);
-      chunk_step<T, EXACT>(v, w, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1);
+      if (!EXACT && ML == 0) pad_last(v, mlast, is_last, right);
+      chunk_step<T, EXACT, ML>(v, w, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1, is_last, rE, DE);
 #pragma unroll
       for (int j = 0; j < M; ++j) v[j] = w[j];
     }
@@ -386,7 +408,22 @@ __global__ __launch_bounds__(NT) void explicit_block_kernel(
       return;
     }
   }
-  block_body<T, false, RK4, NT>(bt, d, src, dst, steps, stage, s_first, s_last);
+  if constexpr (RK4) {
+    block_body<T, false, true, NT>(bt, d, src, dst, steps, stage, s_first, s_last);
+  } else {
+    // the last lane's node count, uniform over the workgroup: one specialised body per count
+    const int mlast = bt.width - kBlockChunk * ((bt.width + kBlockChunk - 1) / kBlockChunk - 1);
+    switch (mlast) {
+#define BURGERS_RAGGED_CASE(K) \
+  case K: block_body<T, false, false, NT, K>(bt, d, src, dst, steps, stage, s_first, s_last); break;
+      BURGERS_RAGGED_CASE(1) BURGERS_RAGGED_CASE(2) BURGERS_RAGGED_CASE(3) BURGERS_RAGGED_CASE(4)
+      BURGERS_RAGGED_CASE(5) BURGERS_RAGGED_CASE(6) BURGERS_RAGGED_CASE(7) BURGERS_RAGGED_CASE(8)
+      BURGERS_RAGGED_CASE(9) BURGERS_RAGGED_CASE(10) BURGERS_RAGGED_CASE(11) BURGERS_RAGGED_CASE(12)
+      BURGERS_RAGGED_CASE(13) BURGERS_RAGGED_CASE(14) BURGERS_RAGGED_CASE(15) BURGERS_RAGGED_CASE(16)
+#undef BURGERS_RAGGED_CASE
+      default: break;
+    }
+  }
 }
 
 // Copy the nodes of a set of tiles (the instances of one subset) from src to dst.
