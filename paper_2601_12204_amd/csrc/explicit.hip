@@ -116,34 +116,30 @@ constexpr int stage_nodes() { return NT * kBlockChunk / 2; }
 __device__ __forceinline__ int spad(int i) { return i + (i >> 4); }
 
 // One step of a lane's chunk: out[j] from in[j-1], in[j], in[j+1], with the neighbours' end values
-// `left` and `right`; fixed nodes keep their value.
-//
-// Every lane holds a full chunk of M nodes except the window's last lane, which holds mlast (the same
-// for the whole workgroup).  That lane's slot mlast holds its right neighbour's value (pad_last), so
-// all lanes run the same unguarded code; the results in the last lane's slots past mlast - 1 are never
-// used.  The fixed last node (fix_last, last lane only) is node mlast - 1.
+// `left` and `right`; fixed nodes (a Dirichlet end, a window edge) keep their value: they run the same
+// update with zero coefficients, which returns the node's value unchanged, so nothing branches.
 //
 // EXACT (every chunk full): the chunk's two end nodes take their own coefficients (r0, D0) and
-// (r1, D1), which are zero at a fixed node, where the update then returns the node's value unchanged;
-// nothing branches, and the interior nodes, which need no neighbour value, come first, so that they
-// run while `left` and `right` are still in flight from LDS.
+// (r1, D1), zero at a fixed node, and the interior nodes, which need no neighbour value, come first,
+// so that they run while `left` and `right` are still in flight from LDS.
 //
-// ML > 0 (the last lane's count known at compile time, 1 <= ML <= M): every lane runs the same code.
-// Node ML - 1 is the last lane's last real node: its right neighbour is `right` there and in[ML] in
-// the other lanes (one select), and it takes (r1, D1), zero only where it is a fixed node; the last
-// lane's slots past ML - 1 are computed from finite values and never used.  With ML = 1, node 0 is
-// both a first and a last node and takes (rE, DE), zero where either end is fixed.
-template <typename T, bool EXACT, int ML = 0>
+// Otherwise every lane holds a full chunk of M nodes except the last, which holds ML (the same for the
+// whole workgroup, and a compile-time constant here), and every lane runs the same code.  Node ML - 1
+// is the last lane's last real node: its right neighbour is `right` there and in[ML] in the other
+// lanes (one select), and it takes (r1, D1), zero only where it is a fixed node; the last lane's slots
+// past ML - 1 are computed from finite values and never used.  With ML = 1, node 0 is both a first and
+// a last node and takes (rE, DE), zero where either end is fixed.
+template <typename T, bool EXACT, int ML>
 __device__ __forceinline__ void chunk_step(const T (&in)[kBlockChunk], T (&out)[kBlockChunk], T left, T right,
-                                           int mlast, bool fix_first, bool fix_last, T r, T D, T r0, T D0,
-                                           T r1, T D1, bool is_last = false, T rE = T(0), T DE = T(0)) {
+                                           T r, T D, T r0, T D0, T r1, T D1, bool is_last, T rE, T DE) {
   constexpr int M = kBlockChunk;
   if constexpr (EXACT) {
 #pragma unroll
     for (int j = 1; j < M - 1; ++j) out[j] = upwind_central(in[j], in[j - 1], in[j + 1], r, D);
     out[0] = upwind_central(in[0], left, in[1], r0, D0);
     out[M - 1] = upwind_central(in[M - 1], in[M - 2], right, r1, D1);
-  } else if constexpr (ML > 0) {
+  } else {
+    static_assert(ML >= 1 && ML <= M, "ragged chunks need the last lane's count at compile time");
 #pragma unroll
     for (int j = 1; j < M; ++j)
       if (j != ML - 1) out[j] = upwind_central(in[j], in[j - 1], j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right, r, D);
@@ -155,26 +151,9 @@ __device__ __forceinline__ void chunk_step(const T (&in)[kBlockChunk], T (&out)[
       out[0] = upwind_central(in[0], left, in[1], r0, D0);
       out[ML - 1] = upwind_central(in[ML - 1], in[ML - 2], up, r1, D1);
     }
-  } else {
-    T prev = left;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const T up = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
-      const bool fixed = (j == 0 && fix_first) || (j == mlast - 1 && fix_last);
-      out[j] = fixed ? in[j] : upwind_central(in[j], prev, up, r, D);
-      prev = in[j];
-    }
   }
 }
 
-// The window's last lane (is_last) takes its right neighbour's value into slot mlast when its chunk is
-// short (see chunk_step); every branch here is uniform.
-template <typename T>
-__device__ __forceinline__ void pad_last(T (&x)[kBlockChunk], int mlast, bool is_last, T right) {
-#pragma unroll
-  for (int j = 0; j < kBlockChunk; ++j)
-    if (j == mlast) x[j] = is_last ? right : x[j];
-}
 
 // One RK4 stage of a lane's chunk (Sec. 2.7.1, eq. 22): K = increment of the stage input `in` (with
 // the neighbours' end values `left`, `right`; fixed nodes have K = 0), then by stage
@@ -345,20 +324,17 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   for (; step + 2 <= steps; step += 2) {
     exchange_ends<T, EXACT, NT, ML>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
-      if (!EXACT && ML == 0) pad_last(v, mlast, is_last, right);
-      chunk_step<T, EXACT, ML>(v, w, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1, is_last, rE, DE);
+      chunk_step<T, EXACT, ML>(v, w, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
     }
     exchange_ends<T, EXACT, NT, ML>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
-      if (!EXACT && ML == 0) pad_last(w, mlast, is_last, right);
-      chunk_step<T, EXACT, ML>(w, v, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1, is_last, rE, DE);
+      chunk_step<T, EXACT, ML>(w, v, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
     }
   }
   if (step < steps) {
     exchange_ends<T, EXACT, NT, ML>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
-      if (!EXACT && ML == 0) pad_last(v, mlast, is_last, right);
-      chunk_step<T, EXACT, ML>(v, w, left, right, mlast, fix_first, fix_last, r, D, r0, D0, r1, D1, is_last, rE, DE);
+      chunk_step<T, EXACT, ML>(v, w, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
 #pragma unroll
       for (int j = 0; j < M; ++j) v[j] = w[j];
     }
