@@ -1021,7 +1021,7 @@ __device__ __forceinline__ int block_iface_solve(const BlockIfaceSpace& w, int P
 
 // A block's chunks eliminated (rows staged in LDS) and its interface system solved; returns the buffer
 // of the final rows.  al/ga/de keep the chunk's interior rows for the recovery.
-template <typename S>
+template <bool FULL, typename S>
 __device__ __forceinline__ int block_iface_step(const BlockIfaceSpace& w, const S* stage, const InstDesc& d,
                                                 const SysDesc& sys, const ChunkBlock& cb, int rs, int Pb, int& s,
                                                 int& m, double (&al)[kRedChunk], double (&ga)[kRedChunk],
@@ -1034,6 +1034,7 @@ __device__ __forceinline__ int block_iface_step(const BlockIfaceSpace& w, const 
   m = 0;
   if (tid < Pb) {
     chunk_span(cb.chunk0 + tid, sys.rows, sys.chunks, s, m);
+    if constexpr (FULL) m = kRedChunk;         // the value chunk_span gives, as a constant
     interface_eliminate<T, kRedChunk, false>(LdsRows<S>{stage, rs, d.r, d.D, DirichletEnds{d.a, d.b, dir}}, s, m,
                                              sys.rows, al, ga, de, ia, ib, ic, id);
 #pragma unroll
@@ -1060,6 +1061,14 @@ __device__ __forceinline__ void block_rows(const SysDesc& sys, int c0, int& rs, 
   } else {
     chunk_span(c1, sys.rows, sys.chunks, re, m);
   }
+}
+
+// Every chunk of the block holds kRedChunk rows (all blocks but those holding a system's shorter last
+// chunks): the block kernels then take a body in which the row counts are compile-time constants, so
+// that no row index is selected at run time.
+__device__ __forceinline__ bool block_full(const SysDesc& sys, int c0, int Pb) {
+  const int q = sys.rows / sys.chunks, rho = sys.rows - q * sys.chunks;
+  return Pb == kReduceBlock && (q == kRedChunk || (q == kRedChunk - 1 && c0 + Pb <= rho));
 }
 
 // Partition level of a reduced system held in (A, C, D) arrays, forward half: every thread eliminates
@@ -1106,6 +1115,30 @@ __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_backsub_kernel(
   chunk_recover<T, kRedChunk>(PtrDst<T>{LX + sys.in_off}, s, m, al, ga, de, F, E);
 }
 
+// Forward half of a block-partition step after the block is staged (FULL: every chunk has kRedChunk rows).
+template <bool FULL, typename S>
+__device__ __forceinline__ void block_reduce_body(const BlockIfaceSpace& w, const S* stage, const InstDesc& d,
+                                                  const SysDesc& sys, const ChunkBlock& cb, int rs, int Pb,
+                                                  double* __restrict__ LA, double* __restrict__ LC,
+                                                  double* __restrict__ LD) {
+  using T = double;
+  const int tid = threadIdx.x;
+  int s, m;
+  T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
+  SpikeRow r;
+  const int b = block_iface_step<FULL>(w, stage, d, sys, cb, rs, Pb, s, m, al, ga, de, r);
+  if (tid == 0) {
+    // first unknown: x = de_0 - al_0 L - ga_0 y_0 with y_0 = D_0 - P_0 L - Q_0 Rt; last: y_{Pb-1}
+    const SpikeRow e = w.load(b, Pb - 1);
+    T AF, CF, DF, AE, CE, DE;
+    partition_rows(__builtin_fma(-ga[0], r.p, al[0]), -(ga[0] * r.q), __builtin_fma(-ga[0], r.d, de[0]), e.p, e.q,
+                   e.d, AF, CF, DF, AE, CE, DE);
+    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock);
+    LA[o] = AF; LC[o] = CF; LD[o] = DF;
+    LA[o + 1] = AE; LC[o + 1] = CE; LD[o + 1] = DE;
+  }
+}
+
 // Block partition, forward half (level 0 of a long system): a workgroup stages its 256 chunks' rows
 // (<= 4096) through LDS, eliminates every chunk, solves the block's interface system in spike form and
 // stores the block's two partition rows at red_off + 2 * (block index within the system).
@@ -1126,62 +1159,31 @@ __global__ __launch_bounds__(kReduceBlock, 4) void btcs_block_reduce_kernel(
   const SysDesc sys = systems[cb.sys];
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
-  const int tid = threadIdx.x;
   const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
   int rs, re;
   block_rows(sys, cb.chunk0, rs, re);
   stage_in(stage, u + d.off + (dir ? 1 : 0) + rs, re - rs);
   __syncthreads();
-  int s, m;
-  T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
-  SpikeRow r;
-  const int b = block_iface_step(w, stage, d, sys, cb, rs, Pb, s, m, al, ga, de, r);
-  if (tid == 0) {
-    // first unknown: x = de_0 - al_0 L - ga_0 y_0 with y_0 = D_0 - P_0 L - Q_0 Rt; last: y_{Pb-1}
-    const SpikeRow e = w.load(b, Pb - 1);
-    T AF, CF, DF, AE, CE, DE;
-    partition_rows(__builtin_fma(-ga[0], r.p, al[0]), -(ga[0] * r.q), __builtin_fma(-ga[0], r.d, de[0]), e.p, e.q,
-                   e.d, AF, CF, DF, AE, CE, DE);
-    const int64_t o = sys.red_off + 2 * static_cast<int64_t>(cb.chunk0 / kReduceBlock);
-    LA[o] = AF; LC[o] = CF; LD[o] = DF;
-    LA[o + 1] = AE; LC[o + 1] = CE; LD[o + 1] = DE;
-  }
+  if (block_full(sys, cb.chunk0, Pb)) block_reduce_body<true>(w, stage, d, sys, cb, rs, Pb, LA, LC, LD);
+  else block_reduce_body<false>(w, stage, d, sys, cb, rs, Pb, LA, LC, LD);
 }
 
-// Block partition, backward half: the block repeats the forward reduction (keeping its chunks'
-// elimination in registers), takes its neighbours' solved end unknowns L (the previous block's last)
-// and Rt (the next block's first; both cyclically for periodic systems), evaluates every interface
-// unknown y_t = D_t - P_t L - Q_t Rt, recovers every chunk and stores the new state coalesced (with
-// the Dirichlet nodes).
-template <typename S>
-__global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
-    const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
-    const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, S* __restrict__ out,
-    const double* __restrict__ LX) {
+
+// Backward half of a block-partition step after the block is staged (FULL: every chunk has kRedChunk rows).
+template <bool FULL, typename S>
+__device__ __forceinline__ void block_backsub_body(const BlockIfaceSpace& w, S* stage, const InstDesc& d,
+                                                   const SysDesc& sys, const ChunkBlock& cb, int rs, int re,
+                                                   int Pb, const S* __restrict__ u, S* __restrict__ out,
+                                                   const double* __restrict__ LX) {
   using T = double;
-  constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
-  constexpr int kBytes = kStageBytes > BlockIfaceSpace::kBytes ? kStageBytes : BlockIfaceSpace::kBytes;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
-  __shared__ int iface_flags[2 * kSpikeWaves];
-  S* stage = reinterpret_cast<S*>(smem);
-  T* lds = reinterpret_cast<T*>(smem);
-  const BlockIfaceSpace w{lds, lds + 3 * BlockIfaceSpace::kN, iface_flags};
-  const ChunkBlock cb = blocks[blockIdx.x];
-  const SysDesc sys = systems[cb.sys];
-  const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
   const int tid = threadIdx.x;
-  const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
   const int blk = cb.chunk0 / kReduceBlock;
   const int nblk = (sys.chunks + kReduceBlock - 1) / kReduceBlock;
-  int rs, re;
-  block_rows(sys, cb.chunk0, rs, re);
-  stage_in(stage, u + d.off + (dir ? 1 : 0) + rs, re - rs);
-  __syncthreads();
   int s, m;
   T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
   SpikeRow r;
-  const int b = block_iface_step(w, stage, d, sys, cb, rs, Pb, s, m, al, ga, de, r);
+  const int b = block_iface_step<FULL>(w, stage, d, sys, cb, rs, Pb, s, m, al, ga, de, r);
   // neighbours' end unknowns; a Dirichlet system's outer blocks have P = 0 or Q = 0 and ignore them
   const T* X = LX + sys.red_off;
   const bool periodic = !dir;
@@ -1214,6 +1216,37 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
     if (cb.chunk0 == 0) out[d.off] = static_cast<S>(d.a);
     if (cb.chunk0 + kReduceBlock >= sys.chunks) out[d.off + d.n - 1] = static_cast<S>(d.b);
   }
+}
+
+// Block partition, backward half: the block repeats the forward reduction (keeping its chunks'
+// elimination in registers), takes its neighbours' solved end unknowns L (the previous block's last)
+// and Rt (the next block's first; both cyclically for periodic systems), evaluates every interface
+// unknown y_t = D_t - P_t L - Q_t Rt, recovers every chunk and stores the new state coalesced (with
+// the Dirichlet nodes).
+template <typename S>
+__global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
+    const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
+    const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, S* __restrict__ out,
+    const double* __restrict__ LX) {
+  using T = double;
+  constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
+  constexpr int kBytes = kStageBytes > BlockIfaceSpace::kBytes ? kStageBytes : BlockIfaceSpace::kBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  __shared__ int iface_flags[2 * kSpikeWaves];
+  S* stage = reinterpret_cast<S*>(smem);
+  T* lds = reinterpret_cast<T*>(smem);
+  const BlockIfaceSpace w{lds, lds + 3 * BlockIfaceSpace::kN, iface_flags};
+  const ChunkBlock cb = blocks[blockIdx.x];
+  const SysDesc sys = systems[cb.sys];
+  const InstDesc d = inst[sys.inst];
+  const bool dir = d.bc == kDirichlet;
+  const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
+  int rs, re;
+  block_rows(sys, cb.chunk0, rs, re);
+  stage_in(stage, u + d.off + (dir ? 1 : 0) + rs, re - rs);
+  __syncthreads();
+  if (block_full(sys, cb.chunk0, Pb)) block_backsub_body<true>(w, stage, d, sys, cb, rs, re, Pb, u, out, LX);
+  else block_backsub_body<false>(w, stage, d, sys, cb, rs, re, Pb, u, out, LX);
 }
 
 // The reduced systems of a partition level, one workgroup each, in the narrowest width that holds the
