@@ -1071,20 +1071,17 @@ __device__ __forceinline__ bool block_full(const SysDesc& sys, int c0, int Pb) {
   return Pb == kReduceBlock && (q == kRedChunk || (q == kRedChunk - 1 && c0 + Pb <= rho));
 }
 
-// Partition level of a reduced system held in (A, C, D) arrays, forward half: every thread eliminates
-// one chunk and stores its two reduced rows.
-__global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_reduce_kernel(
-    const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, double* __restrict__ LA,
-    double* __restrict__ LC, double* __restrict__ LD) {
+// One chunk of a partition level held in arrays (FULL: every chunk of the workgroup has kRedChunk rows,
+// so the row count is a constant): eliminate it and store its two reduced rows ...
+template <bool FULL>
+__device__ __forceinline__ void array_reduce_chunk(const SysDesc& sys, int k, double* __restrict__ LA,
+                                                   double* __restrict__ LC, double* __restrict__ LD) {
   using T = double;
-  const ChunkBlock cb = blocks[blockIdx.x];
-  const SysDesc sys = systems[cb.sys];
-  const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
-  if (k >= sys.chunks) return;
   T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
   T AF, CF, DF, AE, CE, DE;
   int s, m;
   chunk_span(k, sys.rows, sys.chunks, s, m);
+  if constexpr (FULL) m = kRedChunk;
   RegRows<T, kRedChunk> rows;
   rows.load(LA + sys.in_off, LC + sys.in_off, LD + sys.in_off, s, m);
   chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
@@ -1093,19 +1090,17 @@ __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_reduce_kernel(
   LA[o + 1] = AE; LC[o + 1] = CE; LD[o + 1] = DE;
 }
 
-// Backward half: re-eliminate the chunk and recover its rows from the solved reduced unknowns.
-__global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_backsub_kernel(
-    const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, const double* __restrict__ LA,
-    const double* __restrict__ LC, const double* __restrict__ LD, double* __restrict__ LX) {
+// ... and, once the reduced unknowns are solved, eliminate it again and recover its rows.
+template <bool FULL>
+__device__ __forceinline__ void array_backsub_chunk(const SysDesc& sys, int k, const double* __restrict__ LA,
+                                                    const double* __restrict__ LC, const double* __restrict__ LD,
+                                                    double* __restrict__ LX) {
   using T = double;
-  const ChunkBlock cb = blocks[blockIdx.x];
-  const SysDesc sys = systems[cb.sys];
-  const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
-  if (k >= sys.chunks) return;
   T al[kRedChunk], ga[kRedChunk], de[kRedChunk];
   T AF, CF, DF, AE, CE, DE;
   int s, m;
   chunk_span(k, sys.rows, sys.chunks, s, m);
+  if constexpr (FULL) m = kRedChunk;
   const int64_t o = sys.red_off + 2 * static_cast<int64_t>(k);
   const T F = LX[o];
   const T E = LX[o + 1];
@@ -1113,6 +1108,31 @@ __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_backsub_kernel(
   rows.load(LA + sys.in_off, LC + sys.in_off, LD + sys.in_off, s, m);
   chunk_eliminate<T, kRedChunk>(rows, s, m, sys.rows, al, ga, de, AF, CF, DF, AE, CE, DE);
   chunk_recover<T, kRedChunk>(PtrDst<T>{LX + sys.in_off}, s, m, al, ga, de, F, E);
+}
+
+// Partition level of a reduced system held in (A, C, D) arrays, forward half: every thread eliminates
+// one chunk and stores its two reduced rows.
+__global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_reduce_kernel(
+    const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, double* __restrict__ LA,
+    double* __restrict__ LC, double* __restrict__ LD) {
+  const ChunkBlock cb = blocks[blockIdx.x];
+  const SysDesc sys = systems[cb.sys];
+  const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
+  if (k >= sys.chunks) return;
+  if (block_full(sys, cb.chunk0, min(kReduceBlock, sys.chunks - cb.chunk0))) array_reduce_chunk<true>(sys, k, LA, LC, LD);
+  else array_reduce_chunk<false>(sys, k, LA, LC, LD);
+}
+
+// Backward half: re-eliminate the chunk and recover its rows from the solved reduced unknowns.
+__global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_backsub_kernel(
+    const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, const double* __restrict__ LA,
+    const double* __restrict__ LC, const double* __restrict__ LD, double* __restrict__ LX) {
+  const ChunkBlock cb = blocks[blockIdx.x];
+  const SysDesc sys = systems[cb.sys];
+  const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
+  if (k >= sys.chunks) return;
+  if (block_full(sys, cb.chunk0, min(kReduceBlock, sys.chunks - cb.chunk0))) array_backsub_chunk<true>(sys, k, LA, LC, LD, LX);
+  else array_backsub_chunk<false>(sys, k, LA, LC, LD, LX);
 }
 
 // Forward half of a block-partition step after the block is staged (FULL: every chunk has kRedChunk rows).
