@@ -1281,7 +1281,11 @@ void reduced_wg_launch(const BtcsPlan::Level& lv, const InstDesc* inst, const S*
     case 128: btcs_wg_kernel<S, false, 128, kWgChunk><<<n, 128, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
     case 256: btcs_wg_kernel<S, false, 256, kWgChunk><<<n, 256, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
     default:
-      btcs_wg_kernel<S, false, kWgThreads, kWgChunk><<<n, kWgThreads, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX);
+      if (lv.wg_exact)   // the full layout as a constant: no row is selected at a run-time index
+        btcs_wg_kernel<S, false, kWgThreads, kWgChunk, true><<<n, kWgThreads, 0, st>>>(inst, sys, u, out, LA, LC, LD,
+                                                                                      LX);
+      else
+        btcs_wg_kernel<S, false, kWgThreads, kWgChunk><<<n, kWgThreads, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX);
       break;
   }
 }
@@ -1424,6 +1428,12 @@ int btcs_wg_chunks(int rows) {
 }
 
 int btcs_reduce_chunk() { return kRedChunk; }
+
+bool btcs_wg_exact(const std::vector<SysDesc>& systems) {
+  for (const SysDesc& sd : systems)
+    if (sd.rows != kWgRows || sd.chunks != kWgThreads) return false;
+  return !systems.empty();
+}
 
 int btcs_wg_lanes(const std::vector<SysDesc>& systems) {
   int lanes = 64;

@@ -329,6 +329,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     lv.n_blocks = static_cast<int32_t>(blocks.size());
     lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
     lv.wg_lanes = burgers::btcs_wg_lanes(wg_sys[l]);
+    lv.wg_exact = burgers::btcs_wg_exact(wg_sys[l]);
   }
   ctx->btcs[set] = std::move(plan);
   return BURGERS_OK;
@@ -557,6 +558,7 @@ hipError_t build_array_solve(burgers_ctx* ctx, const std::vector<std::tuple<int3
     lv.n_blocks = static_cast<int32_t>(blocks.size());
     lv.n_wg = static_cast<int32_t>(wg_sys[l].size());
     lv.wg_lanes = burgers::btcs_wg_lanes(wg_sys[l]);
+    lv.wg_exact = burgers::btcs_wg_exact(wg_sys[l]);
   }
   return hipSuccess;
 }

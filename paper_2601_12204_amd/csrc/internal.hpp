@@ -151,6 +151,7 @@ struct BtcsPlan {
     std::unique_ptr<DevBuf> wg;              // SysDesc[] of the reduced systems solved whole
     int32_t n_wg = 0;
     int32_t wg_lanes = 512;                  // workgroup width for them (64..512: their widest chunk count)
+    bool wg_exact = false;                   // every one of them has exactly 512 chunks of 16 rows
   };
   std::vector<Level> levels;                 // levels[0] reduces from the state
   int64_t level_rows = 0;                    // rows of A, C, D, X used by this plan
@@ -272,7 +273,8 @@ hipError_t launch_newton_update(const burgers_ctx* ctx, const AdjTile* tiles, in
 // btcs.hip
 int btcs_wg_capacity();                 // longest system one workgroup solves whole
 int btcs_wg_chunks(int rows);
-int btcs_wg_lanes(const std::vector<SysDesc>& systems);   // workgroup width that serves all of them           // chunk count the workgroup solver uses for `rows` rows
+int btcs_wg_lanes(const std::vector<SysDesc>& systems);
+bool btcs_wg_exact(const std::vector<SysDesc>& systems);   // all of 512 chunks x 16 rows (a constant layout)   // workgroup width that serves all of them           // chunk count the workgroup solver uses for `rows` rows
 int btcs_reduce_chunk();                // target rows per chunk in the partition levels
 constexpr int kReduceBlock = 256;       // chunks per workgroup in the partition kernels
 hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out);
