@@ -778,6 +778,36 @@ struct NewtonRows {
   __device__ __forceinline__ void boundary(int, int, int, double&, double&, double&, double&) const {}
 };
 
+// Eliminate the Jacobian's chunks, PCR, recover the increment into the staging buffer and add it to the
+// iterate in HBM (FULL: every lane holds MC rows).
+template <bool FULL, typename S, int NT, int MC>
+__device__ __forceinline__ void newton_solve(const PcrSpace<double, NT>& pcr, double* stage, const NewtonRows<S>& rows,
+                                             S* __restrict__ xs, int R, int P) {
+  using T = double;
+  const int tid = threadIdx.x;
+  T al[MC], ga[MC], de[MC];
+  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
+  int s = 0, m = 0;
+  if (tid < P) {
+    chunk_span(tid, R, P, s, m);
+    if constexpr (FULL) {
+      s = tid * MC;
+      m = MC;
+    }
+    chunk_eliminate<T, MC>(rows, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+  }
+  __syncthreads();                             // the PCR rows overlay the staged iterate
+  T F = T(0), E = T(0);
+  pcr_pairs<T, NT>(pcr, P, AF, CF, DF, AE, CE, DE, F, E);   // ends its use of the rows with a barrier
+  if (tid < P) chunk_recover<T, MC>(PtrDst<T>{stage}, s, m, al, ga, de, F, E);   // increments, unpadded
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    const int i = tid + j * NT;
+    if (i < R) xs[i] = static_cast<S>(static_cast<T>(xs[i]) + stage[i]);
+  }
+}
+
 // One Newton iteration for systems of up to NT x MC rows, one workgroup per system: stage the iterate,
 // eliminate the Jacobian's chunks, PCR, recover the increment into the staging buffer and add it to the
 // iterate in HBM (x is the output state buffer, updated in place).
@@ -815,23 +845,10 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void newton_wg_kernel(const I
     }
     return;
   }
-  T al[MC], ga[MC], de[MC];
-  T AF = T(0), CF = T(0), DF = T(0), AE = T(0), CE = T(0), DE = T(0);
-  int s = 0, m = 0;
-  if (tid < P) {
-    chunk_span(tid, R, P, s, m);
-    chunk_eliminate<T, MC>(rows, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
-  }
-  __syncthreads();                             // the PCR rows overlay the staged iterate
-  T F = T(0), E = T(0);
-  pcr_pairs<T, NT>(pcr, P, AF, CF, DF, AE, CE, DE, F, E);   // ends its use of the rows with a barrier
-  if (tid < P) chunk_recover<T, MC>(PtrDst<T>{stage}, s, m, al, ga, de, F, E);   // increments, unpadded
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < MC; ++j) {
-    const int i = tid + j * NT;
-    if (i < R) xs[i] = static_cast<S>(static_cast<T>(xs[i]) + stage[i]);
-  }
+  // every lane's chunk full (NT x MC rows): the chunk size as a constant, so no row is selected at a
+  // run-time index
+  if (R == NT * MC && P == NT) newton_solve<true, S, NT, MC>(pcr, stage, rows, xs, R, P);
+  else newton_solve<false, S, NT, MC>(pcr, stage, rows, xs, R, P);
 }
 
 // Resident solver: one workgroup keeps one system (<= 8192 rows) in registers, MC rows per lane (NT
@@ -1400,7 +1417,7 @@ hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, con
   return hipGetLastError();
 }
 
-// Width class of a system of up to 8192 rows.// Width class of a system of up to 8192 rows.  A system of exactly 8192 rows runs the exact kernels
+// Width class of a system of up to 8192 rows.  A system of exactly 8192 rows runs the exact kernels
 // (`threads` = 512 lanes of 16 rows, or 1024 of 8); any other size takes the narrowest workgroup whose
 // lanes hold at most 8 rows each, so ragged chunks never need more than 8 registers per row array.
 WidthClass btcs_width_class(int rows, int threads) {
