@@ -138,6 +138,10 @@ int64_t burgers_state_elems(const burgers_ctx* ctx);
  * Advance every instance nsteps >= 0 explicit forward-Euler steps (Sec. 2.3, eq. 21, upwind side by
  * the sign of u_i), whatever its `scheme`.  u: device state buffer in the packed layout, updated in
  * place (the final state always lands in u).  Dirichlet nodes 0 and n-1 are set to left/right.
+ * Rounding: binary64 states evaluate the same update as u_i + alpha (u_{i+1} - u_i) - beta (u_i - u_{i-1})
+ * with beta = D + max(c_i,0), alpha = D - min(c_i,0), in fused multiply-adds (every execution path
+ * gives bitwise the same result; over 10^4 CFL steps it stays within about 1e-13 of an unfused
+ * evaluation of eq. 21, relative to max |u|); binary32 states round exactly as the unfused eq. 21.
  * Errors: BURGERS_E_INVALID (NULL ctx or u, nsteps < 0), BURGERS_E_UNSUPPORTED (forced path unfit),
  * BURGERS_E_DEVICE.
  */
