@@ -183,10 +183,14 @@ __device__ __forceinline__ void rk4_apply(T (&v)[kBlockChunk], T (&out)[kBlockCh
 // EXACT (every chunk full): as in chunk_step, the two end nodes take their own coefficients (zero at a
 // fixed node, where K is then a zero) and come after the interior nodes; the four inputs the end nodes
 // read are kept first, since `out` may overwrite `in`.
-template <typename T, bool EXACT, int STAGE>
+//
+// Otherwise (ML, the last lane's count, a compile-time constant) the coefficients and the right
+// neighbour of each node are chosen as in chunk_step, in one ascending pass that keeps in[j-1] in a
+// register before out[j] may overwrite it.
+template <typename T, bool EXACT, int STAGE, int ML>
 __device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBlockChunk], T (&out)[kBlockChunk],
-                                          T (&acc)[kBlockChunk], T left, T right, int m, bool fix_first,
-                                          bool fix_last, T r, T D, T r0, T D0, T r1, T D1) {
+                                          T (&acc)[kBlockChunk], T left, T right, T r, T D, T r0, T D0, T r1,
+                                          T D1, bool is_last, T rE, T DE) {
   constexpr int M = kBlockChunk;
   if constexpr (EXACT) {
     const T i0 = in[0], i1 = in[1], i2 = in[M - 2], i3 = in[M - 1];
@@ -201,18 +205,18 @@ __device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBl
     rk4_apply<T, STAGE>(v, out, acc, 0, rk4_increment(i0, left, i1, r0, D0));
     rk4_apply<T, STAGE>(v, out, acc, M - 1, rk4_increment(i3, i2, right, r1, D1));
   } else {
+    static_assert(ML >= 1 && ML <= M, "ragged chunks need the last lane's count at compile time");
     T prev = left;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      if (j < m) {
-        T up = right;
-        if (j + 1 < M && j + 1 < m) up = in[j + 1 < M ? j + 1 : j];
-        const bool fixed = (j == 0 && fix_first) || (j == m - 1 && fix_last);
-        const T cur = in[j];
-        const T K = fixed ? T(0) : rk4_increment(cur, prev, up, r, D);
-        prev = cur;
-        rk4_apply<T, STAGE>(v, out, acc, j, K);
-      }
+      const T next = j + 1 < M ? in[j + 1 < M ? j + 1 : j] : right;
+      const T up = (j == ML - 1 && ML < M) ? (is_last ? right : next) : next;
+      const T rr = j == 0 ? (ML == 1 ? rE : r0) : (j == ML - 1 ? r1 : r);
+      const T dd = j == 0 ? (ML == 1 ? DE : D0) : (j == ML - 1 ? D1 : D);
+      const T cur = in[j];
+      const T K = rk4_increment(cur, prev, up, rr, dd);
+      prev = cur;
+      rk4_apply<T, STAGE>(v, out, acc, j, K);
     }
   }
 }
@@ -303,24 +307,24 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   const T r1 = fix_last ? T(0) : r, D1 = fix_last ? T(0) : D;
   const bool fix_either = fix_first || fix_last;
   const T rE = fix_either ? T(0) : r, DE = fix_either ? T(0) : D;
+  const bool is_last = t == P - 1;
   if constexpr (RK4) {
     // four stages per step, each after an exchange of the stage's end values (buffers alternate)
     T acc[M];
     for (int step = 0; step < steps; ++step) {
-      exchange_ends<T, EXACT, NT>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
-      if (active) rk4_stage<T, EXACT, 1>(v, v, w, acc, left, right, m, fix_first, fix_last, r, D, r0, D0, r1, D1);
-      exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
-      if (active) rk4_stage<T, EXACT, 2>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D, r0, D0, r1, D1);
-      exchange_ends<T, EXACT, NT>(w, 0, t, P, mlast, active, s_first, s_last, left, right);
-      if (active) rk4_stage<T, EXACT, 3>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D, r0, D0, r1, D1);
-      exchange_ends<T, EXACT, NT>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
-      if (active) rk4_stage<T, EXACT, 4>(v, w, w, acc, left, right, m, fix_first, fix_last, r, D, r0, D0, r1, D1);
+      exchange_ends<T, EXACT, NT, ML>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+      if (active) rk4_stage<T, EXACT, 1, ML>(v, v, w, acc, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
+      exchange_ends<T, EXACT, NT, ML>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
+      if (active) rk4_stage<T, EXACT, 2, ML>(v, w, w, acc, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
+      exchange_ends<T, EXACT, NT, ML>(w, 0, t, P, mlast, active, s_first, s_last, left, right);
+      if (active) rk4_stage<T, EXACT, 3, ML>(v, w, w, acc, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
+      exchange_ends<T, EXACT, NT, ML>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
+      if (active) rk4_stage<T, EXACT, 4, ML>(v, w, w, acc, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
     }
   } else {
   // two steps per iteration: v -> w, then w -> v (exchange buffers 0 and 1 alternate)
   int step = 0;
   // (a wave with no active lane skips the arithmetic; inside a step nothing branches on the lane)
-  const bool is_last = t == P - 1;
   for (; step + 2 <= steps; step += 2) {
     exchange_ends<T, EXACT, NT, ML>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
@@ -384,14 +388,12 @@ __global__ __launch_bounds__(NT) void explicit_block_kernel(
       return;
     }
   }
-  if constexpr (RK4) {
-    block_body<T, false, true, NT>(bt, d, src, dst, steps, stage, s_first, s_last);
-  } else {
+  {
     // the last lane's node count, uniform over the workgroup: one specialised body per count
     const int mlast = bt.width - kBlockChunk * ((bt.width + kBlockChunk - 1) / kBlockChunk - 1);
     switch (mlast) {
 #define BURGERS_RAGGED_CASE(K) \
-  case K: block_body<T, false, false, NT, K>(bt, d, src, dst, steps, stage, s_first, s_last); break;
+  case K: block_body<T, false, RK4, NT, K>(bt, d, src, dst, steps, stage, s_first, s_last); break;
       BURGERS_RAGGED_CASE(1) BURGERS_RAGGED_CASE(2) BURGERS_RAGGED_CASE(3) BURGERS_RAGGED_CASE(4)
       BURGERS_RAGGED_CASE(5) BURGERS_RAGGED_CASE(6) BURGERS_RAGGED_CASE(7) BURGERS_RAGGED_CASE(8)
       BURGERS_RAGGED_CASE(9) BURGERS_RAGGED_CASE(10) BURGERS_RAGGED_CASE(11) BURGERS_RAGGED_CASE(12)
