@@ -45,7 +45,13 @@ typedef enum {
   BURGERS_E_NOMEM = -3,       /* device allocation failed; the context stays usable */
   BURGERS_E_DEVICE = -4,      /* HIP runtime or kernel error (sticky) */
   BURGERS_E_NONFINITE = -5,   /* reserved: non-finite values reported by a checking call */
-  BURGERS_E_BUDGET = -6       /* reserved: request exceeds a memory budget */
+  BURGERS_E_BUDGET = -6,      /* reserved: request exceeds a memory budget */
+  BURGERS_E_NOT_CONVERGED = -7 /* reported by burgers_sync: since the last report, a Newton step
+                                  (BURGERS_NEWTON) met a Jacobian row that was not strictly diagonally
+                                  dominant, so its unpivoted solve was outside its stated range, or its
+                                  last iteration's increment was not small against the iterate
+                                  (1e-10 relative for binary64 states, 1e-5 for binary32); the states
+                                  hold the iterates reached; the context stays usable */
 } burgers_status;
 
 typedef enum { BURGERS_BC_PERIODIC = 0, BURGERS_BC_DIRICHLET = 1 } burgers_bc; /* eq. 18; eqs. 16-17 */
@@ -55,7 +61,9 @@ typedef enum { BURGERS_BC_PERIODIC = 0, BURGERS_BC_DIRICHLET = 1 } burgers_bc; /
    A = I + N (coefficients lagged at u^n), (I + N/2) u^{n+1} = (I - N/2) u^n; the fully implicit step
    with central convection of eqs. 10-14, F(u^{n+1}) = 0 solved by four Newton-Raphson iterations from
    u^n with the tridiagonal Jacobian of eq. 11 (no pivoting: meant for steps whose Jacobian stays
-   diagonally dominant, e.g. up to a few times the CFL step). */
+   strictly diagonally dominant, e.g. up to a few times the CFL step; every row is checked on the device
+   and burgers_sync reports BURGERS_E_NOT_CONVERGED when one is not, or when the fourth increment is not
+   at rounding level). */
 typedef enum { BURGERS_EXPLICIT = 0, BURGERS_BTCS = 1, BURGERS_RK4 = 2, BURGERS_CN = 3,
                BURGERS_NEWTON = 4 } burgers_scheme;
 typedef enum { BURGERS_F32 = 0, BURGERS_F64 = 1 } burgers_dtype;
@@ -190,7 +198,8 @@ burgers_status burgers_run_mixed(burgers_ctx* ctx, void* u, int64_t explicit_ste
 burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lambda_T, int64_t nsteps,
                                int64_t ckpt_every, void* grad_u0, void* grad_nu);
 
-/* Wait for the context's stream and return the first sticky device error, if any. */
+/* Wait for the context's stream and return the first sticky device error, if any; else
+   BURGERS_E_NOT_CONVERGED once if a Newton check failed since the last report (see burgers_status). */
 burgers_status burgers_sync(burgers_ctx* ctx);
 
 /* Read or force the kernel path selection (see burgers_plan). */

@@ -27,7 +27,8 @@ F64 = 1
 ALIGN = 64
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported request", -3: "out of device memory",
-          -4: "device error", -5: "non-finite value", -6: "memory budget exceeded"}
+          -4: "device error", -5: "non-finite value", -6: "memory budget exceeded",
+          -7: "Newton step not converged or Jacobian not diagonally dominant"}
 
 
 class BurgersError(RuntimeError):

@@ -1,10 +1,12 @@
 """Build the gfx950 shared library libburgers.so from csrc/*.hip with hipcc (cross-compiles without a GPU).
 
-Flags: contraction off (every kernel variant of a scheme rounds identically and like a plain scalar
-evaluation of the update), packed-FP32 instruction forms disabled.
+Each source compiles to an object in parallel, then one link step makes the library.  Flags:
+contraction off (every kernel variant of a scheme rounds identically and like a plain scalar evaluation
+of the update), packed-FP32 instruction forms disabled.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import glob
 import os
 import subprocess
@@ -14,6 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
+OBJDIR = os.path.join(PKG, "_build")
 ARCH = "gfx950"
 
 
@@ -28,17 +31,39 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def compile_command(out: str, extra=()) -> list:
-    sources = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+def sources() -> list:
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def compile_flags(extra=()) -> list:
+    return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
             "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-Wall", "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}", *extra, "-o", out, *sources]
+            "-Wall", "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}", *extra]
 
 
-def build(verbose: bool = False, extra=()) -> str:
+def compile_command(out: str, extra=()) -> list:
+    """One-step command (all sources, one hipcc call)."""
+    return [hipcc(), *compile_flags(extra), "-shared", "-o", out, *sources()]
+
+
+def _compile_one(src: str, extra, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.basename(src)[:-4] + ".o")
+    cmd = [hipcc(), *compile_flags(extra), "-c", "-o", obj, src]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return obj
+
+
+def build(verbose: bool = False, extra=(), jobs: int = 0) -> str:
     out = library_path()
     tmp = out + ".tmp"
-    cmd = compile_command(tmp, extra)
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = sources()
+    jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as pool:
+        objs = list(pool.map(lambda s: _compile_one(s, extra, verbose), srcs))
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -20,6 +20,7 @@
 // rate equals the non-packed binary32 rate, and this step is bound by HBM, so the wider arithmetic costs
 // nothing measurable.
 #include "internal.hpp"
+#include "newton_check.hpp"
 #include "stencil.hpp"
 
 #pragma clang fp contract(off)
@@ -761,6 +762,7 @@ struct NewtonRows {
   const S* __restrict__ u;
   double half_r, D, a, b;
   bool periodic;
+  int* flags;
   __device__ __forceinline__ void row(int, int k, int R, double& al, double& be, double& ga, double& de) const {
     const double xm = k > 0 ? st[padded(k - 1)] : (periodic ? st[padded(R - 1)] : a);
     const double xp = k < R - 1 ? st[padded(k + 1)] : (periodic ? st[padded(0)] : b);
@@ -774,15 +776,17 @@ struct NewtonRows {
       if (k == 0) al = 0.0;
       if (k == R - 1) ga = 0.0;
     }
+    newton_check_row(al, be, ga, flags);
   }
   __device__ __forceinline__ void boundary(int, int, int, double&, double&, double&, double&) const {}
 };
 
 // Eliminate the Jacobian's chunks, PCR, recover the increment into the staging buffer and add it to the
-// iterate in HBM (FULL: every lane holds MC rows).
+// iterate in HBM (FULL: every lane holds MC rows).  On the last iteration the increments are checked
+// against the iterate.
 template <bool FULL, typename S, int NT, int MC>
 __device__ __forceinline__ void newton_solve(const PcrSpace<double, NT>& pcr, double* stage, const NewtonRows<S>& rows,
-                                             S* __restrict__ xs, int R, int P) {
+                                             S* __restrict__ xs, int R, int P, bool last) {
   using T = double;
   const int tid = threadIdx.x;
   T al[MC], ga[MC], de[MC];
@@ -804,7 +808,15 @@ __device__ __forceinline__ void newton_solve(const PcrSpace<double, NT>& pcr, do
 #pragma unroll
   for (int j = 0; j < MC; ++j) {
     const int i = tid + j * NT;
-    if (i < R) xs[i] = static_cast<S>(static_cast<T>(xs[i]) + stage[i]);
+    T delta = T(0), xn = T(0), uo = T(0);
+    if (i < R) {
+      delta = stage[i];
+      const S v = static_cast<S>(static_cast<T>(xs[i]) + delta);
+      xs[i] = v;
+      xn = static_cast<T>(v);
+      if (last) uo = static_cast<T>(rows.u[i]);
+    }
+    if (last) newton_check_increment(i < R, delta, xn, uo, newton_increment_tol<S>(), rows.flags);
   }
 }
 
@@ -814,7 +826,8 @@ __device__ __forceinline__ void newton_solve(const PcrSpace<double, NT>& pcr, do
 template <typename S, int NT, int MC>
 __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void newton_wg_kernel(const InstDesc* __restrict__ inst,
                                                                          const SysDesc* __restrict__ systems,
-                                                                         const S* __restrict__ u, S* __restrict__ x) {
+                                                                         const S* __restrict__ u, S* __restrict__ x,
+                                                                         int last, int* __restrict__ flags) {
   using T = double;
   using Pcr = PcrSpace<T, NT>;
   constexpr int kStageBytes = padded_size(NT * MC) * static_cast<int>(sizeof(T));
@@ -836,19 +849,24 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void newton_wg_kernel(const I
     if (i < R) stage[padded(i)] = static_cast<T>(xs[i]);
   }
   __syncthreads();
-  const NewtonRows<S> rows{stage, u + o, d.r / 2.0, d.D, d.a, d.b, !dir};
+  const NewtonRows<S> rows{stage, u + o, d.r / 2.0, d.D, d.a, d.b, !dir, flags};
   if (R == 1) {   // a single Dirichlet unknown
     if (tid == 0) {
       T al, be, ga, de;
       rows.row(0, 0, 1, al, be, ga, de);
-      xs[0] = static_cast<S>(stage[0] + de / be);
+      const T delta = de / be;
+      const S v = static_cast<S>(stage[0] + delta);
+      xs[0] = v;
+      if (last && !(__builtin_fabs(delta) <= newton_increment_tol<S>() *
+                    __builtin_fmax(__builtin_fabs(static_cast<T>(v)), __builtin_fabs(static_cast<T>(rows.u[0])))))
+        flags[1] = 1;
     }
     return;
   }
   // every lane's chunk full (NT x MC rows): the chunk size as a constant, so no row is selected at a
   // run-time index
-  if (R == NT * MC && P == NT) newton_solve<true, S, NT, MC>(pcr, stage, rows, xs, R, P);
-  else newton_solve<false, S, NT, MC>(pcr, stage, rows, xs, R, P);
+  if (R == NT * MC && P == NT) newton_solve<true, S, NT, MC>(pcr, stage, rows, xs, R, P, last != 0);
+  else newton_solve<false, S, NT, MC>(pcr, stage, rows, xs, R, P, last != 0);
 }
 
 // Resident solver: one workgroup keeps one system (<= 8192 rows) in registers, MC rows per lane (NT
@@ -1397,23 +1415,26 @@ hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, vo
 }
 
 template <typename S>
-void newton_launch(const burgers_ctx* ctx, const WgGroup& g, const S* u, S* x) {
+void newton_launch(const burgers_ctx* ctx, const WgGroup& g, const S* u, S* x, int last, int* flags) {
   const InstDesc* inst = ctx->inst.as<InstDesc>();
   const SysDesc* sys = g.sys->as<SysDesc>();
   const unsigned n = static_cast<unsigned>(g.n);
   hipStream_t st = ctx->stream;
   switch (g.shape.lanes) {   // chunks of at most 8 rows in every class (8192 rows: 1024 lanes)
-    case 128: newton_wg_kernel<S, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, x); break;
-    case 256: newton_wg_kernel<S, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, x); break;
-    case 512: newton_wg_kernel<S, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, x); break;
-    default: newton_wg_kernel<S, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, x); break;
+    case 128: newton_wg_kernel<S, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, x, last, flags); break;
+    case 256: newton_wg_kernel<S, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, x, last, flags); break;
+    case 512: newton_wg_kernel<S, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, x, last, flags); break;
+    default: newton_wg_kernel<S, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, x, last, flags); break;
   }
 }
 
-hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, const void* u, void* x) {
+hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, const void* u, void* x, bool last,
+                               int* flags) {
   if (group.n <= 0) return hipSuccess;
-  if (ctx->dtype == BURGERS_F64) newton_launch<double>(ctx, group, static_cast<const double*>(u), static_cast<double*>(x));
-  else newton_launch<float>(ctx, group, static_cast<const float*>(u), static_cast<float*>(x));
+  if (ctx->dtype == BURGERS_F64)
+    newton_launch<double>(ctx, group, static_cast<const double*>(u), static_cast<double*>(x), last ? 1 : 0, flags);
+  else
+    newton_launch<float>(ctx, group, static_cast<const float*>(u), static_cast<float*>(x), last ? 1 : 0, flags);
   return hipGetLastError();
 }
 

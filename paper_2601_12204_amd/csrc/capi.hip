@@ -417,15 +417,18 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
       const burgers::AdjTile* nt = np.tiles->as<burgers::AdjTile>();
       if ((e = burgers::launch_newton_init(ctx, nt, np.n_tiles, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
       const burgers::AdjTile* lt = np.long_tiles->as<burgers::AdjTile>();
+      int* flags = np.flags.as<int>();
       for (int it = 0; it < burgers::kNewtonIters; ++it) {
+        const bool last = it == burgers::kNewtonIters - 1;
         for (const burgers::WgGroup& g : np.whole)
-          if ((e = burgers::launch_newton_whole(ctx, g, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+          if ((e = burgers::launch_newton_whole(ctx, g, bufs[cur], bufs[cur ^ 1], last, flags)) != hipSuccess) return e;
         if (np.n_long_tiles == 0) continue;
         if ((e = burgers::launch_newton_assemble(ctx, lt, np.n_long_tiles, bufs[cur], bufs[cur ^ 1], np.NA.as<double>(),
-                                                 np.NC.as<double>(), np.ND.as<double>())) != hipSuccess ||
+                                                 np.NC.as<double>(), np.ND.as<double>(), flags)) != hipSuccess ||
             (e = burgers::launch_array_solve(ctx, np.solve, np.NA.as<double>(), np.NC.as<double>(), np.ND.as<double>(),
                                              np.NX.as<double>())) != hipSuccess ||
-            (e = burgers::launch_newton_update(ctx, lt, np.n_long_tiles, bufs[cur ^ 1], np.NX.as<double>())) != hipSuccess)
+            (e = burgers::launch_newton_update(ctx, lt, np.n_long_tiles, bufs[cur], bufs[cur ^ 1], np.NX.as<double>(),
+                                               last, flags)) != hipSuccess)
           return e;
       }
     }
@@ -611,7 +614,9 @@ burgers_status ensure_newton(burgers_ctx* ctx, const std::vector<int32_t>& membe
   if ((e = build_array_solve(ctx, roots, np->solve, rows_used)) != hipSuccess) return from_hip(e);
   const size_t lb = static_cast<size_t>(rows_used) * sizeof(double);
   if ((e = np->NA.alloc(lb, ctx->stream)) != hipSuccess || (e = np->NC.alloc(lb, ctx->stream)) != hipSuccess ||
-      (e = np->ND.alloc(lb, ctx->stream)) != hipSuccess || (e = np->NX.alloc(lb, ctx->stream)) != hipSuccess)
+      (e = np->ND.alloc(lb, ctx->stream)) != hipSuccess || (e = np->NX.alloc(lb, ctx->stream)) != hipSuccess ||
+      (e = np->flags.alloc(2 * sizeof(int), ctx->stream)) != hipSuccess ||
+      (e = hipMemsetAsync(np->flags.ptr, 0, 2 * sizeof(int), ctx->stream)) != hipSuccess)
     return from_hip(e);
   ctx->newton = std::move(np);
   return BURGERS_OK;
@@ -705,6 +710,7 @@ const char* burgers_status_string(burgers_status s) {
     case BURGERS_E_DEVICE: return "device error";
     case BURGERS_E_NONFINITE: return "non-finite value";
     case BURGERS_E_BUDGET: return "memory budget exceeded";
+    case BURGERS_E_NOT_CONVERGED: return "Newton step not converged or Jacobian not diagonally dominant";
   }
   return "unknown status";
 }
@@ -970,7 +976,19 @@ burgers_status burgers_sync(burgers_ctx* ctx) {
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e == hipSuccess) e = hipGetLastError();
   note(ctx, e);
-  return from_hip(ctx->sticky);
+  if (ctx->sticky != hipSuccess) return from_hip(ctx->sticky);
+  if (ctx->newton && ctx->newton->flags.ptr) {
+    // checks of the Newton steps since the last report; cleared once reported
+    int flags[2] = {0, 0};
+    e = hipMemcpy(flags, ctx->newton->flags.ptr, sizeof(flags), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && (flags[0] || flags[1])) {
+      e = hipMemsetAsync(ctx->newton->flags.ptr, 0, sizeof(flags), ctx->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+      if (e == hipSuccess) return BURGERS_E_NOT_CONVERGED;
+    }
+    if (e != hipSuccess) return note(ctx, e);
+  }
+  return BURGERS_OK;
 }
 
 burgers_status burgers_get_plan(const burgers_ctx* ctx, burgers_plan* out) {

@@ -201,6 +201,7 @@ struct NewtonPlan {
   int64_t n_long_tiles = 0;
   BtcsPlan solve;                                   // partition hierarchy over the longer systems
   DevBuf NA, NC, ND, NX;
+  DevBuf flags;                                     // int32[2]: dominance lost, not converged (read by burgers_sync)
 };
 
 }  // namespace burgers
@@ -265,10 +266,12 @@ hipError_t launch_zero_dirichlet_ends(const burgers_ctx* ctx, double* g);
 
 // newton.hip
 hipError_t launch_newton_init(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const void* u, void* x);
+// Jacobian rows and -F (checked for strict diagonal dominance into flags[0]); the update x += delta,
+// whose increments are checked against the iterate into flags[1] when `last`.
 hipError_t launch_newton_assemble(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const void* u,
-                                  const void* x, double* NA, double* NC, double* ND);
-hipError_t launch_newton_update(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, void* x,
-                                const double* NX);
+                                  const void* x, double* NA, double* NC, double* ND, int* flags);
+hipError_t launch_newton_update(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const void* u,
+                                void* x, const double* NX, bool last, int* flags);
 
 // btcs.hip
 int btcs_wg_capacity();                 // longest system one workgroup solves whole
@@ -279,7 +282,8 @@ int btcs_reduce_chunk();                // target rows per chunk in the partitio
 constexpr int kReduceBlock = 256;       // chunks per workgroup in the partition kernels
 hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out);
 hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, void* u, int steps);
-hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, const void* u, void* x);
+hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, const void* u, void* x, bool last,
+                               int* flags);
 WidthClass btcs_width_class(int rows, int threads);
 int btcs_chunks(int rows, int threads);
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,

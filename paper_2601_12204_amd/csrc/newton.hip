@@ -9,6 +9,7 @@
 // Dirichlet nodes are fixed (delta = 0) and enter F as known neighbours.  The iterate x lives in the
 // output state buffer, in the state's type.
 #include "internal.hpp"
+#include "newton_check.hpp"
 
 #pragma clang fp contract(off)
 
@@ -36,7 +37,8 @@ __global__ __launch_bounds__(kNewtonThreads) void newton_init_kernel(const InstD
 template <typename S>
 __global__ __launch_bounds__(kNewtonThreads) void newton_assemble_kernel(
     const InstDesc* __restrict__ inst, const AdjTile* __restrict__ tiles, const S* __restrict__ u,
-    const S* __restrict__ x, double* __restrict__ NA, double* __restrict__ NC, double* __restrict__ ND) {
+    const S* __restrict__ x, double* __restrict__ NA, double* __restrict__ NC, double* __restrict__ ND,
+    int* __restrict__ flags) {
   const AdjTile t = tiles[blockIdx.x];
   const int n = t.n;
   const int i = t.start + static_cast<int>(threadIdx.x);
@@ -65,16 +67,20 @@ __global__ __launch_bounds__(kNewtonThreads) void newton_assemble_kernel(
     if (k == 0) sub = 0.0;
     if (k == m - 1) sup = 0.0;
   }
+  newton_check_row(sub, diag, sup, flags);
   const int64_t o = t.sys_off + k;
   NA[o] = sub / diag;
   NC[o] = sup / diag;
   ND[o] = -F / diag;
 }
 
+// x += delta on the unknowns; on the last iteration the increments are checked against the iterate
+// (every lane takes part in the wave's reduction).
 template <typename S>
 __global__ __launch_bounds__(kNewtonThreads) void newton_update_kernel(const AdjTile* __restrict__ tiles,
-                                                                       S* __restrict__ x,
-                                                                       const double* __restrict__ NX) {
+                                                                       const S* __restrict__ u, S* __restrict__ x,
+                                                                       const double* __restrict__ NX, int last,
+                                                                       int* __restrict__ flags) {
   const AdjTile t = tiles[blockIdx.x];
   const int n = t.n;
   const int i = t.start + static_cast<int>(threadIdx.x);
@@ -82,8 +88,16 @@ __global__ __launch_bounds__(kNewtonThreads) void newton_update_kernel(const Adj
   const int first = periodic ? 0 : 1;
   const int m = periodic ? n : n - 2;
   const int k = i - first;
-  if (i >= n || k < 0 || k >= m) return;
-  x[t.off + i] = static_cast<S>(static_cast<double>(x[t.off + i]) + NX[t.sys_off + k]);
+  const bool active = i < n && k >= 0 && k < m;
+  double delta = 0.0, xn = 0.0, uo = 0.0;
+  if (active) {
+    delta = NX[t.sys_off + k];
+    const S v = static_cast<S>(static_cast<double>(x[t.off + i]) + delta);
+    x[t.off + i] = v;
+    xn = static_cast<double>(v);
+    if (last) uo = static_cast<double>(u[t.off + i]);
+  }
+  if (last) newton_check_increment(active, delta, xn, uo, newton_increment_tol<S>(), flags);
 }
 
 }  // namespace
@@ -101,26 +115,28 @@ hipError_t launch_newton_init(const burgers_ctx* ctx, const AdjTile* tiles, int6
 }
 
 hipError_t launch_newton_assemble(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const void* u,
-                                  const void* x, double* NA, double* NC, double* ND) {
+                                  const void* x, double* NA, double* NC, double* ND, int* flags) {
   if (n_tiles <= 0) return hipSuccess;
   const unsigned g = static_cast<unsigned>(n_tiles);
   if (ctx->dtype == BURGERS_F64)
     newton_assemble_kernel<double><<<g, kNewtonThreads, 0, ctx->stream>>>(
-        ctx->inst.as<InstDesc>(), tiles, static_cast<const double*>(u), static_cast<const double*>(x), NA, NC, ND);
+        ctx->inst.as<InstDesc>(), tiles, static_cast<const double*>(u), static_cast<const double*>(x), NA, NC, ND, flags);
   else
     newton_assemble_kernel<float><<<g, kNewtonThreads, 0, ctx->stream>>>(
-        ctx->inst.as<InstDesc>(), tiles, static_cast<const float*>(u), static_cast<const float*>(x), NA, NC, ND);
+        ctx->inst.as<InstDesc>(), tiles, static_cast<const float*>(u), static_cast<const float*>(x), NA, NC, ND, flags);
   return hipGetLastError();
 }
 
-hipError_t launch_newton_update(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, void* x,
-                                const double* NX) {
+hipError_t launch_newton_update(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const void* u,
+                                void* x, const double* NX, bool last, int* flags) {
   if (n_tiles <= 0) return hipSuccess;
   const unsigned g = static_cast<unsigned>(n_tiles);
   if (ctx->dtype == BURGERS_F64)
-    newton_update_kernel<double><<<g, kNewtonThreads, 0, ctx->stream>>>(tiles, static_cast<double*>(x), NX);
+    newton_update_kernel<double><<<g, kNewtonThreads, 0, ctx->stream>>>(
+        tiles, static_cast<const double*>(u), static_cast<double*>(x), NX, last ? 1 : 0, flags);
   else
-    newton_update_kernel<float><<<g, kNewtonThreads, 0, ctx->stream>>>(tiles, static_cast<float*>(x), NX);
+    newton_update_kernel<float><<<g, kNewtonThreads, 0, ctx->stream>>>(
+        tiles, static_cast<const float*>(u), static_cast<float*>(x), NX, last ? 1 : 0, flags);
   return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_status_strings(lib):
     import paper_2601_12204_amd as B
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         assert B.burgers_status_string(code) == B.STATUS[code]
 
 

@@ -93,3 +93,50 @@ def test_autograd_function():
     s.close()
     assert oracle.rel_max_abs(g, rg) <= TOL
     assert np.max(np.abs(nu.grad.cpu().numpy() - rgn) / np.maximum(np.abs(rgn), 1e-300)) <= 1e-10
+
+
+@pytest.mark.parametrize("scheme", [W.EXPLICIT, W.BTCS])
+def test_c5_adjoint_full_size_sampled(scheme):
+    """The gradient workload at its real size, in the benchmark's configuration: 256 periodic instances
+    of N = 16384 (FP64), 2000 steps (forward Euler at the CFL step, or BTCS at 10x), checkpoints every 100
+    steps, loss 1/2 |u_T - target|^2 with the target the forward solution from a second seeded initial
+    state.  Instances are independent, so sampled instances are recomputed by the oracle's adjoint:
+    dJ/du_T = u_T - target of those instances comes from the oracle's own forward runs; the other
+    instances get seeded values (their gradients are not checked)."""
+    import torch
+    import paper_2601_12204_amd as B
+    first, second = W.adjoint_batch(256, 16384, scheme=scheme)
+    f = 1.0 if scheme == W.EXPLICIT else 10.0
+    for i, (p, q) in enumerate(zip(first.problems, second.problems)):
+        p.dt = f * oracle.cfl_dt(p.n, p.length, p.nu, p.bc, float(first.umax[i]), 0.5)
+        q.dt = p.dt
+    nsteps, ckpt = 2000, 100
+    sample = [0, 129, 255]
+    sub, sub_t = W.subset(first, sample), W.subset(second, sample)
+    lam_sub = (oracle.run(sub.problems, sub.u0, sub.offsets, nsteps, threads=len(sample))
+               - oracle.run(sub_t.problems, sub_t.u0, sub_t.offsets, nsteps, threads=len(sample)))
+    lam = np.random.default_rng(77).standard_normal(len(first.u0))
+    for k, b in enumerate(sample):
+        lam[first.offsets[b]:first.offsets[b + 1]] = lam_sub[sub.offsets[k]:sub.offsets[k + 1]]
+    announce(f"C5 adjoint 256 x 16384 scheme={scheme} {nsteps} steps ckpt {ckpt}")
+    s = B.Solver(first.problems, dtype=torch.float64)
+    try:
+        u0 = s.pack_flat(first.u0, first.offsets)
+        lt = s.pack_flat(lam, first.offsets)
+        g = torch.zeros_like(u0)
+        gn = torch.zeros(first.count, dtype=torch.float64, device="cuda")
+        B.adjoint_into(s, u0, lt, nsteps, ckpt, g, gn)
+        s.sync()
+        g_host = s.unpack_flat(g)
+        gn_host = gn.cpu().numpy()
+    finally:
+        s.close()
+    rg, rgn = oracle.adjoint(sub.problems, sub.u0, sub.offsets, lam_sub, nsteps, threads=len(sample))
+    for k, b in enumerate(sample):
+        got = g_host[first.offsets[b]:first.offsets[b + 1]]
+        ref = rg[sub.offsets[k]:sub.offsets[k + 1]]
+        err = oracle.rel_max_abs(got, ref)
+        nu_err = abs(gn_host[b] - rgn[k]) / abs(rgn[k])
+        announce(f"C5 adjoint scheme={scheme} instance {b}: dJ/du0 rel {err:.3e}, dJ/dnu rel {nu_err:.3e}")
+        assert err <= TOL, (b, err)
+        assert nu_err <= 1e-10, (b, gn_host[b], rgn[k])
