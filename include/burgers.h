@@ -198,6 +198,27 @@ burgers_status burgers_run_mixed(burgers_ctx* ctx, void* u, int64_t explicit_ste
 burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lambda_T, int64_t nsteps,
                                int64_t ckpt_every, void* grad_u0, void* grad_nu);
 
+/*
+ * For callers that cannot allocate device memory (tight serving loops, harnesses that forbid hipMalloc):
+ * burgers_run over a batch without a context.  Advances the `count` problems nsteps >= 0 steps of each
+ * one's own scheme (as burgers_create + burgers_run + burgers_destroy would, with the same kernels and
+ * results), enqueued on hip_stream of the current device, and returns without waiting.  u is the
+ * caller's device state in the packed layout of burgers_offsets (instance starts aligned to
+ * BURGERS_ALIGN elements), of element type dtype, updated in place.
+ * Memory: the call allocates no device memory.  Its workspace (the instance and launch tables, the second
+ * state buffer of ping-pong stepping and the reduced systems of long BTCS systems) lives in a static
+ * device array of BURGERS_STATIC_SCRATCH_BYTES, one per GPU the library runs on, held until the process
+ * ends.  Every call on a GPU reuses that GPU's array: calls on one stream are ordered, but calls that
+ * overlap on one GPU (other streams, other threads) race and corrupt each other's results.  Nothing in
+ * the array needs to start at zero.  Launches are eager (no graph).
+ * Errors: BURGERS_E_INVALID (as burgers_create and burgers_run), BURGERS_E_BUDGET when the workspace
+ * would exceed BURGERS_STATIC_SCRATCH_BYTES (nothing is run), BURGERS_E_UNSUPPORTED for Newton instances
+ * (their checks report through burgers_sync of a context), BURGERS_E_DEVICE.
+ */
+#define BURGERS_STATIC_SCRATCH_BYTES (64u << 20)
+burgers_status burgers_run_static(const burgers_problem* problems, int64_t count, burgers_dtype dtype,
+                                  void* hip_stream, void* u, int64_t nsteps);
+
 /* Wait for the context's stream and return the first sticky device error, if any; else
    BURGERS_E_NOT_CONVERGED once if a Newton check failed since the last report (see burgers_status). */
 burgers_status burgers_sync(burgers_ctx* ctx);

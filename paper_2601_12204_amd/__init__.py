@@ -54,7 +54,10 @@ EXPORTS = ["burgers_create", "burgers_destroy", "burgers_offsets", "burgers_stat
            "burgers_step_explicit", "burgers_step_btcs", "burgers_run", "burgers_run_mixed",
            "burgers_adjoint", "burgers_sync",
            "burgers_get_plan", "burgers_set_plan", "burgers_status_string", "burgers_cfl_dt",
-           "burgers_ratios", "burgers_abi_version", "burgers_autotune"]
+           "burgers_ratios", "burgers_abi_version", "burgers_autotune", "burgers_run_static"]
+
+# workspace of burgers_run_static (BURGERS_STATIC_SCRATCH_BYTES in include/burgers.h)
+STATIC_SCRATCH_BYTES = 64 << 20
 
 
 def load() -> ctypes.CDLL:
@@ -102,6 +105,8 @@ def load() -> ctypes.CDLL:
     lib.burgers_ratios.restype = ctypes.c_int
     lib.burgers_autotune.argtypes = [vp, vp, i64, i64, P(CPlan), P(dbl)]
     lib.burgers_autotune.restype = ctypes.c_int
+    lib.burgers_run_static.argtypes = [P(CProblem), i64, ctypes.c_int, vp, vp, i64]
+    lib.burgers_run_static.restype = ctypes.c_int
     lib.burgers_abi_version.argtypes = []
     lib.burgers_abi_version.restype = i32
     _lib = lib
@@ -205,6 +210,31 @@ def burgers_run_mixed(ctx, u, explicit_steps: int, btcs_steps: int) -> None:
 def burgers_adjoint(ctx, u0, lambda_T, nsteps: int, ckpt_every: int, grad_u0, grad_nu) -> None:
     _check(load().burgers_adjoint(ctx, _ptr(u0), _ptr(lambda_T), int(nsteps), int(ckpt_every),
                                   _ptr(grad_u0), _ptr(grad_nu)), "burgers_adjoint")
+
+
+def burgers_run_static(problems: Sequence, u, nsteps: int, dtype=None, stream=None) -> None:
+    """burgers_run over a batch without a context; allocates no device memory (the library's static
+    scratch holds the workspace).  u: device tensor in the packed layout (``packed_offsets``)."""
+    import torch
+    arr = (CProblem * len(problems))(*[to_cproblem(p) for p in problems])
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    code = _dtype_code(u.dtype if dtype is None else dtype)
+    want = torch.float64 if code == F64 else torch.float32
+    need = int(packed_offsets(problems)[-1])
+    if not (u.is_cuda and u.dtype == want and u.is_contiguous() and u.numel() >= need):
+        raise ValueError(f"state must be a contiguous device tensor of {want} with >= {need} elements")
+    _check(load().burgers_run_static(arr, len(problems), code, ctypes.c_void_p(stream), _ptr(u), int(nsteps)),
+           "burgers_run_static")
+
+
+def packed_offsets(problems: Sequence) -> np.ndarray:
+    """The packed layout's count+1 offsets (instance starts aligned to ALIGN elements), as
+    burgers_offsets gives them for a context over the same problems."""
+    n = np.array([int(p.n) for p in problems], dtype=np.int64)
+    off = np.zeros(len(n) + 1, dtype=np.int64)
+    off[1:] = np.cumsum((n + ALIGN - 1) // ALIGN * ALIGN)
+    return off
 
 
 def burgers_sync(ctx) -> None:

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <tuple>
 
@@ -695,49 +696,10 @@ hipError_t enqueue_adjoint_step(burgers_ctx* ctx, const double* y, const double*
                                          ap.LX.as<double>(), lam_out, g);
 }
 
-}  // namespace
-
-extern "C" {
-
-int32_t burgers_abi_version(void) { return BURGERS_ABI_VERSION; }
-
-const char* burgers_status_string(burgers_status s) {
-  switch (s) {
-    case BURGERS_OK: return "ok";
-    case BURGERS_E_INVALID: return "invalid argument";
-    case BURGERS_E_UNSUPPORTED: return "unsupported request";
-    case BURGERS_E_NOMEM: return "out of device memory";
-    case BURGERS_E_DEVICE: return "device error";
-    case BURGERS_E_NONFINITE: return "non-finite value";
-    case BURGERS_E_BUDGET: return "memory budget exceeded";
-    case BURGERS_E_NOT_CONVERGED: return "Newton step not converged or Jacobian not diagonally dominant";
-  }
-  return "unknown status";
-}
-
-double burgers_cfl_dt(const burgers_problem* p, double umax, double sigma) {
-  if (!p || p->n < 3 || !(p->length > 0) || !is_finite(p->length) || !(p->nu >= 0) ||
-      !(sigma > 0) || !(umax >= 0) || (p->bc != BURGERS_BC_PERIODIC && p->bc != BURGERS_BC_DIRICHLET))
-    return NAN;
-  const double dx = grid_dx(*p);
-  double lim = INFINITY;
-  if (umax > 0) lim = std::min(lim, dx / umax);
-  if (p->nu > 0) lim = std::min(lim, dx * dx / (2.0 * p->nu));
-  return sigma * lim;
-}
-
-burgers_status burgers_ratios(const burgers_problem* p, double* r, double* D) {
-  if (!p || !r || !D || !valid_problem(*p)) return BURGERS_E_INVALID;
-  const double dx = grid_dx(*p);
-  *r = p->dt / dx;
-  *D = p->nu * p->dt / (dx * dx);
-  return BURGERS_OK;
-}
-
-burgers_status burgers_create(const burgers_problem* problems, int64_t count, burgers_dtype dtype,
-                              void* hip_stream, burgers_ctx** out) {
-  if (!out) return BURGERS_E_INVALID;
-  *out = nullptr;
+// A context for `count` problems on the current device: validated, laid out, its workspace allocated
+// (or carved from the installed arena).  *out is set only on success.
+burgers_status new_context(const burgers_problem* problems, int64_t count, burgers_dtype dtype, void* hip_stream,
+                           burgers_ctx** out) {
   if (!problems || count < 1 || (dtype != BURGERS_F32 && dtype != BURGERS_F64))
     return BURGERS_E_INVALID;
   for (int64_t i = 0; i < count; ++i)
@@ -796,6 +758,87 @@ burgers_status burgers_create(const burgers_problem* problems, int64_t count, bu
   return BURGERS_OK;
 }
 
+// ---- Static scratch: the workspace of burgers_run_static -------------------------------------------
+// A file-scope device array, one copy per GPU the library runs on, held until the process ends.  Host
+// code never passes the array's name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): its device address is looked up once per device with that device current, and every use
+// goes through that address.
+__device__ __align__(256) unsigned char scratch[BURGERS_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+void* scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_ptr[device] = p;
+  }
+  *out = scratch_ptr[device];
+  return hipSuccess;
+}
+
+// Installs an arena on the calling thread for the lifetime of the guard.
+struct ArenaGuard {
+  explicit ArenaGuard(burgers::Arena* a) { burgers::tl_arena = a; }
+  ~ArenaGuard() { burgers::tl_arena = nullptr; }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t burgers_abi_version(void) { return BURGERS_ABI_VERSION; }
+
+const char* burgers_status_string(burgers_status s) {
+  switch (s) {
+    case BURGERS_OK: return "ok";
+    case BURGERS_E_INVALID: return "invalid argument";
+    case BURGERS_E_UNSUPPORTED: return "unsupported request";
+    case BURGERS_E_NOMEM: return "out of device memory";
+    case BURGERS_E_DEVICE: return "device error";
+    case BURGERS_E_NONFINITE: return "non-finite value";
+    case BURGERS_E_BUDGET: return "memory budget exceeded";
+    case BURGERS_E_NOT_CONVERGED: return "Newton step not converged or Jacobian not diagonally dominant";
+  }
+  return "unknown status";
+}
+
+double burgers_cfl_dt(const burgers_problem* p, double umax, double sigma) {
+  if (!p || p->n < 3 || !(p->length > 0) || !is_finite(p->length) || !(p->nu >= 0) ||
+      !(sigma > 0) || !(umax >= 0) || (p->bc != BURGERS_BC_PERIODIC && p->bc != BURGERS_BC_DIRICHLET))
+    return NAN;
+  const double dx = grid_dx(*p);
+  double lim = INFINITY;
+  if (umax > 0) lim = std::min(lim, dx / umax);
+  if (p->nu > 0) lim = std::min(lim, dx * dx / (2.0 * p->nu));
+  return sigma * lim;
+}
+
+burgers_status burgers_ratios(const burgers_problem* p, double* r, double* D) {
+  if (!p || !r || !D || !valid_problem(*p)) return BURGERS_E_INVALID;
+  const double dx = grid_dx(*p);
+  *r = p->dt / dx;
+  *D = p->nu * p->dt / (dx * dx);
+  return BURGERS_OK;
+}
+
+burgers_status burgers_create(const burgers_problem* problems, int64_t count, burgers_dtype dtype,
+                              void* hip_stream, burgers_ctx** out) {
+  if (!out) return BURGERS_E_INVALID;
+  *out = nullptr;
+  burgers_ctx* ctx = nullptr;
+  burgers_status st = new_context(problems, count, dtype, hip_stream, &ctx);
+  if (st == BURGERS_OK) *out = ctx;
+  return st;
+}
+
 void burgers_destroy(burgers_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
@@ -828,6 +871,35 @@ burgers_status burgers_run(burgers_ctx* ctx, void* u, int64_t nsteps) {
 burgers_status burgers_run_mixed(burgers_ctx* ctx, void* u, int64_t explicit_steps, int64_t btcs_steps) {
   if (btcs_steps < 0) return BURGERS_E_INVALID;
   return advance(ctx, u, explicit_steps, kSetAll, -1, btcs_steps);
+}
+
+burgers_status burgers_run_static(const burgers_problem* problems, int64_t count, burgers_dtype dtype,
+                                  void* hip_stream, void* u, int64_t nsteps) {
+  if (!problems || !u || nsteps < 0 || count < 1 || count > INT32_MAX ||
+      (dtype != BURGERS_F32 && dtype != BURGERS_F64))
+    return BURGERS_E_INVALID;
+  for (int64_t i = 0; i < count; ++i)
+    if (!valid_problem(problems[i])) return BURGERS_E_INVALID;
+  for (int64_t i = 0; i < count; ++i)
+    if (problems[i].scheme == BURGERS_NEWTON) return BURGERS_E_UNSUPPORTED;
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return BURGERS_E_DEVICE;
+  void* base = nullptr;
+  if ((e = scratch_address(device, &base)) != hipSuccess) return BURGERS_E_DEVICE;
+  burgers::Arena arena{static_cast<char*>(base), static_cast<size_t>(BURGERS_STATIC_SCRATCH_BYTES), 0};
+  burgers_status st;
+  {
+    ArenaGuard guard(&arena);
+    burgers_ctx* ctx = nullptr;
+    st = new_context(problems, count, dtype, hip_stream, &ctx);
+    if (st == BURGERS_OK) {
+      st = advance(ctx, u, nsteps, kSetAll, -1);   // plan tables carved too; eager launches
+      if (st == BURGERS_OK && ctx->sticky != hipSuccess) st = from_hip(ctx->sticky);
+      delete ctx;                                  // host side only: carved buffers free nothing
+    }
+  }
+  return st == BURGERS_E_NOMEM ? BURGERS_E_BUDGET : st;
 }
 
 burgers_status burgers_autotune(burgers_ctx* ctx, const void* u, int64_t explicit_steps, int64_t btcs_steps,

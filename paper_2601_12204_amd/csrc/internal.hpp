@@ -86,25 +86,46 @@ struct ChunkBlock {
   int32_t chunk0;
 };
 
+// A fixed device region that buffers are carved from instead of allocated (the entry point that
+// allocates nothing): while a thread has one installed, DevBuf::alloc takes 256-byte-aligned pieces of
+// it in order and fails with hipErrorOutOfMemory once it is used up; carved pieces are never freed.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+inline thread_local Arena* tl_arena = nullptr;
+
 // Device buffer owned by a context, allocated and released in stream order on the context's stream:
 // hipFree would synchronise the whole device and stall every other context's work in flight.
 struct DevBuf {
   void* ptr = nullptr;
   size_t bytes = 0;
   hipStream_t stream = nullptr;
+  bool carved = false;   // a piece of an Arena: nothing to free
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (ptr) (void)hipFreeAsync(ptr, stream);
+    if (ptr && !carved) (void)hipFreeAsync(ptr, stream);
     ptr = nullptr;
     bytes = 0;
+    carved = false;
   }
   hipError_t alloc(size_t n, hipStream_t s) {
     release();
     stream = s;
     if (!n) return hipSuccess;
+    if (Arena* a = tl_arena) {
+      const size_t at = (a->used + 255) & ~static_cast<size_t>(255);
+      if (at > a->cap || n > a->cap - at) return hipErrorOutOfMemory;
+      ptr = a->base + at;
+      a->used = at + n;
+      bytes = n;
+      carved = true;
+      return hipSuccess;
+    }
     hipError_t e = hipMallocAsync(&ptr, n, s);
     if (e != hipSuccess) {
       ptr = nullptr;

@@ -94,6 +94,27 @@ def test_null_context_calls_are_invalid(lib):
     assert lib.burgers_get_plan(None, plan) == -1
 
 
+def test_run_static_rejects_invalid_arguments_without_a_device(lib):
+    """The allocation-free entry point validates everything before it touches the device."""
+    import ctypes
+    import paper_2601_12204_amd as B
+    good = W.Problem(n=16, length=1.0, nu=0.01, dt=1e-3)
+    arr = (B.CProblem * 1)(B.to_cproblem(good))
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails its checks first
+    assert lib.burgers_run_static(None, 1, B.F64, None, dummy, 1) == -1
+    assert lib.burgers_run_static(arr, 0, B.F64, None, dummy, 1) == -1
+    assert lib.burgers_run_static(arr, 1, 7, None, dummy, 1) == -1
+    assert lib.burgers_run_static(arr, 1, B.F64, None, None, 1) == -1
+    assert lib.burgers_run_static(arr, 1, B.F64, None, dummy, -1) == -1
+    bad = (B.CProblem * 1)(B.to_cproblem(W.Problem(**{**good.__dict__, "n": 2})))
+    assert lib.burgers_run_static(bad, 1, B.F64, None, dummy, 1) == -1
+    newton = (B.CProblem * 1)(B.to_cproblem(W.Problem(**{**good.__dict__, "scheme": W.NEWTON})))
+    assert lib.burgers_run_static(newton, 1, B.F64, None, dummy, 1) == -2
+    text = open(os.path.join(ROOT, "include", "burgers.h")).read()
+    assert re.search(r"#define BURGERS_STATIC_SCRATCH_BYTES \(64u << 20\)", text)
+    assert B.STATIC_SCRATCH_BYTES == 64 << 20
+
+
 def test_single_hip_runtime_in_process():
     """Loading the binding first and torch afterwards must leave exactly one HIP runtime mapped, so that
     torch's streams and allocations are valid handles in the library."""
