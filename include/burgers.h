@@ -110,6 +110,18 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *   btcs_block     lanes per system for BTCS systems of exactly 8192 rows (512 lanes of 16 rows or
  *                  1024 of 8; 0 automatic = 512).  Other whole systems take the narrowest of 128, 256,
  *                  512 or 1024 lanes that holds them at <= 8 rows per lane.
+ *   btcs_long      solver of the systems longer than 8192 rows (every BTCS and Crank-Nicolson step of
+ *                  them goes through HBM):
+ *                  0 truncated windows (default): each window of 8192 rows is solved as a plain system
+ *                    whose neighbours beyond its ends take their old values, and only its rows at least
+ *                    256 rows inside are kept.  By the discrete maximum principle of the M-matrix
+ *                    (strictly diagonally dominant rows, non-positive couplings) a kept row then differs
+ *                    from the exact solution by at most 2^-54 max|u| whenever theta^257 <= 2^-56, with
+ *                    theta = 2(D + C)/(1 + 2D + C + sqrt((1 + C)^2 + 4D)), C = r max|u| over the
+ *                    window; every window checks this on the device each step, and an instance with a
+ *                    window that fails it is solved again that step by the partition levels;
+ *                  1 partition levels: the exact partition method across workgroups (three passes over
+ *                    the state per step).
  * burgers_set_plan rejects values outside these ranges with BURGERS_E_INVALID.
  */
 typedef struct {
@@ -118,7 +130,9 @@ typedef struct {
   int32_t btcs_path;
   int32_t use_graph;
   int32_t btcs_block;      /* lanes for 8192-row BTCS systems: 512, 1024, or 0 = automatic */
-  int32_t reserved[3];
+  int32_t btcs_long;       /* systems of more than 8192 rows stepped through HBM: 0 truncated windows,
+                              1 partition levels (see below) */
+  int32_t reserved[2];
 } burgers_plan;
 
 /*

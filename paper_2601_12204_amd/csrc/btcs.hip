@@ -19,6 +19,8 @@
 // path within its one rounding per step of the exact discrete solution.  On CDNA the binary64 vector
 // rate equals the non-packed binary32 rate, and this step is bound by HBM, so the wider arithmetic costs
 // nothing measurable.
+#include <cmath>
+
 #include "internal.hpp"
 #include "newton_check.hpp"
 #include "stencil.hpp"
@@ -624,7 +626,7 @@ template <typename S, bool FromState, int NT, int MC, bool EXACT = false>
 __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_wg_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, const S* __restrict__ u,
     S* __restrict__ out, const double* __restrict__ LA, const double* __restrict__ LC,
-    const double* __restrict__ LD, double* __restrict__ LX) {
+    const double* __restrict__ LD, double* __restrict__ LX, const int* __restrict__ only) {
   using T = double;
   using Pcr = PcrSpace<T, NT>;
   using IS = InterfaceSpace<T, NT>;
@@ -641,6 +643,7 @@ __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_w
   T* tstage = reinterpret_cast<T*>(smem);   // reduced systems: one coefficient array at a time
 
   const SysDesc sys = systems[blockIdx.x];
+  if (only && only[sys.inst] == 0) return;   // partition fallback: this instance's windows held
   const int R = sys.rows, P = sys.chunks;
   const int tid = threadIdx.x;
 
@@ -932,6 +935,148 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
   }
 }
 
+// ---- Truncated windows of a long system ------------------------------------------------------------
+// A long system's rows are covered by windows of kWgRows rows.  A window keeps the rows at least
+// kWinHalo rows inside its ends and solves them together with the halo as a plain system, in which the
+// unknowns just beyond its two ends (its ghosts) take their old values u^n (at a Dirichlet end of the
+// system, the exact boundary value).
+//
+// Error of a kept row.  Let e be the window solution minus the exact one, extended to the ghosts by
+// the ghosts' errors g_L, g_R.  Every window row gives l_i e_{i-1} + d_i e_i + p_i e_{i+1} = 0 with
+// l_i, p_i <= 0 and d_i - |l_i| - |p_i| = 1, so a vector w with that operator >= 0 on the window rows and
+// w >= 0 at the ghosts is >= 0 throughout (at a negative minimum the row would give 1 * w_i < 0).  The
+// barrier v_i = theta^(i+1) (ghost at i = -1) meets -|l_i| + d_i theta - |p_i| theta^2 >= 0 whenever
+// theta is at least the smaller root of that quadratic, which for the BTCS rows (c = r u_i, the
+// couplings D + max(c,0) and D - min(c,0)) is at most
+//     g(C) = 2 (D + C) / (1 + 2D + C + sqrt((1 + C)^2 + 4D)),   C = r max|u_i| over the window
+// (g increases with C, and the mirrored barrier from the right end takes the same bound).  With w =
+// |g_L| v + |g_R| v' -+ e:  |e_i| <= |g_L| theta^(i+1) + |g_R| theta^(W-i).  A ghost's error is its old
+// value minus its new one, at most 2 max|u^n| by the maximum principle of the step, so a kept row (at
+// least kWinHalo + 1 rows from either ghost) is within 4 max|u^n| theta^(kWinHalo+1) of the exact value:
+// at most 2^-54 max|u^n| when theta^(kWinHalo+1) <= 2^-56.  Each window evaluates g(C) from its own
+// rows and flags its instance when the bound fails; the partition levels, which solve the whole system
+// exactly, then redo that instance's step (the old state is still in the step's input buffer).
+//
+// This is the truncation the partition method's PCR already makes when it drops couplings below
+// 2^-54, applied to the spikes between windows (the decay of the inverse of a diagonally dominant
+// tridiagonal matrix behind truncated SPIKE solvers).  One pass over the state per step: the rows are
+// read once (plus 2 kWinHalo rows per window) and the kept rows written once.
+constexpr int kWinHalo = 256;
+
+// A value every lane holds alike, moved to scalar registers.
+__device__ __forceinline__ double uniform(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(b & 0xffffffffu)));
+  const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32)));
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+// The largest theta the windows accept: theta^(kWinHalo + 1) <= 2^-56, less a relative 1e-12 for the
+// rounding of the device's evaluation of g.
+double window_theta_limit() { return std::exp2(-56.0 / (kWinHalo + 1)) * (1.0 - 1e-12); }
+
+template <typename S>
+__global__ __launch_bounds__(kWgThreads, 4) void btcs_window_kernel(
+    const InstDesc* __restrict__ inst, const WinDesc* __restrict__ wins, const S* __restrict__ u,
+    S* __restrict__ out, int* __restrict__ flag_now, int* __restrict__ flag_next, double theta_lim) {
+  using T = double;
+  constexpr int NT = kWgThreads, MC = kWgChunk, W = kWgRows;
+  using IS = InterfaceSpace<T, NT>;
+  constexpr int kStageBytes = padded_size(W) * static_cast<int>(sizeof(S));
+  constexpr int kBytes = kStageBytes > IS::kBytes ? kStageBytes : IS::kBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  __shared__ uint64_t iface_votes[2 * IS::kVoteWords];
+  __shared__ T wave_max[NT / 64];
+  const IS iws{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + 3 * NT, iface_votes};
+  iws.clear_votes();
+  S* stage = reinterpret_cast<S*>(smem);
+  const WinDesc wd = wins[blockIdx.x];
+  const InstDesc d = inst[wd.inst];
+  const bool dir = d.bc == kDirichlet;
+  const int R = dir ? d.n - 2 : d.n;           // > W: only long systems have windows
+  const S* __restrict__ x = u + d.off + (dir ? 1 : 0);
+  S* __restrict__ y = out + d.off + (dir ? 1 : 0);
+  const int tid = threadIdx.x;
+  // the window's rows (periodic windows wrap), every load in flight at once
+  S v[MC];
+  if (wd.start + W <= R) {                     // (uniform) no wrap: one base address
+    const S* __restrict__ xs = x + wd.start + tid;
+#pragma unroll
+    for (int j = 0; j < MC; ++j) v[j] = xs[j * NT];
+  } else {
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      int k = wd.start + tid + j * NT;
+      if (k >= R) k -= R;
+      v[j] = x[k];
+    }
+  }
+  // ghosts: the old values beyond both ends (a Dirichlet end of the system: its boundary value); the
+  // same for every lane, so kept in scalar registers
+  T gl, gr;
+  if (dir && wd.start == 0) gl = d.a;
+  else gl = uniform(static_cast<T>(x[wd.start == 0 ? R - 1 : wd.start - 1]));
+  {
+    const int k = wd.start + W;
+    if (dir && k == R) gr = d.b;
+    else gr = uniform(static_cast<T>(x[k >= R ? k - R : k]));
+  }
+  T big = T(0);
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    big = __builtin_fmax(big, __builtin_fabs(static_cast<T>(v[j])));
+    stage[padded(tid + j * NT)] = v[j];
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) big = __builtin_fmax(big, __shfl_xor(big, m, 64));
+  if ((tid & 63) == 0) wave_max[tid >> 6] = big;
+  __syncthreads();
+  if (tid == 0) {
+    T M = T(0);
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) M = __builtin_fmax(M, wave_max[k]);
+    const T C = d.r * M;
+    const T theta = 2.0 * (d.D + C) / ((1.0 + 2.0 * d.D + C) + __builtin_sqrt((1.0 + C) * (1.0 + C) + 4.0 * d.D));
+    flag_next[wd.inst] = 0;                    // the next step's slot (its last readers have finished)
+    if (!(theta <= theta_lim)) flag_now[wd.inst] = 1;
+  }
+  T al[MC], ga[MC], de[MC];
+  const int s = tid * MC;
+  load_staged<S>(stage, 0, s, MC, de);
+  __syncthreads();                             // every lane's rows read: the interface LDS overlays them
+  T yv, yp;
+  interface_step<T, NT, MC>(iws, ValueRows{d.r, d.D, DirichletEnds{gl, gr, true}}, true, s, MC, W, NT, al, ga, de,
+                            yv, yp);
+  __syncthreads();                             // the interface unknowns read before the rows are rewritten
+  const LdsDst<S> sdst{stage, 0};
+#pragma unroll
+  for (int j = 0; j < MC; ++j) {
+    if (j < MC - 1) sdst.write(j, s + j, __builtin_fma(-ga[j], yv, __builtin_fma(-al[j], yp, de[j])));
+    else sdst.write(j, s + j, yv);
+  }
+  __syncthreads();
+  // kept rows, counted from the first one (the window's rows [lo, lo + count)).  The lane index is
+  // passed through an empty asm statement so that the compiler recomputes these row indices instead of
+  // keeping the staging loop's ones alive (and spilled) across the solve.
+  const int first = wd.start + wd.lo;         // < 2R
+  int lane = tid;
+  asm volatile("" : "+v"(lane));
+#pragma unroll
+  for (int j = 0; j < (W - 2 * kWinHalo + NT - 1) / NT; ++j) {
+    const int o = lane + j * NT;
+    if (o < wd.count) {
+      int k = first + o;
+      if (k >= R) k -= R;
+      const S val = stage[padded(wd.lo + o)];
+      y[k] = wd.cn ? static_cast<S>(2.0 * static_cast<T>(val) - static_cast<T>(x[k])) : val;
+    }
+  }
+  if (dir && tid == 0) {
+    if (wd.start == 0) out[d.off] = static_cast<S>(d.a);
+    if (wd.start + W == R) out[d.off + d.n - 1] = static_cast<S>(d.b);
+  }
+}
+
 constexpr int kSpikeWaves = kReduceBlock / 64;
 
 // One row of a block's interface system in spike form: unit diagonal, couplings a (row i - s) and c
@@ -1149,9 +1294,10 @@ __device__ __forceinline__ void array_backsub_chunk(const SysDesc& sys, int k, c
 // one chunk and stores its two reduced rows.
 __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_reduce_kernel(
     const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, double* __restrict__ LA,
-    double* __restrict__ LC, double* __restrict__ LD) {
+    double* __restrict__ LC, double* __restrict__ LD, const int* __restrict__ only) {
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
+  if (only && only[sys.inst] == 0) return;
   const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
   if (k >= sys.chunks) return;
   if (block_full(sys, cb.chunk0, min(kReduceBlock, sys.chunks - cb.chunk0))) array_reduce_chunk<true>(sys, k, LA, LC, LD);
@@ -1161,9 +1307,11 @@ __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_reduce_kernel(
 // Backward half: re-eliminate the chunk and recover its rows from the solved reduced unknowns.
 __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_backsub_kernel(
     const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, const double* __restrict__ LA,
-    const double* __restrict__ LC, const double* __restrict__ LD, double* __restrict__ LX) {
+    const double* __restrict__ LC, const double* __restrict__ LD, double* __restrict__ LX,
+    const int* __restrict__ only) {
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
+  if (only && only[sys.inst] == 0) return;
   const int k = cb.chunk0 + static_cast<int>(threadIdx.x);
   if (k >= sys.chunks) return;
   if (block_full(sys, cb.chunk0, min(kReduceBlock, sys.chunks - cb.chunk0))) array_backsub_chunk<true>(sys, k, LA, LC, LD, LX);
@@ -1201,7 +1349,7 @@ template <typename S>
 __global__ __launch_bounds__(kReduceBlock, 4) void btcs_block_reduce_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
     const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, double* __restrict__ LA,
-    double* __restrict__ LC, double* __restrict__ LD) {
+    double* __restrict__ LC, double* __restrict__ LD, const int* __restrict__ only) {
   using T = double;
   constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
   constexpr int kBytes = kStageBytes > BlockIfaceSpace::kBytes ? kStageBytes : BlockIfaceSpace::kBytes;
@@ -1212,6 +1360,7 @@ __global__ __launch_bounds__(kReduceBlock, 4) void btcs_block_reduce_kernel(
   const BlockIfaceSpace w{lds, lds + 3 * BlockIfaceSpace::kN, iface_flags};
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
+  if (only && only[sys.inst] == 0) return;   // partition fallback: this instance's windows held
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
   const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
@@ -1282,7 +1431,7 @@ template <typename S>
 __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems,
     const ChunkBlock* __restrict__ blocks, const S* __restrict__ u, S* __restrict__ out,
-    const double* __restrict__ LX) {
+    const double* __restrict__ LX, const int* __restrict__ only) {
   using T = double;
   constexpr int kStageBytes = padded_size(kRedRows) * static_cast<int>(sizeof(S));
   constexpr int kBytes = kStageBytes > BlockIfaceSpace::kBytes ? kStageBytes : BlockIfaceSpace::kBytes;
@@ -1293,6 +1442,7 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   const BlockIfaceSpace w{lds, lds + 3 * BlockIfaceSpace::kN, iface_flags};
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
+  if (only && only[sys.inst] == 0) return;   // partition fallback: this instance's windows held
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
   const int Pb = min(kReduceBlock, sys.chunks - cb.chunk0);
@@ -1308,25 +1458,25 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
 // level's widest system (small reduced systems leave most of a 512-lane workgroup idle).
 template <typename S>
 void reduced_wg_launch(const BtcsPlan::Level& lv, const InstDesc* inst, const S* u, S* out, double* LA,
-                       double* LC, double* LD, double* LX, hipStream_t st) {
+                       double* LC, double* LD, double* LX, hipStream_t st, const int* only) {
   const SysDesc* sys = lv.wg->as<SysDesc>();
   const unsigned n = static_cast<unsigned>(lv.n_wg);
   switch (lv.wg_lanes) {
-    case 64: btcs_wg_kernel<S, false, 64, kWgChunk><<<n, 64, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
-    case 128: btcs_wg_kernel<S, false, 128, kWgChunk><<<n, 128, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
-    case 256: btcs_wg_kernel<S, false, 256, kWgChunk><<<n, 256, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
+    case 64: btcs_wg_kernel<S, false, 64, kWgChunk><<<n, 64, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, only); break;
+    case 128: btcs_wg_kernel<S, false, 128, kWgChunk><<<n, 128, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, only); break;
+    case 256: btcs_wg_kernel<S, false, 256, kWgChunk><<<n, 256, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, only); break;
     default:
       if (lv.wg_exact)   // the full layout as a constant: no row is selected at a run-time index
         btcs_wg_kernel<S, false, kWgThreads, kWgChunk, true><<<n, kWgThreads, 0, st>>>(inst, sys, u, out, LA, LC, LD,
-                                                                                      LX);
+                                                                                      LX, only);
       else
-        btcs_wg_kernel<S, false, kWgThreads, kWgChunk><<<n, kWgThreads, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX);
+        btcs_wg_kernel<S, false, kWgThreads, kWgChunk><<<n, kWgThreads, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, only);
       break;
   }
 }
 
 template <typename S>
-hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* uv, void* outv) {
+hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* uv, void* outv, int64_t step) {
   const S* u = static_cast<const S*>(uv);
   S* out = static_cast<S*>(outv);
   double* LA = ctx->level_a.as<double>();
@@ -1336,6 +1486,16 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   const InstDesc* inst = plan.inst_half && plan.inst_half->ptr ? plan.inst_half->as<InstDesc>()
                                                                : ctx->inst.as<InstDesc>();
   hipStream_t st = ctx->stream;
+  // truncated windows of the long systems; the partition levels below then serve only the instances
+  // whose windows flagged a failed bound this step
+  const int* only = nullptr;
+  if (plan.n_win > 0) {
+    int* now = plan.win_flags.as<int>() + (step & 1) * ctx->count;
+    int* next = plan.win_flags.as<int>() + ((step + 1) & 1) * ctx->count;
+    btcs_window_kernel<S><<<static_cast<unsigned>(plan.n_win), kWgThreads, 0, st>>>(
+        inst, plan.win->as<WinDesc>(), u, out, now, next, window_theta_limit());
+    only = now;
+  }
   const int L = static_cast<int>(plan.levels.size());
   // forward: reduce level by level
   for (int l = 0; l < L; ++l) {
@@ -1343,45 +1503,51 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
     if (lv.n_blocks == 0) continue;
     if (l == 0) {
       btcs_block_reduce_kernel<S><<<lv.n_blocks, kReduceBlock, 0, st>>>(
-          inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, LA, LC, LD);
+          inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, LA, LC, LD, only);
     } else {
       btcs_array_reduce_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
-                                                                     lv.blocks->as<ChunkBlock>(), LA, LC, LD);
+                                                                     lv.blocks->as<ChunkBlock>(), LA, LC, LD, only);
     }
   }
   // backward: whole-system solves of each level, then back-substitution of the reduced systems
   for (int l = L - 1; l >= 1; --l) {
     const auto& lv = plan.levels[l];
-    if (lv.n_wg) reduced_wg_launch<S>(lv, inst, u, out, LA, LC, LD, LX, st);
+    if (lv.n_wg) reduced_wg_launch<S>(lv, inst, u, out, LA, LC, LD, LX, st, only);
     if (lv.n_blocks) {
-      btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
-                                                                      lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);
+      btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(
+          lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX, only);
     }
   }
+  const int* all = nullptr;
   for (const WgGroup& g : plan.wg_state) {
     if (!g.n) continue;
     const SysDesc* sys = g.sys->as<SysDesc>();
     const unsigned n = static_cast<unsigned>(g.n);
     if (g.shape.exact) {
       if (g.shape.lanes == 1024)
-        btcs_wg_kernel<S, true, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX);
+        btcs_wg_kernel<S, true, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all);
       else
-        btcs_wg_kernel<S, true, 512, 16, true><<<n, 512, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX);
+        btcs_wg_kernel<S, true, 512, 16, true><<<n, 512, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all);
       continue;
     }
     switch (g.shape.lanes) {
-      case 128: btcs_wg_kernel<S, true, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
-      case 256: btcs_wg_kernel<S, true, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
-      case 512: btcs_wg_kernel<S, true, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
-      default: btcs_wg_kernel<S, true, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX); break;
+      case 128: btcs_wg_kernel<S, true, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all); break;
+      case 256: btcs_wg_kernel<S, true, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all); break;
+      case 512: btcs_wg_kernel<S, true, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all); break;
+      default: btcs_wg_kernel<S, true, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all); break;
     }
   }
   if (L > 0 && plan.levels[0].n_blocks) {
     const auto& lv = plan.levels[0];
     btcs_block_backsub_kernel<S><<<lv.n_blocks, kReduceBlock, 0, st>>>(
-        inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, out, LX);
+        inst, lv.sys->as<SysDesc>(), lv.blocks->as<ChunkBlock>(), u, out, LX, only);
   }
   return hipGetLastError();
+}
+
+__global__ void clear_flags_kernel(int* __restrict__ p, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 }  // namespace
@@ -1493,21 +1659,31 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
     const auto& lv = plan.levels[l];
     if (lv.n_blocks)
       btcs_array_reduce_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
-                                                                     lv.blocks->as<ChunkBlock>(), LA, LC, LD);
+                                                                     lv.blocks->as<ChunkBlock>(), LA, LC, LD, nullptr);
   }
   for (int l = L - 1; l >= 0; --l) {
     const auto& lv = plan.levels[l];
-    if (lv.n_wg) reduced_wg_launch<double>(lv, inst, none, none_out, LA, LC, LD, LX, st);
+    if (lv.n_wg) reduced_wg_launch<double>(lv, inst, none, none_out, LA, LC, LD, LX, st, nullptr);
     if (lv.n_blocks)
       btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
-                                                                      lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX);
+                                                                      lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX,
+                                                                      nullptr);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out) {
-  if (ctx->dtype == BURGERS_F64) return launch_step<double>(ctx, plan, u, out);
-  return launch_step<float>(ctx, plan, u, out);
+hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out, int64_t step) {
+  if (ctx->dtype == BURGERS_F64) return launch_step<double>(ctx, plan, u, out, step);
+  return launch_step<float>(ctx, plan, u, out, step);
 }
+
+hipError_t launch_btcs_window_reset(const burgers_ctx* ctx, const BtcsPlan& plan) {
+  if (plan.n_win == 0) return hipSuccess;
+  const int64_t n = 2 * ctx->count;
+  clear_flags_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, ctx->stream>>>(plan.win_flags.as<int>(), n);
+  return hipGetLastError();
+}
+
+int btcs_window_halo() { return kWinHalo; }
 
 }  // namespace burgers

@@ -213,14 +213,32 @@ int32_t reduced_rows(int level, int32_t chunks) {
 burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   const int want = ctx->plan.btcs_path;
   const int threads = ctx->plan.btcs_block ? ctx->plan.btcs_block : burgers::kResidentThreadsDefault;
+  const int longmode = ctx->plan.btcs_long;
   auto found = ctx->btcs.find(set);
-  if (found != ctx->btcs.end() && found->second->path == want && found->second->threads == threads)
+  if (found != ctx->btcs.end() && found->second->path == want && found->second->threads == threads &&
+      found->second->longmode == longmode)
     return BURGERS_OK;
   auto plan = std::make_unique<burgers::BtcsPlan>();
   plan->path = want;
   plan->threads = threads;
+  plan->longmode = longmode;
   const int cap = burgers::btcs_wg_capacity();
   const int chunk = burgers::btcs_reduce_chunk();
+  // truncated windows of the long systems (automatic and per-step paths): `cap` rows each, keeping all
+  // but `halo` rows at either end; the partition levels stay as the fallback for failed bounds
+  const int halo = burgers::btcs_window_halo();
+  std::vector<burgers::WinDesc> windows;
+  auto add_windows = [&](int32_t i, int32_t R, bool is_cn) {
+    const bool periodic = ctx->probs[i].bc == BURGERS_BC_PERIODIC;
+    const int64_t W = cap, kept = cap - 2 * halo;
+    for (int64_t lo = 0; lo < R; lo += kept) {
+      const int64_t hi = std::min<int64_t>(R, lo + kept);
+      const int64_t start = periodic ? ((lo - halo) % R + R) % R : std::min<int64_t>(std::max<int64_t>(lo - halo, 0), R - W);
+      const int64_t rel = periodic ? halo : lo - start;
+      windows.push_back(burgers::WinDesc{i, static_cast<int32_t>(start), static_cast<int32_t>(rel),
+                                         static_cast<int32_t>(hi - lo), is_cn ? 1 : 0, 0});
+    }
+  };
   // whole-system systems grouped by width class (lanes, chunk, exact)
   std::map<std::tuple<int, int, bool>, std::vector<SysDesc>> wg_state, resident;
   auto whole = [&](std::map<std::tuple<int, int, bool>, std::vector<SysDesc>>& groups, int32_t rows, int32_t i,
@@ -257,6 +275,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
       whole(wg_state, R0, i, is_cn);
       continue;
     }
+    if (want != 3 && longmode == 0) add_windows(i, R0, is_cn);
     int32_t R = R0;
     int64_t in_off = 0;
     for (int level = 0;; ++level) {
@@ -313,6 +332,11 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   if ((e = upload_groups(wg_state, plan->wg_state)) != hipSuccess ||
       (e = upload_groups(resident, plan->resident)) != hipSuccess ||
       (e = upload_on(ctx->stream, *plan->copy, ct)) != hipSuccess)
+    return from_hip(e);
+  plan->win = std::make_unique<DevBuf>();
+  if ((e = upload_on(ctx->stream, *plan->win, windows)) != hipSuccess) return from_hip(e);
+  plan->n_win = static_cast<int64_t>(windows.size());
+  if (plan->n_win > 0 && (e = plan->win_flags.alloc(2 * static_cast<size_t>(ctx->count) * sizeof(int), ctx->stream)) != hipSuccess)
     return from_hip(e);
   plan->levels.resize(red_sys.size());
   for (size_t l = 0; l < red_sys.size(); ++l) {
@@ -411,8 +435,9 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
   if (pl.n_copy == 0) return e;
   void* bufs[2] = {u, ctx->work.ptr};
   int cur = 0;
+  if (nsteps > 0 && (e = burgers::launch_btcs_window_reset(ctx, pl)) != hipSuccess) return e;
   for (int64_t s = 0; s < nsteps; ++s) {
-    if ((e = burgers::launch_btcs_step(ctx, pl, bufs[cur], bufs[cur ^ 1])) != hipSuccess) return e;
+    if ((e = burgers::launch_btcs_step(ctx, pl, bufs[cur], bufs[cur ^ 1], s)) != hipSuccess) return e;
     if (pl.newton) {
       burgers::NewtonPlan& np = *ctx->newton;
       const burgers::AdjTile* nt = np.tiles->as<burgers::AdjTile>();
@@ -1073,11 +1098,13 @@ burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan) {
   if (!ctx || !plan) return BURGERS_E_INVALID;
   if (plan->explicit_path < 0 || plan->explicit_path > 3 || plan->btcs_path < 0 || plan->btcs_path > 3 ||
       plan->tblock_depth < 0 || plan->tblock_depth > kMaxDepth || plan->use_graph < -1 || plan->use_graph > 1 ||
-      (plan->btcs_block != 0 && plan->btcs_block != 512 && plan->btcs_block != 1024))
+      (plan->btcs_block != 0 && plan->btcs_block != 512 && plan->btcs_block != 1024) ||
+      plan->btcs_long < 0 || plan->btcs_long > 1)
     return BURGERS_E_INVALID;
   const bool explicit_changed = plan->explicit_path != ctx->plan.explicit_path ||
                                 plan->tblock_depth != ctx->plan.tblock_depth;
-  const bool btcs_changed = plan->btcs_path != ctx->plan.btcs_path || plan->btcs_block != ctx->plan.btcs_block;
+  const bool btcs_changed = plan->btcs_path != ctx->plan.btcs_path || plan->btcs_block != ctx->plan.btcs_block ||
+                            plan->btcs_long != ctx->plan.btcs_long;
   ctx->plan = *plan;
   if (explicit_changed) ctx->explicit_plans.clear();
   if (btcs_changed) ctx->btcs.clear();

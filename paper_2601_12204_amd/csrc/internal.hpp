@@ -80,6 +80,18 @@ struct SysDesc {
   int32_t pad = 0;
 };
 
+// A window of a long BTCS system (truncated partition): rows [start, start + 8192) of the system (mod its
+// row count for periodic systems) are solved as a plain system whose neighbours beyond both ends take
+// their old values; rows [start + lo, start + lo + count) of that solve are written to the new state.
+struct WinDesc {
+  int32_t inst;
+  int32_t start;
+  int32_t lo;
+  int32_t count;
+  int32_t cn;    // Crank-Nicolson system: the half-dt solve y is stored as 2y - u
+  int32_t pad;
+};
+
 // A block of consecutive chunks of one system (reduce and back-substitution kernels).
 struct ChunkBlock {
   int32_t sys;
@@ -176,6 +188,12 @@ struct BtcsPlan {
   };
   std::vector<Level> levels;                 // levels[0] reduces from the state
   int64_t level_rows = 0;                    // rows of A, C, D, X used by this plan
+  // truncated windows of the long systems (every system of the partition levels at level 0 when
+  // present); the partition levels then solve only the systems whose windows flag a failed bound
+  int longmode = 0;                          // burgers_plan.btcs_long the plan was built for
+  std::unique_ptr<DevBuf> win;               // WinDesc[]
+  int64_t n_win = 0;
+  DevBuf win_flags;                          // int32[2][count]: per step parity, instance needs the partition
 };
 
 // Launch lists of the explicit scheme for a set of instances.
@@ -301,7 +319,11 @@ int btcs_wg_lanes(const std::vector<SysDesc>& systems);
 bool btcs_wg_exact(const std::vector<SysDesc>& systems);   // all of 512 chunks x 16 rows (a constant layout)   // workgroup width that serves all of them           // chunk count the workgroup solver uses for `rows` rows
 int btcs_reduce_chunk();                // target rows per chunk in the partition levels
 constexpr int kReduceBlock = 256;       // chunks per workgroup in the partition kernels
-hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out);
+// One BTCS step of the plan from u to out; `step` counts the steps of the current call from 0 (it selects
+// the parity slot of the window flags, which launch_btcs_window_reset clears at the start of a call).
+hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* u, void* out, int64_t step);
+hipError_t launch_btcs_window_reset(const burgers_ctx* ctx, const BtcsPlan& plan);
+int btcs_window_halo();                 // halo rows on each side of a window's output rows
 hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, void* u, int steps);
 hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, const void* u, void* x, bool last,
                                int* flags);
