@@ -258,11 +258,24 @@ def bench_c3(B, torch, n_exp=1024, n_btcs=128):
     s2.step_btcs(u, n_btcs)
     timer.mark("end2")
     spans = timer.spans()
-    s2.close()
     upd = p.n - 2
-    return {"explicit_glups": upd * n_exp / (spans["explicit"][0] * 1e-3) / 1e9,
-            "btcs_glups": upd * n_btcs / (spans["btcs"][0] * 1e-3) / 1e9,
-            "explicit_steps": n_exp, "btcs_steps": n_btcs}
+    out = {"explicit_glups": upd * n_exp / (spans["explicit"][0] * 1e-3) / 1e9,
+           "btcs_glups": upd * n_btcs / (spans["btcs"][0] * 1e-3) / 1e9,
+           "explicit_steps": n_exp, "btcs_steps": n_btcs}
+    # the long-system solvers side by side (same state, same step count), eager and graph-replayed
+    for name, plan in (("btcs_windows_graph", dict(use_graph=1)),
+                       ("btcs_windows8192", dict(btcs_long=2)),
+                       ("btcs_partition", dict(btcs_long=1))):
+        s2.set_plan(**plan)
+        s2.step_btcs(u, n_btcs)
+        t = PhaseTimer()
+        t.mark("x")
+        s2.step_btcs(u, n_btcs)
+        t.mark("end")
+        ms = t.spans()["x"][0]
+        out[name] = {"glups": upd * n_btcs / (ms * 1e-3) / 1e9, "us_per_step": 1e3 * ms / n_btcs}
+    s2.close()
+    return out
 
 
 # r*u; (u - u_m), (u_p - u); the two clipped products and the two subtractions; (u_p + u_m), 2u and

@@ -112,7 +112,8 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *                  512 or 1024 lanes that holds them at <= 8 rows per lane.
  *   btcs_long      solver of the systems longer than 8192 rows (every BTCS and Crank-Nicolson step of
  *                  them goes through HBM):
- *                  0 truncated windows (default): each window of 8192 rows is solved as a plain system
+ *                  0 truncated windows (default): each window of 4096 rows (2: of 8192 rows, in
+ *                    wider workgroups) is solved as a plain system
  *                    whose neighbours beyond its ends take their old values, and only its rows at least
  *                    256 rows inside are kept.  By the discrete maximum principle of the M-matrix
  *                    (strictly diagonally dominant rows, non-positive couplings) a kept row then differs
@@ -130,8 +131,8 @@ typedef struct {
   int32_t btcs_path;
   int32_t use_graph;
   int32_t btcs_block;      /* lanes for 8192-row BTCS systems: 512, 1024, or 0 = automatic */
-  int32_t btcs_long;       /* systems of more than 8192 rows stepped through HBM: 0 truncated windows,
-                              1 partition levels (see below) */
+  int32_t btcs_long;       /* systems of more than 8192 rows stepped through HBM: 0 truncated windows
+                              of 4096 rows, 1 partition levels, 2 windows of 8192 rows (see below) */
   int32_t reserved[2];
 } burgers_plan;
 

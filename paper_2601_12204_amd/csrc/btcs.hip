@@ -936,7 +936,7 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
 }
 
 // ---- Truncated windows of a long system ------------------------------------------------------------
-// A long system's rows are covered by windows of kWgRows rows.  A window keeps the rows at least
+// A long system's rows are covered by windows of W = 16 x (workgroup lanes) rows (4096 or 8192).  A window keeps the rows at least
 // kWinHalo rows inside its ends and solves them together with the halo as a plain system, in which the
 // unknowns just beyond its two ends (its ghosts) take their old values u^n (at a Dirichlet end of the
 // system, the exact boundary value).
@@ -975,12 +975,12 @@ __device__ __forceinline__ double uniform(double v) {
 // rounding of the device's evaluation of g.
 double window_theta_limit() { return std::exp2(-56.0 / (kWinHalo + 1)) * (1.0 - 1e-12); }
 
-template <typename S>
-__global__ __launch_bounds__(kWgThreads, 4) void btcs_window_kernel(
+template <typename S, int NT>
+__global__ __launch_bounds__(NT, 4) void btcs_window_kernel(
     const InstDesc* __restrict__ inst, const WinDesc* __restrict__ wins, const S* __restrict__ u,
     S* __restrict__ out, int* __restrict__ flag_now, int* __restrict__ flag_next, double theta_lim) {
   using T = double;
-  constexpr int NT = kWgThreads, MC = kWgChunk, W = kWgRows;
+  constexpr int MC = kWgChunk, W = NT * MC;
   using IS = InterfaceSpace<T, NT>;
   constexpr int kStageBytes = padded_size(W) * static_cast<int>(sizeof(S));
   constexpr int kBytes = kStageBytes > IS::kBytes ? kStageBytes : IS::kBytes;
@@ -1492,8 +1492,12 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   if (plan.n_win > 0) {
     int* now = plan.win_flags.as<int>() + (step & 1) * ctx->count;
     int* next = plan.win_flags.as<int>() + ((step + 1) & 1) * ctx->count;
-    btcs_window_kernel<S><<<static_cast<unsigned>(plan.n_win), kWgThreads, 0, st>>>(
-        inst, plan.win->as<WinDesc>(), u, out, now, next, window_theta_limit());
+    if (plan.win_rows == kWgRows)
+      btcs_window_kernel<S, kWgThreads><<<static_cast<unsigned>(plan.n_win), kWgThreads, 0, st>>>(
+          inst, plan.win->as<WinDesc>(), u, out, now, next, window_theta_limit());
+    else
+      btcs_window_kernel<S, 256><<<static_cast<unsigned>(plan.n_win), 256, 0, st>>>(
+          inst, plan.win->as<WinDesc>(), u, out, now, next, window_theta_limit());
     only = now;
   }
   const int L = static_cast<int>(plan.levels.size());

@@ -193,6 +193,7 @@ struct BtcsPlan {
   int longmode = 0;                          // burgers_plan.btcs_long the plan was built for
   std::unique_ptr<DevBuf> win;               // WinDesc[]
   int64_t n_win = 0;
+  int win_rows = 8192;                       // rows per window: 8192 (512 lanes) or 4096 (256 lanes)
   DevBuf win_flags;                          // int32[2][count]: per step parity, instance needs the partition
 };
 

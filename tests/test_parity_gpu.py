@@ -262,6 +262,51 @@ def test_btcs_stiff_steps(factor, path):
     assert errs.max() <= TOL_F64, errs
 
 
+def _long_btcs_batch(seed, factor):
+    """Long BTCS systems (periodic and Dirichlet) whose windows tile raggedly, at `factor` x the CFL step."""
+    sizes = [8193, 8194, 3 * 7680 + 5, 20000, 100003]
+    problems, states = [], []
+    for k, n in enumerate(sizes):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            b = W.random_batch(seed + 5 * k + bc, 1, n, n, bc=bc, scheme=W.BTCS, amplitude=2.0)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    return set_cfl_steps(W._pack(problems, states), scheme=W.BTCS, btcs_factor=factor)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("longmode", [0, 1, 2])
+def test_long_btcs_solvers(dtype, longmode):
+    """Systems longer than 8192 rows at 10x the CFL step: truncated windows of 8192 and 4096 rows (where
+    every window's bound holds) and the partition levels, each against the oracle."""
+    batch = _long_btcs_batch(1401, 10.0)
+    announce(f"long btcs {dtype} btcs_long={longmode} 6 steps")
+    got = device_run(batch, 6, dtype, how="step_btcs", plan=dict(btcs_long=longmode))
+    check_batch(batch, got, 6, dtype, scheme=W.BTCS)
+
+
+@pytest.mark.parametrize("longmode", [0, 2])
+def test_long_btcs_fallback_is_the_partition_solve(longmode):
+    """At 10^3 x the CFL step (diffusion numbers in the hundreds) the windows' bound fails, so every step of
+    those instances is redone by the partition levels: bitwise the partition-only result.  In a context
+    that also holds instances at 10x (whose windows hold), each instance still matches the oracle."""
+    stiff = _long_btcs_batch(1501, 1000.0)
+    announce(f"long btcs fallback btcs_long={longmode} 4 steps")
+    got = device_run(stiff, 4, "f64", how="step_btcs", plan=dict(btcs_long=longmode))
+    part = device_run(stiff, 4, "f64", how="step_btcs", plan=dict(btcs_long=1))
+    assert np.array_equal(got, part)
+    check_batch(stiff, got, 4, "f64", scheme=W.BTCS)
+    mild = _long_btcs_batch(1601, 10.0)
+    mixed = W._pack(stiff.problems + mild.problems,
+                    [stiff.instance(k) for k in range(len(stiff.problems))] +
+                    [mild.instance(k) for k in range(len(mild.problems))])
+    announce(f"long btcs mixed fallback btcs_long={longmode} 4 steps")
+    got = device_run(mixed, 4, "f64", how="step_btcs", plan=dict(btcs_long=longmode))
+    check_batch(mixed, got, 4, "f64", scheme=W.BTCS)
+    ns = int(stiff.offsets[-1])
+    assert np.array_equal(got[:ns], part)
+
+
 def test_repeatable_and_resumable():
     """Identical runs are bitwise identical (no races); run(n1) then run(n2) equals run(n1 + n2)."""
     batch = set_cfl_steps(W.random_batch(25, 20, 3, 20000, amplitude=2.0))
