@@ -407,30 +407,42 @@ def bench_c5_adjoint(B, torch, scheme, count=256, n=16384, nsteps=2000, ckpt=100
             "steps": nsteps, "ckpt_every": ckpt, "instances": count, "n": n}
 
 
-def bench_serve(B, torch, duration=2.0, rate=2000.0, pool=800, budget=8 << 30):
-    """Poisson request stream (rate 2000/s) over the ragged mix (N log-uniform in [64, 65536], half
-    periodic / half Dirichlet, half explicit (10^3 steps) / half BTCS (10^2 steps), half FP32 / half FP64),
-    admitted by HBM budget into batched cohorts; latency = completion - arrival."""
+def bench_serve(B, torch, duration=10.0, rate=2000.0, pool=800, budget=8 << 30, runs=1):
+    """Poisson request stream (rate 2000/s for `duration` s) over the ragged mix (N log-uniform in
+    [64, 65536], half periodic / half Dirichlet, half explicit (10^3 steps) / half BTCS (10^2 steps), half
+    FP32 / half FP64), admitted by HBM budget into resident slot pools (one per precision and scheme,
+    ticks of 1000 explicit / 100 BTCS steps); latency = completion - arrival.  `runs` streams are served
+    in turn by the same pools (warm), each with its own arrivals."""
     import workloads as W
-    from paper_2601_12204_amd.serve import Request, Server
+    from paper_2601_12204_amd.serve import GpuBackend, Request, Server
     batch, dtypes = W.ragged_batch(pool, seed=W.SEED_BASE + 4, dtype_mix=True)
     for i, p in enumerate(batch.problems):
         f = 1.0 if p.scheme == W.EXPLICIT else 10.0
         p.dt = f * B.burgers_cfl_dt(p, float(batch.umax[i]), 0.5)
-    arrivals = W.poisson_arrivals(rate, duration)
 
     def make(k, rid):
         p = batch.problems[k]
         return Request(rid=rid, problem=p, u0=batch.instance(k), dtype="f64" if dtypes[k] else "f32",
                        nsteps=1000 if p.scheme == W.EXPLICIT else 100)
 
-    warm = [make(k, k) for k in range(min(pool, 64))]
-    Server(hbm_budget=budget).run(warm, np.zeros(len(warm)))
-    reqs = [make(k % pool, k) for k in range(len(arrivals))]
-    srv = Server(hbm_budget=budget, batch_window=0.001)
-    stats = srv.run(reqs, arrivals)
-    stats.update({"rate_per_s": rate, "duration_s": duration, "pool": pool})
-    return stats
+    backend = GpuBackend(slots=128, max_nodes=65536)
+    warm = [make(k, k) for k in range(min(pool, 256))]
+    Server(backend=backend, hbm_budget=budget).run(warm, np.linspace(0.0, 0.1, len(warm)))
+    out = []
+    for run in range(runs):
+        arrivals = W.poisson_arrivals(rate, duration, seed=W.SEED_BASE + 40 + run)
+        reqs = [make(k % pool, k) for k in range(len(arrivals))]
+        srv = Server(backend=backend, hbm_budget=budget)
+        stats = srv.run(reqs, arrivals)
+        stats.update({"rate_per_s": rate, "duration_s": duration, "pool": pool,
+                      "pooled": sum(r.path == "pool" for r in reqs)})
+        out.append(stats)
+    res = dict(out[0])
+    if runs > 1:
+        res["runs"] = [{k: o[k] for k in ("p50_ms", "p99_ms", "glups", "requests")} for o in out]
+        p99 = [o["p99_ms"] for o in out]
+        res["p99_spread"] = max(p99) / min(p99)
+    return res
 
 
 def cpu_baseline(target_s=15.0):
@@ -495,6 +507,8 @@ def main():
     ap.add_argument("--explicit-path", type=int, default=0, help="force an explicit kernel path (0 auto)")
     ap.add_argument("--btcs-path", type=int, default=0, help="force a BTCS kernel path (0 auto)")
     ap.add_argument("--btcs-block", type=int, default=0, help="lanes per system of the BTCS solver (0 auto)")
+    ap.add_argument("--serve-runs", type=int, default=1, help="serving streams of 10 s each")
+    ap.add_argument("--serve-seconds", type=float, default=10.0, help="length of each serving stream")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the instances are "
@@ -548,7 +562,7 @@ def main():
         extra["c5_adjoint_btcs"] = bench_c5_adjoint(B, torch, W.BTCS)
     if "serve" in legs:
         log("serving")
-        extra["serve"] = bench_serve(B, torch)
+        extra["serve"] = bench_serve(B, torch, duration=args.serve_seconds, runs=args.serve_runs)
     if c2 is None:
         print(json.dumps({"metric": METRIC, "partial": True, "extra": extra}), flush=True)
         return

@@ -46,6 +46,10 @@ typedef enum {
   BURGERS_E_DEVICE = -4,      /* HIP runtime or kernel error (sticky) */
   BURGERS_E_NONFINITE = -5,   /* reserved: non-finite values reported by a checking call */
   BURGERS_E_BUDGET = -6,      /* reserved: request exceeds a memory budget */
+  BURGERS_E_BOUND = -8,       /* reported by burgers_pool_retire: a truncated-window BTCS step of the
+                                 slot failed its accuracy bound (far beyond the CFL step); pools do not
+                                 redo such steps, so the state returned is not within the solver's
+                                 accuracy: solve the problem through a context instead */
   BURGERS_E_NOT_CONVERGED = -7 /* reported by burgers_sync: since the last report, a Newton step
                                   (BURGERS_NEWTON) met a Jacobian row that was not strictly diagonally
                                   dominant, so its unpivoted solve was outside its stated range, or its
@@ -233,6 +237,49 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
 #define BURGERS_STATIC_SCRATCH_BYTES (64u << 20)
 burgers_status burgers_run_static(const burgers_problem* problems, int64_t count, burgers_dtype dtype,
                                   void* hip_stream, void* u, int64_t nsteps);
+
+/*
+ * Resident slot pools: continuous batching of solve requests (the serving workload of the paper's
+ * solvers).  A pool holds `slots` device slots of one precision and one scheme (BURGERS_EXPLICIT or
+ * BURGERS_BTCS), each able to hold a problem of up to max_nodes nodes (max_nodes <= 2^24), allocated
+ * once at creation (two state buffers of slots x max_nodes elements when long problems fit, and the
+ * slot tables).  Requests are admitted into free slots and retired between ticks; every tick advances
+ * all occupied slots by up to tick_steps steps of their own problem in one launch sequence, replayed from
+ * one of two HIP graphs (with and without the windows of long problems).  A slot runs exactly the kernels and arithmetic a
+ * context holding its problem alone would run (on-chip whole instances up to 8192 nodes; explicit
+ * windows or truncated BTCS windows beyond), so its result equals a burgers_run of the same problem,
+ * except that a BTCS window whose accuracy bound fails is reported (BURGERS_E_BOUND) instead of redone.
+ * All work is enqueued on hip_stream; a pool is not thread-safe.
+ *
+ * burgers_pool_create   Errors: BURGERS_E_INVALID, BURGERS_E_NOMEM, BURGERS_E_DEVICE.
+ * burgers_pool_destroy  drains the stream and frees the pool (NULL is a no-op).
+ * burgers_pool_admit    places problem p (scheme equal to the pool's, n <= max_nodes) with initial
+ *                       state u0 (n values of the pool's precision, host or device memory; a host
+ *                       buffer must stay unchanged until the stream has passed this call) and nsteps >= 1
+ *                       steps to run into slot *slot (on entry: a free slot's index, or -1 for the lowest
+ *                       free slot; on return: the slot used, -1 on error).  Errors: BURGERS_E_INVALID,
+ *                       BURGERS_E_UNSUPPORTED (too long for the pool), BURGERS_E_BUDGET (the slot, or
+ *                       every slot, is occupied), BURGERS_E_DEVICE.
+ * burgers_pool_tick     enqueues one tick; each occupied slot advances min(tick_steps, its remaining
+ *                       steps) steps.  Returns at once.
+ * burgers_pool_busy     1 while the last enqueued tick has not finished, else 0.
+ * burgers_pool_remaining  steps the slot has still to run (0: finished, awaiting retirement; -1: free;
+ *                       -2: bad arguments).
+ * burgers_pool_retire   enqueues a copy of a finished slot's state (n values) to dst (host or device) and
+ *                       frees the slot.  Returns BURGERS_E_BOUND if one of its truncated-window steps
+ *                       failed the accuracy bound (the copy is still made), BURGERS_E_INVALID for a slot
+ *                       that is not finished.
+ */
+typedef struct burgers_pool burgers_pool;
+burgers_status burgers_pool_create(burgers_dtype dtype, int32_t scheme, int64_t slots, int64_t max_nodes,
+                                   int64_t tick_steps, void* hip_stream, burgers_pool** out);
+void burgers_pool_destroy(burgers_pool* pool);
+burgers_status burgers_pool_admit(burgers_pool* pool, const burgers_problem* p, const void* u0, int64_t nsteps,
+                                  int64_t* slot);
+burgers_status burgers_pool_tick(burgers_pool* pool);
+int32_t burgers_pool_busy(burgers_pool* pool);
+int64_t burgers_pool_remaining(const burgers_pool* pool, int64_t slot);
+burgers_status burgers_pool_retire(burgers_pool* pool, int64_t slot, void* dst);
 
 /* Wait for the context's stream and return the first sticky device error, if any; else
    BURGERS_E_NOT_CONVERGED once if a Newton check failed since the last report (see burgers_status). */

@@ -28,7 +28,8 @@ ALIGN = 64
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "unsupported request", -3: "out of device memory",
           -4: "device error", -5: "non-finite value", -6: "memory budget exceeded",
-          -7: "Newton step not converged or Jacobian not diagonally dominant"}
+          -7: "Newton step not converged or Jacobian not diagonally dominant",
+          -8: "truncated-window step outside its accuracy bound"}
 
 
 class BurgersError(RuntimeError):
@@ -54,7 +55,9 @@ EXPORTS = ["burgers_create", "burgers_destroy", "burgers_offsets", "burgers_stat
            "burgers_step_explicit", "burgers_step_btcs", "burgers_run", "burgers_run_mixed",
            "burgers_adjoint", "burgers_sync",
            "burgers_get_plan", "burgers_set_plan", "burgers_status_string", "burgers_cfl_dt",
-           "burgers_ratios", "burgers_abi_version", "burgers_autotune", "burgers_run_static"]
+           "burgers_ratios", "burgers_abi_version", "burgers_autotune", "burgers_run_static",
+           "burgers_pool_create", "burgers_pool_destroy", "burgers_pool_admit", "burgers_pool_tick",
+           "burgers_pool_busy", "burgers_pool_remaining", "burgers_pool_retire"]
 
 # workspace of burgers_run_static (BURGERS_STATIC_SCRATCH_BYTES in include/burgers.h)
 STATIC_SCRATCH_BYTES = 64 << 20
@@ -107,6 +110,20 @@ def load() -> ctypes.CDLL:
     lib.burgers_autotune.restype = ctypes.c_int
     lib.burgers_run_static.argtypes = [P(CProblem), i64, ctypes.c_int, vp, vp, i64]
     lib.burgers_run_static.restype = ctypes.c_int
+    lib.burgers_pool_create.argtypes = [ctypes.c_int, i32, i64, i64, i64, vp, P(vp)]
+    lib.burgers_pool_create.restype = ctypes.c_int
+    lib.burgers_pool_destroy.argtypes = [vp]
+    lib.burgers_pool_destroy.restype = None
+    lib.burgers_pool_admit.argtypes = [vp, P(CProblem), vp, i64, P(i64)]
+    lib.burgers_pool_admit.restype = ctypes.c_int
+    lib.burgers_pool_tick.argtypes = [vp]
+    lib.burgers_pool_tick.restype = ctypes.c_int
+    lib.burgers_pool_busy.argtypes = [vp]
+    lib.burgers_pool_busy.restype = i32
+    lib.burgers_pool_remaining.argtypes = [vp, i64]
+    lib.burgers_pool_remaining.restype = i64
+    lib.burgers_pool_retire.argtypes = [vp, i64, vp]
+    lib.burgers_pool_retire.restype = ctypes.c_int
     lib.burgers_abi_version.argtypes = []
     lib.burgers_abi_version.restype = i32
     _lib = lib
@@ -226,6 +243,64 @@ def burgers_run_static(problems: Sequence, u, nsteps: int, dtype=None, stream=No
         raise ValueError(f"state must be a contiguous device tensor of {want} with >= {need} elements")
     _check(load().burgers_run_static(arr, len(problems), code, ctypes.c_void_p(stream), _ptr(u), int(nsteps)),
            "burgers_run_static")
+
+
+class Pool:
+    """A resident slot pool (burgers_pool_*): `slots` device slots of one precision and scheme for problems
+    of up to max_nodes nodes, advanced tick by tick.  States cross through caller-owned buffers (host
+    arrays or device tensors) whose addresses the library reads or writes on the pool's stream."""
+
+    def __init__(self, dtype, scheme: int, slots: int, max_nodes: int, tick_steps: int, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.code = _dtype_code(dtype)
+        self.word = 8 if self.code == F64 else 4
+        self.scheme = int(scheme)
+        self.slots = int(slots)
+        self.handle = ctypes.c_void_p()
+        _check(load().burgers_pool_create(self.code, self.scheme, self.slots, int(max_nodes), int(tick_steps),
+                                          ctypes.c_void_p(stream), ctypes.byref(self.handle)), "burgers_pool_create")
+
+    def admit(self, problem, u0_ptr: int, nsteps: int, slot: int = -1) -> int:
+        """Place a problem whose initial state is at address u0_ptr into `slot` (-1: the lowest free one);
+        returns the slot used, or -1 if it (or every slot) is taken."""
+        slot = ctypes.c_int64(int(slot))
+        st = load().burgers_pool_admit(self.handle, ctypes.byref(to_cproblem(problem)), ctypes.c_void_p(u0_ptr),
+                                       int(nsteps), ctypes.byref(slot))
+        if st == -6:
+            return -1
+        _check(st, "burgers_pool_admit")
+        return int(slot.value)
+
+    def tick(self) -> None:
+        _check(load().burgers_pool_tick(self.handle), "burgers_pool_tick")
+
+    def busy(self) -> bool:
+        return bool(load().burgers_pool_busy(self.handle))
+
+    def remaining(self, slot: int) -> int:
+        return int(load().burgers_pool_remaining(self.handle, int(slot)))
+
+    def retire(self, slot: int, dst_ptr: int) -> int:
+        """Copy a finished slot's state to address dst_ptr (enqueued) and free the slot.  Returns 0, or -8
+        when a truncated-window step of the slot failed its accuracy bound."""
+        st = load().burgers_pool_retire(self.handle, int(slot), ctypes.c_void_p(dst_ptr))
+        if st == -8:
+            return st
+        _check(st, "burgers_pool_retire")
+        return 0
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().burgers_pool_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def packed_offsets(problems: Sequence) -> np.ndarray:

@@ -887,6 +887,8 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
   const IS ws{iface_lds, iface_lds + 3 * NT, iface_votes};
   ws.clear_votes();
   const SysDesc sys = systems[blockIdx.x];
+  if (sys.rows <= 0) return;                   // an empty slot of a resident pool
+  if (sys.limit > 0 && sys.limit < steps) steps = sys.limit;
   const InstDesc d = inst[sys.inst];
   const bool dir = d.bc == kDirichlet;
   const int R = sys.rows, P = sys.chunks;
@@ -978,7 +980,8 @@ double window_theta_limit() { return std::exp2(-56.0 / (kWinHalo + 1)) * (1.0 - 
 template <typename S, int NT>
 __global__ __launch_bounds__(NT, 4) void btcs_window_kernel(
     const InstDesc* __restrict__ inst, const WinDesc* __restrict__ wins, const S* __restrict__ u,
-    S* __restrict__ out, int* __restrict__ flag_now, int* __restrict__ flag_next, double theta_lim) {
+    S* __restrict__ out, int* __restrict__ flag_now, int* __restrict__ flag_next, int* __restrict__ sticky,
+    double theta_lim, int step) {
   using T = double;
   constexpr int MC = kWgChunk, W = NT * MC;
   using IS = InterfaceSpace<T, NT>;
@@ -991,12 +994,25 @@ __global__ __launch_bounds__(NT, 4) void btcs_window_kernel(
   iws.clear_votes();
   S* stage = reinterpret_cast<S*>(smem);
   const WinDesc wd = wins[blockIdx.x];
+  if (wd.count <= 0) return;                   // an empty slot of a resident pool
   const InstDesc d = inst[wd.inst];
   const bool dir = d.bc == kDirichlet;
   const int R = dir ? d.n - 2 : d.n;           // > W: only long systems have windows
   const S* __restrict__ x = u + d.off + (dir ? 1 : 0);
   S* __restrict__ y = out + d.off + (dir ? 1 : 0);
   const int tid = threadIdx.x;
+  if (wd.limit > 0 && step >= wd.limit) {      // a slot whose steps are done: carry its kept rows over
+    for (int o = tid; o < wd.count; o += NT) {
+      int k = wd.start + wd.lo + o;
+      if (k >= R) k -= R;
+      y[k] = x[k];
+    }
+    if (dir && tid == 0) {
+      if (wd.start == 0) out[d.off] = static_cast<S>(d.a);
+      if (wd.start + W == R) out[d.off + d.n - 1] = static_cast<S>(d.b);
+    }
+    return;
+  }
   // the window's rows (periodic windows wrap), every load in flight at once
   S v[MC];
   if (wd.start + W <= R) {                     // (uniform) no wrap: one base address
@@ -1038,7 +1054,10 @@ __global__ __launch_bounds__(NT, 4) void btcs_window_kernel(
     const T C = d.r * M;
     const T theta = 2.0 * (d.D + C) / ((1.0 + 2.0 * d.D + C) + __builtin_sqrt((1.0 + C) * (1.0 + C) + 4.0 * d.D));
     flag_next[wd.inst] = 0;                    // the next step's slot (its last readers have finished)
-    if (!(theta <= theta_lim)) flag_now[wd.inst] = 1;
+    if (!(theta <= theta_lim)) {
+      flag_now[wd.inst] = 1;
+      sticky[wd.inst] = 1;                     // kept until its owner clears it (resident pools report it)
+    }
   }
   T al[MC], ga[MC], de[MC];
   const int s = tid * MC;
@@ -1492,12 +1511,13 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   if (plan.n_win > 0) {
     int* now = plan.win_flags.as<int>() + (step & 1) * ctx->count;
     int* next = plan.win_flags.as<int>() + ((step + 1) & 1) * ctx->count;
+    int* sticky = plan.win_flags.as<int>() + 2 * ctx->count;
     if (plan.win_rows == kWgRows)
       btcs_window_kernel<S, kWgThreads><<<static_cast<unsigned>(plan.n_win), kWgThreads, 0, st>>>(
-          inst, plan.win->as<WinDesc>(), u, out, now, next, window_theta_limit());
+          inst, plan.win->as<WinDesc>(), u, out, now, next, sticky, window_theta_limit(), static_cast<int>(step));
     else
       btcs_window_kernel<S, 256><<<static_cast<unsigned>(plan.n_win), 256, 0, st>>>(
-          inst, plan.win->as<WinDesc>(), u, out, now, next, window_theta_limit());
+          inst, plan.win->as<WinDesc>(), u, out, now, next, sticky, window_theta_limit(), static_cast<int>(step));
     only = now;
   }
   const int L = static_cast<int>(plan.levels.size());
@@ -1689,5 +1709,11 @@ hipError_t launch_btcs_window_reset(const burgers_ctx* ctx, const BtcsPlan& plan
 }
 
 int btcs_window_halo() { return kWinHalo; }
+
+hipError_t launch_clear_ints(const burgers_ctx* ctx, int* p, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  clear_flags_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, ctx->stream>>>(p, n);
+  return hipGetLastError();
+}
 
 }  // namespace burgers

@@ -16,9 +16,76 @@ using burgers::SysDesc;
 using burgers::Tile;
 using burgers::BlockTile;
 
+namespace burgers {
+
+bool explicit_windows(int32_t i, int32_t n, bool periodic, int depth, bool rk4, std::vector<BlockTile>& out) {
+  const int cap = explicit_block_capacity();
+  // each step consumes one halo node per side per stage
+  const int32_t halo = depth * (rk4 ? 4 : 1);
+  const int32_t wout = cap - 2 * halo;
+  if (wout < 1) return false;
+  const int64_t nn = n;
+  for (int64_t lo = 0; lo < nn; lo += wout) {
+    const int64_t hi = std::min<int64_t>(nn, lo + wout);
+    BlockTile bt{i, 0, 0, 0, static_cast<int32_t>(hi - lo), 0, rk4 ? 1 : 0, 0};
+    if (periodic) {
+      bt.first = static_cast<int32_t>(((lo - halo) % nn + nn) % nn);
+      bt.width = static_cast<int32_t>((hi - lo) + 2 * halo);
+      bt.lo = halo;
+    } else {
+      const int64_t first = std::max<int64_t>(0, lo - halo);
+      bt.first = static_cast<int32_t>(first);
+      bt.width = static_cast<int32_t>(std::min<int64_t>(nn, hi + halo) - first);
+      bt.lo = static_cast<int32_t>(lo - first);
+    }
+    out.push_back(bt);
+  }
+  return true;
+}
+
+void btcs_windows(int32_t i, int32_t R, bool periodic, int W, bool cn, std::vector<WinDesc>& out) {
+  const int64_t halo = btcs_window_halo(), kept = W - 2 * halo;
+  for (int64_t lo = 0; lo < R; lo += kept) {
+    const int64_t hi = std::min<int64_t>(R, lo + kept);
+    const int64_t start =
+        periodic ? ((lo - halo) % R + R) % R : std::min<int64_t>(std::max<int64_t>(lo - halo, 0), R - W);
+    const int64_t rel = periodic ? halo : lo - start;
+    out.push_back(WinDesc{i, static_cast<int32_t>(start), static_cast<int32_t>(rel), static_cast<int32_t>(hi - lo),
+                          cn ? 1 : 0, 0});
+  }
+}
+
+}  // namespace burgers
+
 namespace {
 
 enum SetId { kSetAll = 0, kSetExplicit = 1, kSetBtcs = 2 };
+
+bool valid_problem(const burgers_problem& p);
+double grid_dx(const burgers_problem& p);
+
+}  // namespace
+
+namespace burgers {
+
+bool problem_valid(const burgers_problem& p) { return valid_problem(p); }
+
+InstDesc inst_desc(const burgers_problem& p, int64_t off) {
+  InstDesc d{};
+  d.off = off;
+  d.n = static_cast<int32_t>(p.n);
+  d.bc = p.bc;
+  burgers_ratios(&p, &d.r, &d.D);
+  const double dxv = grid_dx(p);
+  d.dtdx2 = p.dt / (dxv * dxv);
+  d.a = p.bc == BURGERS_BC_DIRICHLET ? p.left : 0.0;
+  d.b = p.bc == BURGERS_BC_DIRICHLET ? p.right : 0.0;
+  return d;
+}
+
+}  // namespace burgers
+
+namespace {
 
 bool is_finite(double x) { return std::isfinite(x); }
 
@@ -139,26 +206,7 @@ burgers_status ensure_explicit(burgers_ctx* ctx, int set) {
       }
       if (plan->path == 2) return BURGERS_E_UNSUPPORTED;
       windowed.push_back(i);
-      // each step consumes one halo node per side per stage
-      const int32_t halo = T * (rk4 ? 4 : 1);
-      const int32_t wout = cap - 2 * halo;
-      if (wout < 1) return BURGERS_E_UNSUPPORTED;
-      const int64_t nn = n;
-      for (int64_t lo = 0; lo < nn; lo += wout) {
-        const int64_t hi = std::min<int64_t>(nn, lo + wout);
-        BlockTile bt{i, 0, 0, 0, static_cast<int32_t>(hi - lo), 0, rk4};
-        if (periodic) {
-          bt.first = static_cast<int32_t>(((lo - halo) % nn + nn) % nn);
-          bt.width = static_cast<int32_t>((hi - lo) + 2 * halo);
-          bt.lo = halo;
-        } else {
-          const int64_t first = std::max<int64_t>(0, lo - halo);
-          bt.first = static_cast<int32_t>(first);
-          bt.width = static_cast<int32_t>(std::min<int64_t>(nn, hi + halo) - first);
-          bt.lo = static_cast<int32_t>(lo - first);
-        }
-        win.push_back(bt);
-      }
+      if (!burgers::explicit_windows(i, n, periodic, T, rk4 != 0, win)) return BURGERS_E_UNSUPPORTED;
     }
     auto fe_first = [](const BlockTile& x, const BlockTile& y) { return x.rk4 < y.rk4; };
     // whole instances: by workgroup width (widest first), then forward Euler before RK4
@@ -229,19 +277,10 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   // failed bounds.  Narrower windows read 14% more rows than 8192-row ones but take 256-lane workgroups,
   // four per CU instead of two, whose loads, solves and stores overlap better (C3: 52.6 against 60.8 us
   // per step).
-  const int halo = burgers::btcs_window_halo();
   plan->win_rows = longmode == 2 ? cap : 4096;
   std::vector<burgers::WinDesc> windows;
   auto add_windows = [&](int32_t i, int32_t R, bool is_cn) {
-    const bool periodic = ctx->probs[i].bc == BURGERS_BC_PERIODIC;
-    const int64_t W = plan->win_rows, kept = W - 2 * halo;
-    for (int64_t lo = 0; lo < R; lo += kept) {
-      const int64_t hi = std::min<int64_t>(R, lo + kept);
-      const int64_t start = periodic ? ((lo - halo) % R + R) % R : std::min<int64_t>(std::max<int64_t>(lo - halo, 0), R - W);
-      const int64_t rel = periodic ? halo : lo - start;
-      windows.push_back(burgers::WinDesc{i, static_cast<int32_t>(start), static_cast<int32_t>(rel),
-                                         static_cast<int32_t>(hi - lo), is_cn ? 1 : 0, 0});
-    }
+    burgers::btcs_windows(i, R, ctx->probs[i].bc == BURGERS_BC_PERIODIC, plan->win_rows, is_cn, windows);
   };
   // whole-system systems grouped by width class (lanes, chunk, exact)
   std::map<std::tuple<int, int, bool>, std::vector<SysDesc>> wg_state, resident;
@@ -340,7 +379,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   plan->win = std::make_unique<DevBuf>();
   if ((e = upload_on(ctx->stream, *plan->win, windows)) != hipSuccess) return from_hip(e);
   plan->n_win = static_cast<int64_t>(windows.size());
-  if (plan->n_win > 0 && (e = plan->win_flags.alloc(2 * static_cast<size_t>(ctx->count) * sizeof(int), ctx->stream)) != hipSuccess)
+  if (plan->n_win > 0 && (e = plan->win_flags.alloc(3 * static_cast<size_t>(ctx->count) * sizeof(int), ctx->stream)) != hipSuccess)
     return from_hip(e);
   plan->levels.resize(red_sys.size());
   for (size_t l = 0; l < red_sys.size(); ++l) {
@@ -753,17 +792,7 @@ burgers_status new_context(const burgers_problem* problems, int64_t count, burge
   ctx->inst_host.resize(count);
   for (int64_t i = 0; i < count; ++i) {
     const burgers_problem& p = problems[i];
-    InstDesc& d = ctx->inst_host[i];
-    d.off = ctx->offsets[i];
-    d.n = static_cast<int32_t>(p.n);
-    d.bc = p.bc;
-    burgers_ratios(&p, &d.r, &d.D);
-    {
-      const double dxv = grid_dx(p);
-      d.dtdx2 = p.dt / (dxv * dxv);
-    }
-    d.a = p.bc == BURGERS_BC_DIRICHLET ? p.left : 0.0;
-    d.b = p.bc == BURGERS_BC_DIRICHLET ? p.right : 0.0;
+    ctx->inst_host[i] = burgers::inst_desc(p, ctx->offsets[i]);
     ctx->set_all.push_back(static_cast<int32_t>(i));
     (p.scheme == BURGERS_EXPLICIT || p.scheme == BURGERS_RK4 ? ctx->set_explicit : ctx->set_btcs)
         .push_back(static_cast<int32_t>(i));
@@ -835,6 +864,7 @@ const char* burgers_status_string(burgers_status s) {
     case BURGERS_E_NONFINITE: return "non-finite value";
     case BURGERS_E_BUDGET: return "memory budget exceeded";
     case BURGERS_E_NOT_CONVERGED: return "Newton step not converged or Jacobian not diagonally dominant";
+    case BURGERS_E_BOUND: return "truncated-window step outside its accuracy bound";
   }
   return "unknown status";
 }

@@ -373,12 +373,16 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
 template <typename T, bool RK4, int NT = kBlockThreads>
 __global__ __launch_bounds__(NT) void explicit_block_kernel(
     const InstDesc* __restrict__ inst, const BlockTile* __restrict__ tiles, const T* __restrict__ u,
-    T* __restrict__ out, int steps) {
+    T* __restrict__ out, int steps, int first_step) {
   constexpr int kStage = stage_nodes<NT>();
   __shared__ T s_first[2][NT];
   __shared__ T s_last[2][NT];
   __shared__ T stage[kStage + kStage / 16 + 1];
   const BlockTile bt = tiles[blockIdx.x];
+  if (bt.width <= 0) return;                   // an empty slot of a resident pool
+  // a slot with `limit` steps left in the call takes those of this launch's steps (steps [first_step,
+  // first_step + steps) of the call) that remain; with none left it still carries its window over
+  if (bt.limit > 0) steps = max(0, min(steps, bt.limit - first_step));
   const InstDesc d = inst[bt.inst];
   const T* src = u + d.off;
   T* dst = out + d.off;
@@ -464,34 +468,34 @@ hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int
 
 template <typename T, int NT>
 void block_launch(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4, const void* u,
-                  void* out, int steps) {
+                  void* out, int steps, int first_step) {
   const InstDesc* inst = ctx->inst.as<InstDesc>();
   const T* src = static_cast<const T*>(u);
   T* dst = static_cast<T*>(out);
   if (n_fe > 0)
     explicit_block_kernel<T, false, NT><<<static_cast<unsigned>(n_fe), NT, 0, ctx->stream>>>(inst, tiles, src, dst,
-                                                                                            steps);
+                                                                                            steps, first_step);
   if (n_rk4 > 0)
     explicit_block_kernel<T, true, NT><<<static_cast<unsigned>(n_rk4), NT, 0, ctx->stream>>>(inst, tiles + n_fe, src,
-                                                                                            dst, steps);
+                                                                                            dst, steps, first_step);
 }
 
 template <typename T>
 void block_launch_lanes(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4, const void* u,
-                        void* out, int steps, int lanes) {
+                        void* out, int steps, int lanes, int first_step) {
   switch (lanes) {
-    case 64: block_launch<T, 64>(ctx, tiles, n_fe, n_rk4, u, out, steps); break;
-    case 128: block_launch<T, 128>(ctx, tiles, n_fe, n_rk4, u, out, steps); break;
-    case 256: block_launch<T, 256>(ctx, tiles, n_fe, n_rk4, u, out, steps); break;
-    default: block_launch<T, kBlockThreads>(ctx, tiles, n_fe, n_rk4, u, out, steps); break;
+    case 64: block_launch<T, 64>(ctx, tiles, n_fe, n_rk4, u, out, steps, first_step); break;
+    case 128: block_launch<T, 128>(ctx, tiles, n_fe, n_rk4, u, out, steps, first_step); break;
+    case 256: block_launch<T, 256>(ctx, tiles, n_fe, n_rk4, u, out, steps, first_step); break;
+    default: block_launch<T, kBlockThreads>(ctx, tiles, n_fe, n_rk4, u, out, steps, first_step); break;
   }
 }
 
 hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4,
-                                 const void* u, void* out, int steps, int lanes) {
+                                 const void* u, void* out, int steps, int lanes, int first_step) {
   if (n_fe + n_rk4 <= 0 || steps <= 0) return hipSuccess;
-  if (ctx->dtype == BURGERS_F64) block_launch_lanes<double>(ctx, tiles, n_fe, n_rk4, u, out, steps, lanes);
-  else block_launch_lanes<float>(ctx, tiles, n_fe, n_rk4, u, out, steps, lanes);
+  if (ctx->dtype == BURGERS_F64) block_launch_lanes<double>(ctx, tiles, n_fe, n_rk4, u, out, steps, lanes, first_step);
+  else block_launch_lanes<float>(ctx, tiles, n_fe, n_rk4, u, out, steps, lanes, first_step);
   return hipGetLastError();
 }
 

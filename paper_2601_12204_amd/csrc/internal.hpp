@@ -50,6 +50,7 @@ struct BlockTile {
   int32_t count;
   int32_t wrap;   // 1: the window is a whole periodic instance and its ends are neighbours
   int32_t rk4;    // 1: classical RK4 steps (4 stages) instead of forward Euler
+  int32_t limit;  // > 0: advance at most this many of the launch's steps (a slot finishing mid-tick)
 };
 
 // A run of 256 nodes of one instance in the adjoint sweep; `slot` indexes the tile's accumulator of
@@ -77,7 +78,7 @@ struct SysDesc {
   int32_t inst;
   int32_t level;
   int32_t cn = 0;   // level-0 Crank-Nicolson system: the solve is the half-dt BTCS one, stored as 2y - u
-  int32_t pad = 0;
+  int32_t limit = 0;  // > 0: the on-chip solver advances at most this many of the launch's steps
 };
 
 // A window of a long BTCS system (truncated partition): rows [start, start + 8192) of the system (mod its
@@ -89,7 +90,7 @@ struct WinDesc {
   int32_t lo;
   int32_t count;
   int32_t cn;    // Crank-Nicolson system: the half-dt solve y is stored as 2y - u
-  int32_t pad;
+  int32_t limit; // > 0: only the first `limit` steps of a call solve; later ones copy the kept rows
 };
 
 // A block of consecutive chunks of one system (reduce and back-substitution kernels).
@@ -194,7 +195,8 @@ struct BtcsPlan {
   std::unique_ptr<DevBuf> win;               // WinDesc[]
   int64_t n_win = 0;
   int win_rows = 8192;                       // rows per window: 8192 (512 lanes) or 4096 (256 lanes)
-  DevBuf win_flags;                          // int32[2][count]: per step parity, instance needs the partition
+  DevBuf win_flags;                          // int32[3][count]: per step parity, instance needs the partition;
+                                             // then a sticky copy (set by any failed window, never cleared here)
 };
 
 // Launch lists of the explicit scheme for a set of instances.
@@ -282,8 +284,19 @@ hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int
                                   const void* u, void* out);
 // Windows tiles[0, n_fe) advance by forward Euler and tiles[n_fe, n_fe + n_rk4) by RK4.
 // Temporal-blocking launch over `lanes`-wide workgroups (64, 128, 256 or 512; windows always take 512).
+// `first_step`: the launch's first step counted from the start of the call (tiles with a step limit
+// take only the steps of the call they have left).
 hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4,
-                                 const void* u, void* out, int steps, int lanes = 512);
+                                 const void* u, void* out, int steps, int lanes = 512, int first_step = 0);
+// Windows of a long explicit instance `i` of n nodes advanced `depth` steps per launch (halo = depth x
+// stages per side); appends them to `out`.  Returns false when the halo leaves no kept node.
+bool explicit_windows(int32_t i, int32_t n, bool periodic, int depth, bool rk4, std::vector<BlockTile>& out);
+// Truncated BTCS windows of `W` rows over a system of R rows of instance i; appends them to `out`.
+void btcs_windows(int32_t i, int32_t R, bool periodic, int W, bool cn, std::vector<WinDesc>& out);
+hipError_t launch_clear_ints(const burgers_ctx* ctx, int* p, int64_t n);
+// capi.hip: argument checks and the kernels' per-instance scalars of a problem at state offset `off`
+bool problem_valid(const burgers_problem& p);
+InstDesc inst_desc(const burgers_problem& p, int64_t off);
 int explicit_block_lanes(int n);   // narrowest workgroup that holds a whole instance of n nodes
 hipError_t launch_copy_tiles(const burgers_ctx* ctx, const Tile* tiles, int64_t n_tiles, const void* src,
                              void* dst);
