@@ -343,19 +343,23 @@ def dominant_roofline(c2):
             "launches": c2["btcs_launches"], "algorithmic_bytes_per_launch": bytes_}
 
 
-def bench_c4(B, torch, dtype, graph, batch, n_exp=1_000, n_btcs=100):
+def bench_c4(B, torch, dtype, graph, batch, n_exp=1_000, n_btcs=100, plan=None, tune=False):
     """Ragged batch: 10^4 instances, N log-uniform in [64, 65536], half periodic / half Dirichlet, half
-    explicit / half BTCS; explicit instances 10^3 steps at CFL 0.5, BTCS 10^2 steps at 10x, in one call."""
+    explicit / half BTCS; explicit instances 10^3 steps at CFL 0.5, BTCS 10^2 steps at 10x, in one call.
+    `plan`: knobs to force; `tune`: run the autotuner first and time its choice."""
     import workloads as W
     count = batch.count
     for i, p in enumerate(batch.problems):
         f = 1.0 if p.scheme == W.EXPLICIT else 10.0
         p.dt = f * B.burgers_cfl_dt(p, float(batch.umax[i]), 0.5)
     s = B.Solver(batch.problems, dtype=dtype)
-    s.set_plan(use_graph=1 if graph else 0)
+    s.set_plan(use_graph=1 if graph else 0, **(plan or {}))
     u0 = s.pack_flat(batch.u0, batch.offsets)
     u = torch.empty_like(u0)
     u.copy_(u0)
+    tuned = None
+    if tune:
+        tuned, tuned_ms, _ = s.autotune(u0, n_exp, n_btcs)
     s.run_mixed(u, n_exp, n_btcs)                # warm-up (plans, graph capture)
     s.sync()
     timer = PhaseTimer()
@@ -371,8 +375,14 @@ def bench_c4(B, torch, dtype, graph, batch, n_exp=1_000, n_btcs=100):
     upd_exp = sum((p.n if p.bc == W.BC_PERIODIC else p.n - 2) for p in batch.problems if p.scheme == W.EXPLICIT)
     upd_btcs = sum((p.n if p.bc == W.BC_PERIODIC else p.n - 2) for p in batch.problems if p.scheme == W.BTCS)
     updates = upd_exp * n_exp + upd_btcs * n_btcs
-    return {"ms": ms, "glups": updates / (ms * 1e-3) / 1e9, "instances": count,
-            "nodes": int(batch.offsets[-1]), "updates": int(updates), "graph": bool(graph)}
+    out = {"ms": ms, "glups": updates / (ms * 1e-3) / 1e9, "instances": count,
+           "nodes": int(batch.offsets[-1]), "updates": int(updates), "graph": bool(graph)}
+    if plan:
+        out["plan"] = plan
+    if tuned is not None:
+        out["tuned_plan"] = tuned
+        out["tuned_ms_in_autotune"] = tuned_ms
+    return out
 
 
 def bench_c5_adjoint(B, torch, scheme, count=256, n=16384, nsteps=2000, ckpt=100):
@@ -555,6 +565,8 @@ def main():
         c4 = W.ragged_batch(10_000)
         extra["c4_f64_graph"] = bench_c4(B, torch, torch.float64, True, c4)
         extra["c4_f64_eager"] = bench_c4(B, torch, torch.float64, False, c4)
+        extra["c4_f64_graph_serial"] = bench_c4(B, torch, torch.float64, True, c4, plan={"serial": 1})
+        extra["c4_f64_tuned"] = bench_c4(B, torch, torch.float64, True, c4, tune=True)
         extra["c4_f32_graph"] = bench_c4(B, torch, torch.float32, True, c4)
     if "c5" in legs:
         log("C5 adjoint")

@@ -127,6 +127,11 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *                    window that fails it is solved again that step by the partition levels;
  *                  1 partition levels: the exact partition method across workgroups (three passes over
  *                    the state per step).
+ *   serial         a call advances disjoint groups of instances: those held on chip (whole instances
+ *                  of each scheme) and those stepped through HBM (explicit windows, per-step BTCS
+ *                  solves).  0 (default): the groups run concurrently, on side streams of the context
+ *                  forked from and joined back into its stream with events (parallel branches of a
+ *                  captured graph); 1: one after another on the context's stream.
  * burgers_set_plan rejects values outside these ranges with BURGERS_E_INVALID.
  */
 typedef struct {
@@ -137,7 +142,8 @@ typedef struct {
   int32_t btcs_block;      /* lanes for 8192-row BTCS systems: 512, 1024, or 0 = automatic */
   int32_t btcs_long;       /* systems of more than 8192 rows stepped through HBM: 0 truncated windows
                               of 4096 rows, 1 partition levels, 2 windows of 8192 rows (see below) */
-  int32_t reserved[2];
+  int32_t serial;          /* 1: one stream; 0: the independent launch groups run concurrently */
+  int32_t reserved[1];
 } burgers_plan;
 
 /*
@@ -292,12 +298,15 @@ burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan);
 /*
  * Autotuner.  Times candidate plans on a scratch copy of the device state u (u itself is not modified)
  * for explicit_steps / btcs_steps steps (as burgers_run_mixed), with HIP events on the context's
- * stream, and keeps the fastest plan in the context.  Only the knobs that matter for the context's
- * instances are searched: the explicit path and temporal-blocking depth (4, 8, 16, 32) when explicit
- * instances exist (the depth only when some exceed the on-chip limit), lanes per BTCS system (512,
- * 1024) when BTCS instances exist, and graph replay on or off.  *best (optional) receives the chosen
- * plan and *best_ms (optional) its time.  The call synchronises the stream and allocates one scratch
- * state, released before it returns.
+ * stream, and keeps the fastest plan in the context.  It tunes one knob at a time, each over its values
+ * with the others at their best so far, and only the knobs that matter for the context's instances:
+ * the explicit path and, when some instance exceeds the on-chip limit, the temporal-blocking depth of
+ * its windows (4, 8, 16, 32, 64, 128, 256 steps per pass over HBM); the lanes per 8192-row BTCS system
+ * (512, 1024); the solver of BTCS systems longer than 8192 rows (truncated windows of 4096 or 8192 rows,
+ * or the partition levels: the crossover between one-pass windows and the three-pass partition method);
+ * concurrent launch groups on or off; and graph replay on or off.  Each candidate runs twice and the
+ * second run is timed.  *best (optional) receives the chosen plan and *best_ms (optional) its time.  The
+ * call synchronises the stream and allocates one scratch state, released before it returns.
  * Errors: BURGERS_E_INVALID, BURGERS_E_NOMEM, BURGERS_E_DEVICE.
  */
 burgers_status burgers_autotune(burgers_ctx* ctx, const void* u, int64_t explicit_steps, int64_t btcs_steps,

@@ -47,7 +47,8 @@ class CProblem(ctypes.Structure):
 class CPlan(ctypes.Structure):
     _fields_ = [("explicit_path", ctypes.c_int32), ("tblock_depth", ctypes.c_int32),
                 ("btcs_path", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("btcs_block", ctypes.c_int32), ("btcs_long", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("btcs_block", ctypes.c_int32), ("btcs_long", ctypes.c_int32), ("serial", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 1)]
 
 
 _lib = None
@@ -159,7 +160,8 @@ def burgers_autotune(ctx, u, explicit_steps: int, btcs_steps: int):
     _check(load().burgers_autotune(ctx, _ptr(u), int(explicit_steps), int(btcs_steps), ctypes.byref(plan),
                                    ctypes.byref(ms)), "burgers_autotune")
     return ({"explicit_path": plan.explicit_path, "tblock_depth": plan.tblock_depth, "btcs_path": plan.btcs_path,
-             "use_graph": plan.use_graph, "btcs_block": plan.btcs_block, "btcs_long": plan.btcs_long}, ms.value)
+             "use_graph": plan.use_graph, "btcs_block": plan.btcs_block, "btcs_long": plan.btcs_long,
+             "serial": plan.serial}, ms.value)
 
 
 def burgers_status_string(status: int) -> str:
@@ -321,13 +323,13 @@ def burgers_get_plan(ctx) -> dict:
     _check(load().burgers_get_plan(ctx, ctypes.byref(plan)), "burgers_get_plan")
     return {"explicit_path": plan.explicit_path, "tblock_depth": plan.tblock_depth,
             "btcs_path": plan.btcs_path, "use_graph": plan.use_graph, "btcs_block": plan.btcs_block,
-            "btcs_long": plan.btcs_long}
+            "btcs_long": plan.btcs_long, "serial": plan.serial}
 
 
 def burgers_set_plan(ctx, explicit_path=0, tblock_depth=0, btcs_path=0, use_graph=-1, btcs_block=0,
-                     btcs_long=0) -> None:
+                     btcs_long=0, serial=0) -> None:
     plan = CPlan(int(explicit_path), int(tblock_depth), int(btcs_path), int(use_graph), int(btcs_block),
-                 int(btcs_long))
+                 int(btcs_long), int(serial))
     _check(load().burgers_set_plan(ctx, ctypes.byref(plan)), "burgers_set_plan")
 
 
@@ -414,14 +416,26 @@ class Solver:
     def sync(self) -> None:
         burgers_sync(self.ctx)
 
-    def autotune(self, u, explicit_steps: int, btcs_steps: int, cache: Optional[str] = None):
-        """Pick the fastest plan for this workload (burgers_autotune); with `cache`, a JSON file keyed by a
-        signature of the batch (sizes, boundary types, schemes, dtype) stores and reuses the choice."""
+    def tuning_key(self, explicit_steps: int, btcs_steps: int) -> str:
+        """Cache key of a tuned plan: the precision, the step counts and how many instances fall in each
+        (size class, boundary type, scheme), size classes being powers of two of n.  Batches drawn from
+        the same mix share it, so a plan tuned once serves them all."""
         import hashlib
         import json
-        key = hashlib.sha1(json.dumps([self.torch_dtype == __import__("torch").float64, explicit_steps, btcs_steps,
-                                       sorted((int(p.n), int(p.bc), int(p.scheme)) for p in self.problems)]
-                                      ).encode()).hexdigest()
+        classes = {}
+        for p in self.problems:
+            c = (int(np.ceil(np.log2(max(int(p.n), 2)))), int(p.bc), int(p.scheme))
+            classes[c] = classes.get(c, 0) + 1
+        # counts rounded to two significant figures, so that draws of one mix agree
+        hist = sorted((list(c), int(float(f"{k:.2g}"))) for c, k in classes.items())
+        sig = [self.torch_dtype == __import__("torch").float64, int(explicit_steps), int(btcs_steps), hist]
+        return hashlib.sha1(json.dumps(sig).encode()).hexdigest()
+
+    def autotune(self, u, explicit_steps: int, btcs_steps: int, cache: Optional[str] = None):
+        """Pick the fastest plan for this workload (burgers_autotune); with `cache`, a JSON file keyed by
+        tuning_key stores and reuses the choice."""
+        import json
+        key = self.tuning_key(explicit_steps, btcs_steps)
         store = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:

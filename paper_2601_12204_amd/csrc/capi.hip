@@ -422,12 +422,17 @@ int64_t level_rows_needed(const burgers_ctx* ctx) {
   return rows;
 }
 
-// Enqueue nsteps explicit steps of one subset; the final state lands in u.
-hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
+// Independent launch groups of a call (they advance disjoint instances): the whole instances held on chip,
+// and the instances stepped through HBM (windows, per-step solves), of each scheme.
+enum Part { kPartAll = 0, kPartOnChip = 1, kPartThroughHbm = 2 };
+
+// Enqueue nsteps explicit steps of one subset (or of one part of it); the final state lands in u.
+hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps, int part = kPartAll) {
   const burgers::ExplicitPlan& pl = *ctx->explicit_plans[set];
   void* work = ctx->work.ptr;
   hipError_t e = hipSuccess;
   if (pl.path == 1) {
+    if (part == kPartOnChip) return e;
     void* bufs[2] = {u, work};
     int cur = 0;
     for (int64_t s = 0; s < nsteps; ++s) {
@@ -440,7 +445,7 @@ hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) 
   }
   // whole instances, in place: all steps at once, or `depth` per launch on path 3
   const int64_t whole_chunk = pl.path == 3 ? pl.depth : (int64_t{1} << 30);
-  for (int64_t done = 0; done < nsteps;) {
+  for (int64_t done = 0; part != kPartThroughHbm && done < nsteps;) {
     const int k = static_cast<int>(std::min(whole_chunk, nsteps - done));
     for (const auto& c : pl.whole_classes)
       if ((e = burgers::launch_explicit_block(ctx, pl.whole->as<BlockTile>() + c.offset, c.n_fe, c.n_rk4, u, u, k,
@@ -449,7 +454,7 @@ hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) 
     done += k;
   }
   // windows of long instances: `depth` steps per launch, ping-pong
-  if (pl.n_win > 0) {
+  if (pl.n_win > 0 && part != kPartOnChip) {
     void* bufs[2] = {u, work};
     int cur = 0;
     for (int64_t done = 0; done < nsteps;) {
@@ -465,17 +470,17 @@ hipError_t enqueue_explicit(burgers_ctx* ctx, int set, void* u, int64_t nsteps) 
   return e;
 }
 
-// Enqueue nsteps BTCS steps of one subset; the final state lands in u.
-hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
+// Enqueue nsteps BTCS steps of one subset (or of one part of it); the final state lands in u.
+hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps, int part = kPartAll) {
   const burgers::BtcsPlan& pl = *ctx->btcs[set];
   hipError_t e = hipSuccess;
-  for (int64_t done = 0; done < nsteps;) {   // on-chip systems, in place
+  for (int64_t done = 0; part != kPartThroughHbm && done < nsteps;) {   // on-chip systems, in place
     const int k = static_cast<int>(std::min<int64_t>(nsteps - done, int64_t{1} << 30));
     for (const burgers::WgGroup& g : pl.resident)
       if ((e = burgers::launch_btcs_resident(ctx, g, u, k)) != hipSuccess) return e;
     done += k;
   }
-  if (pl.n_copy == 0) return e;
+  if (pl.n_copy == 0 || part == kPartOnChip) return e;
   void* bufs[2] = {u, ctx->work.ptr};
   int cur = 0;
   if (nsteps > 0 && (e = burgers::launch_btcs_window_reset(ctx, pl)) != hipSuccess) return e;
@@ -507,16 +512,68 @@ hipError_t enqueue_btcs(burgers_ctx* ctx, int set, void* u, int64_t nsteps) {
   return e;
 }
 
+// Whether a part of a plan launches anything.
+bool explicit_part_busy(const burgers::ExplicitPlan& pl, int part) {
+  if (pl.path == 1) return part != kPartOnChip && pl.n_stream > 0;
+  return part == kPartOnChip ? !pl.whole_classes.empty() : pl.n_win > 0;
+}
+bool btcs_part_busy(const burgers::BtcsPlan& pl, int part) {
+  return part == kPartOnChip ? !pl.resident.empty() : pl.n_copy > 0;
+}
+
 // scheme -1: each instance's own scheme, explicit instances nsteps steps and BTCS ones nsteps_btcs.
+// The independent parts (on-chip and through-HBM instances of each scheme) run concurrently: the first on
+// the context's stream, the others on side streams forked from it and joined back with events (under
+// graph capture they become parallel branches of the graph), unless the plan asks for one stream.
 hipError_t enqueue_all(burgers_ctx* ctx, int set, int scheme, void* u, int64_t nsteps, int64_t nsteps_btcs = -1) {
-  hipError_t e = hipSuccess;
-  if (scheme == BURGERS_EXPLICIT) return enqueue_explicit(ctx, set, u, nsteps);
-  if (scheme == BURGERS_BTCS) return enqueue_btcs(ctx, set, u, nsteps);
   if (nsteps_btcs < 0) nsteps_btcs = nsteps;
-  if (!ctx->set_explicit.empty() && nsteps > 0 && (e = enqueue_explicit(ctx, kSetExplicit, u, nsteps)) != hipSuccess)
-    return e;
-  if (!ctx->set_btcs.empty() && nsteps_btcs > 0) e = enqueue_btcs(ctx, kSetBtcs, u, nsteps_btcs);
-  return e;
+  struct Group {
+    bool btcs;
+    int set, part;
+    int64_t steps;
+  };
+  std::vector<Group> groups;
+  const bool mixed = scheme < 0;
+  const int es = mixed ? kSetExplicit : set, bs = mixed ? kSetBtcs : set;
+  const bool want_exp = scheme == BURGERS_EXPLICIT || (mixed && !ctx->set_explicit.empty() && nsteps > 0);
+  const bool want_btcs = scheme == BURGERS_BTCS || (mixed && !ctx->set_btcs.empty() && nsteps_btcs > 0);
+  const int64_t bsteps = mixed ? nsteps_btcs : nsteps;
+  for (int part : {kPartOnChip, kPartThroughHbm}) {
+    if (want_exp && explicit_part_busy(*ctx->explicit_plans[es], part)) groups.push_back({false, es, part, nsteps});
+    if (want_btcs && btcs_part_busy(*ctx->btcs[bs], part)) groups.push_back({true, bs, part, bsteps});
+  }
+  auto run = [&](const Group& g) {
+    return g.btcs ? enqueue_btcs(ctx, g.set, u, g.steps, g.part) : enqueue_explicit(ctx, g.set, u, g.steps, g.part);
+  };
+  if (groups.size() <= 1 || ctx->plan.serial == 1) {
+    for (const Group& g : groups) {
+      hipError_t e = run(g);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  hipError_t e;
+  const size_t nside = groups.size() - 1;
+  for (size_t k = 0; k < nside; ++k) {
+    if (!ctx->side[k] && (e = hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking)) != hipSuccess) return e;
+    if (!ctx->joined[k] && (e = hipEventCreateWithFlags(&ctx->joined[k], hipEventDisableTiming)) != hipSuccess)
+      return e;
+  }
+  if (!ctx->forked && (e = hipEventCreateWithFlags(&ctx->forked, hipEventDisableTiming)) != hipSuccess) return e;
+  hipStream_t main = ctx->stream;
+  if ((e = hipEventRecord(ctx->forked, main)) != hipSuccess) return e;
+  hipError_t err = hipSuccess;
+  for (size_t k = 0; k < nside && err == hipSuccess; ++k) {
+    if ((err = hipStreamWaitEvent(ctx->side[k], ctx->forked, 0)) != hipSuccess) break;
+    ctx->stream = ctx->side[k];
+    err = run(groups[k + 1]);
+    ctx->stream = main;
+    if (err == hipSuccess) err = hipEventRecord(ctx->joined[k], ctx->side[k]);
+    if (err == hipSuccess) err = hipStreamWaitEvent(main, ctx->joined[k], 0);
+  }
+  ctx->stream = main;
+  if (err != hipSuccess) return err;
+  return run(groups[0]);
 }
 
 burgers_status prepare(burgers_ctx* ctx, int set, int scheme) {
@@ -904,6 +961,11 @@ void burgers_destroy(burgers_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (auto& kv : ctx->graph_cache) (void)hipGraphExecDestroy(kv.second);
   if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+  for (int k = 0; k < 3; ++k) {
+    if (ctx->side[k]) (void)hipStreamDestroy(ctx->side[k]);
+    if (ctx->joined[k]) (void)hipEventDestroy(ctx->joined[k]);
+  }
+  if (ctx->forked) (void)hipEventDestroy(ctx->forked);
   delete ctx;
 }
 
@@ -970,57 +1032,84 @@ burgers_status burgers_autotune(burgers_ctx* ctx, const void* u, int64_t explici
   if (e != hipSuccess) return note(ctx, e);
   const bool has_exp = !ctx->set_explicit.empty() && explicit_steps > 0;
   const bool has_btcs = !ctx->set_btcs.empty() && btcs_steps > 0;
-  bool long_exp = false;
+  bool long_exp = false, long_btcs = false;
   for (int32_t i : ctx->set_explicit)
     if (ctx->probs[i].n > burgers::explicit_block_capacity()) long_exp = true;
-  std::vector<burgers_plan> cands;
-  const burgers_plan base = ctx->plan;
-  std::vector<std::pair<int, int>> exp_opts = {{0, 0}};            // (path, depth)
-  if (has_exp) {
-    exp_opts.clear();
-    if (long_exp) for (int d : {32, 64, 128, 256}) exp_opts.push_back({0, d});
-    else exp_opts.push_back({0, 0});
-    exp_opts.push_back({1, 0});
+  for (int32_t i : ctx->set_btcs) {
+    const burgers_problem& p = ctx->probs[i];
+    if ((p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2) > burgers::btcs_wg_capacity()) long_btcs = true;
   }
-  std::vector<int> blocks = {0};
-  if (has_btcs) blocks = {512, 1024};
-  for (auto eo : exp_opts)
-    for (int bl : blocks)
-      for (int g : {0, 1}) {
-        burgers_plan p = base;
-        p.explicit_path = eo.first;
-        p.tblock_depth = eo.second;
-        p.btcs_path = 0;
-        p.btcs_block = bl;
-        p.use_graph = g;
-        cands.push_back(p);
-      }
+  // One knob at a time (coordinate descent from the current plan): the explicit path and window depth,
+  // the lanes per 8192-row BTCS system, the long-system BTCS solver, concurrent launch groups, graph
+  // replay.  Each candidate runs twice on a scratch copy of u (the first run builds its plans and
+  // graphs) and the second run is timed.
+  using Setter = void (*)(burgers_plan&, int);
+  struct Knob {
+    std::vector<int> values;
+    Setter set;
+  };
+  std::vector<Knob> knobs;
+  if (has_exp) {
+    std::vector<int> v = {0};                                     // automatic (whole instances, windows)
+    if (long_exp) v = {4, 8, 16, 32, 64, 128, 256};               // window depth (steps per HBM pass)
+    v.push_back(-1);                                              // one step per HBM pass
+    knobs.push_back({v, [](burgers_plan& p, int x) {
+                       p.explicit_path = x < 0 ? 1 : 0;
+                       p.tblock_depth = x > 0 ? x : 0;
+                     }});
+  }
+  if (has_btcs) {
+    knobs.push_back({{512, 1024}, [](burgers_plan& p, int x) { p.btcs_block = x; }});
+    if (long_btcs) knobs.push_back({{0, 2, 1}, [](burgers_plan& p, int x) { p.btcs_long = x; }});
+  }
+  knobs.push_back({{0, 1}, [](burgers_plan& p, int x) { p.serial = x; }});
+  knobs.push_back({{0, 1}, [](burgers_plan& p, int x) { p.use_graph = x; }});
+  const burgers_plan base = ctx->plan;
   DevBuf scratch;
   if ((e = scratch.alloc(static_cast<size_t>(ctx->total) * ctx->word, ctx->stream)) != hipSuccess) return from_hip(e);
   hipEvent_t t0, t1;
   if ((e = hipEventCreate(&t0)) != hipSuccess) return from_hip(e);
   if ((e = hipEventCreate(&t1)) != hipSuccess) { (void)hipEventDestroy(t0); return from_hip(e); }
   const size_t bytes = static_cast<size_t>(ctx->total) * ctx->word;
-  double best_t = INFINITY;
-  burgers_plan best_p = base;
   burgers_status st = BURGERS_OK;
-  for (const burgers_plan& p : cands) {
-    if ((st = burgers_set_plan(ctx, &p)) != BURGERS_OK) break;
+  // time one plan; +inf when it cannot serve the batch
+  auto time_plan = [&](const burgers_plan& p, double& ms_out) -> bool {
+    ms_out = INFINITY;
+    if ((st = burgers_set_plan(ctx, &p)) != BURGERS_OK) return false;
     float ms = 0.0f;
-    for (int rep = 0; rep < 2; ++rep) {      // first run builds plans and graphs
-      if ((e = hipMemcpyAsync(scratch.ptr, u, bytes, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess) break;
-      if ((e = hipEventRecord(t0, ctx->stream)) != hipSuccess) break;
+    for (int rep = 0; rep < 2; ++rep) {
+      if ((e = hipMemcpyAsync(scratch.ptr, u, bytes, hipMemcpyDeviceToDevice, ctx->stream)) != hipSuccess) return false;
+      if ((e = hipEventRecord(t0, ctx->stream)) != hipSuccess) return false;
       st = advance(ctx, scratch.ptr, explicit_steps, kSetAll, -1, btcs_steps);
-      if (st != BURGERS_OK) break;
-      if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess) break;
-      if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) break;
+      if (st == BURGERS_E_UNSUPPORTED) {
+        st = BURGERS_OK;
+        return true;
+      }
+      if (st != BURGERS_OK) return false;
+      if ((e = hipEventRecord(t1, ctx->stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess) return false;
+      if ((e = hipEventElapsedTime(&ms, t0, t1)) != hipSuccess) return false;
     }
-    if (st == BURGERS_E_UNSUPPORTED) { st = BURGERS_OK; continue; }
-    if (e != hipSuccess || st != BURGERS_OK) break;
-    if (ms < best_t) {
-      best_t = ms;
-      best_p = p;
+    ms_out = ms;
+    return true;
+  };
+  burgers_plan best_p = base;
+  best_p.explicit_path = 0;
+  best_p.btcs_path = 0;
+  double best_t = INFINITY;
+  bool ok = time_plan(best_p, best_t);
+  for (size_t k = 0; ok && k < knobs.size(); ++k) {
+    burgers_plan knob_best = best_p;
+    for (int v : knobs[k].values) {
+      burgers_plan p = best_p;
+      knobs[k].set(p, v);
+      double t;
+      if (!(ok = time_plan(p, t))) break;
+      if (t < best_t) {
+        best_t = t;
+        knob_best = p;
+      }
     }
+    best_p = knob_best;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
@@ -1028,9 +1117,9 @@ burgers_status burgers_autotune(burgers_ctx* ctx, const void* u, int64_t explici
     (void)burgers_set_plan(ctx, &base);
     return note(ctx, e);
   }
-  if (st != BURGERS_OK) {
+  if (st != BURGERS_OK || !std::isfinite(best_t)) {
     (void)burgers_set_plan(ctx, &base);
-    return st;
+    return st != BURGERS_OK ? st : BURGERS_E_UNSUPPORTED;
   }
   (void)burgers_set_plan(ctx, &best_p);
   if (best) *best = best_p;
@@ -1133,7 +1222,7 @@ burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan) {
   if (plan->explicit_path < 0 || plan->explicit_path > 3 || plan->btcs_path < 0 || plan->btcs_path > 3 ||
       plan->tblock_depth < 0 || plan->tblock_depth > kMaxDepth || plan->use_graph < -1 || plan->use_graph > 1 ||
       (plan->btcs_block != 0 && plan->btcs_block != 512 && plan->btcs_block != 1024) ||
-      plan->btcs_long < 0 || plan->btcs_long > 2)
+      plan->btcs_long < 0 || plan->btcs_long > 2 || plan->serial < 0 || plan->serial > 1)
     return BURGERS_E_INVALID;
   const bool explicit_changed = plan->explicit_path != ctx->plan.explicit_path ||
                                 plan->tblock_depth != ctx->plan.tblock_depth;

@@ -272,6 +272,10 @@ struct burgers_ctx {
   // launch sequences captured as graphs, keyed by (subset, scheme, steps, BTCS steps, state buffer)
   std::map<std::tuple<int, int, int64_t, int64_t, void*>, hipGraphExec_t> graph_cache;
   hipStream_t capture_stream = nullptr;      // private non-blocking stream used only for capture
+  // side streams (default priority) and events of the concurrent launch groups of a call
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t joined[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t forked = nullptr;
   std::unique_ptr<burgers::AdjointPlan> adjoint;
   std::unique_ptr<burgers::NewtonPlan> newton;
   hipError_t sticky = hipSuccess;

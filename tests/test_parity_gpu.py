@@ -490,6 +490,22 @@ def test_run_mixed_step_counts(graph):
         assert rel_err(got[lo:hi], ref[lo:hi]) <= TOL_F64, b
 
 
+@pytest.mark.parametrize("graph", [0, 1])
+def test_concurrent_groups_equal_serial(graph):
+    """The launch groups of a call (on-chip and through-HBM instances of each scheme) run concurrently on
+    side streams by default: results bitwise equal to running them one after another, eager and as a
+    graph, and within the oracle bars."""
+    batch = W.random_batch(141, 40, 3, 40000, amplitude=2.0)
+    for k, p in enumerate(batch.problems):
+        p.scheme = (W.EXPLICIT, W.BTCS, W.RK4, W.CN, W.EXPLICIT, W.BTCS)[k % 6]
+    set_cfl_steps(batch, btcs_factor=2.0)
+    announce(f"concurrent vs serial groups graph={graph}")
+    a = device_run(batch, 9, "f64", how="run", plan=dict(use_graph=graph, serial=0), reps=2)
+    b = device_run(batch, 9, "f64", how="run", plan=dict(use_graph=graph, serial=1), reps=2)
+    assert np.array_equal(a, b)
+    check_batch(batch, a, 18, "f64")
+
+
 def test_autotune_keeps_state_and_results(tmp_path):
     """The autotuner times candidates on a scratch copy: u is untouched, the chosen plan still matches
     the oracle, and a cached choice is reused."""
