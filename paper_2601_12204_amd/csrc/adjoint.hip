@@ -22,57 +22,100 @@ namespace burgers {
 namespace {
 
 constexpr int kAdjThreads = 256;
+constexpr int kAdjLaneNodes = 4;                          // consecutive nodes per lane (two 16-byte vectors)
+constexpr int kAdjTile = kAdjThreads * kAdjLaneNodes;     // nodes of one adjoint tile (one dJ/dD slot)
 
+// Sum over the workgroup in a fixed order (a butterfly within each wave, lane 0's result, then the waves
+// in order), so that the per-tile partials of dJ/dD are deterministic.  Valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = kAdjThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] = red[t] + red[t + s];
-    __syncthreads();
-  }
-  return red[0];
+  double tot = red[0];
+#pragma unroll
+  for (int w = 1; w < kAdjThreads / 64; ++w) tot = tot + red[w];
+  return tot;
 }
 
-// lam = (dE/du)^T lamp at state u; partial dJ/dD of the tile added to gslot[tile.slot].
+// lam = (dE/du)^T lamp at state u; partial dJ/dD of the tile added to gslot[tile.slot].  Each lane takes
+// kAdjLaneNodes consecutive nodes, loaded as 16-byte vectors with one neighbour on each side.
 __global__ __launch_bounds__(kAdjThreads) void adj_explicit_kernel(
     const InstDesc* __restrict__ inst, const AdjTile* __restrict__ tiles, const double* __restrict__ u,
     const double* __restrict__ lamp, double* __restrict__ lam, double* __restrict__ gslot) {
-  __shared__ double red[kAdjThreads];
+  constexpr int V = kAdjLaneNodes;
+  __shared__ double red[kAdjThreads / 64];
   const AdjTile t = tiles[blockIdx.x];
   const InstDesc d = inst[t.inst];
   const int n = t.n;
-  const int j = t.start + static_cast<int>(threadIdx.x);
+  const int j0 = t.start + V * static_cast<int>(threadIdx.x);
   const bool periodic = t.bc == kPeriodic;
   const double* __restrict__ y = u + t.off;
   const double* __restrict__ lp = lamp + t.off;
   const double r = d.r, D = d.D;
   double g = 0.0;
-  if (j < n) {
-    double acc = 0.0;
-    if (periodic || (j > 0 && j < n - 1)) {
-      const int jm = j == 0 ? n - 1 : j - 1;
-      const int jp = j == n - 1 ? 0 : j + 1;
-      const double uj = y[j];
-      const double um = (!periodic && j == 1) ? d.a : y[jm];
-      const double up = (!periodic && j == n - 2) ? d.b : y[jp];
-      // own update
-      const double self = uj >= 0.0 ? ((1.0 - r * (uj - um)) - r * uj) - 2.0 * D
-                                    : ((1.0 - r * (up - uj)) + r * uj) - 2.0 * D;
-      acc = self * lp[j];
-      g = lp[j] * ((up + um) - 2.0 * uj);
-      // node j+1 reads u_j as its left neighbour
-      if (periodic || j + 1 <= n - 2) {
-        const double uk = y[jp];
-        acc = acc + (uk >= 0.0 ? r * uk + D : D) * lp[jp];
-      }
-      // node j-1 reads u_j as its right neighbour
-      if (periodic || j - 1 >= 1) {
-        const double uk = y[jm];
-        acc = acc + (uk >= 0.0 ? D : D - r * uk) * lp[jm];
+  if (j0 < n) {
+    // Y[q], L[q]: state and lamp at node j0 - 1 + q (periodic neighbours wrap; positions outside a
+    // Dirichlet grid are never used)
+    double Y[V + 2], L[V + 2];
+    if (j0 + V <= n) {
+      const double2 y0 = *reinterpret_cast<const double2*>(y + j0);
+      const double2 y1 = *reinterpret_cast<const double2*>(y + j0 + 2);
+      const double2 l0 = *reinterpret_cast<const double2*>(lp + j0);
+      const double2 l1 = *reinterpret_cast<const double2*>(lp + j0 + 2);
+      Y[1] = y0.x; Y[2] = y0.y; Y[3] = y1.x; Y[4] = y1.y;
+      L[1] = l0.x; L[2] = l0.y; L[3] = l1.x; L[4] = l1.y;
+    } else {
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const int j = j0 + q < n ? j0 + q : (periodic ? j0 + q - n : n - 1);
+        Y[q + 1] = y[j];
+        L[q + 1] = lp[j];
       }
     }
-    lam[t.off + j] = acc;
+    const int jl = j0 > 0 ? j0 - 1 : (periodic ? n - 1 : 0);
+    int jr = j0 + V;
+    if (jr >= n) jr = periodic ? jr - n : n - 1;
+    Y[0] = y[jl];
+    L[0] = lp[jl];
+    Y[V + 1] = y[jr];
+    L[V + 1] = lp[jr];
+    double out[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int j = j0 + q;
+      double acc = 0.0;
+      if (j < n && (periodic || (j > 0 && j < n - 1))) {
+        const double uj = Y[q + 1];
+        const double um = (!periodic && j == 1) ? d.a : Y[q];
+        const double up = (!periodic && j == n - 2) ? d.b : Y[q + 2];
+        // own update
+        const double self = uj >= 0.0 ? ((1.0 - r * (uj - um)) - r * uj) - 2.0 * D
+                                      : ((1.0 - r * (up - uj)) + r * uj) - 2.0 * D;
+        acc = self * L[q + 1];
+        g = g + L[q + 1] * ((up + um) - 2.0 * uj);
+        // node j+1 reads u_j as its left neighbour
+        if (periodic || j + 1 <= n - 2) {
+          const double uk = Y[q + 2];
+          acc = acc + (uk >= 0.0 ? r * uk + D : D) * L[q + 2];
+        }
+        // node j-1 reads u_j as its right neighbour
+        if (periodic || j - 1 >= 1) {
+          const double uk = Y[q];
+          acc = acc + (uk >= 0.0 ? D : D - r * uk) * L[q];
+        }
+      }
+      out[q] = acc;
+    }
+    double* __restrict__ dst = lam + t.off;
+    if (j0 + V <= n) {
+      *reinterpret_cast<double2*>(dst + j0) = double2{out[0], out[1]};
+      *reinterpret_cast<double2*>(dst + j0 + 2) = double2{out[2], out[3]};
+    } else {
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        if (j0 + q < n) dst[j0 + q] = out[q];
+    }
   }
   const double tot = block_sum(g, red);
   if (threadIdx.x == 0) gslot[t.slot] = gslot[t.slot] + tot;
@@ -83,15 +126,18 @@ __global__ __launch_bounds__(kAdjThreads) void adj_explicit_kernel(
 __global__ __launch_bounds__(kAdjThreads) void adj_btcs_assemble_kernel(
     const InstDesc* __restrict__ inst, const AdjTile* __restrict__ tiles, const double* __restrict__ u,
     const double* __restrict__ lamp, double* __restrict__ LA, double* __restrict__ LC,
-    double* __restrict__ LD) {
+    double* __restrict__ LD, const int* __restrict__ only) {
   const AdjTile t = tiles[blockIdx.x];
+  if (only && only[t.inst] == 0) return;      // this instance's windows held
   const InstDesc d = inst[t.inst];
   const int n = t.n;
   const bool periodic = t.bc == kPeriodic;
   const int first = periodic ? 0 : 1;
   const int m = periodic ? n : n - 2;
-  const int k = t.start + static_cast<int>(threadIdx.x) - first;   // unknown index of this node
-  if (t.start + static_cast<int>(threadIdx.x) >= n || k < 0 || k >= m) return;
+  for (int q = 0; q < kAdjLaneNodes; ++q) {
+  const int node = t.start + static_cast<int>(threadIdx.x) + q * kAdjThreads;
+  const int k = node - first;   // unknown index of this node
+  if (node >= n || k < 0 || k >= m) continue;
   const double* __restrict__ y = u + t.off;
   double sub, diag, sup, tmp1, tmp2;
   btcs_row(y[first + k], d.r, d.D, sub, diag, sup);
@@ -108,20 +154,30 @@ __global__ __launch_bounds__(kAdjThreads) void adj_btcs_assemble_kernel(
   LA[o] = sub_t / diag;
   LC[o] = sup_t / diag;
   LD[o] = lamp[t.off + first + k] / diag;
+  }
 }
 
-// lam = (1 - G) mu and the tile's partial -mu . (L x); boundary nodes get zero.
+// lam = (1 - G) mu and the tile's partial -mu . (L x); boundary nodes get zero.  With windows (n_win > 0),
+// workgroup b first adds window b's partial (wpart) to the window's slot unless its instance was flagged,
+// and only the flagged instances' tiles are finished here.
 __global__ __launch_bounds__(kAdjThreads) void adj_btcs_finish_kernel(
     const InstDesc* __restrict__ inst, const AdjTile* __restrict__ tiles, const double* __restrict__ u,
     const double* __restrict__ x, const double* __restrict__ X, double* __restrict__ lam,
-    double* __restrict__ gslot) {
-  __shared__ double red[kAdjThreads];
+    double* __restrict__ gslot, const int* __restrict__ only, const WinDesc* __restrict__ wins, int64_t n_win,
+    const int32_t* __restrict__ win_slot, const double* __restrict__ wpart) {
+  __shared__ double red[kAdjThreads / 64];
+  if (static_cast<int64_t>(blockIdx.x) < n_win && threadIdx.x == 0) {
+    const int wi = wins[blockIdx.x].inst;
+    if (only[wi] == 0) gslot[win_slot[blockIdx.x]] = gslot[win_slot[blockIdx.x]] + wpart[blockIdx.x];
+  }
   const AdjTile t = tiles[blockIdx.x];
+  if (only && only[t.inst] == 0) return;
   const InstDesc d = inst[t.inst];
   const int n = t.n;
-  const int j = t.start + static_cast<int>(threadIdx.x);
   const bool periodic = t.bc == kPeriodic;
   double g = 0.0;
+  for (int q = 0; q < kAdjLaneNodes; ++q) {
+  const int j = t.start + static_cast<int>(threadIdx.x) + q * kAdjThreads;
   if (j < n) {
     double out = 0.0;
     if (periodic || (j > 0 && j < n - 1)) {
@@ -133,9 +189,10 @@ __global__ __launch_bounds__(kAdjThreads) void adj_btcs_finish_kernel(
       const double xj = xs[j];
       const double G = u[t.off + j] >= 0.0 ? d.r * (xj - xm) : d.r * (xp - xj);
       out = (1.0 - G) * mu;
-      g = -(mu * ((2.0 * xj - xm) - xp));
+      g = g - mu * ((2.0 * xj - xm) - xp);
     }
     lam[t.off + j] = out;
+  }
   }
   const double tot = block_sum(g, red);
   if (threadIdx.x == 0) gslot[t.slot] = gslot[t.slot] + tot;
@@ -169,7 +226,7 @@ __global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
 
 }  // namespace
 
-int adjoint_tile_nodes() { return kAdjThreads; }
+int adjoint_tile_nodes() { return kAdjTile; }
 
 hipError_t launch_adj_explicit(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const double* u,
                                const double* lamp, double* lam, double* gslot) {
@@ -180,19 +237,22 @@ hipError_t launch_adj_explicit(const burgers_ctx* ctx, const AdjTile* tiles, int
 }
 
 hipError_t launch_adj_btcs_assemble(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles,
-                                    const double* u, const double* lamp, double* LA, double* LC, double* LD) {
+                                    const double* u, const double* lamp, double* LA, double* LC, double* LD,
+                                    const int* only) {
   if (n_tiles <= 0) return hipSuccess;
   adj_btcs_assemble_kernel<<<static_cast<unsigned>(n_tiles), kAdjThreads, 0, ctx->stream>>>(
-      ctx->inst.as<InstDesc>(), tiles, u, lamp, LA, LC, LD);
+      ctx->inst.as<InstDesc>(), tiles, u, lamp, LA, LC, LD, only);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_btcs_finish(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles,
                                   const double* u, const double* x, const double* X, double* lam,
-                                  double* gslot) {
+                                  double* gslot, const int* only, const WinDesc* wins, int64_t n_win,
+                                  const int32_t* win_slot, const double* wpart) {
   if (n_tiles <= 0) return hipSuccess;
+  if (n_win > n_tiles) return hipErrorInvalidValue;   // every window's partial needs a workgroup
   adj_btcs_finish_kernel<<<static_cast<unsigned>(n_tiles), kAdjThreads, 0, ctx->stream>>>(
-      ctx->inst.as<InstDesc>(), tiles, u, x, X, lam, gslot);
+      ctx->inst.as<InstDesc>(), tiles, u, x, X, lam, gslot, only, wins, n_win, win_slot, wpart);
   return hipGetLastError();
 }
 

@@ -1096,6 +1096,149 @@ __global__ __launch_bounds__(NT, 4) void btcs_window_kernel(
   }
 }
 
+// ---- Adjoint BTCS step on truncated windows of the transposed system -----------------------------
+// The discrete adjoint of a BTCS step (y = u^k -> x = u^{k+1}) solves A(y)^T mu = lam' and then sets
+// lam = (1 - G) mu with G_i = r (x_i - x_{i-1}) for y_i >= 0, r (x_{i+1} - x_i) otherwise, and adds
+// -mu . (2 x_i - x_{i-1} - x_{i+1}) to dJ/dD.  Row i of A^T couples mu_{i-1} with p_{i-1} (the
+// super-diagonal entry of row i-1 of A), mu_i with d_i and mu_{i+1} with l_{i+1}.
+//
+// A window of W rows solves those rows of A^T with the unknowns beyond its ends taken as zero, keeps the
+// rows at least kWinHalo inside, and finishes them in the same kernel.  The error of a kept row: the window
+// solution differs from the exact one by A_w^{-T} applied to the two dropped couplings times the exact
+// mu at the ghosts, i.e. |e_i| <= (A_w^{-1})_{f,i} |p_{s-1}| |mu| + (A_w^{-1})_{l,i} |l_{s+W}| |mu| for the
+// window's first and last rows f, l.  A_w is a strictly row-diagonally dominant M-matrix with row sums
+// >= 1, so A_w^{-1} >= 0 with row sums <= 1, and a column of A_w^{-1} decays from its diagonal like the
+// barrier of the forward windows: (A_w^{-1})_{f,i} <= theta^(i-f).  The couplings are at most D + C.  A
+// kept row is therefore within 2 (D + C) theta^(kWinHalo+1) max|mu| of the exact solution, and each
+// window checks (kWinHalo + 1) log2 theta + log2(D + C) <= -55 (error <= 2^-54 max|mu|).  A window that
+// fails flags its instance; the array path (assembled rows, partition levels, finish) then redoes that
+// instance's step.  The window writes its partial sum of dJ/dD (kept rows, fixed order) to wpart; the
+// finish launch adds it to the window's slot unless the instance was redone.
+struct AdjRows {
+  const double* ys;   // y of window row k at ys[padded(k + 1)], k = -1..W
+  double r, D;
+  DirichletEnds ends; // zero ghosts: the dropped couplings just vanish
+  __device__ __forceinline__ void row_value(double lamp, int k, int, double& al, double& be, double& ga,
+                                            double& de) const {
+    double t0, t1, t2, t3;
+    btcs_row(ys[padded(k)], r, D, t0, t1, al);       // p_{k-1}
+    btcs_row(ys[padded(k + 1)], r, D, t2, be, t3);   // d_k
+    btcs_row(ys[padded(k + 2)], r, D, ga, t0, t1);   // l_{k+1}
+    de = lamp;
+  }
+};
+
+template <int NT>
+__global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
+    const InstDesc* __restrict__ inst, const WinDesc* __restrict__ wins, const double* __restrict__ u,
+    const double* __restrict__ x, const double* __restrict__ lamp, double* __restrict__ lam,
+    double* __restrict__ wpart, int* __restrict__ flag_now, int* __restrict__ flag_next) {
+  using T = double;
+  constexpr int MC = kWgChunk, W = NT * MC;
+  using IS = InterfaceSpace<T, NT>;
+  constexpr int kStageBytes = padded_size(W + 2) * 8;
+  constexpr int kBytes = kStageBytes > IS::kBytes ? kStageBytes : IS::kBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  __shared__ uint64_t iface_votes[2 * IS::kVoteWords];
+  __shared__ T wave_val[NT / 64];
+  const IS iws{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + 3 * NT, iface_votes};
+  iws.clear_votes();
+  T* stage = reinterpret_cast<T*>(smem);
+  const WinDesc wd = wins[blockIdx.x];
+  const InstDesc d = inst[wd.inst];
+  const bool dir = d.bc == kDirichlet;
+  const int first = dir ? 1 : 0;
+  const int R = dir ? d.n - 2 : d.n;           // > W
+  const int n = d.n;
+  const double* __restrict__ yn = u + d.off;   // by node
+  const int tid = threadIdx.x;
+  // node of window row k (k = -1..W): periodic rows wrap; Dirichlet rows -1 and R are the end nodes
+  auto node_of = [&](int k) {
+    int row = wd.start + k;
+    if (!dir) {
+      if (row < 0) row += R;
+      if (row >= R) row -= R;
+    }
+    return row + first;
+  };
+  // lam' of the window's rows into the lanes' chunks (through LDS, coalesced)
+  T de[MC];
+#pragma unroll
+  for (int j = 0; j < MC; ++j) stage[padded(tid + j * NT)] = lamp[d.off + node_of(tid + j * NT)];
+  __syncthreads();
+  const int s = tid * MC;
+#pragma unroll
+  for (int j = 0; j < MC; ++j) de[j] = stage[padded(s + j)];
+  __syncthreads();
+  // y of rows -1..W, and max |y| over them
+  T big = T(0);
+  for (int k = tid - 1; k <= W; k += NT) {
+    const T v = yn[node_of(k)];
+    stage[padded(k + 1)] = v;
+    big = __builtin_fmax(big, __builtin_fabs(v));
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) big = __builtin_fmax(big, __shfl_xor(big, m, 64));
+  if ((tid & 63) == 0) wave_val[tid >> 6] = big;
+  __syncthreads();
+  if (tid == 0) {
+    T M = T(0);
+#pragma unroll
+    for (int k = 0; k < NT / 64; ++k) M = __builtin_fmax(M, wave_val[k]);
+    const T C = d.r * M;
+    const T theta = 2.0 * (d.D + C) / ((1.0 + 2.0 * d.D + C) + __builtin_sqrt((1.0 + C) * (1.0 + C) + 4.0 * d.D));
+    const T coup = d.D + C;
+    flag_next[wd.inst] = 0;
+    const bool ok = coup == 0.0 || theta == 0.0 ||
+                    (kWinHalo + 1) * log2(theta) + log2(coup) <= -55.0;
+    if (!ok) flag_now[wd.inst] = 1;
+  }
+  T al[MC], ga[MC];
+  T ia = T(0), ib = T(1), ic = T(0), id = T(0);
+  const AdjRows rows{stage, d.r, d.D, DirichletEnds{0.0, 0.0, true}};
+  interface_eliminate<T, MC, true>(rows, s, MC, W, al, ga, de, ia, ib, ic, id);
+  __syncthreads();                             // every row read: the interface LDS overlays the stage
+  T yv, yp;
+  interface_solve<T, NT>(iws, NT, al[0], ga[0], de[0], al[MC - 2], ga[MC - 2], de[MC - 2], ia, ib, ic, id, yv, yp);
+  __syncthreads();                             // the interface unknowns read before mu is written
+#pragma unroll
+  for (int j = 0; j < MC; ++j)
+    stage[padded(s + j)] = j < MC - 1 ? __builtin_fma(-ga[j], yv, __builtin_fma(-al[j], yp, de[j])) : yv;
+  __syncthreads();
+  // finish the kept rows: lam = (1 - G) mu, and the partial sum of -mu (2 x_j - x_{j-1} - x_{j+1})
+  const double* __restrict__ xn = x + d.off;
+  T g = T(0);
+  int lane = tid;
+  asm volatile("" : "+v"(lane));
+  for (int o = lane; o < wd.count; o += NT) {
+    const int k = wd.lo + o;
+    const int j = node_of(k);
+    const T mu = stage[padded(k)];
+    const T xm = dir ? (j == 1 ? d.a : xn[j - 1]) : xn[j == 0 ? n - 1 : j - 1];
+    const T xp = dir ? (j == n - 2 ? d.b : xn[j + 1]) : xn[j == n - 1 ? 0 : j + 1];
+    const T xj = xn[j];
+    const T G = yn[j] >= 0.0 ? d.r * (xj - xm) : d.r * (xp - xj);
+    lam[d.off + j] = (1.0 - G) * mu;
+    g = g - mu * ((2.0 * xj - xm) - xp);
+  }
+  if (dir && tid == 0) {
+    if (wd.start == 0) lam[d.off] = 0.0;
+    if (wd.start + W == R) lam[d.off + n - 1] = 0.0;
+  }
+  // the window's partial, summed in a fixed order
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) g = g + __shfl_xor(g, m, 64);
+  __syncthreads();
+  if ((tid & 63) == 0) wave_val[tid >> 6] = g;
+  __syncthreads();
+  if (tid == 0) {
+    T tot = wave_val[0];
+#pragma unroll
+    for (int k = 1; k < NT / 64; ++k) tot = tot + wave_val[k];
+    wpart[blockIdx.x] = tot;
+  }
+}
+
 constexpr int kSpikeWaves = kReduceBlock / 64;
 
 // One row of a block's interface system in spike form: unit diagonal, couplings a (row i - s) and c
@@ -1673,7 +1816,7 @@ int btcs_wg_lanes(const std::vector<SysDesc>& systems) {
 // Solve systems stored in (A, C, D) arrays with unit diagonal (all levels array-sourced); the solution
 // lands in X at each root system's offset.  levels[0] holds the roots that need partitioning.
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
-                              double* LD, double* LX) {
+                              double* LD, double* LX, const int* only) {
   const InstDesc* inst = ctx->inst.as<InstDesc>();
   hipStream_t st = ctx->stream;
   const double* none = nullptr;
@@ -1683,15 +1826,15 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
     const auto& lv = plan.levels[l];
     if (lv.n_blocks)
       btcs_array_reduce_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
-                                                                     lv.blocks->as<ChunkBlock>(), LA, LC, LD, nullptr);
+                                                                     lv.blocks->as<ChunkBlock>(), LA, LC, LD, only);
   }
   for (int l = L - 1; l >= 0; --l) {
     const auto& lv = plan.levels[l];
-    if (lv.n_wg) reduced_wg_launch<double>(lv, inst, none, none_out, LA, LC, LD, LX, st, nullptr);
+    if (lv.n_wg) reduced_wg_launch<double>(lv, inst, none, none_out, LA, LC, LD, LX, st, only);
     if (lv.n_blocks)
       btcs_array_backsub_kernel<<<lv.n_blocks, kReduceBlock, 0, st>>>(lv.sys->as<SysDesc>(),
                                                                       lv.blocks->as<ChunkBlock>(), LA, LC, LD, LX,
-                                                                      nullptr);
+                                                                      only);
   }
   return hipGetLastError();
 }
@@ -1709,6 +1852,15 @@ hipError_t launch_btcs_window_reset(const burgers_ctx* ctx, const BtcsPlan& plan
 }
 
 int btcs_window_halo() { return kWinHalo; }
+
+hipError_t launch_adj_btcs_windows(const burgers_ctx* ctx, const WinDesc* wins, int64_t n_win, const double* u,
+                                   const double* x, const double* lamp, double* lam, double* wpart, int* flag_now,
+                                   int* flag_next) {
+  if (n_win <= 0) return hipSuccess;
+  adj_btcs_window_kernel<256><<<static_cast<unsigned>(n_win), 256, 0, ctx->stream>>>(
+      ctx->inst.as<InstDesc>(), wins, u, x, lamp, lam, wpart, flag_now, flag_next);
+  return hipGetLastError();
+}
 
 hipError_t launch_clear_ints(const burgers_ctx* ctx, int* p, int64_t n) {
   if (n <= 0) return hipSuccess;

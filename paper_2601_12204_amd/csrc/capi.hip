@@ -59,7 +59,9 @@ void btcs_windows(int32_t i, int32_t R, bool periodic, int W, bool cn, std::vect
 
 namespace {
 
-enum SetId { kSetAll = 0, kSetExplicit = 1, kSetBtcs = 2 };
+// Instance subsets a plan is built for; kSetBtcsHbm holds the BTCS-scheme instances like kSetBtcs but
+// steps every one through HBM (the adjoint's out-of-place recompute of a checkpoint segment).
+enum SetId { kSetAll = 0, kSetExplicit = 1, kSetBtcs = 2, kSetBtcsHbm = 3 };
 
 bool valid_problem(const burgers_problem& p);
 double grid_dx(const burgers_problem& p);
@@ -124,6 +126,8 @@ burgers_status note(burgers_ctx* ctx, hipError_t e) {
 const std::vector<int32_t>& set_members(const burgers_ctx* ctx, int set) {
   return set == kSetAll ? ctx->set_all : (set == kSetExplicit ? ctx->set_explicit : ctx->set_btcs);
 }
+
+bool own_scheme_set(int set) { return set == kSetBtcs || set == kSetBtcsHbm; }
 
 // Copy a host table to a new device buffer, in stream order (a pageable source may be released as soon
 // as the call returns).
@@ -259,7 +263,7 @@ int32_t reduced_rows(int level, int32_t chunks) {
 }
 
 burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
-  const int want = ctx->plan.btcs_path;
+  const int want = set == kSetBtcsHbm ? 1 : ctx->plan.btcs_path;
   const int threads = ctx->plan.btcs_block ? ctx->plan.btcs_block : burgers::kResidentThreadsDefault;
   const int longmode = ctx->plan.btcs_long;
   auto found = ctx->btcs.find(set);
@@ -299,9 +303,9 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     const bool fits = R0 <= cap;
     // Crank-Nicolson instances (advanced by their own scheme) need the old state after each solve, so
     // they always step through HBM
-    const bool is_cn = set == kSetBtcs && p.scheme == BURGERS_CN;
+    const bool is_cn = own_scheme_set(set) && p.scheme == BURGERS_CN;
     if (is_cn) cn.push_back(i);
-    const bool is_newton = set == kSetBtcs && p.scheme == BURGERS_NEWTON;
+    const bool is_newton = own_scheme_set(set) && p.scheme == BURGERS_NEWTON;
     if (want == 2 && (!fits || is_cn || is_newton)) return BURGERS_E_UNSUPPORTED;
     if (is_newton) {            // Newton iterations of their own, through HBM every step
       stepped.push_back(i);
@@ -766,15 +770,31 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   }
   std::vector<std::tuple<int32_t, int64_t, int32_t>> roots;
   int64_t rows_used = sys_rows;
+  // windows of the transposed systems when every BTCS instance is longer than the on-chip limit
+  bool windows = false;
+  for (int32_t i : ctx->set_btcs) {
+    const burgers_problem& p = ctx->probs[i];
+    windows = (p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2) > burgers::btcs_wg_capacity();
+    if (!windows) break;
+  }
+  std::vector<burgers::WinDesc> wins;
+  std::vector<int32_t> win_slot;
   for (int32_t i = 0; i < ctx->count; ++i) {
     const burgers_problem& p = ctx->probs[i];
     const int32_t n = static_cast<int32_t>(p.n);
+    const int32_t R = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
     slot_begin[i] = slot;
     for (int64_t s = 0; s < n; s += tile)
       (p.scheme == BURGERS_BTCS ? bt : et)
           .push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, static_cast<int32_t>(s), slot++, 0});
-    if (p.scheme == BURGERS_BTCS)
-      roots.emplace_back(i, sys_off[i], static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2));
+    if (p.scheme == BURGERS_BTCS) {
+      roots.emplace_back(i, sys_off[i], R);
+      if (windows) {
+        const size_t w0 = wins.size();
+        burgers::btcs_windows(i, R, p.bc == BURGERS_BC_PERIODIC, 4096, false, wins);
+        for (size_t w = w0; w < wins.size(); ++w) win_slot.push_back(slot++);
+      }
+    }
   }
   slot_begin[ctx->count] = slot;
   hipError_t e;
@@ -787,6 +807,16 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   ap->n_exp_tiles = static_cast<int64_t>(et.size());
   ap->n_btcs_tiles = static_cast<int64_t>(bt.size());
   ap->n_slots = slot;
+  ap->win = std::make_unique<DevBuf>();
+  ap->win_slot = std::make_unique<DevBuf>();
+  if ((e = upload_on(ctx->stream, *ap->win, wins)) != hipSuccess ||
+      (e = upload_on(ctx->stream, *ap->win_slot, win_slot)) != hipSuccess)
+    return from_hip(e);
+  ap->n_win = static_cast<int64_t>(wins.size());
+  if (ap->n_win > ap->n_btcs_tiles) return BURGERS_E_UNSUPPORTED;   // (tiles of 1024 nodes outnumber windows)
+  if (ap->n_win > 0 && ((e = ap->wpart.alloc(static_cast<size_t>(ap->n_win) * sizeof(double), ctx->stream)) != hipSuccess ||
+                        (e = ap->flags.alloc(2 * static_cast<size_t>(ctx->count) * sizeof(int), ctx->stream)) != hipSuccess))
+    return from_hip(e);
   if ((e = build_array_solve(ctx, roots, ap->solve, rows_used)) != hipSuccess) return from_hip(e);
   const size_t lb = static_cast<size_t>(rows_used) * sizeof(double);
   if ((e = ap->LA.alloc(lb, ctx->stream)) != hipSuccess || (e = ap->LC.alloc(lb, ctx->stream)) != hipSuccess ||
@@ -802,23 +832,34 @@ hipError_t grow(DevBuf& b, size_t bytes, hipStream_t stream) {
   return b.alloc(bytes, stream);
 }
 
-// One adjoint step: lam_out from lam_in at the forward pair (y = u^k, x = u^{k+1}).
+// One adjoint step: lam_out from lam_in at the forward pair (y = u^k, x = u^{k+1}); `step` counts the
+// steps of the reverse sweep (it selects the parity slot of the window flags).
 hipError_t enqueue_adjoint_step(burgers_ctx* ctx, const double* y, const double* x, const double* lam_in,
-                                double* lam_out) {
+                                double* lam_out, int64_t step) {
   burgers::AdjointPlan& ap = *ctx->adjoint;
   double* g = ap.gslot.as<double>();
   hipError_t e = burgers::launch_adj_explicit(ctx, ap.exp_tiles->as<burgers::AdjTile>(), ap.n_exp_tiles, y,
                                               lam_in, lam_out, g);
   if (e != hipSuccess || ap.n_btcs_tiles == 0) return e;
+  const int* only = nullptr;
+  if (ap.n_win > 0) {
+    int* now = ap.flags.as<int>() + (step & 1) * ctx->count;
+    int* next = ap.flags.as<int>() + ((step + 1) & 1) * ctx->count;
+    if ((e = burgers::launch_adj_btcs_windows(ctx, ap.win->as<burgers::WinDesc>(), ap.n_win, y, x, lam_in, lam_out,
+                                              ap.wpart.as<double>(), now, next)) != hipSuccess)
+      return e;
+    only = now;
+  }
   if ((e = burgers::launch_adj_btcs_assemble(ctx, ap.btcs_tiles->as<burgers::AdjTile>(), ap.n_btcs_tiles, y,
                                              lam_in, ap.LA.as<double>(), ap.LC.as<double>(),
-                                             ap.LD.as<double>())) != hipSuccess)
+                                             ap.LD.as<double>(), only)) != hipSuccess)
     return e;
   if ((e = burgers::launch_array_solve(ctx, ap.solve, ap.LA.as<double>(), ap.LC.as<double>(), ap.LD.as<double>(),
-                                       ap.LX.as<double>())) != hipSuccess)
+                                       ap.LX.as<double>(), only)) != hipSuccess)
     return e;
   return burgers::launch_adj_btcs_finish(ctx, ap.btcs_tiles->as<burgers::AdjTile>(), ap.n_btcs_tiles, y, x,
-                                         ap.LX.as<double>(), lam_out, g);
+                                         ap.LX.as<double>(), lam_out, g, only, ap.win->as<burgers::WinDesc>(),
+                                         ap.n_win, ap.win_slot->as<int32_t>(), ap.wpart.as<double>());
 }
 
 // A context for `count` problems on the current device: validated, laid out, its workspace allocated
@@ -1139,6 +1180,7 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   if (e != hipSuccess) return note(ctx, e);
   burgers_status st = prepare(ctx, kSetAll, -1);
   if (st != BURGERS_OK) return st;
+  if (!ctx->set_btcs.empty() && (st = ensure_btcs(ctx, kSetBtcsHbm)) != BURGERS_OK) return st;
   if ((st = ensure_adjoint(ctx)) != BURGERS_OK) return st;
   burgers::AdjointPlan& ap = *ctx->adjoint;
   const size_t state_bytes = static_cast<size_t>(ctx->total) * sizeof(double);
@@ -1162,20 +1204,30 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   double* lam = ap.lam0.as<double>();
   double* lam_next = ap.lam1.as<double>();
   if ((e = hipMemcpyAsync(lam, lambda_T, state_bytes, d2d, ctx->stream)) != hipSuccess ||
-      (e = burgers::launch_fill(ctx, ap.gslot.as<double>(), ap.n_slots, 0.0)) != hipSuccess)
+      (e = burgers::launch_fill(ctx, ap.gslot.as<double>(), ap.n_slots, 0.0)) != hipSuccess ||
+      (ap.n_win > 0 && (e = burgers::launch_clear_ints(ctx, ap.flags.as<int>(), 2 * ctx->count)) != hipSuccess))
     return note(ctx, e);
+  int64_t rstep = 0;
+  // the segment's states are recomputed out of place, one step per launch from seg[k-1] straight into
+  // seg[k]: the streaming kernel for the explicit instances, the per-step solves for the BTCS ones
+  const burgers::ExplicitPlan* ep = ctx->set_explicit.empty() ? nullptr : ctx->explicit_plans[kSetExplicit].get();
+  const burgers::BtcsPlan* bp = ctx->set_btcs.empty() ? nullptr : ctx->btcs[kSetBtcsHbm].get();
   for (int64_t c = ncp - 1; c >= 0; --c) {
     const int64_t len = std::min(K, nsteps - c * K);
     if ((e = hipMemcpyAsync(state(ap.seg, 0), state(ap.ckpt, c), state_bytes, d2d, ctx->stream)) != hipSuccess)
       return note(ctx, e);
+    if (bp && (e = burgers::launch_btcs_window_reset(ctx, *bp)) != hipSuccess) return note(ctx, e);
     for (int64_t k = 1; k <= len; ++k) {
-      if ((e = hipMemcpyAsync(state(ap.seg, k), state(ap.seg, k - 1), state_bytes, d2d, ctx->stream)) != hipSuccess ||
-          (e = enqueue_all(ctx, kSetAll, -1, state(ap.seg, k), 1)) != hipSuccess)
+      if (ep && (e = burgers::launch_explicit_stream(ctx, ep->stream->as<Tile>(), ep->n_stream, state(ap.seg, k - 1),
+                                                     state(ap.seg, k))) != hipSuccess)
+        return note(ctx, e);
+      if (bp && (e = burgers::launch_btcs_step(ctx, *bp, state(ap.seg, k - 1), state(ap.seg, k), k - 1)) != hipSuccess)
         return note(ctx, e);
     }
     for (int64_t k = len - 1; k >= 0; --k) {
       if ((e = enqueue_adjoint_step(ctx, reinterpret_cast<const double*>(state(ap.seg, k)),
-                                    reinterpret_cast<const double*>(state(ap.seg, k + 1)), lam, lam_next)) != hipSuccess)
+                                    reinterpret_cast<const double*>(state(ap.seg, k + 1)), lam, lam_next,
+                                    rstep++)) != hipSuccess)
         return note(ctx, e);
       std::swap(lam, lam_next);
     }

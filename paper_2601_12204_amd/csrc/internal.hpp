@@ -229,6 +229,11 @@ struct AdjointPlan {
   BtcsPlan solve;                                   // partition hierarchy over the transposed systems
   DevBuf LA, LC, LD, LX, gslot;
   DevBuf ckpt, seg, lam0, lam1;                     // grown on demand
+  // truncated windows of the transposed systems (when every BTCS instance has more than 8192 rows); the
+  // array path above is then the fallback of the instances whose windows flag a failed bound
+  std::unique_ptr<DevBuf> win, win_slot;           // WinDesc[], int32[] (dJ/dD slot of each window)
+  int64_t n_win = 0;
+  DevBuf wpart, flags;                              // double[n_win]; int32[2][count] per step parity
 };
 
 // Fully implicit central-convection instances (Newton-Raphson, a fixed number of iterations per step):
@@ -311,11 +316,15 @@ int explicit_block_capacity();
 int adjoint_tile_nodes();
 hipError_t launch_adj_explicit(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const double* u,
                                const double* lamp, double* lam, double* gslot);
+// `only` (optional): only the instances whose entry is nonzero (those whose windows flagged a failed
+// bound); the finish launch also adds the windows' partials (wins/win_slot/wpart, n_win may be 0).
 hipError_t launch_adj_btcs_assemble(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles,
-                                    const double* u, const double* lamp, double* LA, double* LC, double* LD);
+                                    const double* u, const double* lamp, double* LA, double* LC, double* LD,
+                                    const int* only);
 hipError_t launch_adj_btcs_finish(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles,
                                   const double* u, const double* x, const double* X, double* lam,
-                                  double* gslot);
+                                  double* gslot, const int* only, const WinDesc* wins, int64_t n_win,
+                                  const int32_t* win_slot, const double* wpart);
 hipError_t launch_adj_nu(const burgers_ctx* ctx, const int32_t* slot_begin, const double* gslot,
                          double* grad_nu);
 hipError_t launch_fill(const burgers_ctx* ctx, double* p, int64_t n, double v);
@@ -347,8 +356,14 @@ hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, con
                                int* flags);
 WidthClass btcs_width_class(int rows, int threads);
 int btcs_chunks(int rows, int threads);
+// `only` (optional): solve only the systems of instances whose entry is nonzero.
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
-                              double* LD, double* LX);
+                              double* LD, double* LX, const int* only = nullptr);
+// Adjoint BTCS step of the long instances on truncated windows of the transposed system (lam from lamp
+// at the forward pair u -> x); per-window partials of dJ/dD into wpart; failed bounds flag instances.
+hipError_t launch_adj_btcs_windows(const burgers_ctx* ctx, const WinDesc* wins, int64_t n_win, const double* u,
+                                   const double* x, const double* lamp, double* lam, double* wpart, int* flag_now,
+                                   int* flag_next);
 constexpr int kResidentThreadsDefault = 512;
 
 }  // namespace burgers

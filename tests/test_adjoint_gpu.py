@@ -95,6 +95,38 @@ def test_autograd_function():
     assert np.max(np.abs(nu.grad.cpu().numpy() - rgn) / np.maximum(np.abs(rgn), 1e-300)) <= 1e-10
 
 
+@pytest.mark.parametrize("factor", [10.0, 1000.0])
+def test_adjoint_long_btcs_windows(factor):
+    """Every BTCS instance longer than 8192 rows: the transposed systems are solved on truncated windows
+    (at 10x the CFL step every window's bound holds) or, where a window's bound fails (10^3 x), that
+    instance's step is redone on the array path; gradients against the oracle, and bitwise equal for two
+    checkpoint intervals."""
+    sizes = [8195, 9000, 16385, 3 * 3584 + 11]
+    problems, states = [], []
+    for k, n in enumerate(sizes):
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            b = W.random_batch(900 + 7 * k + bc, 1, n, n, bc=bc, scheme=W.BTCS, amplitude=2.0)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    for k, n in enumerate([40, 3000]):
+        b = W.random_batch(950 + k, 1, n, n, scheme=W.EXPLICIT, amplitude=2.0)
+        problems.append(b.problems[0])
+        states.append(b.instance(0))
+    batch = set_cfl_steps(W._pack(problems, states), btcs_factor=factor)
+    lam = np.random.default_rng(9).standard_normal(len(batch.u0))
+    nsteps = 5
+    announce(f"adjoint long BTCS windows x{factor}, {nsteps} steps")
+    g, gn, raw, offs = _device_adjoint(batch, lam, nsteps, 2)
+    rg, rgn = oracle.adjoint(batch.problems, batch.u0, batch.offsets, lam, nsteps)
+    _check_padding(raw, offs, batch)
+    for b in range(batch.count):
+        lo, hi = batch.offsets[b], batch.offsets[b + 1]
+        assert oracle.rel_max_abs(g[lo:hi], rg[lo:hi]) <= TOL, (b, batch.problems[b])
+    assert np.max(np.abs(gn - rgn) / np.maximum(np.abs(rgn), 1e-300)) <= 1e-10, (gn, rgn)
+    g2 = _device_adjoint(batch, lam, nsteps, 5)
+    assert np.array_equal(g2[0], g) and np.array_equal(g2[1], gn)
+
+
 @pytest.mark.parametrize("scheme", [W.EXPLICIT, W.BTCS])
 def test_c5_adjoint_full_size_sampled(scheme):
     """The gradient workload at its real size, in the benchmark's configuration: 256 periodic instances
