@@ -60,7 +60,7 @@ class PhaseTimer:
 
 
 def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000, explicit_path=0, btcs_path=0,
-             btcs_block=0):
+             btcs_block=0, btcs_pipeline=0):
     """Time `steps` passes (after `warmup`) of the explicit and BTCS runs over the 4096 x 8192 batch."""
     import workloads as W
     batch = W.c2_batch()
@@ -71,7 +71,7 @@ def bench_c2(B, torch, dtype, steps, warmup, n_exp=10_000, n_btcs=1_000, explici
     s_exp = B.Solver(exp_batch.problems, dtype=dtype)
     s_btcs = B.Solver(btcs_batch.problems, dtype=dtype)
     s_exp.set_plan(explicit_path=explicit_path)
-    s_btcs.set_plan(btcs_path=btcs_path, btcs_block=btcs_block)
+    s_btcs.set_plan(btcs_path=btcs_path, btcs_block=btcs_block, btcs_pipeline=btcs_pipeline)
     u_init = s_exp.pack_flat(batch.u0, batch.offsets)
     u = torch.empty_like(u_init)
     timer = PhaseTimer()
@@ -126,7 +126,13 @@ def bench_c2_plain(B, torch, n_exp=200, n_btcs=50):
     nodes = 4096 * 8192
     for name, dtype, word in (("f64", torch.float64, 8), ("f32", torch.float32, 4)):
         r = bench_c2(B, torch, dtype, 1, 1, n_exp=n_exp, n_btcs=n_btcs, explicit_path=1, btcs_path=1)
-        for leg, ms in (("explicit_stream", r["explicit_launch_ms"]), ("btcs_per_step", r["btcs_step_ms"])):
+        variants = {}
+        for tag, block, pipe in (("pipelined", 512, 1), ("1024x8", 1024, 2), ("1024x8_pipelined", 1024, 1)):
+            v = bench_c2(B, torch, dtype, 1, 1, n_exp=0, n_btcs=n_btcs, explicit_path=1, btcs_path=1,
+                         btcs_block=block, btcs_pipeline=pipe)
+            variants[f"btcs_per_step_{tag}"] = v["btcs_step_ms"]
+        for leg, ms in (("explicit_stream", r["explicit_launch_ms"]), ("btcs_per_step", r["btcs_step_ms"]),
+                        *variants.items()):
             gbs = 2 * word * nodes / (ms * 1e-3) / 1e9
             out[f"{leg}_{name}"] = {"ms_per_step": ms, "glups": nodes / (ms * 1e-3) / 1e9,
                                     "algorithmic_gbs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}

@@ -132,6 +132,11 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *                  solves).  0 (default): the groups run concurrently, on side streams of the context
  *                  forked from and joined back into its stream with events (parallel branches of a
  *                  captured graph); 1: one after another on the context's stream.
+ *   btcs_pipeline  how the per-step path (btcs_path 1, and Crank-Nicolson) solves systems of exactly 8192
+ *                  rows: 1 persistent workgroups, one per CU, each walking its share of the systems with
+ *                  the next system's loads in flight while it solves the current one; 2 one workgroup
+ *                  per system, several per CU; 0 automatic (the faster on this GPU, see the design notes).
+ *                  Both give bitwise the same results.
  * burgers_set_plan rejects values outside these ranges with BURGERS_E_INVALID.
  */
 typedef struct {
@@ -143,7 +148,9 @@ typedef struct {
   int32_t btcs_long;       /* systems of more than 8192 rows stepped through HBM: 0 truncated windows
                               of 4096 rows, 1 partition levels, 2 windows of 8192 rows (see below) */
   int32_t serial;          /* 1: one stream; 0: the independent launch groups run concurrently */
-  int32_t reserved[1];
+  int32_t btcs_pipeline;   /* per-step solves of exact 8192-row systems: 0 automatic, 1 persistent
+                              workgroups that load the next system while solving one, 2 one workgroup
+                              per system */
 } burgers_plan;
 
 /*

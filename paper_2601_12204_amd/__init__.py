@@ -48,7 +48,7 @@ class CPlan(ctypes.Structure):
     _fields_ = [("explicit_path", ctypes.c_int32), ("tblock_depth", ctypes.c_int32),
                 ("btcs_path", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("btcs_block", ctypes.c_int32), ("btcs_long", ctypes.c_int32), ("serial", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 1)]
+                ("btcs_pipeline", ctypes.c_int32)]
 
 
 _lib = None
@@ -161,7 +161,7 @@ def burgers_autotune(ctx, u, explicit_steps: int, btcs_steps: int):
                                    ctypes.byref(ms)), "burgers_autotune")
     return ({"explicit_path": plan.explicit_path, "tblock_depth": plan.tblock_depth, "btcs_path": plan.btcs_path,
              "use_graph": plan.use_graph, "btcs_block": plan.btcs_block, "btcs_long": plan.btcs_long,
-             "serial": plan.serial}, ms.value)
+             "serial": plan.serial, "btcs_pipeline": plan.btcs_pipeline}, ms.value)
 
 
 def burgers_status_string(status: int) -> str:
@@ -323,13 +323,13 @@ def burgers_get_plan(ctx) -> dict:
     _check(load().burgers_get_plan(ctx, ctypes.byref(plan)), "burgers_get_plan")
     return {"explicit_path": plan.explicit_path, "tblock_depth": plan.tblock_depth,
             "btcs_path": plan.btcs_path, "use_graph": plan.use_graph, "btcs_block": plan.btcs_block,
-            "btcs_long": plan.btcs_long, "serial": plan.serial}
+            "btcs_long": plan.btcs_long, "serial": plan.serial, "btcs_pipeline": plan.btcs_pipeline}
 
 
 def burgers_set_plan(ctx, explicit_path=0, tblock_depth=0, btcs_path=0, use_graph=-1, btcs_block=0,
-                     btcs_long=0, serial=0) -> None:
+                     btcs_long=0, serial=0, btcs_pipeline=0) -> None:
     plan = CPlan(int(explicit_path), int(tblock_depth), int(btcs_path), int(use_graph), int(btcs_block),
-                 int(btcs_long), int(serial))
+                 int(btcs_long), int(serial), int(btcs_pipeline))
     _check(load().burgers_set_plan(ctx, ctypes.byref(plan)), "burgers_set_plan")
 
 

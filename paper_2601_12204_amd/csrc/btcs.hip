@@ -755,6 +755,85 @@ __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_w
   }
 }
 
+// Per-step whole-system solver for systems of exactly 512 x 16 rows, persistent and pipelined: each
+// workgroup walks a strided share of the systems, and while it solves one system the coalesced loads of
+// its next system are already in flight into registers, so the step's HBM traffic overlaps the solves
+// (the one-system-per-workgroup kernel above loads, solves and stores in turn and overlaps only with the
+// other workgroup on its CU).  Same operations in the same order as btcs_wg_kernel<S, true, 512, 16,
+// true>: bitwise the same results.
+template <typename S, int NT, int MC>
+__global__ __launch_bounds__(NT, NT == 1024 ? 4 : 2) void btcs_stream_kernel(const InstDesc* __restrict__ inst,
+                                                                            const SysDesc* __restrict__ systems,
+                                                                            int n_sys, const S* __restrict__ u,
+                                                                            S* __restrict__ out) {
+  using T = double;
+  constexpr int W = NT * MC;
+  using IS = InterfaceSpace<T, NT>;
+  constexpr int kStageBytes = padded_size(W) * static_cast<int>(sizeof(S));
+  constexpr int kBytes = kStageBytes > IS::kBytes ? kStageBytes : IS::kBytes;
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  __shared__ uint64_t iface_votes[2 * IS::kVoteWords];
+  const IS iws{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + 3 * NT, iface_votes};
+  iws.clear_votes();
+  S* stage = reinterpret_cast<S*>(smem);
+  const int tid = threadIdx.x;
+  int b = blockIdx.x;
+  if (b >= n_sys) return;
+  // the first system's rows
+  SysDesc sys = systems[b];
+  InstDesc d = inst[sys.inst];
+  S v[MC];
+  {
+    const S* __restrict__ x = u + d.off + (d.bc == kDirichlet ? 1 : 0) + tid;
+#pragma unroll
+    for (int j = 0; j < MC; ++j) v[j] = x[j * NT];
+  }
+  for (;;) {
+    const bool dir = d.bc == kDirichlet;
+#pragma unroll
+    for (int j = 0; j < MC; ++j) stage[padded(tid + j * NT)] = v[j];
+    __syncthreads();
+    // the next system's rows, in flight while this one is solved
+    const int nb = b + static_cast<int>(gridDim.x);
+    SysDesc nsys{};
+    InstDesc nd{};
+    if (nb < n_sys) {
+      nsys = systems[nb];
+      nd = inst[nsys.inst];
+      const S* __restrict__ x = u + nd.off + (nd.bc == kDirichlet ? 1 : 0) + tid;
+#pragma unroll
+      for (int j = 0; j < MC; ++j) v[j] = x[j * NT];
+    }
+    if (dir && tid == 0) {
+      out[d.off] = static_cast<S>(d.a);
+      out[d.off + d.n - 1] = static_cast<S>(d.b);
+    }
+    T al[MC], ga[MC], de[MC];
+    const int s0 = tid * MC;
+    load_staged<S>(stage, 0, s0, MC, de);
+    __syncthreads();                           // every lane's rows read: the interface LDS overlays them
+    T y, yp;
+    interface_step<T, NT, MC>(iws, ValueRows{d.r, d.D, DirichletEnds{d.a, d.b, dir}}, true, s0, MC, W, NT, al, ga,
+                              de, y, yp);
+    __syncthreads();                           // the interface unknowns read before the rows are rewritten
+    const LdsDst<S> sdst{stage, 0};
+#pragma unroll
+    for (int j = 0; j < MC; ++j) {
+      if (j < MC - 1) sdst.write(j, s0 + j, __builtin_fma(-ga[j], y, __builtin_fma(-al[j], yp, de[j])));
+      else sdst.write(j, s0 + j, y);
+    }
+    __syncthreads();
+    const int64_t o = d.off + (dir ? 1 : 0);
+    if (sys.cn) stage_out_cn<S, NT, MC>(stage, u + o, out + o, W);
+    else stage_out<S, NT, MC>(stage, out + o, W);
+    if (nb >= n_sys) break;
+    __syncthreads();                           // the stage read out before the next system is written
+    b = nb;
+    sys = nsys;
+    d = nd;
+  }
+}
+
 // Rows of a Newton iteration (fully implicit central-convection step, eqs. 10-14) for the whole system of
 // one instance: the Jacobian row of eq. 11 at the iterate x (staged in LDS, unknown k at padded(k)) and
 // the right-hand side -F, with the old state u read from HBM.  The increment of a Dirichlet neighbour is
@@ -1637,6 +1716,22 @@ void reduced_wg_launch(const BtcsPlan::Level& lv, const InstDesc* inst, const S*
   }
 }
 
+// Workgroups of the persistent per-step kernel: as many as the device holds at once.
+template <typename S, int NT, int MC>
+int stream_grid(int device) {
+  static int cached[64] = {};
+  if (device < 0 || device >= 64) return 256;
+  if (!cached[device]) {
+    int cus = 0, per = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, btcs_stream_kernel<S, NT, MC>, NT, 0) != hipSuccess ||
+        per <= 0)
+      per = 1;
+    cached[device] = cus * per;
+  }
+  return cached[device];
+}
+
 template <typename S>
 hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void* uv, void* outv, int64_t step) {
   const S* u = static_cast<const S*>(uv);
@@ -1691,8 +1786,14 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
     const SysDesc* sys = g.sys->as<SysDesc>();
     const unsigned n = static_cast<unsigned>(g.n);
     if (g.shape.exact) {
-      if (g.shape.lanes == 1024)
+      if (plan.stream_exact && g.shape.lanes == 1024)
+        btcs_stream_kernel<S, 1024, 8><<<std::min(n, static_cast<unsigned>(stream_grid<S, 1024, 8>(ctx->device))),
+                                         1024, 0, st>>>(inst, sys, g.n, u, out);
+      else if (g.shape.lanes == 1024)
         btcs_wg_kernel<S, true, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all);
+      else if (plan.stream_exact)
+        btcs_stream_kernel<S, 512, 16><<<std::min(n, static_cast<unsigned>(stream_grid<S, 512, 16>(ctx->device))),
+                                         512, 0, st>>>(inst, sys, g.n, u, out);
       else
         btcs_wg_kernel<S, true, 512, 16, true><<<n, 512, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all);
       continue;

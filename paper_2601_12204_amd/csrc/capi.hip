@@ -267,13 +267,15 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   const int threads = ctx->plan.btcs_block ? ctx->plan.btcs_block : burgers::kResidentThreadsDefault;
   const int longmode = ctx->plan.btcs_long;
   auto found = ctx->btcs.find(set);
+  const bool pipelined = ctx->plan.btcs_pipeline == 1;
   if (found != ctx->btcs.end() && found->second->path == want && found->second->threads == threads &&
-      found->second->longmode == longmode)
+      found->second->longmode == longmode && found->second->stream_exact == pipelined)
     return BURGERS_OK;
   auto plan = std::make_unique<burgers::BtcsPlan>();
   plan->path = want;
   plan->threads = threads;
   plan->longmode = longmode;
+  plan->stream_exact = pipelined;
   const int cap = burgers::btcs_wg_capacity();
   const int chunk = burgers::btcs_reduce_chunk();
   // truncated windows of the long systems (automatic and per-step paths): 4096 rows each (8192 when
@@ -1274,12 +1276,13 @@ burgers_status burgers_set_plan(burgers_ctx* ctx, const burgers_plan* plan) {
   if (plan->explicit_path < 0 || plan->explicit_path > 3 || plan->btcs_path < 0 || plan->btcs_path > 3 ||
       plan->tblock_depth < 0 || plan->tblock_depth > kMaxDepth || plan->use_graph < -1 || plan->use_graph > 1 ||
       (plan->btcs_block != 0 && plan->btcs_block != 512 && plan->btcs_block != 1024) ||
-      plan->btcs_long < 0 || plan->btcs_long > 2 || plan->serial < 0 || plan->serial > 1)
+      plan->btcs_long < 0 || plan->btcs_long > 2 || plan->serial < 0 || plan->serial > 1 ||
+      plan->btcs_pipeline < 0 || plan->btcs_pipeline > 2)
     return BURGERS_E_INVALID;
   const bool explicit_changed = plan->explicit_path != ctx->plan.explicit_path ||
                                 plan->tblock_depth != ctx->plan.tblock_depth;
   const bool btcs_changed = plan->btcs_path != ctx->plan.btcs_path || plan->btcs_block != ctx->plan.btcs_block ||
-                            plan->btcs_long != ctx->plan.btcs_long;
+                            plan->btcs_long != ctx->plan.btcs_long || plan->btcs_pipeline != ctx->plan.btcs_pipeline;
   ctx->plan = *plan;
   if (explicit_changed) ctx->explicit_plans.clear();
   if (btcs_changed) ctx->btcs.clear();

@@ -195,6 +195,7 @@ struct BtcsPlan {
   std::unique_ptr<DevBuf> win;               // WinDesc[]
   int64_t n_win = 0;
   int win_rows = 8192;                       // rows per window: 8192 (512 lanes) or 4096 (256 lanes)
+  bool stream_exact = false;                 // per-step exact 8192-row systems: the persistent pipelined kernel
   DevBuf win_flags;                          // int32[3][count]: per step parity, instance needs the partition;
                                              // then a sticky copy (set by any failed window, never cleared here)
 };
