@@ -503,10 +503,39 @@ def cpu_baseline(target_s=15.0):
         n_btcs, t_exp, t_btcs = timed(n_exp)
     nodes = sub.count * 8192
     glups = nodes * (n_exp + n_btcs) / (t_exp + t_btcs) / 1e9
+    # one thread on one instance, the same step mix, about a fifth of the time
+    one = W.subset(sub, [0])
+    n1 = max(20, int(n_exp * sub.count / threads / 5 / 10) * 10)
+    t = time.perf_counter()
+    oracle.run(one.problems, one.u0, one.offsets, n1, scheme=W.EXPLICIT, threads=1)
+    t1_exp = time.perf_counter() - t
+    for p in one.problems:
+        p.dt *= 10
+    t = time.perf_counter()
+    oracle.run(one.problems, one.u0, one.offsets, max(2, n1 // 10), scheme=W.BTCS, threads=1)
+    t1_btcs = time.perf_counter() - t
+    for p in one.problems:
+        p.dt /= 10
+    single = 8192 * (n1 + max(2, n1 // 10)) / (t1_exp + t1_btcs) / 1e9
     return {"value": glups, "unit": "GLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{sub.count} of the 4096 instances (N=8192, FP64), {n_exp} explicit + {n_btcs} BTCS "
                       f"steps (same 10:1 step mix as the GPU step), {t_exp + t_btcs:.1f} s",
-            "explicit_glups": nodes * n_exp / t_exp / 1e9, "btcs_glups": nodes * n_btcs / t_btcs / 1e9}
+            "explicit_glups": nodes * n_exp / t_exp / 1e9, "btcs_glups": nodes * n_btcs / t_btcs / 1e9,
+            "single_thread": {"value": single, "unit": "GLUPS", "cores": 1,
+                              "sample": f"1 instance, {n1} explicit + {max(2, n1 // 10)} BTCS steps, "
+                                        f"{t1_exp + t1_btcs:.1f} s"},
+            "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
