@@ -16,9 +16,9 @@
 // Arithmetic is binary64 for both state types; a binary32 state is widened on load and rounded once per
 // step on store.  A binary32 partition solve drifts by a systematic bias of a few ulp per step, which
 // over 10^3 steps exceeds the serial binary32 solve's own error; the binary64 solve keeps the binary32
-// path within its one rounding per step of the exact discrete solution.  On CDNA the binary64 vector
-// rate equals the non-packed binary32 rate, and this step is bound by HBM, so the wider arithmetic costs
-// nothing measurable.
+// path within its one rounding per step of the exact discrete solution.  Binary64 instructions issue at
+// half the binary32 rate on gfx950, but the solve is bound by its pivot chain's latency and its barriers
+// rather than by issue rate: a binary32-state step takes about as long as a binary64 one.
 #include <cmath>
 
 #include "internal.hpp"
