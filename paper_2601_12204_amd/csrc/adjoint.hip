@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_btcs_assemble_kernel(
     const InstDesc* __restrict__ inst, const AdjTile* __restrict__ tiles, const double* __restrict__ u,
     const double* __restrict__ lamp, double* __restrict__ LA, double* __restrict__ LC,
     double* __restrict__ LD, const int* __restrict__ only) {
+  if (only && only[-1] == 0) return;          // no window of this step failed
   const AdjTile t = tiles[blockIdx.x];
   if (only && only[t.inst] == 0) return;      // this instance's windows held
   const InstDesc d = inst[t.inst];
@@ -170,6 +171,7 @@ __global__ __launch_bounds__(kAdjThreads) void adj_btcs_finish_kernel(
     const int wi = wins[blockIdx.x].inst;
     if (only[wi] == 0) gslot[win_slot[blockIdx.x]] = gslot[win_slot[blockIdx.x]] + wpart[blockIdx.x];
   }
+  if (only && only[-1] == 0) return;          // no window of this step failed
   const AdjTile t = tiles[blockIdx.x];
   if (only && only[t.inst] == 0) return;
   const InstDesc d = inst[t.inst];

@@ -642,6 +642,7 @@ __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_w
   S* stage = reinterpret_cast<S*>(smem);
   T* tstage = reinterpret_cast<T*>(smem);   // reduced systems: one coefficient array at a time
 
+  if (only && only[-1] == 0) return;         // partition fallback: no window of this step failed
   const SysDesc sys = systems[blockIdx.x];
   if (only && only[sys.inst] == 0) return;   // partition fallback: this instance's windows held
   const int R = sys.rows, P = sys.chunks;
@@ -1133,8 +1134,10 @@ __global__ __launch_bounds__(NT, 4) void btcs_window_kernel(
     const T C = d.r * M;
     const T theta = 2.0 * (d.D + C) / ((1.0 + 2.0 * d.D + C) + __builtin_sqrt((1.0 + C) * (1.0 + C) + 4.0 * d.D));
     flag_next[wd.inst] = 0;                    // the next step's slot (its last readers have finished)
+    flag_next[-1] = 0;
     if (!(theta <= theta_lim)) {
       flag_now[wd.inst] = 1;
+      flag_now[-1] = 1;
       sticky[wd.inst] = 1;                     // kept until its owner clears it (resident pools report it)
     }
   }
@@ -1268,9 +1271,13 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
     const T theta = 2.0 * (d.D + C) / ((1.0 + 2.0 * d.D + C) + __builtin_sqrt((1.0 + C) * (1.0 + C) + 4.0 * d.D));
     const T coup = d.D + C;
     flag_next[wd.inst] = 0;
+    flag_next[-1] = 0;
     const bool ok = coup == 0.0 || theta == 0.0 ||
                     (kWinHalo + 1) * log2(theta) + log2(coup) <= -55.0;
-    if (!ok) flag_now[wd.inst] = 1;
+    if (!ok) {
+      flag_now[wd.inst] = 1;
+      flag_now[-1] = 1;
+    }
   }
   T al[MC], ga[MC];
   T ia = T(0), ib = T(1), ic = T(0), id = T(0);
@@ -1536,6 +1543,7 @@ __device__ __forceinline__ void array_backsub_chunk(const SysDesc& sys, int k, c
 __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_reduce_kernel(
     const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, double* __restrict__ LA,
     double* __restrict__ LC, double* __restrict__ LD, const int* __restrict__ only) {
+  if (only && only[-1] == 0) return;
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   if (only && only[sys.inst] == 0) return;
@@ -1550,6 +1558,7 @@ __global__ __launch_bounds__(kReduceBlock, 2) void btcs_array_backsub_kernel(
     const SysDesc* __restrict__ systems, const ChunkBlock* __restrict__ blocks, const double* __restrict__ LA,
     const double* __restrict__ LC, const double* __restrict__ LD, double* __restrict__ LX,
     const int* __restrict__ only) {
+  if (only && only[-1] == 0) return;
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   if (only && only[sys.inst] == 0) return;
@@ -1599,6 +1608,7 @@ __global__ __launch_bounds__(kReduceBlock, 4) void btcs_block_reduce_kernel(
   S* stage = reinterpret_cast<S*>(smem);
   T* lds = reinterpret_cast<T*>(smem);
   const BlockIfaceSpace w{lds, lds + 3 * BlockIfaceSpace::kN, iface_flags};
+  if (only && only[-1] == 0) return;         // partition fallback: no window of this step failed
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   if (only && only[sys.inst] == 0) return;   // partition fallback: this instance's windows held
@@ -1681,6 +1691,7 @@ __global__ __launch_bounds__(kReduceBlock, 3) void btcs_block_backsub_kernel(
   S* stage = reinterpret_cast<S*>(smem);
   T* lds = reinterpret_cast<T*>(smem);
   const BlockIfaceSpace w{lds, lds + 3 * BlockIfaceSpace::kN, iface_flags};
+  if (only && only[-1] == 0) return;         // partition fallback: no window of this step failed
   const ChunkBlock cb = blocks[blockIdx.x];
   const SysDesc sys = systems[cb.sys];
   if (only && only[sys.inst] == 0) return;   // partition fallback: this instance's windows held
@@ -1747,9 +1758,9 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
   // whose windows flagged a failed bound this step
   const int* only = nullptr;
   if (plan.n_win > 0) {
-    int* now = plan.win_flags.as<int>() + (step & 1) * ctx->count;
-    int* next = plan.win_flags.as<int>() + ((step + 1) & 1) * ctx->count;
-    int* sticky = plan.win_flags.as<int>() + 2 * ctx->count;
+    int* now = win_flag_slot(plan.win_flags.as<int>(), ctx->count, step);
+    int* next = win_flag_slot(plan.win_flags.as<int>(), ctx->count, step + 1);
+    int* sticky = win_sticky(plan.win_flags.as<int>(), ctx->count);
     if (plan.win_rows == kWgRows)
       btcs_window_kernel<S, kWgThreads><<<static_cast<unsigned>(plan.n_win), kWgThreads, 0, st>>>(
           inst, plan.win->as<WinDesc>(), u, out, now, next, sticky, window_theta_limit(), static_cast<int>(step));
@@ -1947,7 +1958,7 @@ hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const 
 
 hipError_t launch_btcs_window_reset(const burgers_ctx* ctx, const BtcsPlan& plan) {
   if (plan.n_win == 0) return hipSuccess;
-  const int64_t n = 2 * ctx->count;
+  const int64_t n = 2 * (ctx->count + 1);     // both parity slots, not the sticky words
   clear_flags_kernel<<<static_cast<unsigned>((n + 255) / 256), 256, 0, ctx->stream>>>(plan.win_flags.as<int>(), n);
   return hipGetLastError();
 }

@@ -385,7 +385,9 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   plan->win = std::make_unique<DevBuf>();
   if ((e = upload_on(ctx->stream, *plan->win, windows)) != hipSuccess) return from_hip(e);
   plan->n_win = static_cast<int64_t>(windows.size());
-  if (plan->n_win > 0 && (e = plan->win_flags.alloc(3 * static_cast<size_t>(ctx->count) * sizeof(int), ctx->stream)) != hipSuccess)
+  if (plan->n_win > 0 &&
+      (e = plan->win_flags.alloc(static_cast<size_t>(burgers::win_flags_words(ctx->count)) * sizeof(int), ctx->stream)) !=
+          hipSuccess)
     return from_hip(e);
   plan->levels.resize(red_sys.size());
   for (size_t l = 0; l < red_sys.size(); ++l) {
@@ -817,7 +819,8 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   ap->n_win = static_cast<int64_t>(wins.size());
   if (ap->n_win > ap->n_btcs_tiles) return BURGERS_E_UNSUPPORTED;   // (tiles of 1024 nodes outnumber windows)
   if (ap->n_win > 0 && ((e = ap->wpart.alloc(static_cast<size_t>(ap->n_win) * sizeof(double), ctx->stream)) != hipSuccess ||
-                        (e = ap->flags.alloc(2 * static_cast<size_t>(ctx->count) * sizeof(int), ctx->stream)) != hipSuccess))
+                        (e = ap->flags.alloc(static_cast<size_t>(burgers::win_flags_words(ctx->count)) * sizeof(int),
+                                                          ctx->stream)) != hipSuccess))
     return from_hip(e);
   if ((e = build_array_solve(ctx, roots, ap->solve, rows_used)) != hipSuccess) return from_hip(e);
   const size_t lb = static_cast<size_t>(rows_used) * sizeof(double);
@@ -845,8 +848,8 @@ hipError_t enqueue_adjoint_step(burgers_ctx* ctx, const double* y, const double*
   if (e != hipSuccess || ap.n_btcs_tiles == 0) return e;
   const int* only = nullptr;
   if (ap.n_win > 0) {
-    int* now = ap.flags.as<int>() + (step & 1) * ctx->count;
-    int* next = ap.flags.as<int>() + ((step + 1) & 1) * ctx->count;
+    int* now = burgers::win_flag_slot(ap.flags.as<int>(), ctx->count, step);
+    int* next = burgers::win_flag_slot(ap.flags.as<int>(), ctx->count, step + 1);
     if ((e = burgers::launch_adj_btcs_windows(ctx, ap.win->as<burgers::WinDesc>(), ap.n_win, y, x, lam_in, lam_out,
                                               ap.wpart.as<double>(), now, next)) != hipSuccess)
       return e;
@@ -1207,7 +1210,7 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   double* lam_next = ap.lam1.as<double>();
   if ((e = hipMemcpyAsync(lam, lambda_T, state_bytes, d2d, ctx->stream)) != hipSuccess ||
       (e = burgers::launch_fill(ctx, ap.gslot.as<double>(), ap.n_slots, 0.0)) != hipSuccess ||
-      (ap.n_win > 0 && (e = burgers::launch_clear_ints(ctx, ap.flags.as<int>(), 2 * ctx->count)) != hipSuccess))
+      (ap.n_win > 0 && (e = burgers::launch_clear_ints(ctx, ap.flags.as<int>(), 2 * (ctx->count + 1))) != hipSuccess))
     return note(ctx, e);
   int64_t rstep = 0;
   // the segment's states are recomputed out of place, one step per launch from seg[k-1] straight into

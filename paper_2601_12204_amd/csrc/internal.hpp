@@ -93,6 +93,14 @@ struct WinDesc {
   int32_t limit; // > 0: only the first `limit` steps of a call solve; later ones copy the kept rows
 };
 
+// Flags of truncated windows over `count` instances, one slot per step parity: slot p starts with a word
+// that is nonzero when any window of that step failed its bound, followed by one word per instance (the
+// instance must be redone); after both slots, a sticky word per instance (resident pools report it).
+// Fallback kernels read the slot's first word before anything else and exit when it is zero.
+inline int64_t win_flags_words(int64_t count) { return 3 * count + 2; }
+inline int* win_flag_slot(int* base, int64_t count, int64_t step) { return base + (step & 1) * (count + 1) + 1; }
+inline int* win_sticky(int* base, int64_t count) { return base + 2 * (count + 1); }
+
 // A block of consecutive chunks of one system (reduce and back-substitution kernels).
 struct ChunkBlock {
   int32_t sys;
@@ -196,8 +204,7 @@ struct BtcsPlan {
   int64_t n_win = 0;
   int win_rows = 8192;                       // rows per window: 8192 (512 lanes) or 4096 (256 lanes)
   bool stream_exact = false;                 // per-step exact 8192-row systems: the persistent pipelined kernel
-  DevBuf win_flags;                          // int32[3][count]: per step parity, instance needs the partition;
-                                             // then a sticky copy (set by any failed window, never cleared here)
+  DevBuf win_flags;                          // win_flags_words(count) int32 (see win_flag_slot)
 };
 
 // Launch lists of the explicit scheme for a set of instances.
@@ -234,7 +241,7 @@ struct AdjointPlan {
   // array path above is then the fallback of the instances whose windows flag a failed bound
   std::unique_ptr<DevBuf> win, win_slot;           // WinDesc[], int32[] (dJ/dD slot of each window)
   int64_t n_win = 0;
-  DevBuf wpart, flags;                              // double[n_win]; int32[2][count] per step parity
+  DevBuf wpart, flags;                              // double[n_win]; win_flags_words(count) int32
 };
 
 // Fully implicit central-convection instances (Newton-Raphson, a fixed number of iterations per step):

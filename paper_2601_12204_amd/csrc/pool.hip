@@ -329,8 +329,10 @@ burgers_status burgers_pool_create(burgers_dtype dtype, int32_t scheme, int64_t 
     pl->bplan.n_win = slots * pl->wx;
     pl->bplan.win_rows = 4096;
     if (pl->bplan.n_win > 0) {
-      if ((e = pl->bplan.win_flags.alloc(3 * static_cast<size_t>(slots) * sizeof(int), st)) != hipSuccess ||
-          (e = burgers::launch_clear_ints(&pl->ctx, pl->bplan.win_flags.as<int>(), 3 * slots)) != hipSuccess) {
+      if ((e = pl->bplan.win_flags.alloc(static_cast<size_t>(burgers::win_flags_words(slots)) * sizeof(int), st)) !=
+              hipSuccess ||
+          (e = burgers::launch_clear_ints(&pl->ctx, pl->bplan.win_flags.as<int>(), burgers::win_flags_words(slots))) !=
+              hipSuccess) {
         pool_free(pl);
         return status_of(e);
       }
@@ -367,7 +369,7 @@ burgers_status burgers_pool_admit(burgers_pool* pool, const burgers_problem* p, 
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(dst, u0, static_cast<size_t>(p->n) * pool->ctx.word, hipMemcpyDefault, st);
   if (e == hipSuccess && pool->bplan.n_win > 0)
-    e = burgers::launch_clear_ints(&pool->ctx, pool->bplan.win_flags.as<int>() + 2 * pool->slots + s, 1);
+    e = burgers::launch_clear_ints(&pool->ctx, burgers::win_sticky(pool->bplan.win_flags.as<int>(), pool->slots) + s, 1);
   if (e != hipSuccess) {
     pool->sticky_err = e;
     return status_of(e);
@@ -403,7 +405,7 @@ burgers_status burgers_pool_tick(burgers_pool* pool) {
   if (e == hipSuccess) e = tick_graph(pool, mask, &g);
   if (e == hipSuccess) e = hipGraphLaunch(g, pool->ctx.stream);
   if (e == hipSuccess && pool->bplan.n_win > 0)
-    e = hipMemcpyAsync(pool->sticky_host, pool->bplan.win_flags.as<int>() + 2 * pool->slots,
+    e = hipMemcpyAsync(pool->sticky_host, burgers::win_sticky(pool->bplan.win_flags.as<int>(), pool->slots),
                        static_cast<size_t>(pool->slots) * sizeof(int), hipMemcpyDeviceToHost, pool->ctx.stream);
   if (e == hipSuccess) e = hipEventRecord(pool->done, pool->ctx.stream);
   if (e != hipSuccess) {
