@@ -132,11 +132,13 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *                  solves).  0 (default): the groups run concurrently, on side streams of the context
  *                  forked from and joined back into its stream with events (parallel branches of a
  *                  captured graph); 1: one after another on the context's stream.
- *   btcs_pipeline  how the per-step path (btcs_path 1, and Crank-Nicolson) solves systems of exactly 8192
- *                  rows: 1 persistent workgroups, one per CU, each walking its share of the systems with
- *                  the next system's loads in flight while it solves the current one; 2 one workgroup
- *                  per system, several per CU; 0 automatic (the faster on this GPU, see the design notes).
- *                  Both give bitwise the same results.
+ *   btcs_pipeline  how the per-step path (btcs_path 1) solves systems of exactly 8192 rows: 1 persistent
+ *                  workgroups, one per CU, each walking its share of the systems with the next system's
+ *                  rows streaming into LDS while it solves the current one (systems whose first row is
+ *                  16-byte aligned in 16-byte aligned state buffers, i.e. periodic ones; Dirichlet and
+ *                  Crank-Nicolson systems keep one workgroup each); 2 one workgroup per system, several
+ *                  per CU; 0 automatic (one workgroup per system, the faster on this GPU).  Both give
+ *                  bitwise the same results.
  * burgers_set_plan rejects values outside these ranges with BURGERS_E_INVALID.
  */
 typedef struct {

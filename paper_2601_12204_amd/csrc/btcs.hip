@@ -458,6 +458,15 @@ __device__ __forceinline__ void interface_eliminate(const Src& src, int s, int m
   }
 }
 
+// Workgroup barrier.  LdsOnly: for exchanges through LDS alone, it waits for this wave's LDS accesses but
+// not for its vector memory accesses, so that rows streaming into another LDS buffer (global_load_lds,
+// whose LDS writes a full barrier would wait for) stay in flight across it.
+template <bool LdsOnly>
+__device__ __forceinline__ void wg_barrier() {
+  if constexpr (LdsOnly) asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else __syncthreads();
+}
+
 // LDS of the interface solve: the first interior rows exchanged between neighbouring lanes, and two
 // buffers of the interface rows for PCR (three arrays of NT each), plus one stop flag per wave and buffer.
 template <typename T, int NT>
@@ -477,7 +486,7 @@ struct InterfaceSpace {
 // last interior row (alL, gaL, deL) and its interface row (ia, ib, ic, id); on return y = y_t and
 // yp = y_{t-1}.  Ends with a barrier after its last write to LDS; its last reads (yp) follow that
 // barrier, so a caller that reuses the LDS for anything else must synchronise first.
-template <typename T, int NT>
+template <typename T, int NT, bool LdsOnly = false>
 __device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, int P, T al0, T ga0, T de0,
                                                 T alL, T gaL, T deL, T ia, T ib, T ic, T id, T& y, T& yp) {
   constexpr int kR = NT;
@@ -489,7 +498,7 @@ __device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, 
     w.xchg[NT + t] = ga0;
     w.xchg[2 * NT + t] = de0;
   }
-  __syncthreads();
+  wg_barrier<LdsOnly>();
   T a = T(0), c = T(0), d = T(0);
   if (own) {
     const int n = (t + 1) & mask;
@@ -501,7 +510,7 @@ __device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, 
     T* A = w.rows;
     A[t] = a; A[kR + t] = c; A[2 * kR + t] = d;
   }
-  __syncthreads();
+  wg_barrier<LdsOnly>();
   int b = 0;
   bool done = false;
   for (int s = 1; s < P && !done; s <<= 1) {
@@ -519,7 +528,7 @@ __device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, 
     const bool wave_live = __ballot(live) != 0;
     constexpr int kV = InterfaceSpace<T, NT>::kVoteWords;
     if ((t & 63) == 0) reinterpret_cast<unsigned char*>(w.votes + (1 - b) * kV)[t >> 6] = wave_live ? 1 : 0;
-    __syncthreads();
+    wg_barrier<LdsOnly>();
     b = 1 - b;
     uint64_t any = 0;
 #pragma unroll
@@ -544,7 +553,7 @@ __device__ __forceinline__ void interface_solve(const InterfaceSpace<T, NT>& w, 
 
 // One interface-partition solve of a whole system: eliminate (lanes with rows), exchange, PCR.  On
 // return y = y_t and yp = y_{t-1} (see interface_solve for the LDS contract).
-template <typename T, int NT, int M>
+template <typename T, int NT, int M, bool LdsOnly = false>
 __device__ __forceinline__ void interface_step(const InterfaceSpace<T, NT>& w, const ValueRows& src, bool own, int s,
                                                int m, int R, int P, T (&al)[M], T (&ga)[M], T (&de)[M], T& y,
                                                T& yp) {
@@ -561,8 +570,8 @@ __device__ __forceinline__ void interface_step(const InterfaceSpace<T, NT>& w, c
       }
     }
   }
-  interface_solve<T, NT>(w, P, own ? al[0] : T(0), own ? ga[0] : T(0), own ? de[0] : T(0), alL, gaL, deL, ia, ib,
-                         ic, id, y, yp);
+  interface_solve<T, NT, LdsOnly>(w, P, own ? al[0] : T(0), own ? ga[0] : T(0), own ? de[0] : T(0), alL, gaL, deL,
+                                  ia, ib, ic, id, y, yp);
 }
 
 // Interior rows from the interface unknowns (in place, rounded through the state type S as a store to
@@ -756,82 +765,147 @@ __global__ __launch_bounds__(NT, MC == 16 ? (FromState ? 4 : 2) : 1) void btcs_w
   }
 }
 
-// Per-step whole-system solver for systems of exactly 512 x 16 rows, persistent and pipelined: each
-// workgroup walks a strided share of the systems, and while it solves one system the coalesced loads of
-// its next system are already in flight into registers, so the step's HBM traffic overlaps the solves
-// (the one-system-per-workgroup kernel above loads, solves and stores in turn and overlaps only with the
-// other workgroup on its CU).  Same operations in the same order as btcs_wg_kernel<S, true, 512, 16,
-// true>: bitwise the same results.
+// Per-step whole-system solver for systems of exactly NT x MC rows whose first row is 16-byte aligned,
+// persistent and pipelined through LDS.  Each workgroup walks a strided share of the systems with two
+// staging buffers: while it solves system k (its rows in registers), the rows of system k + 1 stream from
+// HBM straight into the other buffer (global_load_lds, which holds no registers) and the stores of
+// system k - 1 drain, so the only wait for memory comes after the solve, at the top of the next system.
+// Loads and stores of a system go out as 16-byte chunks, every wave instruction covering 1 KB of
+// consecutive chunks.  In LDS the chunks are swizzled: chunk q = H t + h (lane t's h-th chunk of its
+// H = MC * sizeof(S) / 16) sits at H t + (h ^ f(t)), f(t) = (t / (16 / H)) mod H, so that 16 lanes
+// reading either their own chunks (one h each) or 16 consecutive chunks touch 16 different 16-byte bank
+// groups.  The interface solve's LDS overlays the buffer of the system being solved (its rows are in
+// registers by then).  Same operations in the same order as btcs_wg_kernel<S, true, NT, MC, true>:
+// bitwise the same results.
+template <typename S>
+struct Chunk16;
+template <>
+struct Chunk16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Chunk16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+
 template <typename S, int NT, int MC>
-__global__ __launch_bounds__(NT, NT == 1024 ? 4 : 2) void btcs_stream_kernel(const InstDesc* __restrict__ inst,
-                                                                            const SysDesc* __restrict__ systems,
-                                                                            int n_sys, const S* __restrict__ u,
-                                                                            S* __restrict__ out) {
+struct StreamLayout {
+  using V = typename Chunk16<S>::type;
+  static constexpr int kPer = 16 / static_cast<int>(sizeof(S));               // elements per chunk
+  static constexpr int kLane = MC / kPer;                                     // H: chunks of a lane's rows
+  static constexpr int kWaves = NT / 64;
+  static constexpr int kShift = kLane == 8 ? 1 : kLane == 4 ? 2 : 3;          // log2(16 / H)
+  static_assert(kLane == 2 || kLane == 4 || kLane == 8, "a lane's rows must be 2, 4 or 8 chunks");
+  static constexpr int kBuf = (NT * MC * static_cast<int>(sizeof(S)) > InterfaceSpace<double, NT>::kBytes
+                                   ? NT * MC * static_cast<int>(sizeof(S))
+                                   : InterfaceSpace<double, NT>::kBytes);
+  // LDS position of chunk q (an involution: the XOR leaves q / H unchanged)
+  __device__ static __forceinline__ int swz(int q) { return q ^ (((q / kLane) >> kShift) & (kLane - 1)); }
+  // Issue the loads of a system's rows (src: its first row) into the buffer buf: instruction k of wave w
+  // fills the LDS chunks 64 (k kWaves + w) + lane, each lane fetching the chunk that belongs there.
+  __device__ static __forceinline__ void load_async(unsigned char* buf, const S* src) {
+    const int lane = static_cast<int>(threadIdx.x) & 63, wave = static_cast<int>(threadIdx.x) >> 6;
+    const unsigned char* s = reinterpret_cast<const unsigned char*>(src);
+#pragma unroll
+    for (int k = 0; k < kLane; ++k) {
+      const int p0 = (k * kWaves + wave) * 64;
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(s + 16 * swz(p0 + lane)),
+          (__attribute__((address_space(3))) void*)(buf + 16 * p0), 16, 0, 0);
+    }
+  }
+  // Coalesced stores of a system's new rows from buf (dst: its first row).
+  __device__ static __forceinline__ void store(const unsigned char* buf, S* dst) {
+    const int lane = static_cast<int>(threadIdx.x) & 63, wave = static_cast<int>(threadIdx.x) >> 6;
+    const V* b = reinterpret_cast<const V*>(buf);
+    V* d = reinterpret_cast<V*>(dst);
+#pragma unroll
+    for (int k = 0; k < kLane; ++k) {
+      const int q = (k * kWaves + wave) * 64 + lane;
+      d[q] = b[swz(q)];
+    }
+  }
+};
+
+// vmcnt(0) with the other counters left alone: every vector memory access of this wave is complete,
+// including the LDS writes of global_load_lds (which the compiler does not track).
+__device__ __forceinline__ void wait_vector_memory() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+template <typename S, int NT, int MC>
+__global__ __launch_bounds__(NT, 2) void btcs_stream_kernel(const InstDesc* __restrict__ inst,
+                                                            const SysDesc* __restrict__ systems, int n_sys,
+                                                            const S* __restrict__ u, S* __restrict__ out) {
   using T = double;
-  constexpr int W = NT * MC;
+  using L = StreamLayout<S, NT, MC>;
+  using V = typename L::V;
+  constexpr int W = NT * MC, H = L::kLane, E = L::kPer;
   using IS = InterfaceSpace<T, NT>;
-  constexpr int kStageBytes = padded_size(W) * static_cast<int>(sizeof(S));
-  constexpr int kBytes = kStageBytes > IS::kBytes ? kStageBytes : IS::kBytes;
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kBytes];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[2 * L::kBuf];
   __shared__ uint64_t iface_votes[2 * IS::kVoteWords];
-  const IS iws{reinterpret_cast<T*>(smem), reinterpret_cast<T*>(smem) + 3 * NT, iface_votes};
-  iws.clear_votes();
-  S* stage = reinterpret_cast<S*>(smem);
   const int tid = threadIdx.x;
   int b = blockIdx.x;
   if (b >= n_sys) return;
-  // the first system's rows
+  if (tid < 2 * IS::kVoteWords) iface_votes[tid] = 0;
   SysDesc sys = systems[b];
   InstDesc d = inst[sys.inst];
-  S v[MC];
-  {
-    const S* __restrict__ x = u + d.off + (d.bc == kDirichlet ? 1 : 0) + tid;
-#pragma unroll
-    for (int j = 0; j < MC; ++j) v[j] = x[j * NT];
-  }
+  L::load_async(smem, u + d.off + (d.bc == kDirichlet ? 1 : 0));
+  // lane tid's chunks in LDS: H tid + (h ^ f(tid))
+  const int own = H * tid, fx = (tid >> L::kShift) & (H - 1);
+  int cur = 0;
+  S* prev_dst = nullptr;                       // rows of the previous system, still to be stored
   for (;;) {
+    wait_vector_memory();
+    __syncthreads();                           // this system's rows have landed; last system's results written
+    unsigned char* bc = smem + cur * L::kBuf;
+    unsigned char* bn = smem + (cur ^ 1) * L::kBuf;
+    if (prev_dst) L::store(bn, prev_dst);
     const bool dir = d.bc == kDirichlet;
+    T al[MC], ga[MC], de[MC];
 #pragma unroll
-    for (int j = 0; j < MC; ++j) stage[padded(tid + j * NT)] = v[j];
-    __syncthreads();
-    // the next system's rows, in flight while this one is solved
+    for (int h = 0; h < H; ++h) {
+      const V v = reinterpret_cast<const V*>(bc)[own + (h ^ fx)];
+#pragma unroll
+      for (int e = 0; e < E; ++e) de[h * E + e] = static_cast<T>(v[e]);
+    }
+    __syncthreads();                           // every read of both buffers done: bn takes the next rows
     const int nb = b + static_cast<int>(gridDim.x);
     SysDesc nsys{};
     InstDesc nd{};
     if (nb < n_sys) {
       nsys = systems[nb];
       nd = inst[nsys.inst];
-      const S* __restrict__ x = u + nd.off + (nd.bc == kDirichlet ? 1 : 0) + tid;
-#pragma unroll
-      for (int j = 0; j < MC; ++j) v[j] = x[j * NT];
+      L::load_async(bn, u + nd.off + (nd.bc == kDirichlet ? 1 : 0));
     }
     if (dir && tid == 0) {
       out[d.off] = static_cast<S>(d.a);
       out[d.off + d.n - 1] = static_cast<S>(d.b);
     }
-    T al[MC], ga[MC], de[MC];
-    const int s0 = tid * MC;
-    load_staged<S>(stage, 0, s0, MC, de);
-    __syncthreads();                           // every lane's rows read: the interface LDS overlays them
+    const IS iws{reinterpret_cast<T*>(bc), reinterpret_cast<T*>(bc) + 3 * NT, iface_votes};
     T y, yp;
-    interface_step<T, NT, MC>(iws, ValueRows{d.r, d.D, DirichletEnds{d.a, d.b, dir}}, true, s0, MC, W, NT, al, ga,
-                              de, y, yp);
-    __syncthreads();                           // the interface unknowns read before the rows are rewritten
-    const LdsDst<S> sdst{stage, 0};
+    interface_step<T, NT, MC, true>(iws, ValueRows{d.r, d.D, DirichletEnds{d.a, d.b, dir}}, true, tid * MC, MC, W,
+                                    NT, al, ga, de, y, yp);
+    wg_barrier<true>();                        // the interface unknowns read before bc takes the results
 #pragma unroll
-    for (int j = 0; j < MC; ++j) {
-      if (j < MC - 1) sdst.write(j, s0 + j, __builtin_fma(-ga[j], y, __builtin_fma(-al[j], yp, de[j])));
-      else sdst.write(j, s0 + j, y);
+    for (int h = 0; h < H; ++h) {
+      V v;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int j = h * E + e;
+        v[e] = static_cast<S>(j < MC - 1 ? __builtin_fma(-ga[j], y, __builtin_fma(-al[j], yp, de[j])) : y);
+      }
+      reinterpret_cast<V*>(bc)[own + (h ^ fx)] = v;
     }
-    __syncthreads();
-    const int64_t o = d.off + (dir ? 1 : 0);
-    if (sys.cn) stage_out_cn<S, NT, MC>(stage, u + o, out + o, W);
-    else stage_out<S, NT, MC>(stage, out + o, W);
-    if (nb >= n_sys) break;
-    __syncthreads();                           // the stage read out before the next system is written
+    S* dst = out + d.off + (dir ? 1 : 0);
+    if (nb >= n_sys) {
+      __syncthreads();
+      L::store(bc, dst);
+      break;
+    }
+    prev_dst = dst;
     b = nb;
     sys = nsys;
     d = nd;
+    cur ^= 1;
   }
 }
 
@@ -1797,12 +1871,15 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
     const SysDesc* sys = g.sys->as<SysDesc>();
     const unsigned n = static_cast<unsigned>(g.n);
     if (g.shape.exact) {
-      if (plan.stream_exact && g.shape.lanes == 1024)
+      // the pipelined kernel moves 16-byte chunks: the state buffers must be 16-byte aligned too
+      const bool stream =
+          g.shape.stream && ((reinterpret_cast<uintptr_t>(u) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+      if (stream && g.shape.lanes == 1024)
         btcs_stream_kernel<S, 1024, 8><<<std::min(n, static_cast<unsigned>(stream_grid<S, 1024, 8>(ctx->device))),
                                          1024, 0, st>>>(inst, sys, g.n, u, out);
       else if (g.shape.lanes == 1024)
         btcs_wg_kernel<S, true, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all);
-      else if (plan.stream_exact)
+      else if (stream)
         btcs_stream_kernel<S, 512, 16><<<std::min(n, static_cast<unsigned>(stream_grid<S, 512, 16>(ctx->device))),
                                          512, 0, st>>>(inst, sys, g.n, u, out);
       else

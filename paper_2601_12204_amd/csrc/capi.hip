@@ -289,7 +289,8 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     burgers::btcs_windows(i, R, ctx->probs[i].bc == BURGERS_BC_PERIODIC, plan->win_rows, is_cn, windows);
   };
   // whole-system systems grouped by width class (lanes, chunk, exact)
-  std::map<std::tuple<int, int, bool>, std::vector<SysDesc>> wg_state, resident;
+  std::map<std::tuple<int, int, bool>, std::vector<SysDesc>> wg_state, resident, streamed;
+  const int64_t elem = ctx->dtype == BURGERS_F64 ? 8 : 4;
   auto whole = [&](std::map<std::tuple<int, int, bool>, std::vector<SysDesc>>& groups, int32_t rows, int32_t i,
                    bool is_cn) {
     const burgers::WidthClass w = burgers::btcs_width_class(rows, threads);
@@ -321,7 +322,11 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     stepped.push_back(i);
     const bool partition = want == 3 ? R0 >= 32 : !fits;
     if (!partition) {
-      whole(wg_state, R0, i, is_cn);
+      // exact 8192-row systems whose first row is 16-byte aligned may take the pipelined kernel
+      const int64_t first = ctx->inst_host[i].off + (p.bc == BURGERS_BC_PERIODIC ? 0 : 1);
+      const bool streams = pipelined && !is_cn && burgers::btcs_width_class(R0, threads).exact &&
+                           (first * elem) % 16 == 0;
+      whole(streams ? streamed : wg_state, R0, i, is_cn);
       continue;
     }
     if (want != 3 && longmode != 1) add_windows(i, R0, is_cn);
@@ -349,10 +354,10 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   plan->level_rows = rows_used;
   hipError_t e;
   auto upload_groups = [&](std::map<std::tuple<int, int, bool>, std::vector<SysDesc>>& groups,
-                           std::vector<burgers::WgGroup>& out) -> hipError_t {
+                           std::vector<burgers::WgGroup>& out, bool stream) -> hipError_t {
     for (auto& kv : groups) {
       burgers::WgGroup g;
-      g.shape = burgers::WidthClass{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first)};
+      g.shape = burgers::WidthClass{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), stream};
       g.sys = std::make_unique<DevBuf>();
       g.n = static_cast<int32_t>(kv.second.size());
       hipError_t err = upload_on(ctx->stream, *g.sys, kv.second);
@@ -378,8 +383,9 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     }
     if ((e = upload_on(ctx->stream, *plan->inst_half, half)) != hipSuccess) return from_hip(e);
   }
-  if ((e = upload_groups(wg_state, plan->wg_state)) != hipSuccess ||
-      (e = upload_groups(resident, plan->resident)) != hipSuccess ||
+  if ((e = upload_groups(wg_state, plan->wg_state, false)) != hipSuccess ||
+      (e = upload_groups(streamed, plan->wg_state, true)) != hipSuccess ||
+      (e = upload_groups(resident, plan->resident, false)) != hipSuccess ||
       (e = upload_on(ctx->stream, *plan->copy, ct)) != hipSuccess)
     return from_hip(e);
   plan->win = std::make_unique<DevBuf>();

@@ -164,6 +164,7 @@ struct WidthClass {
   int lanes = 0;
   int chunk = 0;
   bool exact = false;
+  bool stream = false;   // exact systems with 16-byte aligned rows: the persistent pipelined per-step kernel
 };
 
 // Systems of one width class, one workgroup each.

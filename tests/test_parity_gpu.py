@@ -452,6 +452,31 @@ def test_btcs_resident_bitwise_equals_per_step(dtype, block):
     check_batch(batch, res, 25, dtype, scheme=W.BTCS)
 
 
+@pytest.mark.parametrize("block", [512, 1024])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_btcs_pipelined_per_step_bitwise(dtype, block):
+    """The persistent pipelined per-step kernel (btcs_pipeline 1: rows streamed into LDS while the
+    previous system is solved) equals one workgroup per system bitwise, and the oracle.  700 periodic
+    8192-row systems give every persistent workgroup two or three systems; Dirichlet 8192-row systems
+    (first row not 16-byte aligned) and other sizes in the same batch take the other kernels."""
+    problems, states = [], []
+    for k in range(700):
+        b = W.random_batch(900 + k, 1, 8192, 8192, bc=W.BC_PERIODIC, amplitude=3.0)
+        problems.append(b.problems[0])
+        states.append(b.instance(0))
+    for k, (n, bc) in enumerate([(8194, W.BC_DIRICHLET), (8192, W.BC_DIRICHLET), (4099, W.BC_PERIODIC),
+                                 (1000, W.BC_DIRICHLET), (8194, W.BC_DIRICHLET)]):
+        b = W.random_batch(1700 + k, 1, n, n, bc=bc, amplitude=3.0)
+        problems.insert(97 * k + 5, b.problems[0])
+        states.insert(97 * k + 5, b.instance(0))
+    batch = set_cfl_steps(W._pack(problems, states), scheme=W.BTCS)
+    announce(f"btcs pipelined per-step {dtype} block={block} 5 steps, {batch.count} instances")
+    piped = device_run(batch, 5, dtype, how="step_btcs", plan=dict(btcs_path=1, btcs_block=block, btcs_pipeline=1))
+    one = device_run(batch, 5, dtype, how="step_btcs", plan=dict(btcs_path=1, btcs_block=block, btcs_pipeline=2))
+    assert np.array_equal(piped, one)
+    check_batch(batch, piped, 5, dtype, scheme=W.BTCS)
+
+
 @pytest.mark.parametrize("path", [1, 2, 3, 0])
 def test_btcs_paths_against_oracle(path):
     """Per-step whole-system solves, the on-chip solver, partition levels for every system of >= 32 rows,
