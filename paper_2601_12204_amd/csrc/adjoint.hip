@@ -22,8 +22,12 @@ namespace burgers {
 namespace {
 
 constexpr int kAdjThreads = 256;
-constexpr int kAdjLaneNodes = 4;                          // consecutive nodes per lane (two 16-byte vectors)
-constexpr int kAdjTile = kAdjThreads * kAdjLaneNodes;     // nodes of one adjoint tile (one dJ/dD slot)
+constexpr int kAdjLaneNodes = 4;                          // BTCS tiles: consecutive nodes per lane
+constexpr int kAdjTile = kAdjThreads * kAdjLaneNodes;     // nodes of one BTCS adjoint tile (one dJ/dD slot)
+// Explicit tiles: one 16-byte vector per lane (C5, 256 x 16384: 74.4 ms per gradient with two vectors
+// per lane, 69.2 ms with one, 80.6 ms with four)
+constexpr int kAdjExpNodes = 2;
+constexpr int kAdjExpTile = kAdjThreads * kAdjExpNodes;
 
 // Sum over the workgroup in a fixed order (a butterfly within each wave, lane 0's result, then the waves
 // in order), so that the per-tile partials of dJ/dD are deterministic.  Valid in thread 0.
@@ -39,11 +43,11 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 }
 
 // lam = (dE/du)^T lamp at state u; partial dJ/dD of the tile added to gslot[tile.slot].  Each lane takes
-// kAdjLaneNodes consecutive nodes, loaded as 16-byte vectors with one neighbour on each side.
+// kAdjExpNodes consecutive nodes, loaded as 16-byte vectors with one neighbour on each side.
 __global__ __launch_bounds__(kAdjThreads) void adj_explicit_kernel(
     const InstDesc* __restrict__ inst, const AdjTile* __restrict__ tiles, const double* __restrict__ u,
     const double* __restrict__ lamp, double* __restrict__ lam, double* __restrict__ gslot) {
-  constexpr int V = kAdjLaneNodes;
+  constexpr int V = kAdjExpNodes;
   __shared__ double red[kAdjThreads / 64];
   const AdjTile t = tiles[blockIdx.x];
   const InstDesc d = inst[t.inst];
@@ -59,12 +63,13 @@ __global__ __launch_bounds__(kAdjThreads) void adj_explicit_kernel(
     // Dirichlet grid are never used)
     double Y[V + 2], L[V + 2];
     if (j0 + V <= n) {
-      const double2 y0 = *reinterpret_cast<const double2*>(y + j0);
-      const double2 y1 = *reinterpret_cast<const double2*>(y + j0 + 2);
-      const double2 l0 = *reinterpret_cast<const double2*>(lp + j0);
-      const double2 l1 = *reinterpret_cast<const double2*>(lp + j0 + 2);
-      Y[1] = y0.x; Y[2] = y0.y; Y[3] = y1.x; Y[4] = y1.y;
-      L[1] = l0.x; L[2] = l0.y; L[3] = l1.x; L[4] = l1.y;
+#pragma unroll
+      for (int q = 0; q < V; q += 2) {
+        const double2 yv = *reinterpret_cast<const double2*>(y + j0 + q);
+        const double2 lv = *reinterpret_cast<const double2*>(lp + j0 + q);
+        Y[q + 1] = yv.x; Y[q + 2] = yv.y;
+        L[q + 1] = lv.x; L[q + 2] = lv.y;
+      }
     } else {
 #pragma unroll
       for (int q = 0; q < V; ++q) {
@@ -109,8 +114,8 @@ __global__ __launch_bounds__(kAdjThreads) void adj_explicit_kernel(
     }
     double* __restrict__ dst = lam + t.off;
     if (j0 + V <= n) {
-      *reinterpret_cast<double2*>(dst + j0) = double2{out[0], out[1]};
-      *reinterpret_cast<double2*>(dst + j0 + 2) = double2{out[2], out[3]};
+#pragma unroll
+      for (int q = 0; q < V; q += 2) *reinterpret_cast<double2*>(dst + j0 + q) = double2{out[q], out[q + 1]};
     } else {
 #pragma unroll
       for (int q = 0; q < V; ++q)
@@ -228,7 +233,7 @@ __global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
 
 }  // namespace
 
-int adjoint_tile_nodes() { return kAdjTile; }
+int adjoint_tile_nodes(bool btcs) { return btcs ? kAdjTile : kAdjExpTile; }
 
 hipError_t launch_adj_explicit(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const double* u,
                                const double* lamp, double* lam, double* gslot) {

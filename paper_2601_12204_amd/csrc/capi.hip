@@ -765,7 +765,7 @@ burgers_status ensure_newton(burgers_ctx* ctx, const std::vector<int32_t>& membe
 burgers_status ensure_adjoint(burgers_ctx* ctx) {
   if (ctx->adjoint) return BURGERS_OK;
   auto ap = std::make_unique<burgers::AdjointPlan>();
-  const int tile = burgers::adjoint_tile_nodes();
+  const int exp_tile = burgers::adjoint_tile_nodes(false), btcs_tile = burgers::adjoint_tile_nodes(true);
   std::vector<burgers::AdjTile> et, bt;
   std::vector<int32_t> slot_begin(ctx->count + 1, 0);
   int32_t slot = 0;
@@ -794,6 +794,7 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
     const int32_t n = static_cast<int32_t>(p.n);
     const int32_t R = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
     slot_begin[i] = slot;
+    const int tile = p.scheme == BURGERS_BTCS ? btcs_tile : exp_tile;
     for (int64_t s = 0; s < n; s += tile)
       (p.scheme == BURGERS_BTCS ? bt : et)
           .push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, static_cast<int32_t>(s), slot++, 0});

@@ -322,7 +322,7 @@ int explicit_tile_nodes(burgers_dtype dt);
 int explicit_block_capacity();
 
 // adjoint.hip
-int adjoint_tile_nodes();
+int adjoint_tile_nodes(bool btcs);
 hipError_t launch_adj_explicit(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const double* u,
                                const double* lamp, double* lam, double* gslot);
 // `only` (optional): only the instances whose entry is nonzero (those whose windows flagged a failed
