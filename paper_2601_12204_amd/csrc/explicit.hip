@@ -268,10 +268,13 @@ __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf
 
 // Temporal-blocking body over NT lanes.  EXACT: the window has exactly NT * kBlockChunk nodes, so every lane
 // holds a full chunk and the guards below fold away.
+// t: the lane's index among the NT lanes that take the window (the workgroup's lane, or its lane within
+// its sub-group when several windows share a workgroup).  Every call executes the same sequence of
+// workgroup barriers for a given `steps`, whatever the window (an empty one included).
 template <typename T, bool EXACT, bool RK4, int NT, int ML = 0>
 __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& d, const T* __restrict__ src,
                                            T* __restrict__ dst, int steps, T* stage,
-                                           T (*s_first)[NT], T (*s_last)[NT]) {
+                                           T (*s_first)[NT], T (*s_last)[NT], int t) {
   constexpr int M = kBlockChunk;
   const T r = static_cast<T>(d.r), D = static_cast<T>(d.D);
   const int n = d.n;
@@ -280,7 +283,6 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   // lane t holds nodes [M t, M t + m): full chunks, except that the last of the P lanes holds mlast
   const int P = EXACT ? NT : (W + M - 1) / M;
   const int mlast = EXACT ? M : W - M * (P - 1);
-  const int t = threadIdx.x;
   const bool active = t < P;
   const int s = M * t;
   const int m = !active ? 0 : (t == P - 1 ? mlast : M);
@@ -384,6 +386,32 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   }
 }
 
+// One window on NT lanes: full-size windows of the widest class take the exact body, others the body
+// compiled for their last lane's node count.
+template <typename T, bool RK4, int NT>
+__device__ __forceinline__ void window_body(const BlockTile& bt, const InstDesc& d, const T* __restrict__ src,
+                                            T* __restrict__ dst, int steps, T* stage, T (*s_first)[NT],
+                                            T (*s_last)[NT], int t) {
+  if constexpr (NT == kBlockThreads) {
+    if (bt.width == NT * kBlockChunk) {
+      block_body<T, true, RK4, NT>(bt, d, src, dst, steps, stage, s_first, s_last, t);
+      return;
+    }
+  }
+  // the last lane's node count, uniform over the lanes of the window: one specialised body per count
+  const int mlast = bt.width - kBlockChunk * ((bt.width + kBlockChunk - 1) / kBlockChunk - 1);
+  switch (mlast) {
+#define BURGERS_RAGGED_CASE(K) \
+  case K: block_body<T, false, RK4, NT, K>(bt, d, src, dst, steps, stage, s_first, s_last, t); break;
+    BURGERS_RAGGED_CASE(1) BURGERS_RAGGED_CASE(2) BURGERS_RAGGED_CASE(3) BURGERS_RAGGED_CASE(4)
+    BURGERS_RAGGED_CASE(5) BURGERS_RAGGED_CASE(6) BURGERS_RAGGED_CASE(7) BURGERS_RAGGED_CASE(8)
+    BURGERS_RAGGED_CASE(9) BURGERS_RAGGED_CASE(10) BURGERS_RAGGED_CASE(11) BURGERS_RAGGED_CASE(12)
+    BURGERS_RAGGED_CASE(13) BURGERS_RAGGED_CASE(14) BURGERS_RAGGED_CASE(15) BURGERS_RAGGED_CASE(16)
+#undef BURGERS_RAGGED_CASE
+    default: break;
+  }
+}
+
 // One workgroup of NT lanes per window or whole instance; full-size windows of the widest class take the
 // specialised body.  RK4 windows run in a kernel of their own, so that the forward-Euler kernel keeps its
 // smaller register footprint.  Narrower classes serve smaller whole instances: fewer idle waves at each
@@ -404,25 +432,55 @@ __global__ __launch_bounds__(NT) void explicit_block_kernel(
   const InstDesc d = inst[bt.inst];
   const T* src = u + d.off;
   T* dst = out + d.off;
-  if constexpr (NT == kBlockThreads) {
-    if (bt.width == NT * kBlockChunk) {
-      block_body<T, true, RK4, NT>(bt, d, src, dst, steps, stage, s_first, s_last);
-      return;
-    }
-  }
-  {
-    // the last lane's node count, uniform over the workgroup: one specialised body per count
-    const int mlast = bt.width - kBlockChunk * ((bt.width + kBlockChunk - 1) / kBlockChunk - 1);
-    switch (mlast) {
-#define BURGERS_RAGGED_CASE(K) \
-  case K: block_body<T, false, RK4, NT, K>(bt, d, src, dst, steps, stage, s_first, s_last); break;
-      BURGERS_RAGGED_CASE(1) BURGERS_RAGGED_CASE(2) BURGERS_RAGGED_CASE(3) BURGERS_RAGGED_CASE(4)
-      BURGERS_RAGGED_CASE(5) BURGERS_RAGGED_CASE(6) BURGERS_RAGGED_CASE(7) BURGERS_RAGGED_CASE(8)
-      BURGERS_RAGGED_CASE(9) BURGERS_RAGGED_CASE(10) BURGERS_RAGGED_CASE(11) BURGERS_RAGGED_CASE(12)
-      BURGERS_RAGGED_CASE(13) BURGERS_RAGGED_CASE(14) BURGERS_RAGGED_CASE(15) BURGERS_RAGGED_CASE(16)
-#undef BURGERS_RAGGED_CASE
-      default: break;
-    }
+  window_body<T, RK4, NT>(bt, d, src, dst, steps, stage, s_first, s_last, static_cast<int>(threadIdx.x));
+}
+
+// LDS of a sub-group of NT lanes in the pack kernel: its exchange buffers and staging area.
+template <int NT>
+constexpr int sub_stage_size() {
+  return stage_nodes<NT>() + stage_nodes<NT>() / 16 + 1;
+}
+constexpr int pack_stage_size() {
+  constexpr int a = (kBlockThreads / 64) * sub_stage_size<64>(), b = (kBlockThreads / 128) * sub_stage_size<128>();
+  constexpr int c = (kBlockThreads / 256) * sub_stage_size<256>(), e = sub_stage_size<kBlockThreads>();
+  constexpr int ab = a > b ? a : b, ce = c > e ? c : e;
+  return ab > ce ? ab : ce;
+}
+
+template <typename T, bool RK4, int NT>
+__device__ __forceinline__ void pack_member(const InstDesc* __restrict__ inst, const BlockTile* __restrict__ tiles,
+                                            const BlockPack& pk, const T* __restrict__ u, T* __restrict__ out,
+                                            int steps, T* s_first_all, T* s_last_all, T* stage_all) {
+  const int g = static_cast<int>(threadIdx.x) / NT, t = static_cast<int>(threadIdx.x) % NT;
+  // a sub-group without an instance runs an empty window: no loads or stores, the same barriers
+  BlockTile bt{0, 0, 0, 0, 0, 0, RK4 ? 1 : 0, 0};
+  if (g < pk.count) bt = tiles[pk.first + g];
+  const InstDesc d = inst[bt.inst];
+  auto s_first = reinterpret_cast<T(*)[NT]>(s_first_all + g * 2 * NT);
+  auto s_last = reinterpret_cast<T(*)[NT]>(s_last_all + g * 2 * NT);
+  window_body<T, RK4, NT>(bt, d, u + d.off, out + d.off, steps, stage_all + g * sub_stage_size<NT>(), s_first, s_last,
+                          t);
+}
+
+// The whole instances of a call's narrower width classes (64, 128 and 256 lanes) in one launch over a
+// list of packs, widest class first: a workgroup of 512 lanes runs 512 / lanes instances side by side
+// (instances of 512 lanes would run one per workgroup too, but their own kernel compiles the step loop
+// to fewer registers).  The instances of a pack take the same number of steps, so their barriers
+// coincide.
+template <typename T, bool RK4>
+__global__ __launch_bounds__(kBlockThreads) void explicit_pack_kernel(const InstDesc* __restrict__ inst,
+                                                                      const BlockTile* __restrict__ tiles,
+                                                                      const BlockPack* __restrict__ packs,
+                                                                      T* __restrict__ u, int steps) {
+  __shared__ T s_first[2 * kBlockThreads];
+  __shared__ T s_last[2 * kBlockThreads];
+  __shared__ T stage[pack_stage_size()];
+  const BlockPack pk = packs[blockIdx.x];
+  switch (pk.lanes) {
+    case 64: pack_member<T, RK4, 64>(inst, tiles, pk, u, u, steps, s_first, s_last, stage); break;
+    case 128: pack_member<T, RK4, 128>(inst, tiles, pk, u, u, steps, s_first, s_last, stage); break;
+    case 256: pack_member<T, RK4, 256>(inst, tiles, pk, u, u, steps, s_first, s_last, stage); break;
+    default: pack_member<T, RK4, kBlockThreads>(inst, tiles, pk, u, u, steps, s_first, s_last, stage); break;
   }
 }
 
@@ -520,6 +578,30 @@ hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles,
   else block_launch_lanes<float>(ctx, tiles, n_fe, n_rk4, u, out, steps, lanes, first_step);
   return hipGetLastError();
 }
+
+hipError_t launch_explicit_packs(const burgers_ctx* ctx, const BlockTile* tiles, const BlockPack* packs,
+                                 int64_t n_fe, int64_t n_rk4, void* u, int steps) {
+  if (n_fe + n_rk4 <= 0 || steps <= 0) return hipSuccess;
+  const InstDesc* inst = ctx->inst.as<InstDesc>();
+  if (ctx->dtype == BURGERS_F64) {
+    if (n_fe > 0)
+      explicit_pack_kernel<double, false><<<static_cast<unsigned>(n_fe), kBlockThreads, 0, ctx->stream>>>(
+          inst, tiles, packs, static_cast<double*>(u), steps);
+    if (n_rk4 > 0)
+      explicit_pack_kernel<double, true><<<static_cast<unsigned>(n_rk4), kBlockThreads, 0, ctx->stream>>>(
+          inst, tiles, packs + n_fe, static_cast<double*>(u), steps);
+  } else {
+    if (n_fe > 0)
+      explicit_pack_kernel<float, false><<<static_cast<unsigned>(n_fe), kBlockThreads, 0, ctx->stream>>>(
+          inst, tiles, packs, static_cast<float*>(u), steps);
+    if (n_rk4 > 0)
+      explicit_pack_kernel<float, true><<<static_cast<unsigned>(n_rk4), kBlockThreads, 0, ctx->stream>>>(
+          inst, tiles, packs + n_fe, static_cast<float*>(u), steps);
+  }
+  return hipGetLastError();
+}
+
+int explicit_pack_lanes() { return kBlockThreads; }
 
 int explicit_block_lanes(int n) {
   int lanes = 64;

@@ -53,6 +53,15 @@ struct BlockTile {
   int32_t limit;  // > 0: advance at most this many of the launch's steps (a slot finishing mid-tick)
 };
 
+// Whole instances of one width class (`lanes` lanes each) that share a 512-lane workgroup of the explicit
+// pack kernel: tiles first .. first + count - 1 of the whole-instance list.
+struct BlockPack {
+  int32_t first;
+  int32_t count;
+  int32_t lanes;
+  int32_t unused;
+};
+
 // A run of 256 nodes of one instance in the adjoint sweep; `slot` indexes the tile's accumulator of
 // dJ/dD and `sys_off` the instance's transposed system in the adjoint arrays (BTCS instances).
 struct AdjTile {
@@ -223,6 +232,9 @@ struct ExplicitPlan {
     int64_t offset, n_fe, n_rk4;
   };
   std::vector<WholeClass> whole_classes;
+  // the narrower classes' instances packed for one launch per scheme (forward Euler packs, then RK4)
+  std::unique_ptr<DevBuf> packs;             // BlockPack[]
+  int64_t n_packs_fe = 0, n_packs_rk4 = 0;
   std::unique_ptr<DevBuf> win_copy;          // Tile[] of the windowed instances (copy-back)
   int64_t n_win_copy = 0;
   int path = 1;                              // 1 stream, 2 resident, 3 tiled
@@ -306,6 +318,11 @@ hipError_t launch_explicit_stream(const burgers_ctx* ctx, const Tile* tiles, int
 // take only the steps of the call they have left).
 hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_fe, int64_t n_rk4,
                                  const void* u, void* out, int steps, int lanes = 512, int first_step = 0);
+// Whole instances in place, the narrower width classes in one launch per scheme over packs (n_fe
+// forward-Euler packs, then n_rk4 RK4 packs).
+int explicit_pack_lanes();                  // lanes of a pack kernel workgroup
+hipError_t launch_explicit_packs(const burgers_ctx* ctx, const BlockTile* tiles, const BlockPack* packs,
+                                 int64_t n_fe, int64_t n_rk4, void* u, int steps);
 // Windows of a long explicit instance `i` of n nodes advanced `depth` steps per launch (halo = depth x
 // stages per side); appends them to `out`.  Returns false when the halo leaves no kept node.
 bool explicit_windows(int32_t i, int32_t n, bool periodic, int depth, bool rk4, std::vector<BlockTile>& out);

@@ -365,6 +365,27 @@ def test_explicit_paths_agree_bitwise_f64():
         assert np.array_equal(got, results[0]), (path, depth)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_explicit_packs_equal_streaming(dtype):
+    """Whole instances of the narrower width classes run packed, several per workgroup in lockstep
+    (64-lane instances eight to a workgroup, 128-lane four, 256-lane two; part-filled packs and the
+    widest class's own kernel beside them): bitwise equal to one HBM pass per step, and to the oracle."""
+    sizes = [3, 17, 64, 511, 1024, 1025, 1500, 2047, 2048, 2049, 4000, 4096, 4097, 6000, 8192]
+    problems, states = [], []
+    for k in range(60):
+        base = sizes[k % len(sizes)]
+        n = base if base == 8192 else base + k // len(sizes)
+        b = W.random_batch(2100 + k, 1, n, n, bc=k % 2, scheme=W.EXPLICIT, amplitude=3.0)
+        problems.append(b.problems[0])
+        states.append(b.instance(0))
+    batch = set_cfl_steps(W._pack(problems, states))
+    announce(f"explicit packs vs streaming {dtype}, {batch.count} instances, 23 steps")
+    packed = device_run(batch, 23, dtype, how="step_explicit", plan=dict(explicit_path=2))
+    streamed = device_run(batch, 23, dtype, how="step_explicit", plan=dict(explicit_path=1))
+    assert np.array_equal(packed, streamed)
+    check_batch(batch, packed, 23, dtype, scheme=W.EXPLICIT)
+
+
 @pytest.mark.parametrize("depth", [200, 0])
 def test_explicit_deep_windows(depth):
     """Deep temporal blocking (200 steps per launch, and the default) over 450 steps: several launches
