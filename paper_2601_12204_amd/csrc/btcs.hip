@@ -1253,6 +1253,14 @@ __global__ __launch_bounds__(NT, 4) void btcs_window_kernel(
   }
 }
 
+// An opaque copy of a lane value: address arithmetic built on it cannot be hoisted above this point, so
+// per-lane addresses are formed in the phase that uses them rather than kept live (or spilled) across
+// the kernel.
+__device__ __forceinline__ int opaque_lane(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 // ---- Adjoint BTCS step on truncated windows of the transposed system -----------------------------
 // The discrete adjoint of a BTCS step (y = u^k -> x = u^{k+1}) solves A(y)^T mu = lam' and then sets
 // lam = (1 - G) mu with G_i = r (x_i - x_{i-1}) for y_i >= 0, r (x_{i+1} - x_i) otherwise, and adds
@@ -1327,13 +1335,32 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
 #pragma unroll
   for (int j = 0; j < MC; ++j) de[j] = stage[padded(s + j)];
   __syncthreads();
-  // y of rows -1..W, and max |y| over them
+  // y of rows -1..W (every load in flight at once), and max |y| over them; bit q of ypos: the upwind
+  // side of row tid + q NT (y >= 0), for the finish
   T big = T(0);
-  for (int k = tid - 1; k <= W; k += NT) {
-    const T v = yn[node_of(k)];
-    stage[padded(k + 1)] = v;
-    big = __builtin_fmax(big, __builtin_fabs(v));
+  unsigned ypos = 0;
+  {
+    const int lt = opaque_lane(tid);
+    T ge = T(0);
+    if (tid < 2) ge = yn[node_of(lt == 0 ? -1 : W)];
+#pragma unroll
+    for (int h = 0; h < MC; h += MC / 2) {     // (in two halves, so that lam' and the loads fit registers)
+      T v[MC / 2];
+#pragma unroll
+      for (int j = 0; j < MC / 2; ++j) v[j] = yn[node_of(lt + (h + j) * NT)];
+#pragma unroll
+      for (int j = 0; j < MC / 2; ++j) {
+        stage[padded(lt + (h + j) * NT + 1)] = v[j];
+        big = __builtin_fmax(big, __builtin_fabs(v[j]));
+        ypos |= (v[j] >= 0.0 ? 1u : 0u) << (h + j);
+      }
+    }
+    if (tid < 2) {
+      stage[padded(tid == 0 ? 0 : W + 1)] = ge;
+      big = __builtin_fmax(big, __builtin_fabs(ge));
+    }
   }
+  ypos = static_cast<unsigned>(opaque_lane(static_cast<int>(ypos)));   // (formed here, not from y kept live)
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) big = __builtin_fmax(big, __shfl_xor(big, m, 64));
   if ((tid & 63) == 0) wave_val[tid >> 6] = big;
@@ -1362,23 +1389,46 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
   T yv, yp;
   interface_solve<T, NT>(iws, NT, al[0], ga[0], de[0], al[MC - 2], ga[MC - 2], de[MC - 2], ia, ib, ic, id, yv, yp);
   __syncthreads();                             // the interface unknowns read before mu is written
+  // mu through the stage from the lanes' chunks to rows tid + q NT
 #pragma unroll
   for (int j = 0; j < MC; ++j)
     stage[padded(s + j)] = j < MC - 1 ? __builtin_fma(-ga[j], yv, __builtin_fma(-al[j], yp, de[j])) : yv;
   __syncthreads();
-  // finish the kept rows: lam = (1 - G) mu, and the partial sum of -mu (2 x_j - x_{j-1} - x_{j+1})
+  const int lm = opaque_lane(tid);
+#pragma unroll
+  for (int q = 0; q < MC; ++q) de[q] = stage[padded(lm + q * NT)];
+  __syncthreads();                             // mu read: the stage takes x
+  // x = u^(k+1) of rows -1..W through the stage (every load in flight)
   const double* __restrict__ xn = x + d.off;
+  {
+    const int lt = opaque_lane(tid);
+    T ge = T(0);
+    if (tid < 2) ge = xn[node_of(lt == 0 ? -1 : W)];
+#pragma unroll
+    for (int h = 0; h < MC; h += MC / 2) {
+      T v[MC / 2];
+#pragma unroll
+      for (int j = 0; j < MC / 2; ++j) v[j] = xn[node_of(lt + (h + j) * NT)];
+#pragma unroll
+      for (int j = 0; j < MC / 2; ++j) stage[padded(lt + (h + j) * NT + 1)] = v[j];
+    }
+    if (tid < 2) stage[padded(tid == 0 ? 0 : W + 1)] = ge;
+  }
+  __syncthreads();
+  // finish the kept rows tid + q NT: lam = (1 - G) mu (coalesced stores), and the lane's partial sum of
+  // -mu (2 x_j - x_{j-1} - x_{j+1}) in row order
   T g = T(0);
-  int lane = tid;
-  asm volatile("" : "+v"(lane));
-  for (int o = lane; o < wd.count; o += NT) {
-    const int k = wd.lo + o;
+  const int lf = opaque_lane(tid);
+#pragma unroll
+  for (int q = 0; q < MC; ++q) {
+    const int k = lf + q * NT;
+    if (k < wd.lo || k >= wd.lo + wd.count) continue;
     const int j = node_of(k);
-    const T mu = stage[padded(k)];
-    const T xm = dir ? (j == 1 ? d.a : xn[j - 1]) : xn[j == 0 ? n - 1 : j - 1];
-    const T xp = dir ? (j == n - 2 ? d.b : xn[j + 1]) : xn[j == n - 1 ? 0 : j + 1];
-    const T xj = xn[j];
-    const T G = yn[j] >= 0.0 ? d.r * (xj - xm) : d.r * (xp - xj);
+    const T mu = de[q];
+    const T xm = dir && j == 1 ? d.a : stage[padded(k)];
+    const T xp = dir && j == n - 2 ? d.b : stage[padded(k + 2)];
+    const T xj = stage[padded(k + 1)];
+    const T G = (ypos >> q) & 1u ? d.r * (xj - xm) : d.r * (xp - xj);
     lam[d.off + j] = (1.0 - G) * mu;
     g = g - mu * ((2.0 * xj - xm) - xp);
   }
@@ -1389,7 +1439,6 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
   // the window's partial, summed in a fixed order
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) g = g + __shfl_xor(g, m, 64);
-  __syncthreads();
   if ((tid & 63) == 0) wave_val[tid >> 6] = g;
   __syncthreads();
   if (tid == 0) {
