@@ -913,7 +913,8 @@ __global__ __launch_bounds__(NT, 2) void btcs_stream_kernel(const InstDesc* __re
 // Rows of a Newton iteration (fully implicit central-convection step, eqs. 10-14) for the whole system of
 // one instance: the Jacobian row of eq. 11 at the iterate x (staged in LDS, unknown k at padded(k)) and
 // the right-hand side -F, with the old state u read from HBM.  The increment of a Dirichlet neighbour is
-// zero, so the end rows simply drop that coupling.
+// zero, so the end rows simply drop that coupling.  A row that is not strictly diagonally dominant is
+// noted in `bad` (kept per lane, branch-free, and reported once after the elimination).
 template <typename S>
 struct NewtonRows {
   const double* st;
@@ -921,6 +922,7 @@ struct NewtonRows {
   double half_r, D, a, b;
   bool periodic;
   int* flags;
+  mutable bool bad = false;
   __device__ __forceinline__ void row(int, int k, int R, double& al, double& be, double& ga, double& de) const {
     const double xm = k > 0 ? st[padded(k - 1)] : (periodic ? st[padded(R - 1)] : a);
     const double xp = k < R - 1 ? st[padded(k + 1)] : (periodic ? st[padded(0)] : b);
@@ -934,7 +936,7 @@ struct NewtonRows {
       if (k == 0) al = 0.0;
       if (k == R - 1) ga = 0.0;
     }
-    newton_check_row(al, be, ga, flags);
+    bad = bad || newton_row_not_dominant(al, be, ga);
   }
   __device__ __forceinline__ void boundary(int, int, int, double&, double&, double&, double&) const {}
 };
@@ -957,6 +959,7 @@ __device__ __forceinline__ void newton_solve(const PcrSpace<double, NT>& pcr, do
       m = MC;
     }
     chunk_eliminate<T, MC>(rows, s, m, R, al, ga, de, AF, CF, DF, AE, CE, DE);
+    if (rows.bad) rows.flags[0] = 1;
   }
   __syncthreads();                             // the PCR rows overlay the staged iterate
   T F = T(0), E = T(0);
@@ -1012,6 +1015,7 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void newton_wg_kernel(const I
     if (tid == 0) {
       T al, be, ga, de;
       rows.row(0, 0, 1, al, be, ga, de);
+      if (rows.bad) flags[0] = 1;
       const T delta = de / be;
       const S v = static_cast<S>(stage[0] + delta);
       xs[0] = v;

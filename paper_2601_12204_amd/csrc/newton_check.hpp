@@ -25,9 +25,14 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Row (sub, diag, sup) of the Jacobian: flag a row that is not strictly diagonally dominant.
+// Row (sub, diag, sup) of the Jacobian that is not strictly diagonally dominant (or not finite).
+__device__ __forceinline__ bool newton_row_not_dominant(double sub, double diag, double sup) {
+  return !(__builtin_fabs(diag) > __builtin_fabs(sub) + __builtin_fabs(sup));
+}
+
+// Flag such a row.
 __device__ __forceinline__ void newton_check_row(double sub, double diag, double sup, int* flags) {
-  if (!(__builtin_fabs(diag) > __builtin_fabs(sub) + __builtin_fabs(sup))) flags[0] = 1;
+  if (newton_row_not_dominant(sub, diag, sup)) flags[0] = 1;
 }
 
 // Last iteration of a node: increment delta, new iterate xn, old state u.  `active` is false for lanes
