@@ -106,16 +106,18 @@ typedef struct burgers_ctx burgers_ctx; /* opaque */
  *                  2 resident: a whole instance held on chip for many steps (n <= resident limit);
  *                  3 tiled: temporal blocking, tblock_depth steps per pass over HBM tiles.
  *   tblock_depth   steps per HBM pass of temporal blocking (1..512), 0 = automatic (128).
- *   btcs_path      1 workgroup: one workgroup solves one system per step (n <= workgroup limit);
+ *   btcs_path      1 workgroup: one workgroup solves one system per step (systems of up to 8192 rows,
+ *                    or of exactly 16384: 1024 lanes of 16 rows; longer ones take btcs_long's solver);
  *                  2 resident: one workgroup per system for many steps;
  *                  3 multilevel: recursive partition across workgroups (any n).
  *   use_graph      1 replays the launch sequence of a stepping call from a captured HIP graph,
  *                  0 launches eagerly, -1 automatic.
  *   btcs_block     lanes per system for BTCS systems of exactly 8192 rows (512 lanes of 16 rows or
- *                  1024 of 8; 0 automatic = 512).  Other whole systems take the narrowest of 128, 256,
- *                  512 or 1024 lanes that holds them at <= 8 rows per lane.
- *   btcs_long      solver of the systems longer than 8192 rows (every BTCS and Crank-Nicolson step of
- *                  them goes through HBM):
+ *                  1024 of 8; 0 automatic = 512).  Systems of exactly 16384 rows take 1024 lanes of 16;
+ *                  other whole systems the narrowest of 128, 256, 512 or 1024 lanes that holds them at
+ *                  <= 8 rows per lane.
+ *   btcs_long      solver of the other systems longer than 8192 rows (all but those of exactly 16384;
+ *                  every BTCS and Crank-Nicolson step of them goes through HBM):
  *                  0 truncated windows (default): each window of 4096 rows (2: of 8192 rows, in
  *                    wider workgroups) is solved as a plain system
  *                    whose neighbours beyond its ends take their old values, and only its rows at least
@@ -147,8 +149,9 @@ typedef struct {
   int32_t btcs_path;
   int32_t use_graph;
   int32_t btcs_block;      /* lanes for 8192-row BTCS systems: 512, 1024, or 0 = automatic */
-  int32_t btcs_long;       /* systems of more than 8192 rows stepped through HBM: 0 truncated windows
-                              of 4096 rows, 1 partition levels, 2 windows of 8192 rows (see below) */
+  int32_t btcs_long;       /* systems of more than 8192 rows (other than 16384) stepped through HBM:
+                              0 truncated windows of 4096 rows, 1 partition levels, 2 windows of 8192
+                              rows (see below) */
   int32_t serial;          /* 1: one stream; 0: the independent launch groups run concurrently */
   int32_t btcs_pipeline;   /* per-step solves of exact 8192-row systems: 0 automatic, 1 persistent
                               workgroups that load the next system while solving one, 2 one workgroup

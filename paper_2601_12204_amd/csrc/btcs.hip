@@ -33,7 +33,8 @@ namespace {
 constexpr int kWgThreads = 512;   // threads of the whole-system solver
 constexpr int kWgChunk = 16;      // longest chunk a thread of the whole-system solver eliminates
 constexpr int kRedChunk = 16;     // chunk length in the partition levels
-constexpr int kWgRows = kWgThreads * kWgChunk;            // longest system solved whole
+constexpr int kWgRows = kWgThreads * kWgChunk;            // longest system of the exact 512 x 16 kernels
+constexpr int kWholeRows = 2 * kWgRows;                   // longest system solved whole (1024 lanes x 16)
 constexpr int kRedRows = kReduceBlock * kRedChunk;        // rows one partition workgroup stages
 
 // Rows staged in LDS are padded by one element every 32 rows: a thread reads its chunk with a lane
@@ -1924,6 +1925,10 @@ hipError_t launch_step(const burgers_ctx* ctx, const BtcsPlan& plan, const void*
     if (!g.n) continue;
     const SysDesc* sys = g.sys->as<SysDesc>();
     const unsigned n = static_cast<unsigned>(g.n);
+    if (g.shape.chunk == 16 && g.shape.lanes == 1024) {   // 16384 rows
+      btcs_wg_kernel<S, true, 1024, 16, true><<<n, 1024, 0, st>>>(inst, sys, u, out, LA, LC, LD, LX, all);
+      continue;
+    }
     if (g.shape.exact) {
       // the pipelined kernel moves 16-byte chunks: the state buffers must be 16-byte aligned too
       const bool stream =
@@ -1968,6 +1973,10 @@ void resident_launch(const burgers_ctx* ctx, const WgGroup& g, S* u, int steps) 
   const SysDesc* sys = g.sys->as<SysDesc>();
   const unsigned n = static_cast<unsigned>(g.n);
   hipStream_t st = ctx->stream;
+  if (g.shape.chunk == 16 && g.shape.lanes == 1024) {   // 16384 rows
+    btcs_resident_kernel<S, 1024, 16, true><<<n, 1024, 0, st>>>(inst, sys, u, steps);
+    return;
+  }
   if (g.shape.exact) {
     if (g.shape.lanes == 1024)
       btcs_resident_kernel<S, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, steps);
@@ -2014,11 +2023,14 @@ hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, con
   return hipGetLastError();
 }
 
-// Width class of a system of up to 8192 rows.  A system of exactly 8192 rows runs the exact kernels
-// (`threads` = 512 lanes of 16 rows, or 1024 of 8); any other size takes the narrowest workgroup whose
-// lanes hold at most 8 rows each, so ragged chunks never need more than 8 registers per row array.
+// Width class of a system solved whole (btcs_solved_whole).  A system of exactly 8192 rows runs the
+// exact kernels (`threads` = 512 lanes of 16 rows, or 1024 of 8), one of exactly 16384 rows 1024 lanes
+// of 16; any other size (up to 8192) takes the narrowest workgroup whose lanes hold at most 8 rows each,
+// so ragged chunks never need more than 8 registers per row array (ragged chunks of up to 16 rows would
+// spill: systems of 8193 to 16383 rows stay on the long-system solvers).
 WidthClass btcs_width_class(int rows, int threads) {
   if (rows == kWgRows) return threads == 1024 ? WidthClass{1024, 8, true} : WidthClass{512, 16, true};
+  if (rows == kWholeRows) return WidthClass{1024, 16, true};
   int lanes = 128;
   while (lanes * 8 < rows) lanes *= 2;
   return WidthClass{lanes, 8, false};
@@ -2033,6 +2045,8 @@ int btcs_chunks(int rows, int threads) {
 }
 
 int btcs_wg_capacity() { return kWgRows; }
+int btcs_whole_capacity() { return kWholeRows; }
+bool btcs_solved_whole(int64_t rows) { return rows <= kWgRows || rows == kWholeRows; }
 
 int btcs_wg_chunks(int rows) {
   // largest power of two P <= min(threads, rows / 2); rows <= capacity keeps every chunk <= kWgChunk

@@ -323,7 +323,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
   for (int32_t i : set_members(ctx, set)) {
     const burgers_problem& p = ctx->probs[i];
     const int32_t R0 = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
-    const bool fits = R0 <= cap;
+    const bool fits = burgers::btcs_solved_whole(R0);
     // Crank-Nicolson instances (advanced by their own scheme) need the old state after each solve, so
     // they always step through HBM
     const bool is_cn = own_scheme_set(set) && p.scheme == BURGERS_CN;
@@ -344,8 +344,7 @@ burgers_status ensure_btcs(burgers_ctx* ctx, int set) {
     if (!partition) {
       // exact 8192-row systems whose first row is 16-byte aligned may take the pipelined kernel
       const int64_t first = ctx->inst_host[i].off + (p.bc == BURGERS_BC_PERIODIC ? 0 : 1);
-      const bool streams = pipelined && !is_cn && burgers::btcs_width_class(R0, threads).exact &&
-                           (first * elem) % 16 == 0;
+      const bool streams = pipelined && !is_cn && R0 == burgers::btcs_wg_capacity() && (first * elem) % 16 == 0;
       whole(streams ? streamed : wg_state, R0, i, is_cn);
       continue;
     }
@@ -1114,7 +1113,7 @@ burgers_status burgers_autotune(burgers_ctx* ctx, const void* u, int64_t explici
     if (ctx->probs[i].n > burgers::explicit_block_capacity()) long_exp = true;
   for (int32_t i : ctx->set_btcs) {
     const burgers_problem& p = ctx->probs[i];
-    if ((p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2) > burgers::btcs_wg_capacity()) long_btcs = true;
+    if (!burgers::btcs_solved_whole(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2)) long_btcs = true;
   }
   // One knob at a time (coordinate descent from the current plan): the explicit path and window depth,
   // the lanes per 8192-row BTCS system, the long-system BTCS solver, concurrent launch groups, graph

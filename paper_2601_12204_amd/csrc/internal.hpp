@@ -366,7 +366,10 @@ hipError_t launch_newton_update(const burgers_ctx* ctx, const AdjTile* tiles, in
                                 void* x, const double* NX, bool last, int* flags);
 
 // btcs.hip
-int btcs_wg_capacity();                 // longest system one workgroup solves whole
+int btcs_wg_capacity();                 // longest system of the exact 512-lane kernels and of the
+                                        // partition levels' reduced systems (8192 rows)
+int btcs_whole_capacity();              // longest system one workgroup solves whole (16384 rows)
+bool btcs_solved_whole(int64_t rows);   // up to 8192 rows, or exactly 16384: one workgroup per system
 int btcs_wg_chunks(int rows);
 int btcs_wg_lanes(const std::vector<SysDesc>& systems);
 bool btcs_wg_exact(const std::vector<SysDesc>& systems);   // all of 512 chunks x 16 rows (a constant layout)   // workgroup width that serves all of them           // chunk count the workgroup solver uses for `rows` rows

@@ -498,6 +498,31 @@ def test_btcs_pipelined_per_step_bitwise(dtype, block):
     check_batch(batch, piped, 5, dtype, scheme=W.BTCS)
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_btcs_16384_row_systems_whole(dtype):
+    """Systems of exactly 16384 rows are solved whole by 1024 lanes of 16 rows (periodic N = 16384,
+    Dirichlet N = 16386), on chip for all steps and per step: the two agree bitwise and match the oracle;
+    16383 and 16385 rows stay on the long-system solvers beside them.  A Crank-Nicolson instance of 16384
+    rows takes the per-step kernel's 2y - u store."""
+    problems, states = [], []
+    for k, (n, bc) in enumerate([(16384, W.BC_PERIODIC), (16386, W.BC_DIRICHLET), (16384, W.BC_PERIODIC),
+                                 (16383, W.BC_PERIODIC), (16387, W.BC_DIRICHLET), (100, W.BC_PERIODIC)]):
+        b = W.random_batch(2300 + k, 1, n, n, bc=bc, scheme=W.BTCS, amplitude=3.0)
+        problems.append(b.problems[0])
+        states.append(b.instance(0))
+    batch = set_cfl_steps(W._pack(problems, states), scheme=W.BTCS)
+    announce(f"btcs 16384-row systems {dtype}: resident vs per-step, 11 steps")
+    res = device_run(batch, 11, dtype, how="step_btcs", plan=dict(btcs_path=0))
+    per = device_run(batch, 11, dtype, how="step_btcs", plan=dict(btcs_path=1))
+    assert np.array_equal(res, per)
+    check_batch(batch, res, 11, dtype, scheme=W.BTCS)
+    # Crank-Nicolson at 16384 rows (per-step kernel, 2y - u)
+    cn = W.random_batch(2400, 1, 16384, 16384, bc=W.BC_PERIODIC, scheme=W.CN, amplitude=2.0)
+    cn = set_cfl_steps(cn, scheme=W.CN)
+    got = device_run(cn, 7, dtype, how="run")
+    check_batch(cn, got, 7, dtype)
+
+
 @pytest.mark.parametrize("path", [1, 2, 3, 0])
 def test_btcs_paths_against_oracle(path):
     """Per-step whole-system solves, the on-chip solver, partition levels for every system of >= 32 rows,
