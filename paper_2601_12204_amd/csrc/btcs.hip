@@ -1298,11 +1298,15 @@ struct AdjRows {
   }
 };
 
-template <int NT>
+// WHOLE: the window is a whole system of exactly W rows (start 0, every row kept), solved exactly: cyclic
+// for a periodic instance, no bound to check, and the system's partial of dJ/dD is added straight to its
+// slot (gslot[slots[b]]: one workgroup per slot, so the sums stay deterministic).
+template <int NT, bool WHOLE = false>
 __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
     const InstDesc* __restrict__ inst, const WinDesc* __restrict__ wins, const double* __restrict__ u,
     const double* __restrict__ x, const double* __restrict__ lamp, double* __restrict__ lam,
-    double* __restrict__ wpart, int* __restrict__ flag_now, int* __restrict__ flag_next) {
+    double* __restrict__ wpart, int* __restrict__ flag_now, int* __restrict__ flag_next,
+    double* __restrict__ gslot = nullptr, const int32_t* __restrict__ slots = nullptr) {
   using T = double;
   constexpr int MC = kWgChunk, W = NT * MC;
   using IS = InterfaceSpace<T, NT>;
@@ -1370,7 +1374,7 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
   for (int m = 32; m >= 1; m >>= 1) big = __builtin_fmax(big, __shfl_xor(big, m, 64));
   if ((tid & 63) == 0) wave_val[tid >> 6] = big;
   __syncthreads();
-  if (tid == 0) {
+  if (!WHOLE && tid == 0) {
     T M = T(0);
 #pragma unroll
     for (int k = 0; k < NT / 64; ++k) M = __builtin_fmax(M, wave_val[k]);
@@ -1388,7 +1392,8 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
   }
   T al[MC], ga[MC];
   T ia = T(0), ib = T(1), ic = T(0), id = T(0);
-  const AdjRows rows{stage, d.r, d.D, DirichletEnds{0.0, 0.0, true}};
+  // zero ghosts: a window is a plain system; a whole periodic system keeps its cyclic couplings
+  const AdjRows rows{stage, d.r, d.D, DirichletEnds{0.0, 0.0, WHOLE ? dir : true}};
   interface_eliminate<T, MC, true>(rows, s, MC, W, al, ga, de, ia, ib, ic, id);
   __syncthreads();                             // every row read: the interface LDS overlays the stage
   T yv, yp;
@@ -1450,7 +1455,8 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
     T tot = wave_val[0];
 #pragma unroll
     for (int k = 1; k < NT / 64; ++k) tot = tot + wave_val[k];
-    wpart[blockIdx.x] = tot;
+    if constexpr (WHOLE) gslot[slots[blockIdx.x]] = gslot[slots[blockIdx.x]] + tot;
+    else wpart[blockIdx.x] = tot;
   }
 }
 
@@ -2109,6 +2115,16 @@ hipError_t launch_btcs_window_reset(const burgers_ctx* ctx, const BtcsPlan& plan
 }
 
 int btcs_window_halo() { return kWinHalo; }
+
+hipError_t launch_adj_btcs_whole(const burgers_ctx* ctx, const WinDesc* wins, int64_t n, const double* u,
+                                 const double* x, const double* lamp, double* lam, double* gslot,
+                                 const int32_t* slots) {
+  if (n <= 0) return hipSuccess;
+  adj_btcs_window_kernel<kWholeRows / kWgChunk, true><<<static_cast<unsigned>(n), kWholeRows / kWgChunk, 0,
+                                                         ctx->stream>>>(ctx->inst.as<InstDesc>(), wins, u, x, lamp,
+                                                                        lam, nullptr, nullptr, nullptr, gslot, slots);
+  return hipGetLastError();
+}
 
 hipError_t launch_adj_btcs_windows(const burgers_ctx* ctx, const WinDesc* wins, int64_t n_win, const double* u,
                                    const double* x, const double* lamp, double* lam, double* wpart, int* flag_now,

@@ -803,15 +803,21 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   }
   std::vector<std::tuple<int32_t, int64_t, int32_t>> roots;
   int64_t rows_used = sys_rows;
-  // windows of the transposed systems when every BTCS instance is longer than the on-chip limit
+  // every BTCS instance of exactly 16384 rows: each transposed system solved whole; otherwise windows of
+  // the transposed systems when every BTCS instance is longer than 8192 rows
+  bool whole = !ctx->set_btcs.empty();
+  for (int32_t i : ctx->set_btcs) {
+    const burgers_problem& p = ctx->probs[i];
+    whole = whole && (p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2) == burgers::btcs_whole_capacity();
+  }
   bool windows = false;
   for (int32_t i : ctx->set_btcs) {
     const burgers_problem& p = ctx->probs[i];
-    windows = (p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2) > burgers::btcs_wg_capacity();
+    windows = !whole && (p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2) > burgers::btcs_wg_capacity();
     if (!windows) break;
   }
-  std::vector<burgers::WinDesc> wins;
-  std::vector<int32_t> win_slot;
+  std::vector<burgers::WinDesc> wins, wholes;
+  std::vector<int32_t> win_slot, whole_slot;
   for (int32_t i = 0; i < ctx->count; ++i) {
     const burgers_problem& p = ctx->probs[i];
     const int32_t n = static_cast<int32_t>(p.n);
@@ -828,6 +834,10 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
         burgers::btcs_windows(i, R, p.bc == BURGERS_BC_PERIODIC, 4096, false, wins);
         for (size_t w = w0; w < wins.size(); ++w) win_slot.push_back(slot++);
       }
+      if (whole) {
+        wholes.push_back(burgers::WinDesc{i, 0, 0, R, 0, 0});
+        whole_slot.push_back(slot++);
+      }
     }
   }
   slot_begin[ctx->count] = slot;
@@ -841,6 +851,12 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   ap->n_exp_tiles = static_cast<int64_t>(et.size());
   ap->n_btcs_tiles = static_cast<int64_t>(bt.size());
   ap->n_slots = slot;
+  ap->whole = std::make_unique<DevBuf>();
+  ap->whole_slot = std::make_unique<DevBuf>();
+  if ((e = upload_on(ctx->stream, *ap->whole, wholes)) != hipSuccess ||
+      (e = upload_on(ctx->stream, *ap->whole_slot, whole_slot)) != hipSuccess)
+    return from_hip(e);
+  ap->n_whole = static_cast<int64_t>(wholes.size());
   ap->win = std::make_unique<DevBuf>();
   ap->win_slot = std::make_unique<DevBuf>();
   if ((e = upload_on(ctx->stream, *ap->win, wins)) != hipSuccess ||
@@ -876,6 +892,9 @@ hipError_t enqueue_adjoint_step(burgers_ctx* ctx, const double* y, const double*
   hipError_t e = burgers::launch_adj_explicit(ctx, ap.exp_tiles->as<burgers::AdjTile>(), ap.n_exp_tiles, y,
                                               lam_in, lam_out, g);
   if (e != hipSuccess || ap.n_btcs_tiles == 0) return e;
+  if (ap.n_whole > 0)   // every BTCS system solved whole and exactly: nothing is left for the array path
+    return burgers::launch_adj_btcs_whole(ctx, ap.whole->as<burgers::WinDesc>(), ap.n_whole, y, x, lam_in, lam_out,
+                                          g, ap.whole_slot->as<int32_t>());
   const int* only = nullptr;
   if (ap.n_win > 0) {
     int* now = burgers::win_flag_slot(ap.flags.as<int>(), ctx->count, step);

@@ -255,6 +255,10 @@ struct AdjointPlan {
   std::unique_ptr<DevBuf> win, win_slot;           // WinDesc[], int32[] (dJ/dD slot of each window)
   int64_t n_win = 0;
   DevBuf wpart, flags;                              // double[n_win]; win_flags_words(count) int32
+  // every BTCS instance of exactly 16384 rows: each transposed system solved whole, exactly, by one
+  // workgroup per step (WinDesc covering it, and its dJ/dD slot); the array path is then not used
+  std::unique_ptr<DevBuf> whole, whole_slot;
+  int64_t n_whole = 0;
 };
 
 // Fully implicit central-convection instances (Newton-Raphson, a fixed number of iterations per step):
@@ -390,6 +394,9 @@ hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, doub
                               double* LD, double* LX, const int* only = nullptr);
 // Adjoint BTCS step of the long instances on truncated windows of the transposed system (lam from lamp
 // at the forward pair u -> x); per-window partials of dJ/dD into wpart; failed bounds flag instances.
+hipError_t launch_adj_btcs_whole(const burgers_ctx* ctx, const WinDesc* wins, int64_t n, const double* u,
+                                 const double* x, const double* lamp, double* lam, double* gslot,
+                                 const int32_t* slots);
 hipError_t launch_adj_btcs_windows(const burgers_ctx* ctx, const WinDesc* wins, int64_t n_win, const double* u,
                                    const double* x, const double* lamp, double* lam, double* wpart, int* flag_now,
                                    int* flag_next);

@@ -127,6 +127,34 @@ def test_adjoint_long_btcs_windows(factor):
     assert np.array_equal(g2[0], g) and np.array_equal(g2[1], gn)
 
 
+def test_adjoint_16384_row_systems_whole():
+    """Every BTCS instance of exactly 16384 rows (periodic N = 16384, Dirichlet N = 16386): each
+    transposed system is solved whole and exactly by one workgroup per step (cyclic when periodic),
+    with no array path behind it; gradients against the oracle, and bitwise equal for two checkpoint
+    intervals.  Explicit instances in the same context keep their own adjoint."""
+    problems, states = [], []
+    for k, (n, bc) in enumerate([(16384, W.BC_PERIODIC), (16386, W.BC_DIRICHLET), (16384, W.BC_PERIODIC)]):
+        b = W.random_batch(1900 + k, 1, n, n, bc=bc, scheme=W.BTCS, amplitude=2.0)
+        problems.append(b.problems[0])
+        states.append(b.instance(0))
+    b = W.random_batch(1950, 1, 3000, 3000, scheme=W.EXPLICIT, amplitude=2.0)
+    problems.append(b.problems[0])
+    states.append(b.instance(0))
+    batch = set_cfl_steps(W._pack(problems, states))
+    lam = np.random.default_rng(19).standard_normal(len(batch.u0))
+    nsteps = 6
+    announce(f"adjoint 16384-row systems whole, {nsteps} steps")
+    g, gn, raw, offs = _device_adjoint(batch, lam, nsteps, 2)
+    rg, rgn = oracle.adjoint(batch.problems, batch.u0, batch.offsets, lam, nsteps)
+    _check_padding(raw, offs, batch)
+    for k in range(batch.count):
+        lo, hi = batch.offsets[k], batch.offsets[k + 1]
+        assert oracle.rel_max_abs(g[lo:hi], rg[lo:hi]) <= TOL, (k, batch.problems[k])
+    assert np.max(np.abs(gn - rgn) / np.maximum(np.abs(rgn), 1e-300)) <= 1e-10, (gn, rgn)
+    g2 = _device_adjoint(batch, lam, nsteps, 5)
+    assert np.array_equal(g2[0], g) and np.array_equal(g2[1], gn)
+
+
 @pytest.mark.parametrize("scheme", [W.EXPLICIT, W.BTCS])
 def test_c5_adjoint_full_size_sampled(scheme):
     """The gradient workload at its real size, in the benchmark's configuration: 256 periodic instances
