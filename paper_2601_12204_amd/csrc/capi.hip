@@ -1242,6 +1242,7 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   const int64_t ncp = (nsteps + K - 1) / K;   // checkpoints at steps 0, K, 2K, ...
   if ((e = grow(ap.ckpt, state_bytes * static_cast<size_t>(std::max<int64_t>(ncp, 1)), ctx->stream)) != hipSuccess ||
       (e = grow(ap.seg, state_bytes * static_cast<size_t>(K + 1), ctx->stream)) != hipSuccess ||
+      (ncp > 1 && (e = grow(ap.seg2, state_bytes * static_cast<size_t>(K + 1), ctx->stream)) != hipSuccess) ||
       (e = grow(ap.lam0, state_bytes, ctx->stream)) != hipSuccess || (e = grow(ap.lam1, state_bytes, ctx->stream)) != hipSuccess)
     return from_hip(e);
   auto state = [&](DevBuf& b, int64_t k) { return static_cast<char*>(b.ptr) + static_cast<size_t>(k) * state_bytes; };
@@ -1266,25 +1267,55 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   // seg[k]: the streaming kernel for the explicit instances, the per-step solves for the BTCS ones
   const burgers::ExplicitPlan* ep = ctx->set_explicit.empty() ? nullptr : ctx->explicit_plans[kSetExplicit].get();
   const burgers::BtcsPlan* bp = ctx->set_btcs.empty() ? nullptr : ctx->btcs[kSetBtcsHbm].get();
+  auto recompute = [&](int64_t c, DevBuf& seg) -> hipError_t {
+    const int64_t len = std::min(K, nsteps - c * K);
+    hipError_t err = hipMemcpyAsync(state(seg, 0), state(ap.ckpt, c), state_bytes, d2d, ctx->stream);
+    if (err == hipSuccess && bp) err = burgers::launch_btcs_window_reset(ctx, *bp);
+    for (int64_t k = 1; k <= len && err == hipSuccess; ++k) {
+      if (ep) err = burgers::launch_explicit_stream(ctx, ep->stream->as<Tile>(), ep->n_stream, state(seg, k - 1),
+                                                    state(seg, k));
+      if (err == hipSuccess && bp) err = burgers::launch_btcs_step(ctx, *bp, state(seg, k - 1), state(seg, k), k - 1);
+    }
+    return err;
+  };
+  // Segment c's reverse steps run on the context's stream while segment c - 1 is recomputed into the
+  // other segment buffer on a side stream (the recompute uses none of the reverse steps' buffers): both
+  // are HBM-bound chains of short launches, which fill each other's gaps.  The side stream starts after
+  // the previous segment's reverse steps (which read the buffer it overwrites) and the context's stream
+  // waits for it before the next segment's reverse steps.
+  if (ncp > 1) {
+    if (!ctx->side[0] && (e = hipStreamCreateWithFlags(&ctx->side[0], hipStreamNonBlocking)) != hipSuccess)
+      return note(ctx, e);
+    if (!ctx->joined[0] && (e = hipEventCreateWithFlags(&ctx->joined[0], hipEventDisableTiming)) != hipSuccess)
+      return note(ctx, e);
+    if (!ctx->forked && (e = hipEventCreateWithFlags(&ctx->forked, hipEventDisableTiming)) != hipSuccess)
+      return note(ctx, e);
+  }
+  DevBuf* segs[2] = {&ap.seg, &ap.seg2};
+  if (ncp > 0 && (e = recompute(ncp - 1, ap.seg)) != hipSuccess) return note(ctx, e);
   for (int64_t c = ncp - 1; c >= 0; --c) {
     const int64_t len = std::min(K, nsteps - c * K);
-    if ((e = hipMemcpyAsync(state(ap.seg, 0), state(ap.ckpt, c), state_bytes, d2d, ctx->stream)) != hipSuccess)
-      return note(ctx, e);
-    if (bp && (e = burgers::launch_btcs_window_reset(ctx, *bp)) != hipSuccess) return note(ctx, e);
-    for (int64_t k = 1; k <= len; ++k) {
-      if (ep && (e = burgers::launch_explicit_stream(ctx, ep->stream->as<Tile>(), ep->n_stream, state(ap.seg, k - 1),
-                                                     state(ap.seg, k))) != hipSuccess)
-        return note(ctx, e);
-      if (bp && (e = burgers::launch_btcs_step(ctx, *bp, state(ap.seg, k - 1), state(ap.seg, k), k - 1)) != hipSuccess)
-        return note(ctx, e);
+    DevBuf& cur = *segs[(ncp - 1 - c) & 1];
+    if (c > 0) {   // fork: recompute the next segment beside this one's reverse steps
+      hipStream_t main = ctx->stream;
+      e = hipEventRecord(ctx->forked, main);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side[0], ctx->forked, 0);
+      if (e == hipSuccess) {
+        ctx->stream = ctx->side[0];
+        e = recompute(c - 1, *segs[(ncp - c) & 1]);
+        ctx->stream = main;
+      }
+      if (e == hipSuccess) e = hipEventRecord(ctx->joined[0], ctx->side[0]);
+      if (e != hipSuccess) return note(ctx, e);
     }
     for (int64_t k = len - 1; k >= 0; --k) {
-      if ((e = enqueue_adjoint_step(ctx, reinterpret_cast<const double*>(state(ap.seg, k)),
-                                    reinterpret_cast<const double*>(state(ap.seg, k + 1)), lam, lam_next,
+      if ((e = enqueue_adjoint_step(ctx, reinterpret_cast<const double*>(state(cur, k)),
+                                    reinterpret_cast<const double*>(state(cur, k + 1)), lam, lam_next,
                                     rstep++)) != hipSuccess)
         return note(ctx, e);
       std::swap(lam, lam_next);
     }
+    if (c > 0 && (e = hipStreamWaitEvent(ctx->stream, ctx->joined[0], 0)) != hipSuccess) return note(ctx, e);   // join
   }
   if ((e = ensure_copy(ctx, kSetAll)) != hipSuccess) return from_hip(e);
   auto& all_tiles = ctx->copy_tiles[kSetAll];

@@ -249,7 +249,7 @@ struct AdjointPlan {
   int64_t n_slots = 0;
   BtcsPlan solve;                                   // partition hierarchy over the transposed systems
   DevBuf LA, LC, LD, LX, gslot;
-  DevBuf ckpt, seg, lam0, lam1;                     // grown on demand
+  DevBuf ckpt, seg, seg2, lam0, lam1;               // grown on demand (seg2: the segment recomputed alongside)
   // truncated windows of the transposed systems (when every BTCS instance has more than 8192 rows); the
   // array path above is then the fallback of the instances whose windows flag a failed bound
   std::unique_ptr<DevBuf> win, win_slot;           // WinDesc[], int32[] (dJ/dD slot of each window)
