@@ -1032,18 +1032,71 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void newton_wg_kernel(const I
   else newton_solve<false, S, NT, MC>(pcr, stage, rows, xs, R, P, last != 0);
 }
 
-// Resident solver: one workgroup keeps one system (<= 8192 rows) in registers, MC rows per lane (NT
-// lanes x MC = 8192), for all steps of a launch.  Each step is the whole-system solver's step without the trips to HBM; the
-// state is rounded through S once per step as the per-step kernel's store would, so both solvers agree
-// bitwise.  The state buffer is read once and written once per launch (in place).
-template <typename S, int NT, int MC, bool EXACT = false>
+// An opaque copy of a lane value: address arithmetic built on it cannot be hoisted above this point, so
+// per-lane addresses are formed in the phase that uses them rather than kept live (or spilled) across
+// the kernel.
+__device__ __forceinline__ int opaque_lane(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Stores one step's rows of a system at x (its first unknown; REC of the resident solver): lane t holds
+// rows [s, s + m) in de.  Each wave passes its lanes' rows through a region of LDS of its own, half the
+// wave at a time (32 chunks of MC rows, one slot of padding per chunk), and stores them in row order, 64
+// consecutive slots per instruction.  The region is private to the wave, so no workgroup barrier is
+// needed; a wave's LDS accesses are performed in order, which the wavefront-scope fences keep the
+// compiler from reordering.
+template <typename S, int NT, int MC, bool EXACT>
+__device__ __forceinline__ void record_rows(const double (&de)[MC], double* lds, int R, int P,
+                                            S* __restrict__ x) {
+  constexpr int kHalf = 32, kSlots = kHalf * MC;
+  static_assert(kSlots % 64 == 0, "a half-wave's rows must fill whole store instructions");
+  // (the lane index is formed here, at every step, so that no address of the stores below is kept live
+  // across the solve)
+  const int lt = opaque_lane(static_cast<int>(threadIdx.x));
+  const int lane = lt & 63, wave = lt >> 6;
+  double* region = lds + wave * kHalf * (MC + 1);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if ((lane >> 5) == h) {
+#pragma unroll
+      for (int j = 0; j < MC; ++j) region[(MC + 1) * (lane & 31) + j] = de[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 2   // (fully unrolled, the loads held for the stores spill across the solve)
+    for (int i = 0; i < kSlots / 64; ++i) {
+      const int q = lane + 64 * i;
+      const int owner = 64 * wave + kHalf * h + q / MC, j = q % MC;   // the slot's lane and row in its chunk
+      int so = MC * owner, mo = MC;
+      if constexpr (!EXACT) chunk_span(owner, R, P, so, mo);
+      const double v = region[(MC + 1) * (q / MC) + j];
+      if (owner < P && j < mo) x[so + j] = static_cast<S>(v);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// Resident solver: one workgroup keeps one system (<= 8192 rows, or exactly 16384) in registers, MC rows
+// per lane, for all steps of a launch.  Each step is the whole-system solver's step without the trips to
+// HBM; the state is rounded through S once per step as the per-step kernel's store would, so both solvers
+// agree bitwise.  The state buffer is read once and written once per launch (in place).
+// REC: the source u is only read, and the state after each step k (1 <= k <= steps) is stored at
+// rec + (k - 1) rstride (Dirichlet boundary values included) instead of the final one in place; the
+// step's barriers then wait for LDS only, so those stores stay in flight across the next steps.
+template <typename S, int NT, int MC, bool EXACT = false, bool REC = false>
 __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
     const InstDesc* __restrict__ inst, const SysDesc* __restrict__ systems, S* __restrict__ u,
-    int steps) {
+    int steps, S* __restrict__ rec, int64_t rstride) {
   using T = double;
   using IS = InterfaceSpace<T, NT>;
+  constexpr int kRecSlots = REC ? (NT / 64) * 32 * (MC + 1) : 1;
   __shared__ T iface_lds[IS::kBytes / sizeof(T)];
   __shared__ uint64_t iface_votes[2 * IS::kVoteWords];
+  __shared__ T rec_lds[kRecSlots];
   const IS ws{iface_lds, iface_lds + 3 * NT, iface_votes};
   ws.clear_votes();
   const SysDesc sys = systems[blockIdx.x];
@@ -1054,9 +1107,17 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
   const int R = sys.rows, P = sys.chunks;
   const int tid = threadIdx.x;
   S* __restrict__ x = u + d.off + (dir ? 1 : 0);
+  S* __restrict__ xr = REC ? rec + d.off + (dir ? 1 : 0) : nullptr;
   if (dir && tid == 0) {
-    u[d.off] = static_cast<S>(d.a);
-    u[d.off + d.n - 1] = static_cast<S>(d.b);
+    if constexpr (REC) {
+      for (int step = 0; step < steps; ++step) {
+        rec[step * rstride + d.off] = static_cast<S>(d.a);
+        rec[step * rstride + d.off + d.n - 1] = static_cast<S>(d.b);
+      }
+    } else {
+      u[d.off] = static_cast<S>(d.a);
+      u[d.off + d.n - 1] = static_cast<S>(d.b);
+    }
   }
   if (R == 1) {   // a single Dirichlet unknown
     if (tid == 0) {
@@ -1066,8 +1127,9 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
         btcs_row(v, d.r, d.D, al, be, ga);
         const T de = (v - al * d.a) - ga * d.b;
         v = static_cast<T>(static_cast<S>(de / be));
+        if constexpr (REC) xr[step * rstride] = static_cast<S>(v);
       }
-      x[0] = static_cast<S>(v);
+      if constexpr (!REC) x[0] = static_cast<S>(v);
     }
     return;
   }
@@ -1087,13 +1149,16 @@ __global__ __launch_bounds__(NT, MC == 16 ? 4 : 1) void btcs_resident_kernel(
   const int mm = EXACT ? MC : m;
   for (int step = 0; step < steps; ++step) {
     T y, yp;
-    interface_step<T, NT, MC>(ws, src, tid < P, s, mm, R, P, al, ga, de, y, yp);
+    interface_step<T, NT, MC, REC>(ws, src, tid < P, s, mm, R, P, al, ga, de, y, yp);
     if (tid < P) interface_recover_in_place<S>(mm, al, ga, de, yp, y);
+    if constexpr (REC) record_rows<S, NT, MC, EXACT>(de, rec_lds, R, P, xr + step * rstride);
   }
-  if (tid < P) {
+  if constexpr (!REC) {
+    if (tid < P) {
 #pragma unroll
-    for (int j = 0; j < MC; ++j)
-      if (j < m) x[s + j] = static_cast<S>(de[j]);
+      for (int j = 0; j < MC; ++j)
+        if (j < m) x[s + j] = static_cast<S>(de[j]);
+    }
   }
 }
 
@@ -1258,13 +1323,6 @@ __global__ __launch_bounds__(NT, 4) void btcs_window_kernel(
   }
 }
 
-// An opaque copy of a lane value: address arithmetic built on it cannot be hoisted above this point, so
-// per-lane addresses are formed in the phase that uses them rather than kept live (or spilled) across
-// the kernel.
-__device__ __forceinline__ int opaque_lane(int v) {
-  asm volatile("" : "+v"(v));
-  return v;
-}
 
 // ---- Adjoint BTCS step on truncated windows of the transposed system -----------------------------
 // The discrete adjoint of a BTCS step (y = u^k -> x = u^{k+1}) solves A(y)^T mu = lam' and then sets
@@ -1980,21 +2038,21 @@ void resident_launch(const burgers_ctx* ctx, const WgGroup& g, S* u, int steps) 
   const unsigned n = static_cast<unsigned>(g.n);
   hipStream_t st = ctx->stream;
   if (g.shape.chunk == 16 && g.shape.lanes == 1024) {   // 16384 rows
-    btcs_resident_kernel<S, 1024, 16, true><<<n, 1024, 0, st>>>(inst, sys, u, steps);
+    btcs_resident_kernel<S, 1024, 16, true><<<n, 1024, 0, st>>>(inst, sys, u, steps, nullptr, 0);
     return;
   }
   if (g.shape.exact) {
     if (g.shape.lanes == 1024)
-      btcs_resident_kernel<S, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, steps);
+      btcs_resident_kernel<S, 1024, 8, true><<<n, 1024, 0, st>>>(inst, sys, u, steps, nullptr, 0);
     else
-      btcs_resident_kernel<S, 512, 16, true><<<n, 512, 0, st>>>(inst, sys, u, steps);
+      btcs_resident_kernel<S, 512, 16, true><<<n, 512, 0, st>>>(inst, sys, u, steps, nullptr, 0);
     return;
   }
   switch (g.shape.lanes) {
-    case 128: btcs_resident_kernel<S, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, steps); break;
-    case 256: btcs_resident_kernel<S, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, steps); break;
-    case 512: btcs_resident_kernel<S, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, steps); break;
-    default: btcs_resident_kernel<S, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, steps); break;
+    case 128: btcs_resident_kernel<S, 128, 8><<<n, 128, 0, st>>>(inst, sys, u, steps, nullptr, 0); break;
+    case 256: btcs_resident_kernel<S, 256, 8><<<n, 256, 0, st>>>(inst, sys, u, steps, nullptr, 0); break;
+    case 512: btcs_resident_kernel<S, 512, 8><<<n, 512, 0, st>>>(inst, sys, u, steps, nullptr, 0); break;
+    default: btcs_resident_kernel<S, 1024, 8><<<n, 1024, 0, st>>>(inst, sys, u, steps, nullptr, 0); break;
   }
 }
 
@@ -2002,6 +2060,41 @@ hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, vo
   if (group.n <= 0 || steps <= 0) return hipSuccess;
   if (ctx->dtype == BURGERS_F64) resident_launch<double>(ctx, group, static_cast<double*>(u), steps);
   else resident_launch<float>(ctx, group, static_cast<float*>(u), steps);
+  return hipGetLastError();
+}
+
+// The resident solver recording every step (the adjoint's recompute of a checkpoint segment).
+void record_launch(const burgers_ctx* ctx, const WgGroup& g, const double* src, double* rec, int64_t rstride,
+                   int steps) {
+  const InstDesc* inst = ctx->inst.as<InstDesc>();
+  const SysDesc* sys = g.sys->as<SysDesc>();
+  const unsigned n = static_cast<unsigned>(g.n);
+  hipStream_t st = ctx->stream;
+  double* u = const_cast<double*>(src);   // only read by the recording kernels
+  if (g.shape.chunk == 16 && g.shape.lanes == 1024) {   // 16384 rows
+    btcs_resident_kernel<double, 1024, 16, true, true><<<n, 1024, 0, st>>>(inst, sys, u, steps, rec, rstride);
+    return;
+  }
+  if (g.shape.exact) {
+    if (g.shape.lanes == 1024)
+      btcs_resident_kernel<double, 1024, 8, true, true><<<n, 1024, 0, st>>>(inst, sys, u, steps, rec, rstride);
+    else
+      btcs_resident_kernel<double, 512, 16, true, true><<<n, 512, 0, st>>>(inst, sys, u, steps, rec, rstride);
+    return;
+  }
+  switch (g.shape.lanes) {
+    case 128: btcs_resident_kernel<double, 128, 8, false, true><<<n, 128, 0, st>>>(inst, sys, u, steps, rec, rstride); break;
+    case 256: btcs_resident_kernel<double, 256, 8, false, true><<<n, 256, 0, st>>>(inst, sys, u, steps, rec, rstride); break;
+    case 512: btcs_resident_kernel<double, 512, 8, false, true><<<n, 512, 0, st>>>(inst, sys, u, steps, rec, rstride); break;
+    default: btcs_resident_kernel<double, 1024, 8, false, true><<<n, 1024, 0, st>>>(inst, sys, u, steps, rec, rstride); break;
+  }
+}
+
+hipError_t launch_btcs_record(const burgers_ctx* ctx, const WgGroup& group, const void* src, void* rec,
+                              int64_t rstride, int steps) {
+  if (group.n <= 0 || steps <= 0) return hipSuccess;
+  if (ctx->dtype != BURGERS_F64) return hipErrorInvalidValue;
+  record_launch(ctx, group, static_cast<const double*>(src), static_cast<double*>(rec), rstride, steps);
   return hipGetLastError();
 }
 

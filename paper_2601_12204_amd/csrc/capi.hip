@@ -1241,8 +1241,8 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
   const int64_t K = std::min<int64_t>(ckpt_every, std::max<int64_t>(nsteps, 1));
   const int64_t ncp = (nsteps + K - 1) / K;   // checkpoints at steps 0, K, 2K, ...
   if ((e = grow(ap.ckpt, state_bytes * static_cast<size_t>(std::max<int64_t>(ncp, 1)), ctx->stream)) != hipSuccess ||
-      (e = grow(ap.seg, state_bytes * static_cast<size_t>(K + 1), ctx->stream)) != hipSuccess ||
-      (ncp > 1 && (e = grow(ap.seg2, state_bytes * static_cast<size_t>(K + 1), ctx->stream)) != hipSuccess) ||
+      (e = grow(ap.seg, state_bytes * static_cast<size_t>(K), ctx->stream)) != hipSuccess ||
+      (ncp > 1 && (e = grow(ap.seg2, state_bytes * static_cast<size_t>(K), ctx->stream)) != hipSuccess) ||
       (e = grow(ap.lam0, state_bytes, ctx->stream)) != hipSuccess || (e = grow(ap.lam1, state_bytes, ctx->stream)) != hipSuccess)
     return from_hip(e);
   auto state = [&](DevBuf& b, int64_t k) { return static_cast<char*>(b.ptr) + static_cast<size_t>(k) * state_bytes; };
@@ -1263,18 +1263,41 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
       (ap.n_win > 0 && (e = burgers::launch_clear_ints(ctx, ap.flags.as<int>(), 2 * (ctx->count + 1))) != hipSuccess))
     return note(ctx, e);
   int64_t rstep = 0;
-  // the segment's states are recomputed out of place, one step per launch from seg[k-1] straight into
-  // seg[k]: the streaming kernel for the explicit instances, the per-step solves for the BTCS ones
+  // State k of segment c: the checkpoint for k = 0, else slot k - 1 of the segment's buffer.
+  auto at = [&](int64_t c, DevBuf& seg, int64_t k) { return k == 0 ? state(ap.ckpt, c) : state(seg, k - 1); };
+  // A segment's states are recomputed out of place.  Instances that the forward sweep keeps on chip are
+  // kept on chip here too, by kernels that store the state after every step (one launch per segment, or
+  // per `depth` steps for the explicit windows, whose halos cover that many steps): each state is written
+  // once and nothing is read back.  The others step one launch at a time from state k - 1 straight into
+  // state k: the streaming kernel for explicit instances, the per-step solves for BTCS ones.
   const burgers::ExplicitPlan* ep = ctx->set_explicit.empty() ? nullptr : ctx->explicit_plans[kSetExplicit].get();
-  const burgers::BtcsPlan* bp = ctx->set_btcs.empty() ? nullptr : ctx->btcs[kSetBtcsHbm].get();
+  const bool exp_rec = ep && ep->path != 1;
+  const burgers::BtcsPlan* bres = ctx->set_btcs.empty() ? nullptr : ctx->btcs[kSetBtcs].get();
+  const bool btcs_rec = bres && bres->n_copy == 0 && !bres->resident.empty();
+  const burgers::BtcsPlan* bp = ctx->set_btcs.empty() || btcs_rec ? nullptr : ctx->btcs[kSetBtcsHbm].get();
+  const int64_t stride = ctx->total;
   auto recompute = [&](int64_t c, DevBuf& seg) -> hipError_t {
     const int64_t len = std::min(K, nsteps - c * K);
-    hipError_t err = hipMemcpyAsync(state(seg, 0), state(ap.ckpt, c), state_bytes, d2d, ctx->stream);
+    hipError_t err = hipSuccess;
+    for (int64_t k0 = 0; exp_rec && k0 < len && err == hipSuccess; k0 += ep->depth) {
+      const int k = static_cast<int>(std::min<int64_t>(ep->depth, len - k0));
+      err = burgers::launch_explicit_record(ctx, ep->whole->as<BlockTile>(), ep->n_whole, at(c, seg, k0),
+                                            at(c, seg, k0 + 1), stride, k);
+      if (err == hipSuccess)
+        err = burgers::launch_explicit_record(ctx, ep->win->as<BlockTile>(), ep->n_win, at(c, seg, k0),
+                                              at(c, seg, k0 + 1), stride, k);
+    }
+    if (btcs_rec)
+      for (const burgers::WgGroup& g : bres->resident)
+        if (err == hipSuccess)
+          err = burgers::launch_btcs_record(ctx, g, at(c, seg, 0), at(c, seg, 1), stride, static_cast<int>(len));
+    const bool exp_step = ep && !exp_rec;
     if (err == hipSuccess && bp) err = burgers::launch_btcs_window_reset(ctx, *bp);
-    for (int64_t k = 1; k <= len && err == hipSuccess; ++k) {
-      if (ep) err = burgers::launch_explicit_stream(ctx, ep->stream->as<Tile>(), ep->n_stream, state(seg, k - 1),
-                                                    state(seg, k));
-      if (err == hipSuccess && bp) err = burgers::launch_btcs_step(ctx, *bp, state(seg, k - 1), state(seg, k), k - 1);
+    for (int64_t k = 1; (exp_step || bp) && k <= len && err == hipSuccess; ++k) {
+      if (exp_step)
+        err = burgers::launch_explicit_stream(ctx, ep->stream->as<Tile>(), ep->n_stream, at(c, seg, k - 1),
+                                              at(c, seg, k));
+      if (err == hipSuccess && bp) err = burgers::launch_btcs_step(ctx, *bp, at(c, seg, k - 1), at(c, seg, k), k - 1);
     }
     return err;
   };
@@ -1309,8 +1332,8 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
       if (e != hipSuccess) return note(ctx, e);
     }
     for (int64_t k = len - 1; k >= 0; --k) {
-      if ((e = enqueue_adjoint_step(ctx, reinterpret_cast<const double*>(state(cur, k)),
-                                    reinterpret_cast<const double*>(state(cur, k + 1)), lam, lam_next,
+      if ((e = enqueue_adjoint_step(ctx, reinterpret_cast<const double*>(at(c, cur, k)),
+                                    reinterpret_cast<const double*>(at(c, cur, k + 1)), lam, lam_next,
                                     rstep++)) != hipSuccess)
         return note(ctx, e);
       std::swap(lam, lam_next);

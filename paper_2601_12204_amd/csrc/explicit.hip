@@ -240,7 +240,9 @@ __device__ __forceinline__ void rk4_stage(T (&v)[kBlockChunk], const T (&in)[kBl
 }
 
 // Publish a lane's chunk end values in exchange buffer `buf`, wait, and read the neighbours' ends.
-template <typename T, bool EXACT, int NT, int ML = 0>
+// LdsOnly: the barrier waits for this wave's LDS accesses only, not for its stores to HBM, which then
+// stay in flight across the step (the recording kernel's states).
+template <typename T, bool EXACT, int NT, int ML = 0, bool LdsOnly = false>
 __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf, int t, int P, int mlast,
                                               bool active, T (*s_first)[NT], T (*s_last)[NT],
                                               T& left, T& right) {
@@ -259,10 +261,57 @@ __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf
     }
     s_last[buf][t] = last;
   }
-  __syncthreads();
+  if constexpr (LdsOnly) asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  else __syncthreads();
   if (active) {
     left = t > 0 ? s_last[buf][t - 1] : s_last[buf][P - 1];
     right = t < P - 1 ? s_first[buf][t + 1] : s_first[buf][0];
+  }
+}
+
+// Stores one step's state of the window's output nodes [bt.lo, bt.lo + bt.count) at `rec` (the
+// instance's first node).  Each wave passes its lanes' chunks through a region of the staging buffer of
+// its own, half the wave at a time (32 chunks of 16 nodes, padded like the staging), and stores them as
+// 64 consecutive nodes per instruction.  The region is private to the wave, so no workgroup barrier is
+// needed; a wave's LDS accesses are performed in order, which the wavefront-scope fences keep the
+// compiler from reordering.
+// (The lane index passes through an empty asm statement at every step, so that no address of these
+// stores is formed once and kept live across the step loop.)
+template <typename T, int NT>
+__device__ __forceinline__ void record_window(const T (&x)[kBlockChunk], T* stage, const BlockTile& bt, int n,
+                                              T* __restrict__ rec) {
+  constexpr int M = kBlockChunk, kHalf = 32, kRegion = kHalf * (M + 1);
+  static_assert((NT / 64) * kRegion <= stage_nodes<NT>() + stage_nodes<NT>() / 16 + 1,
+                "every wave's region must fit in the staging buffer");
+  int lt = static_cast<int>(threadIdx.x);
+  asm volatile("" : "+v"(lt));
+  const int lane = lt & 63, wave = lt >> 6;
+  T* region = stage + wave * kRegion;
+  const int lo = bt.lo, hi = bt.lo + bt.count;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if ((lane >> 5) == h) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) region[spad(M * (lane & 31) + j)] = x[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int w0 = M * (64 * wave + kHalf * h);   // window node of the half-wave's first slot
+#pragma unroll
+    for (int i = 0; i < kHalf * M / 64; ++i) {
+      const int q = lane + 64 * i;
+      const T v = region[spad(q)];
+      const int w = w0 + q;
+      if (w >= lo && w < hi) {
+        int g = bt.first + w;
+        if (g >= n) g -= n;
+        rec[g] = v;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -271,10 +320,15 @@ __device__ __forceinline__ void exchange_ends(const T (&x)[kBlockChunk], int buf
 // t: the lane's index among the NT lanes that take the window (the workgroup's lane, or its lane within
 // its sub-group when several windows share a workgroup).  Every call executes the same sequence of
 // workgroup barriers for a given `steps`, whatever the window (an empty one included).
-template <typename T, bool EXACT, bool RK4, int NT, int ML = 0>
+// REC (forward Euler, t the workgroup's lane): instead of the final state, the state after each step k
+// (1 <= k <= steps) is stored at rec + (k - 1) rstride (the instance's first node), so that a segment of
+// states is computed in one pass over HBM that writes each of them once.
+template <typename T, bool EXACT, bool RK4, int NT, int ML = 0, bool REC = false>
 __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& d, const T* __restrict__ src,
                                            T* __restrict__ dst, int steps, T* stage,
-                                           T (*s_first)[NT], T (*s_last)[NT], int t) {
+                                           T (*s_first)[NT], T (*s_last)[NT], int t, T* __restrict__ rec = nullptr,
+                                           int64_t rstride = 0) {
+  static_assert(!(REC && RK4), "recording is for forward Euler");
   constexpr int M = kBlockChunk;
   const T r = static_cast<T>(d.r), D = static_cast<T>(d.D);
   const int n = d.n;
@@ -346,24 +400,28 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
   int step = 0;
   // (a wave with no active lane skips the arithmetic; inside a step nothing branches on the lane)
   for (; step + 2 <= steps; step += 2) {
-    exchange_ends<T, EXACT, NT, ML>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT, NT, ML, REC>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       chunk_step<T, EXACT, ML>(v, w, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
     }
-    exchange_ends<T, EXACT, NT, ML>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
+    if constexpr (REC) record_window<T, NT>(w, stage, bt, n, rec + step * rstride);
+    exchange_ends<T, EXACT, NT, ML, REC>(w, 1, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       chunk_step<T, EXACT, ML>(w, v, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
     }
+    if constexpr (REC) record_window<T, NT>(v, stage, bt, n, rec + (step + 1) * rstride);
   }
   if (step < steps) {
-    exchange_ends<T, EXACT, NT, ML>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
+    exchange_ends<T, EXACT, NT, ML, REC>(v, 0, t, P, mlast, active, s_first, s_last, left, right);
     if (active) {
       chunk_step<T, EXACT, ML>(v, w, left, right, r, D, r0, D0, r1, D1, is_last, rE, DE);
 #pragma unroll
       for (int j = 0; j < M; ++j) v[j] = w[j];
     }
+    if constexpr (REC) record_window<T, NT>(v, stage, bt, n, rec + step * rstride);
   }
   }
+  if constexpr (REC) return;   // the last state is recorded
 
   // store the window's output nodes [bt.lo, bt.lo + bt.count), staged like the load
   for (int h = 0; h < 2; ++h) {
@@ -388,13 +446,14 @@ __device__ __forceinline__ void block_body(const BlockTile& bt, const InstDesc& 
 
 // One window on NT lanes: full-size windows of the widest class take the exact body, others the body
 // compiled for their last lane's node count.
-template <typename T, bool RK4, int NT>
+template <typename T, bool RK4, int NT, bool REC = false>
 __device__ __forceinline__ void window_body(const BlockTile& bt, const InstDesc& d, const T* __restrict__ src,
                                             T* __restrict__ dst, int steps, T* stage, T (*s_first)[NT],
-                                            T (*s_last)[NT], int t) {
+                                            T (*s_last)[NT], int t, T* __restrict__ rec = nullptr,
+                                            int64_t rstride = 0) {
   if constexpr (NT == kBlockThreads) {
     if (bt.width == NT * kBlockChunk) {
-      block_body<T, true, RK4, NT>(bt, d, src, dst, steps, stage, s_first, s_last, t);
+      block_body<T, true, RK4, NT, 0, REC>(bt, d, src, dst, steps, stage, s_first, s_last, t, rec, rstride);
       return;
     }
   }
@@ -402,7 +461,7 @@ __device__ __forceinline__ void window_body(const BlockTile& bt, const InstDesc&
   const int mlast = bt.width - kBlockChunk * ((bt.width + kBlockChunk - 1) / kBlockChunk - 1);
   switch (mlast) {
 #define BURGERS_RAGGED_CASE(K) \
-  case K: block_body<T, false, RK4, NT, K>(bt, d, src, dst, steps, stage, s_first, s_last, t); break;
+  case K: block_body<T, false, RK4, NT, K, REC>(bt, d, src, dst, steps, stage, s_first, s_last, t, rec, rstride); break;
     BURGERS_RAGGED_CASE(1) BURGERS_RAGGED_CASE(2) BURGERS_RAGGED_CASE(3) BURGERS_RAGGED_CASE(4)
     BURGERS_RAGGED_CASE(5) BURGERS_RAGGED_CASE(6) BURGERS_RAGGED_CASE(7) BURGERS_RAGGED_CASE(8)
     BURGERS_RAGGED_CASE(9) BURGERS_RAGGED_CASE(10) BURGERS_RAGGED_CASE(11) BURGERS_RAGGED_CASE(12)
@@ -433,6 +492,24 @@ __global__ __launch_bounds__(NT) void explicit_block_kernel(
   const T* src = u + d.off;
   T* dst = out + d.off;
   window_body<T, RK4, NT>(bt, d, src, dst, steps, stage, s_first, s_last, static_cast<int>(threadIdx.x));
+}
+
+// Forward-Euler windows and whole instances that record every step's state (the adjoint's recompute of
+// a checkpoint segment): states 1..steps of the launch at rec + (k - 1) rstride; the source is only read.
+template <typename T>
+__global__ __launch_bounds__(kBlockThreads) void explicit_record_kernel(
+    const InstDesc* __restrict__ inst, const BlockTile* __restrict__ tiles, const T* __restrict__ u,
+    T* __restrict__ rec, int64_t rstride, int steps) {
+  constexpr int NT = kBlockThreads;
+  constexpr int kStage = stage_nodes<NT>();
+  __shared__ T s_first[2][NT];
+  __shared__ T s_last[2][NT];
+  __shared__ T stage[kStage + kStage / 16 + 1];
+  const BlockTile bt = tiles[blockIdx.x];
+  if (bt.width <= 0) return;
+  const InstDesc d = inst[bt.inst];
+  window_body<T, false, NT, true>(bt, d, u + d.off, nullptr, steps, stage, s_first, s_last,
+                                  static_cast<int>(threadIdx.x), rec + d.off, rstride);
 }
 
 // LDS of a sub-group of NT lanes in the pack kernel: its exchange buffers and staging area.
@@ -598,6 +675,15 @@ hipError_t launch_explicit_packs(const burgers_ctx* ctx, const BlockTile* tiles,
       explicit_pack_kernel<float, true><<<static_cast<unsigned>(n_rk4), kBlockThreads, 0, ctx->stream>>>(
           inst, tiles, packs + n_fe, static_cast<float*>(u), steps);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_explicit_record(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_tiles, const void* u,
+                                  void* rec, int64_t rstride, int steps) {
+  if (n_tiles <= 0 || steps <= 0) return hipSuccess;
+  if (ctx->dtype != BURGERS_F64) return hipErrorInvalidValue;
+  explicit_record_kernel<double><<<static_cast<unsigned>(n_tiles), kBlockThreads, 0, ctx->stream>>>(
+      ctx->inst.as<InstDesc>(), tiles, static_cast<const double*>(u), static_cast<double*>(rec), rstride, steps);
   return hipGetLastError();
 }
 

@@ -327,6 +327,10 @@ hipError_t launch_explicit_block(const burgers_ctx* ctx, const BlockTile* tiles,
 int explicit_pack_lanes();                  // lanes of a pack kernel workgroup
 hipError_t launch_explicit_packs(const burgers_ctx* ctx, const BlockTile* tiles, const BlockPack* packs,
                                  int64_t n_fe, int64_t n_rk4, void* u, int steps);
+// Forward-Euler block tiles (whole instances or windows with a halo of at least `steps`) recording the
+// state after each step k (1 <= k <= steps) at rec + (k - 1) rstride (binary64; u is only read).
+hipError_t launch_explicit_record(const burgers_ctx* ctx, const BlockTile* tiles, int64_t n_tiles, const void* u,
+                                  void* rec, int64_t rstride, int steps);
 // Windows of a long explicit instance `i` of n nodes advanced `depth` steps per launch (halo = depth x
 // stages per side); appends them to `out`.  Returns false when the halo leaves no kept node.
 bool explicit_windows(int32_t i, int32_t n, bool periodic, int depth, bool rk4, std::vector<BlockTile>& out);
@@ -385,6 +389,10 @@ hipError_t launch_btcs_step(const burgers_ctx* ctx, const BtcsPlan& plan, const 
 hipError_t launch_btcs_window_reset(const burgers_ctx* ctx, const BtcsPlan& plan);
 int btcs_window_halo();                 // halo rows on each side of a window's output rows
 hipError_t launch_btcs_resident(const burgers_ctx* ctx, const WgGroup& group, void* u, int steps);
+// The resident solver recording the state after each step k (1 <= k <= steps) at rec + (k - 1) rstride
+// (binary64; src is only read).
+hipError_t launch_btcs_record(const burgers_ctx* ctx, const WgGroup& group, const void* src, void* rec,
+                              int64_t rstride, int steps);
 hipError_t launch_newton_whole(const burgers_ctx* ctx, const WgGroup& group, const void* u, void* x, bool last,
                                int* flags);
 WidthClass btcs_width_class(int rows, int threads);

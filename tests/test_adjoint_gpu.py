@@ -155,6 +155,72 @@ def test_adjoint_16384_row_systems_whole():
     assert np.array_equal(g2[0], g) and np.array_equal(g2[1], gn)
 
 
+def _device_adjoint_plan(batch, lam, nsteps, ckpt, **plan):
+    import torch
+    import paper_2601_12204_amd as B
+    s = B.Solver(batch.problems, dtype=torch.float64)
+    try:
+        if plan:
+            s.set_plan(**plan)
+        u0 = s.pack_flat(batch.u0, batch.offsets)
+        lt = s.pack_flat(lam, batch.offsets)
+        g = torch.zeros_like(u0)
+        gn = torch.zeros(batch.count, dtype=torch.float64, device="cuda")
+        B.adjoint_into(s, u0, lt, nsteps, ckpt, g, gn)
+        s.sync()
+        return s.unpack_flat(g), gn.cpu().numpy()
+    finally:
+        s.close()
+
+
+def _nu_bound(batch, lam, nsteps, rgn):
+    """Allowed |device - oracle| of dJ/dnu per instance.  Its terms carry the second difference
+    u_{i+1} - 2 u_i + u_{i-1} of the states, which on a fine grid of a smooth state is a small fraction
+    of u, so rounding u by an ulp moves the gradient by far more than an ulp of it: two correct
+    evaluations in different association differ by that much.  The oracle's own sensitivity is measured
+    by rerunning it from u0 perturbed by one ulp (seeded signs); the device rounds the state afresh at
+    each of the nsteps steps, so first-order effects of up to nsteps such perturbations add up.  Where
+    the gradient is well conditioned the bound is 1e-10 relative."""
+    signs = np.random.default_rng(5).choice([-1.0, 1.0], size=batch.u0.shape)
+    _, rgn1 = oracle.adjoint(batch.problems, batch.u0 * (1.0 + np.ldexp(1.0, -52) * signs), batch.offsets, lam,
+                             nsteps)
+    return np.maximum(1e-10 * np.abs(rgn), nsteps * np.abs(rgn1 - rgn))
+
+
+@pytest.mark.parametrize("depth", [0, 4])
+def test_adjoint_recording_recompute_equals_per_step(depth):
+    """Segments recomputed on chip (kernels that store every step's state: explicit whole instances and
+    windows, resident BTCS systems of every width class, Dirichlet and periodic) give the same gradients,
+    bitwise, as segments recomputed one step per launch through HBM (the streaming kernel and the
+    per-step solves, forced by the plan), and the oracle's within tolerance.  depth 4: the explicit
+    windows' halo covers 4 steps, so a 7-step segment is recorded in two launches."""
+    problems, states = [], []
+    btcs_sizes = [3, 5, 40, 300, 1000, 4097, 8192, 8194, 16384, 16386]
+    exp_sizes = [3, 5, 40, 300, 8192, 9000, 16385, 30000]
+    for k, n in enumerate(btcs_sizes + exp_sizes):
+        scheme = W.BTCS if k < len(btcs_sizes) else W.EXPLICIT
+        for bc in (W.BC_PERIODIC, W.BC_DIRICHLET):
+            if scheme == W.BTCS and n >= 16384 and (bc == W.BC_PERIODIC) != (n == 16384):
+                continue   # 16384 rows exactly: periodic N = 16384, Dirichlet N = 16386
+            b = W.random_batch(2100 + 37 * k + bc, 1, n, n, bc=bc, scheme=scheme, amplitude=2.0)
+            problems.append(b.problems[0])
+            states.append(b.instance(0))
+    batch = set_cfl_steps(W._pack(problems, states), btcs_factor=5.0)
+    lam = np.random.default_rng(23).standard_normal(len(batch.u0))
+    nsteps, ckpt = 16, 7
+    plan = {"tblock_depth": depth} if depth else {}
+    announce(f"adjoint recording recompute, {batch.count} instances, depth {depth}")
+    g, gn = _device_adjoint_plan(batch, lam, nsteps, ckpt, **plan)
+    gs, gns = _device_adjoint_plan(batch, lam, nsteps, ckpt, explicit_path=1, btcs_path=1)
+    assert np.array_equal(g, gs) and np.array_equal(gn, gns)
+    rg, rgn = oracle.adjoint(batch.problems, batch.u0, batch.offsets, lam, nsteps)
+    for b in range(batch.count):
+        lo, hi = batch.offsets[b], batch.offsets[b + 1]
+        assert oracle.rel_max_abs(g[lo:hi], rg[lo:hi]) <= TOL, (b, batch.problems[b])
+    bound = _nu_bound(batch, lam, nsteps, rgn)
+    assert np.all(np.abs(gn - rgn) <= bound), (np.abs(gn - rgn), bound)
+
+
 @pytest.mark.parametrize("scheme", [W.EXPLICIT, W.BTCS])
 def test_c5_adjoint_full_size_sampled(scheme):
     """The gradient workload at its real size, in the benchmark's configuration: 256 periodic instances
