@@ -12,7 +12,8 @@
 // coefficients (sub p_{i-1}, super l_{i+1}, the cyclic corners swapped); it is assembled with unit
 // diagonal into binary64 arrays and solved by the partition solver's array path.
 //
-// dJ/dD is accumulated per tile, one workgroup per tile per launch, so the sums are deterministic.
+// dJ/dD is accumulated per tile of nodes in a fixed order (for the explicit instances per tile and step,
+// whatever the grouping of steps into launches), so the sums are deterministic.
 #include "internal.hpp"
 #include "stencil.hpp"
 
@@ -24,10 +25,6 @@ namespace {
 constexpr int kAdjThreads = 256;
 constexpr int kAdjLaneNodes = 4;                          // BTCS tiles: consecutive nodes per lane
 constexpr int kAdjTile = kAdjThreads * kAdjLaneNodes;     // nodes of one BTCS adjoint tile (one dJ/dD slot)
-// Explicit tiles: one 16-byte vector per lane (C5, 256 x 16384: 74.4 ms per gradient with two vectors
-// per lane, 69.2 ms with one, 80.6 ms with four)
-constexpr int kAdjExpNodes = 2;
-constexpr int kAdjExpTile = kAdjThreads * kAdjExpNodes;
 
 // Sum over the workgroup in a fixed order (a butterfly within each wave, lane 0's result, then the waves
 // in order), so that the per-tile partials of dJ/dD are deterministic.  Valid in thread 0.
@@ -42,88 +39,205 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return tot;
 }
 
-// lam = (dE/du)^T lamp at state u; partial dJ/dD of the tile added to gslot[tile.slot].  Each lane takes
-// kAdjExpNodes consecutive nodes, loaded as 16-byte vectors with one neighbour on each side.
-__global__ __launch_bounds__(kAdjThreads) void adj_explicit_kernel(
-    const InstDesc* __restrict__ inst, const AdjTile* __restrict__ tiles, const double* __restrict__ u,
-    const double* __restrict__ lamp, double* __restrict__ lam, double* __restrict__ gslot) {
-  constexpr int V = kAdjExpNodes;
-  __shared__ double red[kAdjThreads / 64];
-  const AdjTile t = tiles[blockIdx.x];
-  const InstDesc d = inst[t.inst];
-  const int n = t.n;
-  const int j0 = t.start + V * static_cast<int>(threadIdx.x);
-  const bool periodic = t.bc == kPeriodic;
-  const double* __restrict__ y = u + t.off;
-  const double* __restrict__ lp = lamp + t.off;
-  const double r = d.r, D = d.D;
-  double g = 0.0;
-  if (j0 < n) {
-    // Y[q], L[q]: state and lamp at node j0 - 1 + q (periodic neighbours wrap; positions outside a
-    // Dirichlet grid are never used)
-    double Y[V + 2], L[V + 2];
-    if (j0 + V <= n) {
+// ---- Explicit reverse steps, blocked ----------------------------------------------------------------
+// lam^k = (dE/du at u^k)^T lam^(k+1) is a 3-point gather stencil whose coefficients come from u^k alone.
+// A workgroup of 512 lanes holds lam over a window of up to 8192 nodes (16 consecutive nodes per lane) in
+// registers for a run of reverse steps: each step reads u^k of the window from HBM (coalesced, passed to
+// the lanes' chunks through a region of LDS private to each wave), exchanges the chunks' end values of u
+// and lam through LDS, and updates lam in place.  lam is read once and written once per launch.  Windows
+// of longer instances keep their middle nodes and carry kAdjHalo nodes on either side, recomputed
+// redundantly: an error at a window edge travels one node per step, so a launch takes at most kAdjHalo
+// steps.
+//
+// dJ/dD, the sum over nodes and steps of lam^(k+1)_j (u_{j+1} + u_{j-1} - 2 u_j), is accumulated per
+// tile of kAdjSumTile nodes of an instance: per step, each lane sums its kept nodes in node order, the 16
+// lanes of a tile combine by a butterfly, and the tile's first lane adds the result to the tile's running
+// sum (loaded from its slot at launch start, stored at the end).  Tiles are aligned to 16-lane groups in
+// every window, so each (tile, step) partial is formed alike whichever window and launch computes it:
+// the gradient does not depend on how the steps are grouped into launches (the checkpoint interval).
+constexpr int kAdjWinLanes = 512;
+constexpr int kAdjWinChunk = 16;
+constexpr int kAdjWinRegion = 32 * (kAdjWinChunk + 1);   // a half-wave's chunks, padded by one per chunk
+static_assert(kAdjWinLanes * kAdjWinChunk == kAdjWinNodes, "window capacity");
+static_assert(kAdjSumTile == 16 * kAdjWinChunk, "a tile is 16 lanes' chunks");
+
+__device__ __forceinline__ int apad(int i) { return i + (i >> 4); }
+
+// A lane index that the compiler cannot treat as known, so that the addresses built on it are formed
+// where they are used rather than kept live across the step loop.
+__device__ __forceinline__ int fresh_lane() {
+  int v = static_cast<int>(threadIdx.x);
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Wave-private LDS exchanges are ordered by the wave's own in-order LDS accesses; the fences keep the
+// compiler from moving them.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Window nodes of src (the instance's first node) for the lane's chunk [16 t, 16 t + 16), in two steps so
+// that the loads can be issued long before their values are needed: window_fetch loads, for each of the
+// two halves of the wave, the 512 consecutive window nodes of that half's chunks (64 per instruction,
+// coalesced) into v; window_spread passes them to the lanes' chunks through the wave's region of LDS.
+__device__ __forceinline__ void window_fetch(const double* __restrict__ src, const AdjWindow& w, int n,
+                                             double (&v)[2 * 8]) {
+  const int lt = fresh_lane();
+  const int lane = lt & 63, wave = lt >> 6;
 #pragma unroll
-      for (int q = 0; q < V; q += 2) {
-        const double2 yv = *reinterpret_cast<const double2*>(y + j0 + q);
-        const double2 lv = *reinterpret_cast<const double2*>(lp + j0 + q);
-        Y[q + 1] = yv.x; Y[q + 2] = yv.y;
-        L[q + 1] = lv.x; L[q + 2] = lv.y;
-      }
-    } else {
+  for (int h = 0; h < 2; ++h) {
+    const int w0 = kAdjWinChunk * (64 * wave + 32 * h);
 #pragma unroll
-      for (int q = 0; q < V; ++q) {
-        const int j = j0 + q < n ? j0 + q : (periodic ? j0 + q - n : n - 1);
-        Y[q + 1] = y[j];
-        L[q + 1] = lp[j];
-      }
-    }
-    const int jl = j0 > 0 ? j0 - 1 : (periodic ? n - 1 : 0);
-    int jr = j0 + V;
-    if (jr >= n) jr = periodic ? jr - n : n - 1;
-    Y[0] = y[jl];
-    L[0] = lp[jl];
-    Y[V + 1] = y[jr];
-    L[V + 1] = lp[jr];
-    double out[V];
-#pragma unroll
-    for (int q = 0; q < V; ++q) {
-      const int j = j0 + q;
-      double acc = 0.0;
-      if (j < n && (periodic || (j > 0 && j < n - 1))) {
-        const double uj = Y[q + 1];
-        const double um = (!periodic && j == 1) ? d.a : Y[q];
-        const double up = (!periodic && j == n - 2) ? d.b : Y[q + 2];
-        // own update
-        const double self = uj >= 0.0 ? ((1.0 - r * (uj - um)) - r * uj) - 2.0 * D
-                                      : ((1.0 - r * (up - uj)) + r * uj) - 2.0 * D;
-        acc = self * L[q + 1];
-        g = g + L[q + 1] * ((up + um) - 2.0 * uj);
-        // node j+1 reads u_j as its left neighbour
-        if (periodic || j + 1 <= n - 2) {
-          const double uk = Y[q + 2];
-          acc = acc + (uk >= 0.0 ? r * uk + D : D) * L[q + 2];
-        }
-        // node j-1 reads u_j as its right neighbour
-        if (periodic || j - 1 >= 1) {
-          const double uk = Y[q];
-          acc = acc + (uk >= 0.0 ? D : D - r * uk) * L[q];
-        }
-      }
-      out[q] = acc;
-    }
-    double* __restrict__ dst = lam + t.off;
-    if (j0 + V <= n) {
-#pragma unroll
-      for (int q = 0; q < V; q += 2) *reinterpret_cast<double2*>(dst + j0 + q) = double2{out[q], out[q + 1]};
-    } else {
-#pragma unroll
-      for (int q = 0; q < V; ++q)
-        if (j0 + q < n) dst[j0 + q] = out[q];
+    for (int i = 0; i < 8; ++i) {
+      const int k = w0 + lane + 64 * i;
+      int g = w.first + k;
+      if (g >= n) g -= n;
+      v[8 * h + i] = k < w.width ? src[g] : 0.0;
     }
   }
-  const double tot = block_sum(g, red);
-  if (threadIdx.x == 0) gslot[t.slot] = gslot[t.slot] + tot;
+}
+
+__device__ __forceinline__ void window_spread(const double (&v)[2 * 8], double* lds, double (&out)[kAdjWinChunk]) {
+  const int lt = fresh_lane();
+  const int lane = lt & 63, wave = lt >> 6;
+  double* region = lds + wave * kAdjWinRegion;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) region[apad(lane + 64 * i)] = v[8 * h + i];
+    wave_sync();
+    if ((lane >> 5) == h) {
+#pragma unroll
+      for (int j = 0; j < kAdjWinChunk; ++j) out[j] = region[apad(kAdjWinChunk * (lane & 31) + j)];
+    }
+    wave_sync();
+  }
+}
+
+// The lane's chunk to the window's kept nodes of dst (the instance's first node), the way back.
+__device__ __forceinline__ void window_store(const double (&x)[kAdjWinChunk], const AdjWindow& w, int n,
+                                             double* lds, double* __restrict__ dst) {
+  const int lt = fresh_lane();
+  const int lane = lt & 63, wave = lt >> 6;
+  double* region = lds + wave * kAdjWinRegion;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if ((lane >> 5) == h) {
+#pragma unroll
+      for (int j = 0; j < kAdjWinChunk; ++j) region[apad(kAdjWinChunk * (lane & 31) + j)] = x[j];
+    }
+    wave_sync();
+    const int w0 = kAdjWinChunk * (64 * wave + 32 * h);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int q = lane + 64 * i, k = w0 + q;
+      const double v = region[apad(q)];
+      if (k >= w.lo && k < w.lo + w.count) {
+        int g = w.first + k;
+        if (g >= n) g -= n;
+        dst[g] = v;
+      }
+    }
+    wave_sync();
+  }
+}
+
+// (Two workgroups per CU, 128 registers, the next step's loads in flight: C5, 256 x 16384, 49.0 ms per
+// gradient, against 54.4 ms with 131 registers and one workgroup per CU.)
+// Reverse steps k = k_hi - 1 down to k_lo of a segment: u^k at u0 for k = 0, else at useg + (k - 1) ustride
+// (binary64 states); lam^(k_hi) from lamp, lam^(k_lo) to lam (the window's kept nodes).
+__global__ __launch_bounds__(kAdjWinLanes, 4) void adj_explicit_block_kernel(
+    const InstDesc* __restrict__ inst, const AdjWindow* __restrict__ wins, const double* __restrict__ u0,
+    const double* __restrict__ useg, int64_t ustride, int k_lo, int k_hi, const double* __restrict__ lamp,
+    double* __restrict__ lam, double* __restrict__ gslot) {
+  constexpr int M = kAdjWinChunk, NT = kAdjWinLanes;
+  __shared__ double ends[2][4][NT];            // per step parity: u first, u last, lam first, lam last
+  __shared__ double region[(NT / 64) * kAdjWinRegion];
+  const AdjWindow w = wins[blockIdx.x];
+  const InstDesc d = inst[w.inst];
+  const int n = d.n;
+  const bool periodic = d.bc == kPeriodic;
+  const double r = d.r, D = d.D;
+  const int t = threadIdx.x;
+  const int P = (w.width + M - 1) / M;         // lanes holding nodes; the last holds mlast
+  const int mlast = w.width - M * (P - 1);
+  const int m = t < P ? (t == P - 1 ? mlast : M) : 0;
+  // the lane's tile (16-lane groups start on tile boundaries) and its running dJ/dD sum
+  const bool tile_lane = (t & 15) == 0 && M * t >= w.lo && M * t < w.lo + w.count;
+  const int slot = w.slot0 + (M * t - w.lo) / kAdjSumTile;
+  double tile_sum = tile_lane ? gslot[slot] : 0.0;
+  auto state = [&](int k) { return (k == 0 ? u0 : useg + static_cast<int64_t>(k - 1) * ustride) + d.off; };
+  double L[M], U[M], V[2 * 8];
+  window_fetch(lamp + d.off, w, n, V);
+  window_spread(V, region, L);
+  window_fetch(state(k_hi - 1), w, n, V);
+  for (int k = k_hi - 1; k >= k_lo; --k) {
+    window_spread(V, region, U);
+    // the next step's state is in flight during this step (the barrier below waits for LDS only)
+    if (k > k_lo) window_fetch(state(k - 1), w, n, V);
+    const int b = k & 1;
+    if (t < P) {
+      double ul = U[M - 1], ll = L[M - 1];
+#pragma unroll
+      for (int j = 0; j < M; ++j)
+        if (j == m - 1) {
+          ul = U[j];
+          ll = L[j];
+        }
+      ends[b][0][t] = U[0];
+      ends[b][1][t] = ul;
+      ends[b][2][t] = L[0];
+      ends[b][3][t] = ll;
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    double g = 0.0;
+    if (t < P) {
+      // neighbours beyond the window's ends wrap around it: exact for a whole periodic instance, and
+      // only the halo is affected otherwise
+      const int tl = t > 0 ? t - 1 : P - 1, tr = t < P - 1 ? t + 1 : 0;
+      const double uL = ends[b][1][tl], uR = ends[b][0][tr];
+      const double lL = ends[b][3][tl], lR = ends[b][2][tr];
+      double lprev = lL;                        // lam^(k+1) of the node before, kept before it is overwritten
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        if (j < m) {
+          const int wj = M * t + j;
+          int jn = w.first + wj;
+          if (jn >= n) jn -= n;
+          const double uj = U[j];
+          const double uprev = j == 0 ? uL : U[j > 0 ? j - 1 : 0];
+          const double unext = j + 1 < m ? U[j + 1 < M ? j + 1 : j] : uR;
+          const double lj = L[j];
+          const double lnext = j + 1 < m ? L[j + 1 < M ? j + 1 : j] : lR;
+          double acc = 0.0;
+          if (periodic || (jn > 0 && jn < n - 1)) {
+            const double um = (!periodic && jn == 1) ? d.a : uprev;
+            const double up = (!periodic && jn == n - 2) ? d.b : unext;
+            // own update
+            const double self = uj >= 0.0 ? ((1.0 - r * (uj - um)) - r * uj) - 2.0 * D
+                                          : ((1.0 - r * (up - uj)) + r * uj) - 2.0 * D;
+            acc = self * lj;
+            if (wj >= w.lo && wj < w.lo + w.count) g = g + lj * ((up + um) - 2.0 * uj);
+            // node j+1 reads u_j as its left neighbour
+            if (periodic || jn + 1 <= n - 2) acc = acc + (unext >= 0.0 ? r * unext + D : D) * lnext;
+            // node j-1 reads u_j as its right neighbour
+            if (periodic || jn - 1 >= 1) acc = acc + (uprev >= 0.0 ? D : D - r * uprev) * lprev;
+          }
+          lprev = lj;
+          L[j] = acc;
+        }
+      }
+    }
+    // the tile's partial for this step: a butterfly over its 16 lanes, taken from its first lane
+#pragma unroll
+    for (int s = 8; s >= 1; s >>= 1) g = g + __shfl_xor(g, s, 64);
+    if (tile_lane) tile_sum = tile_sum + g;
+  }
+  window_store(L, w, n, region, lam + d.off);
+  if (tile_lane) gslot[slot] = tile_sum;
 }
 
 // Row k of A(y)^T, normalised by its diagonal, and the right-hand side lamp / d, for every unknown of
@@ -233,13 +347,14 @@ __global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
 
 }  // namespace
 
-int adjoint_tile_nodes(bool btcs) { return btcs ? kAdjTile : kAdjExpTile; }
+int adjoint_tile_nodes() { return kAdjTile; }
 
-hipError_t launch_adj_explicit(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const double* u,
-                               const double* lamp, double* lam, double* gslot) {
-  if (n_tiles <= 0) return hipSuccess;
-  adj_explicit_kernel<<<static_cast<unsigned>(n_tiles), kAdjThreads, 0, ctx->stream>>>(
-      ctx->inst.as<InstDesc>(), tiles, u, lamp, lam, gslot);
+hipError_t launch_adj_explicit_block(const burgers_ctx* ctx, const AdjWindow* wins, int64_t n_wins, const double* u0,
+                                     const double* useg, int64_t ustride, int k_lo, int k_hi, const double* lamp,
+                                     double* lam, double* gslot) {
+  if (n_wins <= 0 || k_hi <= k_lo) return hipSuccess;
+  adj_explicit_block_kernel<<<static_cast<unsigned>(n_wins), kAdjWinLanes, 0, ctx->stream>>>(
+      ctx->inst.as<InstDesc>(), wins, u0, useg, ustride, k_lo, k_hi, lamp, lam, gslot);
   return hipGetLastError();
 }
 

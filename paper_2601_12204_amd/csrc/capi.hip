@@ -788,8 +788,9 @@ burgers_status ensure_newton(burgers_ctx* ctx, const std::vector<int32_t>& membe
 burgers_status ensure_adjoint(burgers_ctx* ctx) {
   if (ctx->adjoint) return BURGERS_OK;
   auto ap = std::make_unique<burgers::AdjointPlan>();
-  const int exp_tile = burgers::adjoint_tile_nodes(false), btcs_tile = burgers::adjoint_tile_nodes(true);
-  std::vector<burgers::AdjTile> et, bt;
+  const int btcs_tile = burgers::adjoint_tile_nodes();
+  std::vector<burgers::AdjTile> bt;
+  std::vector<burgers::AdjWindow> ew;
   std::vector<int32_t> slot_begin(ctx->count + 1, 0);
   int32_t slot = 0;
   int64_t sys_rows = 0;
@@ -823,11 +824,32 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
     const int32_t n = static_cast<int32_t>(p.n);
     const int32_t R = static_cast<int32_t>(p.bc == BURGERS_BC_PERIODIC ? p.n : p.n - 2);
     slot_begin[i] = slot;
-    const int tile = p.scheme == BURGERS_BTCS ? btcs_tile : exp_tile;
-    for (int64_t s = 0; s < n; s += tile)
-      (p.scheme == BURGERS_BTCS ? bt : et)
-          .push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, static_cast<int32_t>(s), slot++, 0});
-    if (p.scheme == BURGERS_BTCS) {
+    if (p.scheme != BURGERS_BTCS) {
+      // explicit: one slot per tile of kAdjSumTile nodes; the whole instance in one window, or windows
+      // keeping kAdjWinNodes - 2 kAdjHalo nodes (whole tiles) with kAdjHalo more on either side
+      constexpr int32_t H = burgers::kAdjHalo, kept = burgers::kAdjWinNodes - 2 * burgers::kAdjHalo;
+      static_assert(kept % burgers::kAdjSumTile == 0, "windows keep whole tiles");
+      if (n <= burgers::kAdjWinNodes) {
+        ew.push_back(burgers::AdjWindow{i, 0, n, 0, n, slot});
+      } else {
+        for (int32_t lo = 0; lo < n; lo += kept) {
+          const int32_t hi = std::min(n, lo + kept);
+          if (p.bc == BURGERS_BC_PERIODIC) {
+            ew.push_back(burgers::AdjWindow{i, ((lo - H) % n + n) % n, (hi - lo) + 2 * H, H, hi - lo,
+                                            slot + lo / burgers::kAdjSumTile});
+          } else {
+            const int32_t first = std::max(0, lo - H), end = std::min(n, hi + H);
+            ew.push_back(burgers::AdjWindow{i, first, end - first, lo - first, hi - lo,
+                                            slot + lo / burgers::kAdjSumTile});
+          }
+        }
+      }
+      slot += (n + burgers::kAdjSumTile - 1) / burgers::kAdjSumTile;
+      continue;
+    }
+    for (int64_t s = 0; s < n; s += btcs_tile)
+      bt.push_back(burgers::AdjTile{ctx->offsets[i], sys_off[i], n, p.bc, i, static_cast<int32_t>(s), slot++, 0});
+    {
       roots.emplace_back(i, sys_off[i], R);
       if (windows) {
         const size_t w0 = wins.size();
@@ -842,13 +864,13 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   }
   slot_begin[ctx->count] = slot;
   hipError_t e;
-  ap->exp_tiles = std::make_unique<DevBuf>();
+  ap->exp_wins = std::make_unique<DevBuf>();
   ap->btcs_tiles = std::make_unique<DevBuf>();
   ap->slot_begin = std::make_unique<DevBuf>();
-  if ((e = upload_on(ctx->stream, *ap->exp_tiles, et)) != hipSuccess || (e = upload_on(ctx->stream, *ap->btcs_tiles, bt)) != hipSuccess ||
+  if ((e = upload_on(ctx->stream, *ap->exp_wins, ew)) != hipSuccess || (e = upload_on(ctx->stream, *ap->btcs_tiles, bt)) != hipSuccess ||
       (e = upload_on(ctx->stream, *ap->slot_begin, slot_begin)) != hipSuccess)
     return from_hip(e);
-  ap->n_exp_tiles = static_cast<int64_t>(et.size());
+  ap->n_exp_wins = static_cast<int64_t>(ew.size());
   ap->n_btcs_tiles = static_cast<int64_t>(bt.size());
   ap->n_slots = slot;
   ap->whole = std::make_unique<DevBuf>();
@@ -883,15 +905,14 @@ hipError_t grow(DevBuf& b, size_t bytes, hipStream_t stream) {
   return b.alloc(bytes, stream);
 }
 
-// One adjoint step: lam_out from lam_in at the forward pair (y = u^k, x = u^{k+1}); `step` counts the
-// steps of the reverse sweep (it selects the parity slot of the window flags).
+// One adjoint step of the BTCS instances: lam_out from lam_in at the forward pair (y = u^k, x = u^{k+1});
+// `step` counts the BTCS steps of the reverse sweep (it selects the parity slot of the window flags).
 hipError_t enqueue_adjoint_step(burgers_ctx* ctx, const double* y, const double* x, const double* lam_in,
                                 double* lam_out, int64_t step) {
   burgers::AdjointPlan& ap = *ctx->adjoint;
   double* g = ap.gslot.as<double>();
-  hipError_t e = burgers::launch_adj_explicit(ctx, ap.exp_tiles->as<burgers::AdjTile>(), ap.n_exp_tiles, y,
-                                              lam_in, lam_out, g);
-  if (e != hipSuccess || ap.n_btcs_tiles == 0) return e;
+  hipError_t e = hipSuccess;
+  if (ap.n_btcs_tiles == 0) return e;
   if (ap.n_whole > 0)   // every BTCS system solved whole and exactly: nothing is left for the array path
     return burgers::launch_adj_btcs_whole(ctx, ap.whole->as<burgers::WinDesc>(), ap.n_whole, y, x, lam_in, lam_out,
                                           g, ap.whole_slot->as<int32_t>());
@@ -1256,8 +1277,12 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
       return note(ctx, e);
   }
   // reverse sweep: recompute each segment's states one step at a time, then step the adjoint back
+  // lam of the BTCS instances (per step) and of the explicit ones (per run of steps) ping-pong between the
+  // same two buffers, each set in its own nodes
   double* lam = ap.lam0.as<double>();
   double* lam_next = ap.lam1.as<double>();
+  double* lam_e = lam;
+  double* lam_e_next = lam_next;
   if ((e = hipMemcpyAsync(lam, lambda_T, state_bytes, d2d, ctx->stream)) != hipSuccess ||
       (e = burgers::launch_fill(ctx, ap.gslot.as<double>(), ap.n_slots, 0.0)) != hipSuccess ||
       (ap.n_win > 0 && (e = burgers::launch_clear_ints(ctx, ap.flags.as<int>(), 2 * (ctx->count + 1))) != hipSuccess))
@@ -1331,7 +1356,19 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
       if (e == hipSuccess) e = hipEventRecord(ctx->joined[0], ctx->side[0]);
       if (e != hipSuccess) return note(ctx, e);
     }
-    for (int64_t k = len - 1; k >= 0; --k) {
+    // explicit instances: runs of up to kAdjHalo reverse steps per launch, lam on chip (out of place)
+    for (int64_t hi = len; ap.n_exp_wins > 0 && hi > 0; hi -= burgers::kAdjHalo) {
+      const int64_t lo = std::max<int64_t>(0, hi - burgers::kAdjHalo);
+      if ((e = burgers::launch_adj_explicit_block(ctx, ap.exp_wins->as<burgers::AdjWindow>(), ap.n_exp_wins,
+                                                  reinterpret_cast<const double*>(at(c, cur, 0)),
+                                                  reinterpret_cast<const double*>(at(c, cur, 1)), ctx->total,
+                                                  static_cast<int>(lo), static_cast<int>(hi), lam_e, lam_e_next,
+                                                  ap.gslot.as<double>())) != hipSuccess)
+        return note(ctx, e);
+      std::swap(lam_e, lam_e_next);
+    }
+    // BTCS instances: one reverse step per launch
+    for (int64_t k = len - 1; ap.n_btcs_tiles > 0 && k >= 0; --k) {
       if ((e = enqueue_adjoint_step(ctx, reinterpret_cast<const double*>(at(c, cur, k)),
                                     reinterpret_cast<const double*>(at(c, cur, k + 1)), lam, lam_next,
                                     rstep++)) != hipSuccess)
@@ -1340,9 +1377,15 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
     }
     if (c > 0 && (e = hipStreamWaitEvent(ctx->stream, ctx->joined[0], 0)) != hipSuccess) return note(ctx, e);   // join
   }
-  if ((e = ensure_copy(ctx, kSetAll)) != hipSuccess) return from_hip(e);
-  auto& all_tiles = ctx->copy_tiles[kSetAll];
-  if ((e = burgers::launch_copy_tiles(ctx, all_tiles.first->as<Tile>(), all_tiles.second, lam, grad_u0)) != hipSuccess ||
+  const bool split = lam_e != lam && !ctx->set_explicit.empty() && !ctx->set_btcs.empty();
+  if ((e = ensure_copy(ctx, split ? kSetExplicit : kSetAll)) != hipSuccess ||
+      (split && (e = ensure_copy(ctx, kSetBtcs)) != hipSuccess))
+    return from_hip(e);
+  auto& first_tiles = ctx->copy_tiles[split ? kSetExplicit : kSetAll];
+  if ((e = burgers::launch_copy_tiles(ctx, first_tiles.first->as<Tile>(), first_tiles.second,
+                                      ctx->set_btcs.empty() || split ? lam_e : lam, grad_u0)) != hipSuccess ||
+      (split && (e = burgers::launch_copy_tiles(ctx, ctx->copy_tiles[kSetBtcs].first->as<Tile>(),
+                                                ctx->copy_tiles[kSetBtcs].second, lam, grad_u0)) != hipSuccess) ||
       (e = burgers::launch_zero_dirichlet_ends(ctx, static_cast<double*>(grad_u0))) != hipSuccess ||
       (e = burgers::launch_adj_nu(ctx, ap.slot_begin->as<int32_t>(), ap.gslot.as<double>(),
                                   static_cast<double*>(grad_nu))) != hipSuccess)

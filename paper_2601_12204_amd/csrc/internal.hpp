@@ -75,6 +75,17 @@ struct AdjTile {
   int32_t pad;
 };
 
+// A window of the explicit adjoint's blocked reverse steps: window node w (0 <= w < width) is instance
+// node (first + w) mod n; nodes [lo, lo + count) are kept, and their tiles of kAdjSumTile nodes take the
+// dJ/dD slots slot0, slot0 + 1, ...  (lo and the instance node of window node lo are multiples of
+// kAdjSumTile.)
+struct AdjWindow {
+  int32_t inst, first, width, lo, count, slot0;
+};
+constexpr int kAdjWinNodes = 8192;   // window capacity (512 lanes x 16 nodes)
+constexpr int kAdjHalo = 256;        // halo nodes per side of a window of a longer instance; steps per launch
+constexpr int kAdjSumTile = 256;     // nodes per dJ/dD slot of an explicit instance
+
 // One tridiagonal system of the BTCS solve at some level of the partition hierarchy.
 //   level 0: rows assembled from the state of instance `inst`; level > 0: rows (A, 1, C, D) stored in
 //   the level arrays starting at row `in_off`.  A system that is reduced writes its 2*chunks reduced
@@ -243,8 +254,8 @@ struct ExplicitPlan {
 
 // Launch lists and buffers of the adjoint sweep (built on the first burgers_adjoint call).
 struct AdjointPlan {
-  std::unique_ptr<DevBuf> exp_tiles, btcs_tiles;   // AdjTile[]
-  int64_t n_exp_tiles = 0, n_btcs_tiles = 0;
+  std::unique_ptr<DevBuf> exp_wins, btcs_tiles;     // AdjWindow[] of the explicit instances, AdjTile[]
+  int64_t n_exp_wins = 0, n_btcs_tiles = 0;
   std::unique_ptr<DevBuf> slot_begin;               // int32[count + 1]
   int64_t n_slots = 0;
   BtcsPlan solve;                                   // partition hierarchy over the transposed systems
@@ -347,9 +358,13 @@ int explicit_tile_nodes(burgers_dtype dt);
 int explicit_block_capacity();
 
 // adjoint.hip
-int adjoint_tile_nodes(bool btcs);
-hipError_t launch_adj_explicit(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles, const double* u,
-                               const double* lamp, double* lam, double* gslot);
+int adjoint_tile_nodes();   // nodes per dJ/dD slot of a BTCS instance
+// Explicit reverse steps k = k_hi - 1 .. k_lo over the windows: u^k at u0 (k = 0) or useg + (k - 1) ustride,
+// lam^(k_hi) in lamp, lam^(k_lo) to lam (out of place), dJ/dD added to the windows' tile slots of gslot.
+// Windows of longer instances take at most kAdjHalo steps per launch.
+hipError_t launch_adj_explicit_block(const burgers_ctx* ctx, const AdjWindow* wins, int64_t n_wins, const double* u0,
+                                     const double* useg, int64_t ustride, int k_lo, int k_hi, const double* lamp,
+                                     double* lam, double* gslot);
 // `only` (optional): only the instances whose entry is nonzero (those whose windows flagged a failed
 // bound); the finish launch also adds the windows' partials (wins/win_slot/wpart, n_win may be 0).
 hipError_t launch_adj_btcs_assemble(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles,
