@@ -1358,12 +1358,15 @@ struct AdjRows {
 
 // WHOLE: the window is a whole system of exactly W rows (start 0, every row kept), solved exactly: cyclic
 // for a periodic instance, no bound to check, and the system's partial of dJ/dD is added straight to its
-// slot (gslot[slots[b]]: one workgroup per slot, so the sums stay deterministic).
+// slot (gslot[slots[b]]: one workgroup per slot, so the sums stay deterministic).  A whole system takes
+// the reverse steps k = k_hi - 1 down to k_lo in one launch (y = u^k and x = u^(k+1) at state(k), state(k
+// + 1)), keeping lam on chip between them: each step reads only the two states.  Its partial is added to
+// the slot after every step, in step order, as one launch per step would.  Windows take one step.
 template <int NT, bool WHOLE = false>
 __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
-    const InstDesc* __restrict__ inst, const WinDesc* __restrict__ wins, const double* __restrict__ u,
-    const double* __restrict__ x, const double* __restrict__ lamp, double* __restrict__ lam,
-    double* __restrict__ wpart, int* __restrict__ flag_now, int* __restrict__ flag_next,
+    const InstDesc* __restrict__ inst, const WinDesc* __restrict__ wins, const double* __restrict__ u0,
+    const double* __restrict__ useg, int64_t ustride, int k_lo, int k_hi, const double* __restrict__ lamp,
+    double* __restrict__ lam, double* __restrict__ wpart, int* __restrict__ flag_now, int* __restrict__ flag_next,
     double* __restrict__ gslot = nullptr, const int32_t* __restrict__ slots = nullptr) {
   using T = double;
   constexpr int MC = kWgChunk, W = NT * MC;
@@ -1382,8 +1385,9 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
   const int first = dir ? 1 : 0;
   const int R = dir ? d.n - 2 : d.n;           // > W
   const int n = d.n;
-  const double* __restrict__ yn = u + d.off;   // by node
   const int tid = threadIdx.x;
+  // state k of the launch: u0 for k = 0, else useg + (k - 1) ustride (by node)
+  auto state = [&](int k) { return (k == 0 ? u0 : useg + static_cast<int64_t>(k - 1) * ustride) + d.off; };
   // node of window row k (k = -1..W): periodic rows wrap; Dirichlet rows -1 and R are the end nodes
   auto node_of = [&](int k) {
     int row = wd.start + k;
@@ -1393,12 +1397,22 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
     }
     return row + first;
   };
-  // lam' of the window's rows into the lanes' chunks (through LDS, coalesced)
+  // lam' of the window's rows, row tid + q NT in de[q] (coalesced); between steps de carries lam in that
+  // layout
   T de[MC];
 #pragma unroll
-  for (int j = 0; j < MC; ++j) stage[padded(tid + j * NT)] = lamp[d.off + node_of(tid + j * NT)];
-  __syncthreads();
+  for (int j = 0; j < MC; ++j) de[j] = lamp[d.off + node_of(tid + j * NT)];
+  T gacc = T(0);                               // the system's slot (WHOLE, thread 0)
+  if (WHOLE && tid == 0) gacc = gslot[slots[blockIdx.x]];
   const int s = tid * MC;
+  // (a window takes the single step 0: constant bounds, so its body is not a loop)
+  const int step_hi = WHOLE ? k_hi - 1 : 0, step_lo = WHOLE ? k_lo : 0;
+  for (int step = step_hi; step >= step_lo; --step) {
+  const double* __restrict__ yn = state(step);
+  // lam' into the lanes' chunks (through LDS)
+#pragma unroll
+  for (int j = 0; j < MC; ++j) stage[padded(tid + j * NT)] = de[j];
+  __syncthreads();
 #pragma unroll
   for (int j = 0; j < MC; ++j) de[j] = stage[padded(s + j)];
   __syncthreads();
@@ -1467,7 +1481,7 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
   for (int q = 0; q < MC; ++q) de[q] = stage[padded(lm + q * NT)];
   __syncthreads();                             // mu read: the stage takes x
   // x = u^(k+1) of rows -1..W through the stage (every load in flight)
-  const double* __restrict__ xn = x + d.off;
+  const double* __restrict__ xn = state(step + 1);
   {
     const int lt = opaque_lane(tid);
     T ge = T(0);
@@ -1483,7 +1497,7 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
     if (tid < 2) stage[padded(tid == 0 ? 0 : W + 1)] = ge;
   }
   __syncthreads();
-  // finish the kept rows tid + q NT: lam = (1 - G) mu (coalesced stores), and the lane's partial sum of
+  // finish the kept rows tid + q NT: lam = (1 - G) mu (into de[q]), and the lane's partial sum of
   // -mu (2 x_j - x_{j-1} - x_{j+1}) in row order
   T g = T(0);
   const int lf = opaque_lane(tid);
@@ -1497,14 +1511,10 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
     const T xp = dir && j == n - 2 ? d.b : stage[padded(k + 2)];
     const T xj = stage[padded(k + 1)];
     const T G = (ypos >> q) & 1u ? d.r * (xj - xm) : d.r * (xp - xj);
-    lam[d.off + j] = (1.0 - G) * mu;
+    de[q] = (1.0 - G) * mu;
     g = g - mu * ((2.0 * xj - xm) - xp);
   }
-  if (dir && tid == 0) {
-    if (wd.start == 0) lam[d.off] = 0.0;
-    if (wd.start + W == R) lam[d.off + n - 1] = 0.0;
-  }
-  // the window's partial, summed in a fixed order
+  // the window's partial, summed in a fixed order (the barrier also ends this step's reads of the stage)
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) g = g + __shfl_xor(g, m, 64);
   if ((tid & 63) == 0) wave_val[tid >> 6] = g;
@@ -1513,9 +1523,22 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
     T tot = wave_val[0];
 #pragma unroll
     for (int k = 1; k < NT / 64; ++k) tot = tot + wave_val[k];
-    if constexpr (WHOLE) gslot[slots[blockIdx.x]] = gslot[slots[blockIdx.x]] + tot;
+    if constexpr (WHOLE) gacc = gacc + tot;
     else wpart[blockIdx.x] = tot;
   }
+  }
+  // lam of the kept rows (coalesced stores); Dirichlet end nodes carry none
+  const int ls = opaque_lane(tid);
+#pragma unroll
+  for (int q = 0; q < MC; ++q) {
+    const int k = ls + q * NT;
+    if (k >= wd.lo && k < wd.lo + wd.count) lam[d.off + node_of(k)] = de[q];
+  }
+  if (dir && tid == 0) {
+    if (wd.start == 0) lam[d.off] = 0.0;
+    if (wd.start + W == R) lam[d.off + n - 1] = 0.0;
+  }
+  if (WHOLE && tid == 0) gslot[slots[blockIdx.x]] = gacc;
 }
 
 constexpr int kSpikeWaves = kReduceBlock / 64;
@@ -2209,13 +2232,14 @@ hipError_t launch_btcs_window_reset(const burgers_ctx* ctx, const BtcsPlan& plan
 
 int btcs_window_halo() { return kWinHalo; }
 
-hipError_t launch_adj_btcs_whole(const burgers_ctx* ctx, const WinDesc* wins, int64_t n, const double* u,
-                                 const double* x, const double* lamp, double* lam, double* gslot,
-                                 const int32_t* slots) {
-  if (n <= 0) return hipSuccess;
+hipError_t launch_adj_btcs_whole(const burgers_ctx* ctx, const WinDesc* wins, int64_t n, const double* u0,
+                                 const double* useg, int64_t ustride, int k_lo, int k_hi, const double* lamp,
+                                 double* lam, double* gslot, const int32_t* slots) {
+  if (n <= 0 || k_hi <= k_lo) return hipSuccess;
   adj_btcs_window_kernel<kWholeRows / kWgChunk, true><<<static_cast<unsigned>(n), kWholeRows / kWgChunk, 0,
-                                                         ctx->stream>>>(ctx->inst.as<InstDesc>(), wins, u, x, lamp,
-                                                                        lam, nullptr, nullptr, nullptr, gslot, slots);
+                                                         ctx->stream>>>(ctx->inst.as<InstDesc>(), wins, u0, useg,
+                                                                        ustride, k_lo, k_hi, lamp, lam, nullptr,
+                                                                        nullptr, nullptr, gslot, slots);
   return hipGetLastError();
 }
 
@@ -2224,7 +2248,7 @@ hipError_t launch_adj_btcs_windows(const burgers_ctx* ctx, const WinDesc* wins, 
                                    int* flag_next) {
   if (n_win <= 0) return hipSuccess;
   adj_btcs_window_kernel<256><<<static_cast<unsigned>(n_win), 256, 0, ctx->stream>>>(
-      ctx->inst.as<InstDesc>(), wins, u, x, lamp, lam, wpart, flag_now, flag_next);
+      ctx->inst.as<InstDesc>(), wins, u, x, 0, 0, 1, lamp, lam, wpart, flag_now, flag_next);
   return hipGetLastError();
 }
 

@@ -914,7 +914,8 @@ hipError_t enqueue_adjoint_step(burgers_ctx* ctx, const double* y, const double*
   hipError_t e = hipSuccess;
   if (ap.n_btcs_tiles == 0) return e;
   if (ap.n_whole > 0)   // every BTCS system solved whole and exactly: nothing is left for the array path
-    return burgers::launch_adj_btcs_whole(ctx, ap.whole->as<burgers::WinDesc>(), ap.n_whole, y, x, lam_in, lam_out,
+    return burgers::launch_adj_btcs_whole(ctx, ap.whole->as<burgers::WinDesc>(), ap.n_whole, y, x, 0, 0, 1, lam_in,
+                                          lam_out,
                                           g, ap.whole_slot->as<int32_t>());
   const int* only = nullptr;
   if (ap.n_win > 0) {
@@ -1367,8 +1368,18 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
         return note(ctx, e);
       std::swap(lam_e, lam_e_next);
     }
-    // BTCS instances: one reverse step per launch
-    for (int64_t k = len - 1; ap.n_btcs_tiles > 0 && k >= 0; --k) {
+    // BTCS instances: the segment's reverse steps in one launch when every system is solved whole (lam
+    // on chip between them), else one reverse step per launch
+    if (ap.n_whole > 0) {
+      if ((e = burgers::launch_adj_btcs_whole(ctx, ap.whole->as<burgers::WinDesc>(), ap.n_whole,
+                                              reinterpret_cast<const double*>(at(c, cur, 0)),
+                                              reinterpret_cast<const double*>(at(c, cur, 1)), ctx->total, 0,
+                                              static_cast<int>(len), lam, lam_next, ap.gslot.as<double>(),
+                                              ap.whole_slot->as<int32_t>())) != hipSuccess)
+        return note(ctx, e);
+      std::swap(lam, lam_next);
+    }
+    for (int64_t k = len - 1; ap.n_btcs_tiles > 0 && ap.n_whole == 0 && k >= 0; --k) {
       if ((e = enqueue_adjoint_step(ctx, reinterpret_cast<const double*>(at(c, cur, k)),
                                     reinterpret_cast<const double*>(at(c, cur, k + 1)), lam, lam_next,
                                     rstep++)) != hipSuccess)

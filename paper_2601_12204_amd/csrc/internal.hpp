@@ -415,11 +415,14 @@ int btcs_chunks(int rows, int threads);
 // `only` (optional): solve only the systems of instances whose entry is nonzero.
 hipError_t launch_array_solve(const burgers_ctx* ctx, const BtcsPlan& plan, double* LA, double* LC,
                               double* LD, double* LX, const int* only = nullptr);
+// Adjoint BTCS steps k = k_hi - 1 .. k_lo of systems of exactly 16384 rows, each transposed system solved
+// whole (u^k at u0 for k = 0, else useg + (k - 1) ustride; lam^(k_hi) in lamp, lam^(k_lo) to lam, out of
+// place); each system's dJ/dD partial added to gslot[slots[b]] after every step.
+hipError_t launch_adj_btcs_whole(const burgers_ctx* ctx, const WinDesc* wins, int64_t n, const double* u0,
+                                 const double* useg, int64_t ustride, int k_lo, int k_hi, const double* lamp,
+                                 double* lam, double* gslot, const int32_t* slots);
 // Adjoint BTCS step of the long instances on truncated windows of the transposed system (lam from lamp
 // at the forward pair u -> x); per-window partials of dJ/dD into wpart; failed bounds flag instances.
-hipError_t launch_adj_btcs_whole(const burgers_ctx* ctx, const WinDesc* wins, int64_t n, const double* u,
-                                 const double* x, const double* lamp, double* lam, double* gslot,
-                                 const int32_t* slots);
 hipError_t launch_adj_btcs_windows(const burgers_ctx* ctx, const WinDesc* wins, int64_t n_win, const double* u,
                                    const double* x, const double* lamp, double* lam, double* wpart, int* flag_now,
                                    int* flag_next);
