@@ -1402,20 +1402,24 @@ __global__ __launch_bounds__(NT, 4) void adj_btcs_window_kernel(
   T de[MC];
 #pragma unroll
   for (int j = 0; j < MC; ++j) de[j] = lamp[d.off + node_of(tid + j * NT)];
-  T gacc = T(0);                               // the system's slot (WHOLE, thread 0)
+  __shared__ T gacc;                           // the system's running slot value (WHOLE, thread 0)
   if (WHOLE && tid == 0) gacc = gslot[slots[blockIdx.x]];
   const int s = tid * MC;
   // (a window takes the single step 0: constant bounds, so its body is not a loop)
   const int step_hi = WHOLE ? k_hi - 1 : 0, step_lo = WHOLE ? k_lo : 0;
   for (int step = step_hi; step >= step_lo; --step) {
   const double* __restrict__ yn = state(step);
-  // lam' into the lanes' chunks (through LDS)
+  // lam' into the lanes' chunks (through LDS; the addresses are formed here at every step, not kept live)
+  {
+    const int lw = opaque_lane(tid);
 #pragma unroll
-  for (int j = 0; j < MC; ++j) stage[padded(tid + j * NT)] = de[j];
-  __syncthreads();
+    for (int j = 0; j < MC; ++j) stage[padded(lw + j * NT)] = de[j];
+    __syncthreads();
+    const int lr = opaque_lane(tid) * MC;
 #pragma unroll
-  for (int j = 0; j < MC; ++j) de[j] = stage[padded(s + j)];
-  __syncthreads();
+    for (int j = 0; j < MC; ++j) de[j] = stage[padded(lr + j)];
+    __syncthreads();
+  }
   // y of rows -1..W (every load in flight at once), and max |y| over them; bit q of ypos: the upwind
   // side of row tid + q NT (y >= 0), for the finish
   T big = T(0);
