@@ -149,6 +149,9 @@ __device__ __forceinline__ void window_store(const double (&x)[kAdjWinChunk], co
 // gradient, against 54.4 ms with 131 registers and one workgroup per CU.)
 // Reverse steps k = k_hi - 1 down to k_lo of a segment: u^k at u0 for k = 0, else at useg + (k - 1) ustride
 // (binary64 states); lam^(k_hi) from lamp, lam^(k_lo) to lam (the window's kept nodes).
+// PERIODIC: every window of the launch belongs to a periodic instance (no boundary cases are compiled);
+// otherwise every window belongs to a Dirichlet one.
+template <bool PERIODIC>
 __global__ __launch_bounds__(kAdjWinLanes, 4) void adj_explicit_block_kernel(
     const InstDesc* __restrict__ inst, const AdjWindow* __restrict__ wins, const double* __restrict__ u0,
     const double* __restrict__ useg, int64_t ustride, int k_lo, int k_hi, const double* __restrict__ lamp,
@@ -159,12 +162,14 @@ __global__ __launch_bounds__(kAdjWinLanes, 4) void adj_explicit_block_kernel(
   const AdjWindow w = wins[blockIdx.x];
   const InstDesc d = inst[w.inst];
   const int n = d.n;
-  const bool periodic = d.bc == kPeriodic;
+  constexpr bool periodic = PERIODIC;
   const double r = d.r, D = d.D;
   const int t = threadIdx.x;
   const int P = (w.width + M - 1) / M;         // lanes holding nodes; the last holds mlast
   const int mlast = w.width - M * (P - 1);
   const int m = t < P ? (t == P - 1 ? mlast : M) : 0;
+  // the lane's kept nodes are a prefix of its chunk (w.lo is a multiple of M): the first kc
+  const int kc = M * t >= w.lo ? min(M, max(0, w.lo + w.count - M * t)) : 0;
   // the lane's tile (16-lane groups start on tile boundaries) and its running dJ/dD sum
   const bool tile_lane = (t & 15) == 0 && M * t >= w.lo && M * t < w.lo + w.count;
   const int slot = w.slot0 + (M * t - w.lo) / kAdjSumTile;
@@ -204,8 +209,7 @@ __global__ __launch_bounds__(kAdjWinLanes, 4) void adj_explicit_block_kernel(
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         if (j < m) {
-          const int wj = M * t + j;
-          int jn = w.first + wj;
+          int jn = w.first + M * t + j;         // instance node (only a Dirichlet window needs it)
           if (jn >= n) jn -= n;
           const double uj = U[j];
           const double uprev = j == 0 ? uL : U[j > 0 ? j - 1 : 0];
@@ -220,7 +224,7 @@ __global__ __launch_bounds__(kAdjWinLanes, 4) void adj_explicit_block_kernel(
             const double self = uj >= 0.0 ? ((1.0 - r * (uj - um)) - r * uj) - 2.0 * D
                                           : ((1.0 - r * (up - uj)) + r * uj) - 2.0 * D;
             acc = self * lj;
-            if (wj >= w.lo && wj < w.lo + w.count) g = g + lj * ((up + um) - 2.0 * uj);
+            if (j < kc) g = g + lj * ((up + um) - 2.0 * uj);
             // node j+1 reads u_j as its left neighbour
             if (periodic || jn + 1 <= n - 2) acc = acc + (unext >= 0.0 ? r * unext + D : D) * lnext;
             // node j-1 reads u_j as its right neighbour
@@ -349,12 +353,16 @@ __global__ void fill_kernel(double* __restrict__ p, int64_t n, double v) {
 
 int adjoint_tile_nodes() { return kAdjTile; }
 
-hipError_t launch_adj_explicit_block(const burgers_ctx* ctx, const AdjWindow* wins, int64_t n_wins, const double* u0,
-                                     const double* useg, int64_t ustride, int k_lo, int k_hi, const double* lamp,
-                                     double* lam, double* gslot) {
+hipError_t launch_adj_explicit_block(const burgers_ctx* ctx, const AdjWindow* wins, int64_t n_wins, int64_t n_periodic,
+                                     const double* u0, const double* useg, int64_t ustride, int k_lo, int k_hi,
+                                     const double* lamp, double* lam, double* gslot) {
   if (n_wins <= 0 || k_hi <= k_lo) return hipSuccess;
-  adj_explicit_block_kernel<<<static_cast<unsigned>(n_wins), kAdjWinLanes, 0, ctx->stream>>>(
-      ctx->inst.as<InstDesc>(), wins, u0, useg, ustride, k_lo, k_hi, lamp, lam, gslot);
+  if (n_periodic > 0)
+    adj_explicit_block_kernel<true><<<static_cast<unsigned>(n_periodic), kAdjWinLanes, 0, ctx->stream>>>(
+        ctx->inst.as<InstDesc>(), wins, u0, useg, ustride, k_lo, k_hi, lamp, lam, gslot);
+  if (n_wins > n_periodic)
+    adj_explicit_block_kernel<false><<<static_cast<unsigned>(n_wins - n_periodic), kAdjWinLanes, 0, ctx->stream>>>(
+        ctx->inst.as<InstDesc>(), wins + n_periodic, u0, useg, ustride, k_lo, k_hi, lamp, lam, gslot);
   return hipGetLastError();
 }
 

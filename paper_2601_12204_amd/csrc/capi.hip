@@ -864,6 +864,13 @@ burgers_status ensure_adjoint(burgers_ctx* ctx) {
   }
   slot_begin[ctx->count] = slot;
   hipError_t e;
+  // windows of periodic instances first (their launch compiles no boundary cases)
+  std::stable_partition(ew.begin(), ew.end(), [&](const burgers::AdjWindow& w) {
+    return ctx->probs[w.inst].bc == BURGERS_BC_PERIODIC;
+  });
+  ap->n_exp_wins_periodic = std::count_if(ew.begin(), ew.end(), [&](const burgers::AdjWindow& w) {
+    return ctx->probs[w.inst].bc == BURGERS_BC_PERIODIC;
+  });
   ap->exp_wins = std::make_unique<DevBuf>();
   ap->btcs_tiles = std::make_unique<DevBuf>();
   ap->slot_begin = std::make_unique<DevBuf>();
@@ -1361,7 +1368,7 @@ burgers_status burgers_adjoint(burgers_ctx* ctx, const void* u0, const void* lam
     for (int64_t hi = len; ap.n_exp_wins > 0 && hi > 0; hi -= burgers::kAdjHalo) {
       const int64_t lo = std::max<int64_t>(0, hi - burgers::kAdjHalo);
       if ((e = burgers::launch_adj_explicit_block(ctx, ap.exp_wins->as<burgers::AdjWindow>(), ap.n_exp_wins,
-                                                  reinterpret_cast<const double*>(at(c, cur, 0)),
+                                                  ap.n_exp_wins_periodic, reinterpret_cast<const double*>(at(c, cur, 0)),
                                                   reinterpret_cast<const double*>(at(c, cur, 1)), ctx->total,
                                                   static_cast<int>(lo), static_cast<int>(hi), lam_e, lam_e_next,
                                                   ap.gslot.as<double>())) != hipSuccess)

@@ -256,6 +256,7 @@ struct ExplicitPlan {
 struct AdjointPlan {
   std::unique_ptr<DevBuf> exp_wins, btcs_tiles;     // AdjWindow[] of the explicit instances, AdjTile[]
   int64_t n_exp_wins = 0, n_btcs_tiles = 0;
+  int64_t n_exp_wins_periodic = 0;                 // the first windows of exp_wins, of periodic instances
   std::unique_ptr<DevBuf> slot_begin;               // int32[count + 1]
   int64_t n_slots = 0;
   BtcsPlan solve;                                   // partition hierarchy over the transposed systems
@@ -359,12 +360,13 @@ int explicit_block_capacity();
 
 // adjoint.hip
 int adjoint_tile_nodes();   // nodes per dJ/dD slot of a BTCS instance
-// Explicit reverse steps k = k_hi - 1 .. k_lo over the windows: u^k at u0 (k = 0) or useg + (k - 1) ustride,
-// lam^(k_hi) in lamp, lam^(k_lo) to lam (out of place), dJ/dD added to the windows' tile slots of gslot.
-// Windows of longer instances take at most kAdjHalo steps per launch.
-hipError_t launch_adj_explicit_block(const burgers_ctx* ctx, const AdjWindow* wins, int64_t n_wins, const double* u0,
-                                     const double* useg, int64_t ustride, int k_lo, int k_hi, const double* lamp,
-                                     double* lam, double* gslot);
+// Explicit reverse steps k = k_hi - 1 .. k_lo over the windows (those of periodic instances first, n_periodic
+// of them): u^k at u0 (k = 0) or useg + (k - 1) ustride, lam^(k_hi) in lamp, lam^(k_lo) to lam (out of
+// place), dJ/dD added to the windows' tile slots of gslot.  Windows of longer instances take at most
+// kAdjHalo steps per launch.
+hipError_t launch_adj_explicit_block(const burgers_ctx* ctx, const AdjWindow* wins, int64_t n_wins, int64_t n_periodic,
+                                     const double* u0, const double* useg, int64_t ustride, int k_lo, int k_hi,
+                                     const double* lamp, double* lam, double* gslot);
 // `only` (optional): only the instances whose entry is nonzero (those whose windows flagged a failed
 // bound); the finish launch also adds the windows' partials (wins/win_slot/wpart, n_win may be 0).
 hipError_t launch_adj_btcs_assemble(const burgers_ctx* ctx, const AdjTile* tiles, int64_t n_tiles,
