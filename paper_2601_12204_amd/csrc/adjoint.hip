@@ -181,8 +181,6 @@ __global__ __launch_bounds__(kAdjWinLanes, 4) void adj_explicit_block_kernel(
   window_fetch(state(k_hi - 1), w, n, V);
   for (int k = k_hi - 1; k >= k_lo; --k) {
     window_spread(V, region, U);
-    // the next step's state is in flight during this step (the barrier below waits for LDS only)
-    if (k > k_lo) window_fetch(state(k - 1), w, n, V);
     const int b = k & 1;
     if (t < P) {
       double ul = U[M - 1], ll = L[M - 1];
@@ -199,12 +197,16 @@ __global__ __launch_bounds__(kAdjWinLanes, 4) void adj_explicit_block_kernel(
     }
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
     double g = 0.0;
+    // neighbours beyond the window's ends wrap around it: exact for a whole periodic instance, and only
+    // the halo is affected otherwise (the indices are formed here, not kept live across the step)
+    const int tf = fresh_lane();
+    const int tl = tf > 0 ? tf - 1 : P - 1, tr = tf < P - 1 ? tf + 1 : 0;
+    const double uL = ends[b][1][tl], uR = ends[b][0][tr];
+    const double lL = ends[b][3][tl], lR = ends[b][2][tr];
+    // the next step's state is in flight during this step's update: issued after every read that the
+    // update waits for, since a wait on the in-order memory counter would also wait for these loads
+    if (k > k_lo) window_fetch(state(k - 1), w, n, V);
     if (t < P) {
-      // neighbours beyond the window's ends wrap around it: exact for a whole periodic instance, and
-      // only the halo is affected otherwise
-      const int tl = t > 0 ? t - 1 : P - 1, tr = t < P - 1 ? t + 1 : 0;
-      const double uL = ends[b][1][tl], uR = ends[b][0][tr];
-      const double lL = ends[b][3][tl], lR = ends[b][2][tr];
       double lprev = lL;                        // lam^(k+1) of the node before, kept before it is overwritten
 #pragma unroll
       for (int j = 0; j < M; ++j) {
