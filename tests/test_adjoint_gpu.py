@@ -221,6 +221,33 @@ def test_adjoint_recording_recompute_equals_per_step(depth):
     assert np.all(np.abs(gn - rgn) <= bound), (np.abs(gn - rgn), bound)
 
 
+def test_adjoint_long_segments():
+    """Segments longer than the explicit windows' halo (256 steps), which the blocked reverse steps split
+    into several launches, and 16384-row BTCS systems whose reverse steps run a whole 600-step segment in
+    one launch: gradients against the oracle, and bitwise equal for checkpoint intervals 600, 250 and 1."""
+    problems, states = [], []
+    for k, (n, bc, scheme) in enumerate([(30000, W.BC_PERIODIC, W.EXPLICIT), (20001, W.BC_DIRICHLET, W.EXPLICIT),
+                                         (777, W.BC_PERIODIC, W.EXPLICIT), (16384, W.BC_PERIODIC, W.BTCS),
+                                         (16386, W.BC_DIRICHLET, W.BTCS)]):
+        b = W.random_batch(2300 + k, 1, n, n, bc=bc, scheme=scheme, amplitude=2.0)
+        problems.append(b.problems[0])
+        states.append(b.instance(0))
+    batch = set_cfl_steps(W._pack(problems, states), btcs_factor=5.0)
+    lam = np.random.default_rng(29).standard_normal(len(batch.u0))
+    nsteps = 600
+    announce(f"adjoint long segments, {batch.count} instances, {nsteps} steps")
+    g, gn = _device_adjoint_plan(batch, lam, nsteps, 600)
+    for K in (250, 1):
+        gk, gnk = _device_adjoint_plan(batch, lam, nsteps, K)
+        assert np.array_equal(gk, g) and np.array_equal(gnk, gn), K
+    rg, rgn = oracle.adjoint(batch.problems, batch.u0, batch.offsets, lam, nsteps)
+    for b in range(batch.count):
+        lo, hi = batch.offsets[b], batch.offsets[b + 1]
+        assert oracle.rel_max_abs(g[lo:hi], rg[lo:hi]) <= TOL, (b, batch.problems[b])
+    bound = _nu_bound(batch, lam, nsteps, rgn)
+    assert np.all(np.abs(gn - rgn) <= bound), (np.abs(gn - rgn), bound)
+
+
 @pytest.mark.parametrize("scheme", [W.EXPLICIT, W.BTCS])
 def test_c5_adjoint_full_size_sampled(scheme):
     """The gradient workload at its real size, in the benchmark's configuration: 256 periodic instances
