@@ -41,7 +41,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // ---- Explicit reverse steps, blocked ----------------------------------------------------------------
 // lam^k = (dE/du at u^k)^T lam^(k+1) is a 3-point gather stencil whose coefficients come from u^k alone.
-// A workgroup of 512 lanes holds lam over a window of up to 8192 nodes (16 consecutive nodes per lane) in
+// A workgroup of 256 lanes holds lam over a window of up to 4096 nodes (16 consecutive nodes per lane) in
 // registers for a run of reverse steps: each step reads u^k of the window from HBM (coalesced, passed to
 // the lanes' chunks through a region of LDS private to each wave), exchanges the chunks' end values of u
 // and lam through LDS, and updates lam in place.  lam is read once and written once per launch.  Windows
@@ -55,7 +55,7 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // sum (loaded from its slot at launch start, stored at the end).  Tiles are aligned to 16-lane groups in
 // every window, so each (tile, step) partial is formed alike whichever window and launch computes it:
 // the gradient does not depend on how the steps are grouped into launches (the checkpoint interval).
-constexpr int kAdjWinLanes = 512;
+constexpr int kAdjWinLanes = 256;
 constexpr int kAdjWinChunk = 16;
 constexpr int kAdjWinRegion = 32 * (kAdjWinChunk + 1);   // a half-wave's chunks, padded by one per chunk
 static_assert(kAdjWinLanes * kAdjWinChunk == kAdjWinNodes, "window capacity");
@@ -145,8 +145,9 @@ __device__ __forceinline__ void window_store(const double (&x)[kAdjWinChunk], co
   }
 }
 
-// (Two workgroups per CU, 128 registers, the next step's loads in flight: C5, 256 x 16384, 49.0 ms per
-// gradient, against 54.4 ms with 131 registers and one workgroup per CU.)
+// (Four workgroups of 256 lanes per CU, 128 registers, the next step's loads in flight: C5, 256 x 16384,
+// 36.6 ms per gradient, against 41.5 ms with windows of 8192 nodes on 512 lanes, two per CU, whose halos
+// are a smaller share; 54.4 ms with 131 registers and one 512-lane workgroup per CU.)
 // Reverse steps k = k_hi - 1 down to k_lo of a segment: u^k at u0 for k = 0, else at useg + (k - 1) ustride
 // (binary64 states); lam^(k_hi) from lamp, lam^(k_lo) to lam (the window's kept nodes).
 // PERIODIC: every window of the launch belongs to a periodic instance (no boundary cases are compiled);

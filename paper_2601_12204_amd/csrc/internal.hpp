@@ -82,7 +82,7 @@ struct AdjTile {
 struct AdjWindow {
   int32_t inst, first, width, lo, count, slot0;
 };
-constexpr int kAdjWinNodes = 8192;   // window capacity (512 lanes x 16 nodes)
+constexpr int kAdjWinNodes = 4096;   // window capacity (256 lanes x 16 nodes)
 constexpr int kAdjHalo = 256;        // halo nodes per side of a window of a longer instance; steps per launch
 constexpr int kAdjSumTile = 256;     // nodes per dJ/dD slot of an explicit instance
 
