@@ -225,7 +225,7 @@ burgers_status burgers_run_mixed(burgers_ctx* ctx, void* u, int64_t explicit_ste
  * and 2.7.3).  Given the initial state u0 and lambda_T = dJ/du(t_T) after nsteps steps of each
  * instance's scheme, write grad_u0 = dJ/du0 (packed layout) and grad_nu[b] = dJ/dnu_b (count values,
  * element type of the context).  Forward states are recomputed from checkpoints stored every
- * ckpt_every >= 1 steps: the context holds ceil(nsteps / ckpt_every) + 2 min(ckpt_every, nsteps) + 2
+ * ckpt_every >= 1 steps: the context holds at most ceil(nsteps / ckpt_every) + 2 min(ckpt_every, nsteps) + 2
  * states of device memory (kept for later calls), and the results do not depend on ckpt_every, bit
  * for bit.  All four pointers are device memory; u0 and lambda_T are not modified.
  * Dirichlet boundary nodes are constants, so their entries of grad_u0 are zero.  The upwind switch is
