@@ -545,7 +545,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--quick", action="store_true", help="skip the side measurements")
     ap.add_argument("--legs", default="c2,c2f32,c2plain,c2rk4,c2cn,c2newton,c1,c3,c4,c5,serve",
-                    help="comma-separated side measurements to run (profiling runs select one)")
+                    help="comma-separated side measurements to run (profiling runs select one; c5seg, "
+                         "one 100-step checkpoint segment of the C5 gradients, only when named)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--exp-steps", type=int, default=10_000, help="explicit steps per step (profiling runs)")
     ap.add_argument("--btcs-steps", type=int, default=1_000, help="BTCS steps per step (profiling runs)")
@@ -607,6 +608,10 @@ def main():
         log("C5 adjoint")
         extra["c5_adjoint_explicit"] = bench_c5_adjoint(B, torch, W.EXPLICIT)
         extra["c5_adjoint_btcs"] = bench_c5_adjoint(B, torch, W.BTCS)
+    if "c5seg" in legs:   # not a default leg: one checkpoint segment on one stream, for counter runs
+        log("C5 adjoint, one segment")
+        extra["c5seg_adjoint_explicit"] = bench_c5_adjoint(B, torch, W.EXPLICIT, nsteps=100, ckpt=100)
+        extra["c5seg_adjoint_btcs"] = bench_c5_adjoint(B, torch, W.BTCS, nsteps=100, ckpt=100)
     if "serve" in legs:
         log("serving")
         extra["serve"] = bench_serve(B, torch, duration=args.serve_seconds, runs=args.serve_runs)
